@@ -1,0 +1,218 @@
+/*
+ * cpd.h -- C ABI of libcpd: CSF-MTTKRP and sparse CP-ALS on one MI355X (gfx950).
+ *
+ * The operations follow "Parallel Sparse Tensor Decomposition in Chapel"
+ * (Rolinger, Simon, Krieger; arXiv:1812.05961): CP-ALS of Algorithm 1
+ * (Section III), whose MTTKRP is computed on one compressed sparse fiber (CSF)
+ * tree per mode order (Section III), after the one-time sort of the nonzeros
+ * (the "Sort" routine of Section V-B / Table III).
+ *
+ * Conventions for every entry point
+ *   - Pointers documented as "device" are HIP device pointers (for example
+ *     torch.Tensor.data_ptr() of a CUDA tensor); "host" pointers are CPU memory.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *     GPU work of a call is ordered on that stream.  A call returns once its
+ *     work is queued unless stated otherwise.
+ *   - Calls return a cpd_status and never abort or throw.  On failure
+ *     cpd_last_error() gives a message for the calling thread.
+ *   - The caller owns every buffer it passes; the library never frees them.
+ *     Objects the library creates (cpd_csf) are freed by their *_free call.
+ *   - Tensors have 2..8 modes, each of length 1..2^31-1, and 1..2^31-1
+ *     nonzeros; ranks are 1..64.  Indices are 0-based int32.
+ *   - Factor matrices are row-major: element (i, r) at ptr[i * ld + r].
+ */
+#ifndef CPD_H
+#define CPD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CPD_OK = 0,
+    CPD_EINVAL = 1,        /* bad argument: sizes, ranges, indices, null pointers */
+    CPD_ENOMEM = 2,        /* a device or host allocation failed */
+    CPD_EHIP = 3,          /* a HIP runtime call failed */
+    CPD_EUNSUPPORTED = 4   /* valid request this build does not handle */
+} cpd_status;
+
+/* Gather precision of the MTTKRP (factor rows read from HBM). */
+enum { CPD_FP32 = 0, CPD_BF16_GATHER = 1 };
+
+/* Conflict handling where output rows collide (Section V-D2: locks versus
+ * privatised buffers).  On the GPU "atomic" replaces the paper's mutex pool. */
+enum { CPD_VARIANT_AUTO = 0, CPD_VARIANT_ATOMIC = 1, CPD_VARIANT_PRIVATE = 2 };
+
+/* Kernel family: AUTO picks; ROW = one factor row per lane (fused
+ * accumulation, for root/internal levels); LANE = the rank spread over lanes
+ * (any level). */
+enum { CPD_KERNEL_AUTO = 0, CPD_KERNEL_ROW = 1, CPD_KERNEL_LANE = 2 };
+
+#define CPD_MAX_MODES 8
+#define CPD_MAX_RANK 64
+
+/* Last error message of the calling thread ("" if none). */
+const char *cpd_last_error(void);
+
+/* ABI version of this library (incremented on incompatible changes). */
+int32_t cpd_abi_version(void);
+
+/* ---------------------------------------------------------------------------
+ * CSF construction (Section III's compressed sparse fiber; the paper's "Sort"
+ * preprocessing, Section V-C).
+ *
+ * Opaque handle to one CSF tree held in device memory owned by the library.
+ * Level l (0 = root) of a tree with mode order `order` holds one node per
+ * distinct index prefix (i_order[0], ..., i_order[l]) of the sorted nonzeros:
+ *   fids[l]  int32, count[l] entries: index i_order[l] of each node;
+ *   fptr[l]  int32, count[l]+1 entries (l < N-1): first child of each node at
+ *            level l+1, and fptr[l][count[l]] = count[l+1];
+ *   vals     float, count[N-1] entries: leaf values.
+ * Nonzeros with equal coordinates are merged into one whose value is the
+ * float32 sum of the duplicates in input order.
+ */
+typedef struct cpd_csf_s *cpd_csf;
+
+/* Build a CSF from COO.
+ *   nmodes  N in [2, 8];  dims: host, N lengths;  nnz in [1, 2^31-1].
+ *   inds    host array of N device pointers, each nnz int32 indices.
+ *   vals    device, nnz floats.
+ *   order   host, a permutation of 0..N-1 (root first), or NULL for modes by
+ *           ascending length, ties to the lower mode.
+ *   out     receives the handle (NULL on failure).
+ * Checks every index against its dim on the device (one 4-byte read back) and
+ * reads the level counts back: the call waits for `stream` before returning.
+ * CPD_EUNSUPPORTED when sum of ceil(log2 dims) exceeds 128 bits.
+ * The input arrays are not modified and may be freed after the call. */
+cpd_status cpd_csf_build(int32_t nmodes, const int64_t *dims, int64_t nnz,
+                         const int32_t *const *inds, const float *vals, const int32_t *order,
+                         void *stream, cpd_csf *out);
+
+/* Mode count, mode order (host, N entries) and level counts (host, N
+ * entries; count[N-1] = nonzeros after merging).  Null outputs are skipped. */
+cpd_status cpd_csf_info(cpd_csf csf, int32_t *nmodes, int32_t *order, int64_t *counts);
+
+/* Copy level `level` to caller device buffers: fids (count[level] int32),
+ * fptr (count[level]+1 int32, levels < N-1 only) and vals (count[N-1]
+ * floats, leaf level only).  Null outputs are skipped. */
+cpd_status cpd_csf_export(cpd_csf csf, int32_t level, int32_t *fids, int32_t *fptr, float *vals,
+                          void *stream);
+
+/* Work split of the MTTKRP kernels: the leaves are cut into tiles of
+ * tile_nnz consecutive nonzeros, and for each tile t the node holding leaf
+ * t*tile_nnz is found at every level l < N-1.  Writes starts[l * ntiles + t]
+ * (device, (N-1) * ntiles int32, or NULL to only query) and *ntiles (host). */
+cpd_status cpd_csf_tiles(cpd_csf csf, int32_t tile_nnz, int32_t *starts, int64_t *ntiles,
+                         void *stream);
+
+/* Free the handle and its device arrays (waits for work queued on them). */
+void cpd_csf_free(cpd_csf csf);
+
+/* ---------------------------------------------------------------------------
+ * MTTKRP (Algorithm 1, lines 5, 8, 11: Y = X_(n) times the Khatri-Rao product
+ * of the other factors), computed on the CSF tree, element-wise:
+ *     Y(i, r) = sum over nonzeros with i_mode = i of x * prod_{m != mode} A_m(i_m, r).
+ * `mode` may sit at any level of the tree (root, internal or leaf). */
+typedef struct {
+    int32_t precision;   /* CPD_FP32 or CPD_BF16_GATHER */
+    int32_t variant;     /* CPD_VARIANT_* */
+    int32_t kernel;      /* CPD_KERNEL_* */
+    int32_t tile_nnz;    /* leaves per work unit; 0 = automatic */
+} cpd_mttkrp_opts;
+
+/* factors: host array of N device pointers (the entry for `mode` is not
+ *          read); float rows for CPD_FP32, bfloat16 bits (uint16) for
+ *          CPD_BF16_GATHER; row stride ld elements (ld >= rank).
+ * out:     device, dims[mode] x rank floats with row stride ldo >= rank;
+ *          overwritten (columns >= rank untouched).
+ * opts:    NULL for defaults.
+ * Uses a library-allocated workspace for CPD_VARIANT_PRIVATE with per-XCD
+ * copies and for the first call with a new tile width. */
+cpd_status cpd_mttkrp(cpd_csf csf, const void *const *factors, int32_t ld, int32_t rank,
+                      int32_t mode, float *out, int32_t ldo, const cpd_mttkrp_opts *opts,
+                      void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Dense steps of Algorithm 1 (FP64 on the GPU). */
+
+/* G = A^T A (the A^T A terms of Algorithm 1, lines 4, 7, 10).
+ * A: device, rows x rank floats, stride ld.  G: device, rank x rank doubles. */
+cpd_status cpd_gram(const float *A, int64_t rows, int32_t rank, int32_t ld, double *G,
+                    void *stream);
+
+/* One mode update after its MTTKRP (Algorithm 1, lines 4-6 and 7-9, ...):
+ *   V = Hadamard product of grams[m] over m != mode;
+ *   A = Y V^+, by Cholesky when every pivot exceeds rank*eps*max(diag V),
+ *       else by the Moore-Penrose inverse from a Jacobi eigendecomposition
+ *       dropping eigenvalues <= rank*eps*max eigenvalue;
+ *   lambda_r = 2-norm of column r of A; A(:, r) /= lambda_r when > 0.
+ * grams:    host array of nmodes device pointers to rank x rank doubles.
+ * Y:        device, rows x rank floats (stride ldy).
+ * A:        device, rows x rank floats written (stride lda).
+ * A_bf16:   device or NULL, rows x rank bfloat16 copy of A (stride ldb),
+ *           round-to-nearest-even of the float values.
+ * lambda:   device, rank doubles written.
+ * G_new:    device or NULL, rank x rank doubles: A^T A of the written A.
+ * used_pinv: device or NULL, one int32 set to 1 when the fallback ran, else 0. */
+cpd_status cpd_solve_normalize(const double *const *grams, int32_t nmodes, int32_t mode,
+                               const float *Y, int64_t rows, int32_t rank, int32_t ldy,
+                               float *A, int32_t lda, uint16_t *A_bf16, int32_t ldb,
+                               double *lambda, double *G_new, int32_t *used_pinv,
+                               void *stream);
+
+/* Fit of K = [[lambda; A_0..A_{N-1}]] (Algorithm 1, line 13):
+ *   fit = 1 - sqrt(max(0, normX2 - 2 <X,K> + ||K||^2)) / sqrt(normX2), with
+ *   <X,K> = sum_r lambda_r sum_i A_last(i, r) Y_last(i, r) (Y_last = MTTKRP of
+ *   the last mode with the other final factors) and
+ *   ||K||^2 = lambda^T (Hadamard of all grams) lambda.
+ * All pointers device except `grams` (host array of nmodes device pointers);
+ * fit: one double written on the device. */
+cpd_status cpd_fit(double normX2, const double *lambda, const float *A_last, int32_t lda,
+                   const float *Y_last, int32_t ldy, int64_t rows, int32_t rank,
+                   const double *const *grams, int32_t nmodes, double *fit, void *stream);
+
+/* out (device, one double) = sum of squares of vals (device, n floats). */
+cpd_status cpd_sumsq(const float *vals, int64_t n, double *out, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * CP-ALS (Algorithm 1) from COO. */
+typedef struct {
+    int32_t precision;       /* CPD_FP32 or CPD_BF16_GATHER (MTTKRP gathers only;
+                                the solve, norms and fit stay FP64; with BF16 the
+                                final fit is recomputed with FP32 gathers) */
+    int32_t variant;         /* CPD_VARIANT_* for every MTTKRP */
+    int32_t kernel;          /* CPD_KERNEL_* */
+    int32_t tile_nnz;        /* 0 = automatic */
+    int32_t single_csf;      /* 0: one CSF per mode, rooted at that mode (the
+                                default: every MTTKRP is a root-level one);
+                                1: one CSF in `order` (or ascending lengths) */
+    int32_t reserved;
+    const int32_t *order;    /* host, N entries, or NULL (used with single_csf) */
+    const float *const *init;/* host array of N device pointers to I_m x rank
+                                floats (stride rank), or NULL: seeded U(0,1) */
+    uint64_t seed;           /* seed of the U(0,1) initialisation */
+    double *fit_trace;       /* host, max_iters doubles, or NULL */
+    double *timing_ms;       /* host, 4 + max_iters*(N+1) doubles, or NULL:
+                                [0] CSF build, [1] all iterations, [2] final fit,
+                                [3] total; then per iteration: N MTTKRP times
+                                and the iteration time */
+} cpd_als_opts;
+
+/* Run CP-ALS with `rank` components for at most max_iters sweeps; when tol > 0
+ * stop from the second sweep on once |fit - previous fit| < tol.
+ * factors_out: host array of N device pointers, I_m x rank floats (stride
+ *              rank), written with unit-norm columns.
+ * lambda_out:  host, rank doubles.  fit_out, iters_out: host.
+ * Waits for `stream` before returning. */
+cpd_status cpd_als(int32_t nmodes, const int64_t *dims, int64_t nnz, const int32_t *const *inds,
+                   const float *vals, int32_t rank, int32_t max_iters, double tol,
+                   const cpd_als_opts *opts, float *const *factors_out, double *lambda_out,
+                   double *fit_out, int32_t *iters_out, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CPD_H */

@@ -1,0 +1,289 @@
+"""Python binding of libcpd (ctypes): argument marshalling only.
+
+Every step runs in the HIP library; this module passes torch tensors' device
+pointers, sizes and the current HIP stream through the C ABI of
+``include/cpd.h`` under the same names.  It raises if the library is missing:
+there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcpd.so")
+
+CPD_OK, CPD_EINVAL, CPD_ENOMEM, CPD_EHIP, CPD_EUNSUPPORTED = range(5)
+FP32, BF16_GATHER = 0, 1
+VARIANT = {"auto": 0, "atomic": 1, "private": 2}
+KERNEL = {"auto": 0, "row": 1, "lane": 2}
+PRECISION = {"fp32": FP32, "bf16": BF16_GATHER}
+MAX_MODES = 8
+
+_P = ctypes.c_void_p
+_I32, _I64, _F64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+
+
+class CpdError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("cpd status %d: %s" % (status, msg))
+        self.status = status
+
+
+class MttkrpOpts(ctypes.Structure):
+    _fields_ = [("precision", _I32), ("variant", _I32), ("kernel", _I32), ("tile_nnz", _I32)]
+
+
+class AlsOpts(ctypes.Structure):
+    _fields_ = [("precision", _I32), ("variant", _I32), ("kernel", _I32), ("tile_nnz", _I32),
+                ("single_csf", _I32), ("reserved", _I32), ("order", _P), ("init", _P),
+                ("seed", ctypes.c_uint64), ("fit_trace", _P), ("timing_ms", _P)]
+
+
+_lib = None
+
+# name -> (restype, argtypes)
+_SIGS = {
+    "cpd_last_error": (ctypes.c_char_p, []),
+    "cpd_abi_version": (_I32, []),
+    "cpd_csf_build": (_I32, [_I32, _P, _I64, _P, _P, _P, _P, _P]),
+    "cpd_csf_info": (_I32, [_P, _P, _P, _P]),
+    "cpd_csf_export": (_I32, [_P, _I32, _P, _P, _P, _P]),
+    "cpd_csf_tiles": (_I32, [_P, _I32, _P, _P, _P]),
+    "cpd_csf_free": (None, [_P]),
+    "cpd_mttkrp": (_I32, [_P, _P, _I32, _I32, _I32, _P, _I32, _P, _P]),
+    "cpd_gram": (_I32, [_P, _I64, _I32, _I32, _P, _P]),
+    "cpd_solve_normalize": (_I32, [_P, _I32, _I32, _P, _I64, _I32, _I32, _P, _I32, _P, _I32, _P,
+                                   _P, _P, _P]),
+    "cpd_fit": (_I32, [_F64, _P, _P, _I32, _P, _I32, _I64, _I32, _P, _I32, _P, _P]),
+    "cpd_sumsq": (_I32, [_P, _I64, _P, _P]),
+    "cpd_als": (_I32, [_I32, _P, _I64, _P, _P, _I32, _I32, _F64, _P, _P, _P, _P, _P, _P]),
+}
+
+
+def lib():
+    """The loaded libcpd.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libcpd.so is not built (run python -m paper_1812_05961_amd.build)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return list(_SIGS)
+
+
+def _check(status):
+    if status != CPD_OK:
+        raise CpdError(status, lib().cpd_last_error().decode())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptrs(ts):
+    arr = (ctypes.c_void_p * len(ts))()
+    for i, t in enumerate(ts):
+        arr[i] = None if t is None else t.data_ptr()
+    return arr
+
+
+def _i64s(xs):
+    return (ctypes.c_int64 * len(xs))(*[int(x) for x in xs])
+
+
+def _need_cuda(t, name, dtype=None):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError("%s must be a CUDA tensor" % name)
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError("%s must be %s, not %s" % (name, dtype, t.dtype))
+    return t
+
+
+def _coo_args(inds, vals, dims):
+    if isinstance(inds, torch.Tensor):
+        inds = [inds[m] for m in range(inds.shape[0])]
+    inds = [_need_cuda(i, "inds").to(torch.int32).contiguous() for i in inds]
+    vals = _need_cuda(vals, "vals").to(torch.float32).contiguous()
+    for i in inds:
+        if i.numel() != vals.numel():
+            raise ValueError("index and value arrays differ in length")
+    return inds, vals, [int(d) for d in dims]
+
+
+class Csf:
+    """A CSF tree held by the library (cpd_csf)."""
+
+    def __init__(self, handle: int):
+        self.handle = ctypes.c_void_p(handle)
+        nm = _I32()
+        order = (_I32 * MAX_MODES)()
+        counts = (_I64 * MAX_MODES)()
+        _check(lib().cpd_csf_info(self.handle, ctypes.byref(nm), order, counts))
+        self.nmodes = nm.value
+        self.order = [order[i] for i in range(self.nmodes)]
+        self.counts = [counts[i] for i in range(self.nmodes)]
+
+    def free(self):
+        if self.handle:
+            lib().cpd_csf_free(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def export(self, level: int, stream=None):
+        """(fids, fptr or None, vals or None) of one level, as CUDA tensors."""
+        dev = torch.device("cuda")
+        fids = torch.empty(self.counts[level], dtype=torch.int32, device=dev)
+        leaf = level == self.nmodes - 1
+        fptr = None if leaf else torch.empty(self.counts[level] + 1, dtype=torch.int32, device=dev)
+        vals = torch.empty(self.counts[level], dtype=torch.float32, device=dev) if leaf else None
+        _check(lib().cpd_csf_export(self.handle, level, fids.data_ptr(),
+                                    None if fptr is None else fptr.data_ptr(),
+                                    None if vals is None else vals.data_ptr(), _stream(stream)))
+        return fids, fptr, vals
+
+    def tiles(self, tile_nnz: int, stream=None):
+        nt = _I64()
+        _check(lib().cpd_csf_tiles(self.handle, tile_nnz, None, ctypes.byref(nt), _stream(stream)))
+        out = torch.empty((self.nmodes - 1, nt.value), dtype=torch.int32, device="cuda")
+        _check(lib().cpd_csf_tiles(self.handle, tile_nnz, out.data_ptr(), ctypes.byref(nt),
+                                   _stream(stream)))
+        return out
+
+
+def csf_build(inds, vals, dims, order=None, stream=None) -> Csf:
+    """cpd_csf_build from COO on the device (inds: N int tensors or (N, nnz))."""
+    inds, vals, dims = _coo_args(inds, vals, dims)
+    h = ctypes.c_void_p()
+    ordarr = None if order is None else (_I32 * len(dims))(*[int(m) for m in order])
+    _check(lib().cpd_csf_build(len(dims), _i64s(dims), vals.numel(), _ptrs(inds), vals.data_ptr(),
+                               ordarr, _stream(stream), ctypes.byref(h)))
+    c = Csf(h.value)
+    c.dims = dims
+    return c
+
+
+def mttkrp(csf: Csf, factors, mode: int, out=None, rank=None, precision="fp32", variant="auto",
+           kernel="auto", tile_nnz=0, stream=None):
+    """cpd_mttkrp: Y (dims[mode] x rank, float32) for the given factors.
+
+    factors: list of N CUDA tensors (row-major, unit column stride; entry
+    `mode` may be None): float32 for "fp32", bfloat16 for "bf16"."""
+    fdt = torch.float32 if precision == "fp32" else torch.bfloat16
+    if out is None and not 0 <= mode < len(csf.dims):
+        raise ValueError("mode %d out of range" % mode)
+    ref = next(f for m, f in enumerate(factors) if m != mode and f is not None)
+    R = int(rank if rank is not None else ref.shape[1])
+    ld = int(ref.stride(0))
+    for m, f in enumerate(factors):
+        if m == mode or f is None:
+            continue
+        _need_cuda(f, "factor %d" % m, fdt)
+        if f.stride(1) != 1 or f.stride(0) != ld:
+            raise ValueError("factors need unit column stride and one common row stride")
+    if out is None:
+        out = torch.empty((csf.dims[mode], R), dtype=torch.float32, device="cuda")
+    _need_cuda(out, "out", torch.float32)
+    opts = MttkrpOpts(PRECISION[precision], VARIANT[variant], KERNEL[kernel], int(tile_nnz))
+    _check(lib().cpd_mttkrp(csf.handle, _ptrs([None if m == mode else f for m, f in enumerate(factors)]),
+                            ld, R, int(mode), out.data_ptr(), int(out.stride(0)), ctypes.byref(opts),
+                            _stream(stream)))
+    return out
+
+
+def gram(A, stream=None):
+    _need_cuda(A, "A", torch.float32)
+    R = A.shape[1]
+    G = torch.empty((R, R), dtype=torch.float64, device="cuda")
+    _check(lib().cpd_gram(A.data_ptr(), A.shape[0], R, A.stride(0), G.data_ptr(), _stream(stream)))
+    return G
+
+
+def solve_normalize(grams, mode, Y, A=None, want_bf16=False, want_gram=True, stream=None):
+    """cpd_solve_normalize -> dict(A, lam, G, used_pinv, A_bf16)."""
+    _need_cuda(Y, "Y", torch.float32)
+    rows, R = Y.shape
+    if A is None:
+        A = torch.empty((rows, R), dtype=torch.float32, device="cuda")
+    Ab = torch.empty((rows, R), dtype=torch.bfloat16, device="cuda") if want_bf16 else None
+    lam = torch.empty(R, dtype=torch.float64, device="cuda")
+    G = torch.empty((R, R), dtype=torch.float64, device="cuda") if want_gram else None
+    used = torch.zeros(1, dtype=torch.int32, device="cuda")
+    _check(lib().cpd_solve_normalize(_ptrs(grams), len(grams), int(mode), Y.data_ptr(), rows, R,
+                                     Y.stride(0), A.data_ptr(), A.stride(0),
+                                     None if Ab is None else Ab.data_ptr(),
+                                     R if Ab is None else Ab.stride(0), lam.data_ptr(),
+                                     None if G is None else G.data_ptr(), used.data_ptr(),
+                                     _stream(stream)))
+    return dict(A=A, lam=lam, G=G, used_pinv=used, A_bf16=Ab)
+
+
+def fit(normX2, lam, A_last, Y_last, grams, stream=None):
+    out = torch.empty(1, dtype=torch.float64, device="cuda")
+    rows, R = A_last.shape
+    _check(lib().cpd_fit(float(normX2), lam.data_ptr(), A_last.data_ptr(), A_last.stride(0),
+                         Y_last.data_ptr(), Y_last.stride(0), rows, R, _ptrs(grams), len(grams),
+                         out.data_ptr(), _stream(stream)))
+    return out
+
+
+def sumsq(vals, stream=None):
+    _need_cuda(vals, "vals", torch.float32)
+    out = torch.empty(1, dtype=torch.float64, device="cuda")
+    _check(lib().cpd_sumsq(vals.data_ptr(), vals.numel(), out.data_ptr(), _stream(stream)))
+    return out
+
+
+def als(inds, vals, dims, rank, iters, tol=0.0, init=None, precision="fp32", variant="auto",
+        kernel="auto", tile_nnz=0, single_csf=False, order=None, seed=0, timing=False,
+        stream=None):
+    """cpd_als -> dict(factors, lam, fit, iters, fits, timing_ms)."""
+    inds, vals, dims = _coo_args(inds, vals, dims)
+    nm = len(dims)
+    outs = [torch.empty((d, rank), dtype=torch.float32, device="cuda") for d in dims]
+    if init is not None:
+        init = [_need_cuda(a, "init").to(torch.float32).contiguous() for a in init]
+        for a, d in zip(init, dims):
+            if tuple(a.shape) != (d, rank):
+                raise ValueError("init factor shape %s, expected %s" % (tuple(a.shape), (d, rank)))
+    trace = (ctypes.c_double * iters)()
+    tms = (ctypes.c_double * (4 + iters * (nm + 1)))() if timing else None
+    ordarr = None if order is None else (_I32 * nm)(*[int(m) for m in order])
+    initarr = None if init is None else _ptrs(init)
+    opts = AlsOpts(PRECISION[precision], VARIANT[variant], KERNEL[kernel], int(tile_nnz),
+                   int(bool(single_csf)), 0,
+                   ctypes.cast(ordarr, ctypes.c_void_p) if ordarr is not None else None,
+                   ctypes.cast(initarr, ctypes.c_void_p) if initarr is not None else None,
+                   int(seed), ctypes.cast(trace, ctypes.c_void_p),
+                   ctypes.cast(tms, ctypes.c_void_p) if tms is not None else None)
+    lam = (ctypes.c_double * rank)()
+    fit_out = ctypes.c_double()
+    it_out = ctypes.c_int32()
+    _check(lib().cpd_als(nm, _i64s(dims), vals.numel(), _ptrs(inds), vals.data_ptr(), int(rank),
+                         int(iters), float(tol), ctypes.byref(opts), _ptrs(outs), lam,
+                         ctypes.byref(fit_out), ctypes.byref(it_out), _stream(stream)))
+    n_it = it_out.value
+    res = dict(factors=outs, lam=list(lam), fit=fit_out.value, iters=n_it,
+               fits=[trace[i] for i in range(n_it)])
+    if timing:
+        t = list(tms)
+        res["timing_ms"] = dict(csf_build=t[0], iterations=t[1], final_fit=t[2], total=t[3],
+                                per_iter=[t[4 + i * (nm + 1): 4 + (i + 1) * (nm + 1)]
+                                          for i in range(n_it)])
+    return res

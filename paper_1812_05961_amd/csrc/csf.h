@@ -1,0 +1,45 @@
+// Internal view of a CSF tree (shared by the CSF builder, the MTTKRP kernels
+// and the ALS driver).
+#pragma once
+
+#include <mutex>
+#include <vector>
+
+#include "common.h"
+
+struct cpd_csf_s {
+    int nmodes = 0;
+    int64_t dims[CPD_MAX_MODES] = {};     // by mode
+    int order[CPD_MAX_MODES] = {};        // level -> mode
+    int64_t counts[CPD_MAX_MODES] = {};   // nodes per level (counts[N-1] = nnz)
+    int32_t *fids[CPD_MAX_MODES] = {};    // per level
+    int32_t *fptr[CPD_MAX_MODES] = {};    // per level < N-1
+    float *vals = nullptr;
+
+    struct Tiles {
+        int32_t tile;
+        int64_t ntiles;
+        int32_t *starts;                  // (N-1) x ntiles
+    };
+    std::vector<Tiles> tiles;
+    std::mutex mu;
+
+    int depth_of(int mode) const {
+        for (int l = 0; l < nmodes; ++l)
+            if (order[l] == mode) return l;
+        return -1;
+    }
+};
+
+namespace cpd {
+
+// Device-wide exclusive scan of f(i) for i in [0, n) into out (int32), with the
+// total written to *total (device).  f is a device functor returning int32.
+template <typename F>
+cpd_status exclusive_scan(F f, int64_t n, int32_t *out, int32_t *total, hipStream_t s);
+
+// Tile start nodes for a tile width (cached in the handle; created on first use).
+cpd_status csf_tiles(cpd_csf_s *c, int32_t tile, const int32_t **starts, int64_t *ntiles,
+                     hipStream_t s);
+
+}  // namespace cpd

@@ -1,0 +1,519 @@
+// CSF construction on the GPU: index check, key packing, stable LSD radix sort,
+// duplicate merge and fiber compression (the one-time "Sort" preprocessing of
+// Section V-C and the compressed sparse fiber tree of Section III), plus the
+// per-tile start nodes that the MTTKRP kernels split their work by.
+#include <algorithm>
+#include <numeric>
+
+#include "csf.h"
+#include "scan.h"
+
+namespace cpd {
+
+namespace {
+
+constexpr int RS_THREADS = 256;            // == radix, one digit per thread in bookkeeping
+constexpr int RS_ITEMS = 16;
+constexpr int RS_TILE = RS_THREADS * RS_ITEMS;
+
+// Where each level's index sits in the packed 128-bit key (root most
+// significant, leaf least).
+struct KeyLayout {
+    int nl;
+    int shift[CPD_MAX_MODES];
+    int bits[CPD_MAX_MODES];
+};
+
+struct LevelInds {
+    const int32_t *p[CPD_MAX_MODES];
+};
+
+__device__ __forceinline__ uint32_t key_field(uint64_t lo, uint64_t hi, int s, int b) {
+    if (b == 0) return 0u;
+    uint64_t mask = (1ull << b) - 1ull;
+    if (s >= 64) return (uint32_t)((hi >> (s - 64)) & mask);
+    if (s + b <= 64) return (uint32_t)((lo >> s) & mask);
+    return (uint32_t)(((lo >> s) | (hi << (64 - s))) & mask);
+}
+
+__global__ void k_validate(LevelInds in, KeyLayout kl, const int64_t *dims_by_level, int64_t n,
+                           int32_t *bad) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    bool ok = true;
+    for (int l = 0; l < kl.nl; ++l) {
+        int32_t v = in.p[l][k];
+        ok = ok && v >= 0 && (int64_t)v < dims_by_level[l];
+    }
+    if (!ok) atomicOr(bad, 1);
+}
+
+__global__ void k_pack(LevelInds in, KeyLayout kl, int64_t n, uint64_t *lo, uint64_t *hi,
+                       int32_t *pay) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    uint64_t a = 0, b = 0;
+    for (int l = 0; l < kl.nl; ++l) {
+        uint64_t x = (uint64_t)(uint32_t)in.p[l][k];
+        int s = kl.shift[l];
+        if (kl.bits[l] == 0) continue;
+        if (s >= 64) {
+            b |= x << (s - 64);
+        } else {
+            a |= x << s;
+            if (s > 0 && s + kl.bits[l] > 64) b |= x >> (64 - s);
+        }
+    }
+    lo[k] = a;
+    if (hi) hi[k] = b;
+    pay[k] = (int32_t)k;
+}
+
+// ---- radix sort: per-tile digit histogram (digit-major output)
+__global__ void __launch_bounds__(RS_THREADS)
+k_radix_hist(const uint64_t *keys, int64_t n, int shift, int32_t *hist, int64_t ntiles) {
+    __shared__ int32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * RS_TILE;
+#pragma unroll
+    for (int j = 0; j < RS_ITEMS; ++j) {
+        int64_t i = base + (int64_t)j * RS_THREADS + threadIdx.x;
+        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1);
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
+}
+
+// ---- radix sort: stable scatter.  Tile items are taken in rounds of 256
+// consecutive keys; inside a round, the rank of a key among equal digits is
+// (earlier rounds) + (earlier waves of this round) + (earlier lanes of its
+// wave), which keeps the input order of equal digits.
+__global__ void __launch_bounds__(RS_THREADS)
+k_radix_scatter(const uint64_t *klo, const uint64_t *khi, const int32_t *pay, uint64_t *olo,
+                uint64_t *ohi, int32_t *opay, const int32_t *offsets, int64_t n, int64_t ntiles,
+                int word, int shift) {
+    __shared__ int32_t base_d[256];
+    __shared__ int32_t wcnt[4][256];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    base_d[tid] = offsets[(int64_t)tid * ntiles + blockIdx.x];
+    for (int w = 0; w < 4; ++w) wcnt[w][tid] = 0;
+    __syncthreads();
+    const int64_t tbase = (int64_t)blockIdx.x * RS_TILE;
+    const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+    for (int r = 0; r < RS_ITEMS; ++r) {
+        int64_t i = tbase + (int64_t)r * RS_THREADS + tid;
+        bool valid = i < n;
+        uint64_t a = valid ? klo[i] : 0ull;
+        uint64_t b = (valid && khi) ? khi[i] : 0ull;
+        uint32_t d = (uint32_t)(((word ? b : a) >> shift) & 255u);
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int bit = 0; bit < 8; ++bit) {
+            bool set = (d >> bit) & 1u;
+            uint64_t m = __ballot(set);
+            peers &= set ? m : ~m;
+        }
+        int rank_w = __popcll(peers & lt);
+        if (valid && rank_w == 0) wcnt[wave][d] = __popcll(peers);
+        __syncthreads();
+        if (valid) {
+            int32_t pos = base_d[d] + rank_w;
+            for (int w = 0; w < wave; ++w) pos += wcnt[w][d];
+            olo[pos] = a;
+            if (ohi) ohi[pos] = b;
+            opay[pos] = pay[i];
+        }
+        __syncthreads();
+        base_d[tid] += wcnt[0][tid] + wcnt[1][tid] + wcnt[2][tid] + wcnt[3][tid];
+        wcnt[0][tid] = wcnt[1][tid] = wcnt[2][tid] = wcnt[3][tid] = 0;
+        __syncthreads();
+    }
+}
+
+struct HistAt {
+    const int32_t *h;
+    __device__ int32_t operator()(int64_t i) const { return h[i]; }
+};
+
+// First level at which sorted key k differs from key k-1 (0 for k = 0, nl for
+// an exact duplicate).
+__global__ void k_first_diff(const uint64_t *lo, const uint64_t *hi, KeyLayout kl, int64_t n,
+                             uint8_t *dl) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    if (k == 0) {
+        dl[0] = 0;
+        return;
+    }
+    uint64_t a = lo[k], b = hi ? hi[k] : 0ull, pa = lo[k - 1], pb = hi ? hi[k - 1] : 0ull;
+    int l = 0;
+    for (; l < kl.nl; ++l)
+        if (key_field(a, b, kl.shift[l], kl.bits[l]) != key_field(pa, pb, kl.shift[l], kl.bits[l]))
+            break;
+    dl[k] = (uint8_t)l;
+}
+
+struct IsNew {
+    const uint8_t *dl;
+    int nl;
+    __device__ int32_t operator()(int64_t i) const { return dl[i] < nl ? 1 : 0; }
+};
+
+struct AtLevel {
+    const uint8_t *dl;
+    int l;
+    __device__ int32_t operator()(int64_t i) const { return dl[i] <= l ? 1 : 0; }
+};
+
+// One thread per run of equal keys: the float sum of the run in input order
+// (the sort is stable, so the run is in input order).
+__global__ void k_merge(const uint64_t *lo, const uint64_t *hi, const int32_t *pay,
+                        const float *vals, const uint8_t *dl, const int32_t *pos, int64_t n,
+                        int nl, uint64_t *ulo, uint64_t *uhi, float *uval, uint8_t *udl) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n || dl[k] >= nl) return;
+    float s = vals[pay[k]];
+    for (int64_t j = k + 1; j < n && dl[j] >= nl; ++j) s += vals[pay[j]];
+    int32_t p = pos[k];
+    ulo[p] = lo[k];
+    if (uhi) uhi[p] = hi[k];
+    uval[p] = s;
+    udl[p] = dl[k];
+}
+
+__global__ void k_compact(const uint64_t *lo, const uint64_t *hi, KeyLayout kl, const uint8_t *dl,
+                          int64_t n, int l, const int32_t *scan_l, const int32_t *scan_next,
+                          int32_t *fids, int32_t *fptr) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n || dl[k] > l) return;
+    int32_t j = scan_l[k];
+    fids[j] = (int32_t)key_field(lo[k], hi ? hi[k] : 0ull, kl.shift[l], kl.bits[l]);
+    fptr[j] = scan_next ? scan_next[k] : (int32_t)k;
+}
+
+__global__ void k_leaf(const uint64_t *lo, const uint64_t *hi, KeyLayout kl, int64_t n,
+                       int32_t *fids) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    int l = kl.nl - 1;
+    fids[k] = (int32_t)key_field(lo[k], hi ? hi[k] : 0ull, kl.shift[l], kl.bits[l]);
+}
+
+__global__ void k_set_last(int32_t *fptr, int64_t at, const int32_t *value) {
+    fptr[at] = *value;
+}
+
+__global__ void k_set_last_const(int32_t *fptr, int64_t at, int32_t value) { fptr[at] = value; }
+
+// Node holding the first leaf of each tile, at every level < N-1.
+struct FptrSet {
+    const int32_t *p[CPD_MAX_MODES];
+    int64_t len[CPD_MAX_MODES];  // count[l] (fptr[l] has count[l]+1 entries)
+};
+
+__global__ void k_tiles(FptrSet fp, int nl, int64_t nleaves, int32_t tile, int64_t ntiles,
+                        int32_t *starts) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ntiles) return;
+    int64_t pos = t * (int64_t)tile;
+    if (pos >= nleaves) pos = nleaves - 1;
+    for (int l = nl - 2; l >= 0; --l) {
+        // largest j in [0, len) with fptr[l][j] <= pos
+        const int32_t *p = fp.p[l];
+        int64_t lo = 0, hi = fp.len[l] - 1;
+        while (lo < hi) {
+            int64_t mid = (lo + hi + 1) >> 1;
+            if (p[mid] <= pos) lo = mid; else hi = mid - 1;
+        }
+        starts[(int64_t)l * ntiles + t] = (int32_t)lo;
+        pos = lo;
+    }
+}
+
+inline unsigned grid1(int64_t n, int t = 256) { return (unsigned)ceil_div(n, t); }
+
+void free_csf(cpd_csf_s *c) {
+    if (!c) return;
+    for (int l = 0; l < CPD_MAX_MODES; ++l) {
+        if (c->fids[l]) (void)hipFree(c->fids[l]);
+        if (c->fptr[l]) (void)hipFree(c->fptr[l]);
+    }
+    if (c->vals) (void)hipFree(c->vals);
+    for (auto &t : c->tiles) (void)hipFree(t.starts);
+    delete c;
+}
+
+cpd_status build(int nm, const int64_t *dims, int64_t nnz, const int32_t *const *inds,
+                 const float *vals, const int32_t *order_in, hipStream_t s, cpd_csf *out) {
+    if (nm < 2 || nm > CPD_MAX_MODES) CPD_FAIL(CPD_EINVAL, "nmodes %d not in [2, %d]", nm, CPD_MAX_MODES);
+    if (!dims || !inds || !vals || !out) CPD_FAIL(CPD_EINVAL, "null argument");
+    if (nnz < 1 || nnz > INT32_MAX) CPD_FAIL(CPD_EINVAL, "nnz %lld not in [1, 2^31-1]", (long long)nnz);
+    for (int m = 0; m < nm; ++m) {
+        if (dims[m] < 1 || dims[m] > INT32_MAX) CPD_FAIL(CPD_EINVAL, "dim %d = %lld out of range", m, (long long)dims[m]);
+        if (!inds[m]) CPD_FAIL(CPD_EINVAL, "null index array for mode %d", m);
+    }
+    int order[CPD_MAX_MODES];
+    if (order_in) {
+        bool seen[CPD_MAX_MODES] = {};
+        for (int l = 0; l < nm; ++l) {
+            int m = order_in[l];
+            if (m < 0 || m >= nm || seen[m]) CPD_FAIL(CPD_EINVAL, "order is not a permutation of the modes");
+            seen[m] = true;
+            order[l] = m;
+        }
+    } else {
+        std::iota(order, order + nm, 0);
+        std::stable_sort(order, order + nm, [&](int a, int b) { return dims[a] < dims[b]; });
+    }
+    KeyLayout kl{};
+    kl.nl = nm;
+    int total_bits = 0;
+    for (int l = nm - 1; l >= 0; --l) {
+        int64_t d = dims[order[l]];
+        int b = 0;
+        while ((1ll << b) < d) ++b;
+        kl.bits[l] = b;
+        kl.shift[l] = total_bits;
+        total_bits += b;
+    }
+    if (total_bits > 128) CPD_FAIL(CPD_EUNSUPPORTED, "packed key needs %d bits (> 128)", total_bits);
+    const bool two = total_bits > 64;
+    LevelInds li{};
+    int64_t dims_l[CPD_MAX_MODES];
+    for (int l = 0; l < nm; ++l) {
+        li.p[l] = inds[order[l]];
+        dims_l[l] = dims[order[l]];
+    }
+
+    // a1: index check
+    DevBuf<int64_t> d_dims;
+    DevBuf<int32_t> d_flag;
+    CPD_TRY(d_dims.alloc(nm, s));
+    CPD_TRY(d_flag.alloc(1 + CPD_MAX_MODES, s));
+    CPD_HIP(hipMemcpyAsync(d_dims.p, dims_l, sizeof(int64_t) * nm, hipMemcpyHostToDevice, s));
+    CPD_HIP(hipMemsetAsync(d_flag.p, 0, sizeof(int32_t) * (1 + CPD_MAX_MODES), s));
+    hipLaunchKernelGGL(k_validate, dim3(grid1(nnz)), dim3(256), 0, s, li, kl, (const int64_t *)d_dims.p,
+                       nnz, d_flag.p);
+    CPD_LAUNCH_CHECK();
+
+    // a3: keys and stable LSD radix sort
+    DevBuf<uint64_t> lo0, lo1, hi0, hi1;
+    DevBuf<int32_t> p0, p1;
+    CPD_TRY(lo0.alloc(nnz, s));
+    CPD_TRY(lo1.alloc(nnz, s));
+    if (two) {
+        CPD_TRY(hi0.alloc(nnz, s));
+        CPD_TRY(hi1.alloc(nnz, s));
+    }
+    CPD_TRY(p0.alloc(nnz, s));
+    CPD_TRY(p1.alloc(nnz, s));
+    hipLaunchKernelGGL(k_pack, dim3(grid1(nnz)), dim3(256), 0, s, li, kl, nnz, lo0.p, hi0.p, p0.p);
+    CPD_LAUNCH_CHECK();
+    const int64_t ntiles = ceil_div(nnz, RS_TILE);
+    DevBuf<int32_t> hist;
+    CPD_TRY(hist.alloc((size_t)256 * ntiles, s));
+    uint64_t *klo = lo0.p, *khi = hi0.p, *olo = lo1.p, *ohi = hi1.p;
+    int32_t *kp = p0.p, *op = p1.p;
+    const int passes = (total_bits + 7) / 8;
+    for (int d = 0; d < passes; ++d) {
+        int word = (8 * d) / 64, shift = (8 * d) % 64;
+        const uint64_t *src = word ? khi : klo;
+        hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)ntiles), dim3(RS_THREADS), 0, s, src, nnz,
+                           shift, hist.p, ntiles);
+        CPD_LAUNCH_CHECK();
+        CPD_TRY(exclusive_scan(HistAt{hist.p}, 256 * ntiles, hist.p, (int32_t *)nullptr, s));
+        hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)ntiles), dim3(RS_THREADS), 0, s, klo, khi,
+                           kp, olo, ohi, op, (const int32_t *)hist.p, nnz, ntiles, word, shift);
+        CPD_LAUNCH_CHECK();
+        std::swap(klo, olo);
+        std::swap(khi, ohi);
+        std::swap(kp, op);
+    }
+    hist.release();
+
+    // a4: duplicate merge
+    DevBuf<uint8_t> dl;
+    DevBuf<int32_t> pos;
+    CPD_TRY(dl.alloc(nnz, s));
+    CPD_TRY(pos.alloc(nnz, s));
+    hipLaunchKernelGGL(k_first_diff, dim3(grid1(nnz)), dim3(256), 0, s, klo, khi, kl, nnz, dl.p);
+    CPD_LAUNCH_CHECK();
+    int32_t *d_nuniq = d_flag.p + 1;
+    CPD_TRY(exclusive_scan(IsNew{dl.p, nm}, nnz, pos.p, d_nuniq, s));
+    // merged arrays reuse the other ping-pong buffers
+    DevBuf<uint8_t> udl;
+    DevBuf<float> uval;
+    CPD_TRY(udl.alloc(nnz, s));
+    CPD_TRY(uval.alloc(nnz, s));
+    hipLaunchKernelGGL(k_merge, dim3(grid1(nnz)), dim3(256), 0, s, klo, khi, kp, vals, dl.p, pos.p,
+                       nnz, nm, olo, ohi, uval.p, udl.p);
+    CPD_LAUNCH_CHECK();
+    std::swap(klo, olo);
+    std::swap(khi, ohi);
+    dl.release();
+    p0.release();
+    p1.release();
+
+    int32_t h_flag[2];
+    CPD_HIP(hipMemcpyAsync(h_flag, d_flag.p, sizeof(int32_t) * 2, hipMemcpyDeviceToHost, s));
+    CPD_HIP(hipStreamSynchronize(s));
+    if (h_flag[0]) CPD_FAIL(CPD_EINVAL, "an index is out of range for its mode");
+    const int64_t n = h_flag[1];
+
+    // a5: fiber compression, levels N-2 .. 0
+    std::vector<DevBuf<int32_t>> scans(nm - 1);
+    for (int l = 0; l < nm - 1; ++l) {
+        CPD_TRY(scans[l].alloc(n, s));
+        CPD_TRY(exclusive_scan(AtLevel{udl.p, l}, n, scans[l].p, d_flag.p + 2 + l, s));
+    }
+    int32_t h_counts[CPD_MAX_MODES] = {};
+    if (nm > 1)
+        CPD_HIP(hipMemcpyAsync(h_counts, d_flag.p + 2, sizeof(int32_t) * (nm - 1), hipMemcpyDeviceToHost, s));
+    CPD_HIP(hipStreamSynchronize(s));
+
+    cpd_csf_s *c = new (std::nothrow) cpd_csf_s();
+    if (!c) CPD_FAIL(CPD_ENOMEM, "host allocation failed");
+    c->nmodes = nm;
+    for (int m = 0; m < nm; ++m) c->dims[m] = dims[m];
+    for (int l = 0; l < nm; ++l) {
+        c->order[l] = order[l];
+        c->counts[l] = (l == nm - 1) ? n : h_counts[l];
+    }
+    cpd_status st = CPD_OK;
+    auto alloc_arr = [&](void **p, size_t bytes) -> bool {
+        if (hipMalloc(p, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            *p = nullptr;
+            return false;
+        }
+        return true;
+    };
+    bool ok = true;
+    for (int l = 0; l < nm && ok; ++l) {
+        ok = alloc_arr((void **)&c->fids[l], sizeof(int32_t) * c->counts[l]);
+        if (ok && l < nm - 1) ok = alloc_arr((void **)&c->fptr[l], sizeof(int32_t) * (c->counts[l] + 1));
+    }
+    if (ok) ok = alloc_arr((void **)&c->vals, sizeof(float) * n);
+    if (!ok) {
+        free_csf(c);
+        CPD_FAIL(CPD_ENOMEM, "device allocation for the CSF failed");
+    }
+    for (int l = nm - 2; l >= 0 && st == CPD_OK; --l) {
+        const int32_t *next = (l == nm - 2) ? nullptr : scans[l + 1].p;
+        hipLaunchKernelGGL(k_compact, dim3(grid1(n)), dim3(256), 0, s, klo, khi, kl, udl.p, n, l,
+                           scans[l].p, next, c->fids[l], c->fptr[l]);
+        if (hipGetLastError() != hipSuccess) st = CPD_EHIP;
+        hipLaunchKernelGGL(k_set_last_const, dim3(1), dim3(1), 0, s, c->fptr[l], c->counts[l],
+                           (int32_t)c->counts[l + 1]);
+    }
+    hipLaunchKernelGGL(k_leaf, dim3(grid1(n)), dim3(256), 0, s, klo, khi, kl, n, c->fids[nm - 1]);
+    if (st == CPD_OK && hipGetLastError() != hipSuccess) st = CPD_EHIP;
+    if (st == CPD_OK && hipMemcpyAsync(c->vals, uval.p, sizeof(float) * n, hipMemcpyDeviceToDevice, s) != hipSuccess)
+        st = CPD_EHIP;
+    if (st == CPD_OK && hipStreamSynchronize(s) != hipSuccess) st = CPD_EHIP;
+    if (st != CPD_OK) {
+        free_csf(c);
+        CPD_FAIL(st, "CSF compression kernels failed");
+    }
+    *out = c;
+    return CPD_OK;
+}
+
+}  // namespace
+
+cpd_status csf_tiles(cpd_csf_s *c, int32_t tile, const int32_t **starts, int64_t *ntiles,
+                     hipStream_t s) {
+    if (tile < 1) CPD_FAIL(CPD_EINVAL, "tile width %d < 1", tile);
+    std::lock_guard<std::mutex> g(c->mu);
+    for (auto &t : c->tiles)
+        if (t.tile == tile) {
+            *starts = t.starts;
+            *ntiles = t.ntiles;
+            return CPD_OK;
+        }
+    const int nm = c->nmodes;
+    const int64_t nl = c->counts[nm - 1];
+    const int64_t nt = ceil_div(nl, tile);
+    int32_t *p = nullptr;
+    if (hipMalloc((void **)&p, sizeof(int32_t) * (size_t)std::max<int64_t>(1, (nm - 1) * nt)) != hipSuccess) {
+        (void)hipGetLastError();
+        CPD_FAIL(CPD_ENOMEM, "device allocation for the tile table failed");
+    }
+    FptrSet fp{};
+    for (int l = 0; l < nm - 1; ++l) {
+        fp.p[l] = c->fptr[l];
+        fp.len[l] = c->counts[l];
+    }
+    hipLaunchKernelGGL(k_tiles, dim3(grid1(nt)), dim3(256), 0, s, fp, nm, nl, tile, nt, p);
+    if (hipGetLastError() != hipSuccess) {
+        (void)hipFree(p);
+        CPD_FAIL(CPD_EHIP, "tile kernel launch failed");
+    }
+    c->tiles.push_back({tile, nt, p});
+    *starts = p;
+    *ntiles = nt;
+    return CPD_OK;
+}
+
+}  // namespace cpd
+
+using namespace cpd;
+
+extern "C" {
+
+cpd_status cpd_csf_build(int32_t nmodes, const int64_t *dims, int64_t nnz, const int32_t *const *inds,
+                         const float *vals, const int32_t *order, void *stream, cpd_csf *out) {
+    clear_error();
+    if (out) *out = nullptr;
+    return build(nmodes, dims, nnz, inds, vals, order, (hipStream_t)stream, out);
+}
+
+cpd_status cpd_csf_info(cpd_csf c, int32_t *nmodes, int32_t *order, int64_t *counts) {
+    clear_error();
+    if (!c) CPD_FAIL(CPD_EINVAL, "null CSF handle");
+    if (nmodes) *nmodes = c->nmodes;
+    for (int l = 0; l < c->nmodes; ++l) {
+        if (order) order[l] = c->order[l];
+        if (counts) counts[l] = c->counts[l];
+    }
+    return CPD_OK;
+}
+
+cpd_status cpd_csf_export(cpd_csf c, int32_t level, int32_t *fids, int32_t *fptr, float *vals,
+                          void *stream) {
+    clear_error();
+    if (!c) CPD_FAIL(CPD_EINVAL, "null CSF handle");
+    if (level < 0 || level >= c->nmodes) CPD_FAIL(CPD_EINVAL, "level %d out of range", level);
+    hipStream_t s = (hipStream_t)stream;
+    if (fids)
+        CPD_HIP(hipMemcpyAsync(fids, c->fids[level], sizeof(int32_t) * c->counts[level],
+                               hipMemcpyDeviceToDevice, s));
+    if (fptr && level < c->nmodes - 1)
+        CPD_HIP(hipMemcpyAsync(fptr, c->fptr[level], sizeof(int32_t) * (c->counts[level] + 1),
+                               hipMemcpyDeviceToDevice, s));
+    if (vals && level == c->nmodes - 1)
+        CPD_HIP(hipMemcpyAsync(vals, c->vals, sizeof(float) * c->counts[level], hipMemcpyDeviceToDevice, s));
+    return CPD_OK;
+}
+
+cpd_status cpd_csf_tiles(cpd_csf c, int32_t tile_nnz, int32_t *starts, int64_t *ntiles, void *stream) {
+    clear_error();
+    if (!c || !ntiles) CPD_FAIL(CPD_EINVAL, "null argument");
+    const int32_t *p;
+    int64_t nt;
+    CPD_TRY(csf_tiles(c, tile_nnz, &p, &nt, (hipStream_t)stream));
+    *ntiles = nt;
+    if (starts && c->nmodes > 1)
+        CPD_HIP(hipMemcpyAsync(starts, p, sizeof(int32_t) * (c->nmodes - 1) * nt, hipMemcpyDeviceToDevice,
+                               (hipStream_t)stream));
+    return CPD_OK;
+}
+
+void cpd_csf_free(cpd_csf c) {
+    if (!c) return;
+    (void)hipDeviceSynchronize();
+    free_csf(c);
+}
+
+}  // extern "C"

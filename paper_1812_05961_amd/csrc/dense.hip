@@ -1,0 +1,494 @@
+// Dense FP64 steps of CP-ALS (Algorithm 1, Section III):
+//   Gram  G = A^T A                       (lines 4, 7, 10)  -- FP64 MFMA
+//   V     Hadamard of the other Grams      (lines 4, 7, 10)
+//   solve A = Y V^+                         (lines 5, 8, 11)  -- Cholesky, or the
+//         Moore-Penrose inverse from a Jacobi eigendecomposition when a pivot
+//         is <= R*eps*max(diag V) (the paper's code uses potrf/potrs, Section V-A)
+//   norms lambda_r = ||A(:, r)||_2, unit columns     (lines 6, 9, 12)
+//   fit   1 - ||X - K|| / ||X||                      (line 13)
+#include "common.h"
+
+namespace cpd {
+namespace {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+constexpr int GRAM_MAX_BLOCKS = 1024;
+constexpr double EPS64 = 2.220446049250313080847e-16;
+
+struct GramSet {
+    const double *g[CPD_MAX_MODES];
+};
+
+// ------------------------------------------------------------------ Gram
+// Each wave accumulates the 16x16 blocks (bi <= bj) of A^T A over chunks of 4
+// rows with v_mfma_f64_16x16x4f64: operand lane l holds A[row0 + l/16][16*b + l%16],
+// which is element (l%16, l/16) of the 16x4 A^T slice and element (l/16, l%16)
+// of the 4x16 A slice; result register v of lane l holds D[4*v + l/16][l%16].
+template <int RB>
+__global__ void __launch_bounds__(256)
+k_gram(const float *__restrict__ A, int64_t rows, int R, int64_t ld, double *__restrict__ partial) {
+    constexpr int P = RB * 16;
+    __shared__ double red[P * P];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int krow = lane >> 4, kcol = lane & 15;
+    v4d acc[RB][RB];
+#pragma unroll
+    for (int i = 0; i < RB; ++i)
+#pragma unroll
+        for (int j = 0; j < RB; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+    const int64_t nchunks = ceil_div(rows, 4);
+    for (int64_t ch = (int64_t)blockIdx.x * 4 + wave; ch < nchunks; ch += (int64_t)gridDim.x * 4) {
+        const int64_t r = ch * 4 + krow;
+        double f[RB];
+#pragma unroll
+        for (int b = 0; b < RB; ++b) {
+            const int col = b * 16 + kcol;
+            f[b] = (r < rows && col < R) ? (double)A[r * ld + col] : 0.0;
+        }
+#pragma unroll
+        for (int i = 0; i < RB; ++i)
+#pragma unroll
+            for (int j = i; j < RB; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(f[i], f[j], acc[i][j], 0, 0, 0);
+    }
+    // deterministic reduction over the four waves
+    for (int w = 0; w < 4; ++w) {
+        if (wave == w) {
+#pragma unroll
+            for (int i = 0; i < RB; ++i)
+#pragma unroll
+                for (int j = i; j < RB; ++j)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int rr = i * 16 + 4 * v + (lane >> 4), cc = j * 16 + (lane & 15);
+                        if (w == 0) red[rr * P + cc] = acc[i][j][v];
+                        else red[rr * P + cc] += acc[i][j][v];
+                    }
+        }
+        __syncthreads();
+    }
+    double *out = partial + (int64_t)blockIdx.x * P * P;
+    for (int t = threadIdx.x; t < P * P; t += 256) {
+        const int rr = t / P, cc = t % P;
+        out[t] = ((rr >> 4) <= (cc >> 4)) ? red[t] : 0.0;
+    }
+}
+
+// Sum the per-block partials in block order; fill both triangles.
+__global__ void k_gram_reduce(const double *__restrict__ partial, int nblocks, int P, int R,
+                              double *__restrict__ G) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= R * R) return;
+    int r = t / R, c = t % R;
+    const int rr = min(r, c), cc = max(r, c);
+    // within a diagonal block both triangles were computed; outside, use the upper block
+    const int src = ((rr >> 4) == (cc >> 4)) ? (r * P + c) : (rr * P + cc);
+    double s = 0.0;
+    for (int b = 0; b < nblocks; ++b) s += partial[(int64_t)b * P * P + src];
+    G[t] = s;
+}
+
+cpd_status gram(const float *A, int64_t rows, int R, int64_t ld, double *G, hipStream_t s) {
+    if (!A || !G) CPD_FAIL(CPD_EINVAL, "null argument");
+    if (R < 1 || R > CPD_MAX_RANK || ld < R || rows < 0) CPD_FAIL(CPD_EINVAL, "bad gram sizes");
+    const int RB = (R + 15) / 16, P = RB * 16;
+    int nb = (int)std::min<int64_t>(GRAM_MAX_BLOCKS, std::max<int64_t>(1, ceil_div(rows, 4 * 4 * 8)));
+    DevBuf<double> part;
+    CPD_TRY(part.alloc((size_t)nb * P * P, s));
+    switch (RB) {
+        case 1: hipLaunchKernelGGL(k_gram<1>, dim3(nb), dim3(256), 0, s, A, rows, R, ld, part.p); break;
+        case 2: hipLaunchKernelGGL(k_gram<2>, dim3(nb), dim3(256), 0, s, A, rows, R, ld, part.p); break;
+        case 3: hipLaunchKernelGGL(k_gram<3>, dim3(nb), dim3(256), 0, s, A, rows, R, ld, part.p); break;
+        default: hipLaunchKernelGGL(k_gram<4>, dim3(nb), dim3(256), 0, s, A, rows, R, ld, part.p); break;
+    }
+    CPD_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)ceil_div(R * R, 256)), dim3(256), 0, s,
+                       (const double *)part.p, nb, P, R, G);
+    CPD_LAUNCH_CHECK();
+    return CPD_OK;
+}
+
+// ------------------------------------------------------------------ W = V^+
+// One block of 256 threads.  V (R x R, FP64) lives in LDS; work matrices in
+// global scratch `wk` (2 R^2 doubles).  Writes W = V^{-1} (Cholesky) or V^+
+// (Jacobi eigendecomposition) to W, and the fallback flag.
+__global__ void __launch_bounds__(256)
+k_make_w(GramSet gs, int nmodes, int mode, int R, double *__restrict__ W, double *__restrict__ wk,
+         int32_t *__restrict__ used_pinv) {
+    __shared__ double V[CPD_MAX_RANK * CPD_MAX_RANK];
+    __shared__ double sh[4];
+    __shared__ int fail;
+    const int tid = threadIdx.x;
+    auto load_v = [&]() {
+        for (int t = tid; t < R * R; t += 256) {
+            double v = 1.0;
+            for (int m = 0; m < nmodes; ++m)
+                if (m != mode) v *= gs.g[m][t];
+            V[t] = v;
+        }
+        __syncthreads();
+    };
+    load_v();
+    if (tid == 0) {
+        double mx = 0.0;
+        for (int r = 0; r < R; ++r) mx = fmax(mx, V[r * R + r]);
+        sh[0] = (double)R * EPS64 * mx;
+        fail = 0;
+    }
+    __syncthreads();
+    const double thresh = sh[0];
+    // Cholesky-Banachiewicz in place (lower triangle of V becomes L)
+    for (int j = 0; j < R; ++j) {
+        if (tid == 0) {
+            double d = V[j * R + j];
+            for (int k = 0; k < j; ++k) d -= V[j * R + k] * V[j * R + k];
+            if (!(d > thresh)) fail = 1;
+            else V[j * R + j] = sqrt(d);
+        }
+        __syncthreads();
+        if (fail) break;
+        for (int i = j + 1 + tid; i < R; i += 256) {
+            double x = V[i * R + j];
+            for (int k = 0; k < j; ++k) x -= V[i * R + k] * V[j * R + k];
+            V[i * R + j] = x / V[j * R + j];
+        }
+        __syncthreads();
+    }
+    if (!fail) {
+        // Linv (lower) column by column into wk, then W = Linv^T Linv
+        double *Li = wk;
+        for (int c = tid; c < R; c += 256) {
+            for (int i = 0; i < R; ++i) {
+                if (i < c) { Li[i * R + c] = 0.0; continue; }
+                double x = (i == c) ? 1.0 : 0.0;
+                for (int k = c; k < i; ++k) x -= V[i * R + k] * Li[k * R + c];
+                Li[i * R + c] = x / V[i * R + i];
+            }
+        }
+        __syncthreads();
+        for (int t = tid; t < R * R; t += 256) {
+            const int r = t / R, c = t % R;
+            double x = 0.0;
+            for (int k = max(r, c); k < R; ++k) x += Li[k * R + r] * Li[k * R + c];
+            W[t] = x;
+        }
+        if (tid == 0 && used_pinv) *used_pinv = 0;
+        return;
+    }
+    // Fallback: cyclic Jacobi on V (A <- J^T A J, Q <- Q J), Golub & Van Loan 8.4.
+    __syncthreads();
+    load_v();
+    double *Q = wk;
+    for (int t = tid; t < R * R; t += 256) Q[t] = (t / R == t % R) ? 1.0 : 0.0;
+    __syncthreads();
+    for (int sweep = 0; sweep < 60; ++sweep) {
+        if (tid == 0) {
+            double off = 0.0, tot = 0.0;
+            for (int t = 0; t < R * R; ++t) {
+                tot += V[t] * V[t];
+                if (t / R != t % R) off += V[t] * V[t];
+            }
+            fail = (off <= EPS64 * EPS64 * tot) ? 2 : 1;
+        }
+        __syncthreads();
+        if (fail == 2) break;
+        for (int p = 0; p < R - 1; ++p) {
+            for (int q = p + 1; q < R; ++q) {
+                if (tid == 0) {
+                    double apq = V[p * R + q];
+                    double c = 1.0, s = 0.0;
+                    if (apq != 0.0) {
+                        double tau = (V[q * R + q] - V[p * R + p]) / (2.0 * apq);
+                        double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                        c = 1.0 / sqrt(1.0 + t * t);
+                        s = t * c;
+                    }
+                    sh[1] = c;
+                    sh[2] = s;
+                }
+                __syncthreads();
+                const double c = sh[1], s = sh[2];
+                if (s != 0.0) {
+                    for (int k = tid; k < R; k += 256) {  // columns p, q
+                        double akp = V[k * R + p], akq = V[k * R + q];
+                        V[k * R + p] = c * akp - s * akq;
+                        V[k * R + q] = s * akp + c * akq;
+                        double qkp = Q[k * R + p], qkq = Q[k * R + q];
+                        Q[k * R + p] = c * qkp - s * qkq;
+                        Q[k * R + q] = s * qkp + c * qkq;
+                    }
+                    __syncthreads();
+                    for (int k = tid; k < R; k += 256) {  // rows p, q
+                        double apk = V[p * R + k], aqk = V[q * R + k];
+                        V[p * R + k] = c * apk - s * aqk;
+                        V[q * R + k] = s * apk + c * aqk;
+                    }
+                }
+                __syncthreads();
+            }
+        }
+    }
+    if (tid == 0) {
+        double wmax = -INFINITY;
+        for (int r = 0; r < R; ++r) wmax = fmax(wmax, V[r * R + r]);
+        sh[3] = (double)R * EPS64 * wmax;
+    }
+    __syncthreads();
+    const double cut = sh[3];
+    for (int t = tid; t < R * R; t += 256) {
+        const int r = t / R, c = t % R;
+        double x = 0.0;
+        for (int k = 0; k < R; ++k) {
+            double w = V[k * R + k];
+            if (w > cut) x += Q[r * R + k] * Q[c * R + k] / w;
+        }
+        W[t] = x;
+    }
+    if (tid == 0 && used_pinv) *used_pinv = 1;
+}
+
+// A' = Y W for one row per thread (FP64), with per-block column sums of
+// squares (pass 0) or the scaled write-out (pass 1).
+template <int RP>
+__global__ void __launch_bounds__(256)
+k_apply_w(const float *__restrict__ Y, int64_t rows, int R, int64_t ldy, const double *__restrict__ Wg,
+          const double *__restrict__ lambda, float *__restrict__ A, int64_t lda,
+          uint16_t *__restrict__ Ab, int64_t ldb, double *__restrict__ partial, int pass) {
+    __shared__ double W[RP * RP];
+    __shared__ double red[4][RP];
+    for (int t = threadIdx.x; t < RP * RP; t += 256) {
+        const int r = t / RP, c = t % RP;
+        W[t] = (r < R && c < R) ? Wg[r * R + c] : 0.0;
+    }
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const bool ok = i < rows;
+    double a[RP];
+#pragma unroll
+    for (int c = 0; c < RP; ++c) a[c] = 0.0;
+    if (ok) {
+        for (int j = 0; j < R; ++j) {
+            const double y = (double)Y[i * ldy + j];
+#pragma unroll
+            for (int c = 0; c < RP; ++c) a[c] = fma(y, W[j * RP + c], a[c]);
+        }
+    }
+    if (pass == 0) {
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+        for (int c = 0; c < RP; ++c) {
+            double v = wave_sum(a[c] * a[c]);
+            if (lane == 0) red[wave][c] = v;
+        }
+        __syncthreads();
+        for (int c = threadIdx.x; c < R; c += 256)
+            partial[(int64_t)blockIdx.x * R + c] = red[0][c] + red[1][c] + red[2][c] + red[3][c];
+        return;
+    }
+    if (!ok) return;
+#pragma unroll
+    for (int c = 0; c < RP; ++c) {
+        if (c >= R) break;
+        const double lam = lambda[c];
+        const float v = lam > 0.0 ? (float)(a[c] / lam) : 0.0f;
+        A[i * lda + c] = v;
+        if (Ab) Ab[i * ldb + c] = f32_to_bf16(v);
+    }
+}
+
+__global__ void k_lambda(const double *__restrict__ partial, int nblocks, int R, double *__restrict__ lambda) {
+    const int c = threadIdx.x;
+    if (c >= R) return;
+    double s = 0.0;
+    for (int b = 0; b < nblocks; ++b) s += partial[(int64_t)b * R + c];
+    lambda[c] = sqrt(s);
+}
+
+// ------------------------------------------------------------------ fit
+// partial[b][r] = sum over this block's rows of A(i, r) * Y(i, r)
+__global__ void __launch_bounds__(256)
+k_fit_partial(const float *__restrict__ A, int64_t lda, const float *__restrict__ Y, int64_t ldy,
+              int64_t rows, int R, double *__restrict__ partial) {
+    __shared__ double red[4][64];
+    const int r = threadIdx.x & 63, grp = threadIdx.x >> 6;
+    double s = 0.0;
+    if (r < R)
+        for (int64_t i = (int64_t)blockIdx.x * 4 + grp; i < rows; i += (int64_t)gridDim.x * 4)
+            s += (double)A[i * lda + r] * (double)Y[i * ldy + r];
+    red[grp][r] = s;
+    __syncthreads();
+    if (threadIdx.x < R)
+        partial[(int64_t)blockIdx.x * R + threadIdx.x] =
+            red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
+}
+
+__global__ void k_fit_final(const double *__restrict__ partial, int nblocks, int R,
+                            const double *__restrict__ lambda, GramSet gs, int nmodes, double normX2,
+                            double *__restrict__ fit) {
+    __shared__ double inner_r[CPD_MAX_RANK], quad_r[CPD_MAX_RANK];
+    const int r = threadIdx.x;
+    if (r < R) {
+        double s = 0.0;
+        for (int b = 0; b < nblocks; ++b) s += partial[(int64_t)b * R + r];
+        inner_r[r] = lambda[r] * s;
+        double q = 0.0;
+        for (int c = 0; c < R; ++c) {
+            double h = 1.0;
+            for (int m = 0; m < nmodes; ++m) h *= gs.g[m][r * R + c];
+            q += h * lambda[c];
+        }
+        quad_r[r] = lambda[r] * q;
+    }
+    __syncthreads();
+    if (r == 0) {
+        double inner = 0.0, normK2 = 0.0;
+        for (int c = 0; c < R; ++c) {
+            inner += inner_r[c];
+            normK2 += quad_r[c];
+        }
+        double resid = normX2 - 2.0 * inner + normK2;
+        resid = resid > 0.0 ? resid : 0.0;
+        *fit = 1.0 - sqrt(resid) / sqrt(normX2);
+    }
+}
+
+__global__ void __launch_bounds__(256)
+k_sumsq_partial(const float *__restrict__ v, int64_t n, double *__restrict__ partial) {
+    __shared__ double red[4];
+    double s = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        double x = (double)v[i];
+        s += x * x;
+    }
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ void k_sum_partials(const double *__restrict__ partial, int n, double *__restrict__ out) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        double s = 0.0;
+        for (int i = 0; i < n; ++i) s += partial[i];
+        *out = s;
+    }
+}
+
+}  // namespace
+
+cpd_status gram_internal(const float *A, int64_t rows, int R, int64_t ld, double *G, hipStream_t s) {
+    return gram(A, rows, R, ld, G, s);
+}
+
+cpd_status solve_normalize(const double *const *grams, int nmodes, int mode, const float *Y, int64_t rows,
+                           int R, int64_t ldy, float *A, int64_t lda, uint16_t *Ab, int64_t ldb,
+                           double *lambda, double *G_new, int32_t *used_pinv, hipStream_t s) {
+    if (nmodes < 2 || nmodes > CPD_MAX_MODES || mode < 0 || mode >= nmodes)
+        CPD_FAIL(CPD_EINVAL, "bad mode %d of %d", mode, nmodes);
+    if (R < 1 || R > CPD_MAX_RANK || rows < 0 || ldy < R || lda < R || (Ab && ldb < R))
+        CPD_FAIL(CPD_EINVAL, "bad solve sizes");
+    if (!grams || !Y || !A || !lambda) CPD_FAIL(CPD_EINVAL, "null argument");
+    GramSet gs{};
+    for (int m = 0; m < nmodes; ++m) {
+        if (m != mode && !grams[m]) CPD_FAIL(CPD_EINVAL, "null gram for mode %d", m);
+        gs.g[m] = grams[m];
+    }
+    DevBuf<double> W, wk, part;
+    CPD_TRY(W.alloc((size_t)R * R, s));
+    CPD_TRY(wk.alloc((size_t)R * R, s));
+    hipLaunchKernelGGL(k_make_w, dim3(1), dim3(256), 0, s, gs, nmodes, mode, R, W.p, wk.p, used_pinv);
+    CPD_LAUNCH_CHECK();
+    const int nb = (int)std::max<int64_t>(1, ceil_div(rows, 256));
+    CPD_TRY(part.alloc((size_t)nb * R, s));
+    const int RP = ((R + 15) / 16) * 16;
+    for (int pass = 0; pass < 2; ++pass) {
+#define CPD_APPLY(rp)                                                                                   \
+    case rp:                                                                                            \
+        hipLaunchKernelGGL(k_apply_w<rp>, dim3(nb), dim3(256), 0, s, Y, rows, R, (int64_t)ldy,          \
+                           (const double *)W.p, (const double *)lambda, A, (int64_t)lda, Ab, (int64_t)ldb, \
+                           part.p, pass);                                                               \
+        break;
+        switch (RP) {
+            CPD_APPLY(16)
+            CPD_APPLY(32)
+            CPD_APPLY(48)
+            CPD_APPLY(64)
+        }
+#undef CPD_APPLY
+        CPD_LAUNCH_CHECK();
+        if (pass == 0) {
+            hipLaunchKernelGGL(k_lambda, dim3(1), dim3(64), 0, s, (const double *)part.p, nb, R, lambda);
+            CPD_LAUNCH_CHECK();
+        }
+    }
+    if (G_new) CPD_TRY(gram(A, rows, R, lda, G_new, s));
+    return CPD_OK;
+}
+
+cpd_status fit(double normX2, const double *lambda, const float *A, int64_t lda, const float *Y,
+               int64_t ldy, int64_t rows, int R, const double *const *grams, int nmodes, double *out,
+               hipStream_t s) {
+    if (!lambda || !A || !Y || !grams || !out) CPD_FAIL(CPD_EINVAL, "null argument");
+    if (R < 1 || R > CPD_MAX_RANK || nmodes < 2 || nmodes > CPD_MAX_MODES || lda < R || ldy < R)
+        CPD_FAIL(CPD_EINVAL, "bad fit sizes");
+    if (!(normX2 > 0.0)) CPD_FAIL(CPD_EINVAL, "||X||^2 must be positive");
+    GramSet gs{};
+    for (int m = 0; m < nmodes; ++m) {
+        if (!grams[m]) CPD_FAIL(CPD_EINVAL, "null gram for mode %d", m);
+        gs.g[m] = grams[m];
+    }
+    const int nb = (int)std::min<int64_t>(1024, std::max<int64_t>(1, ceil_div(rows, 64)));
+    DevBuf<double> part;
+    CPD_TRY(part.alloc((size_t)nb * R, s));
+    hipLaunchKernelGGL(k_fit_partial, dim3(nb), dim3(256), 0, s, A, lda, Y, ldy, rows, R, part.p);
+    CPD_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_fit_final, dim3(1), dim3(64), 0, s, (const double *)part.p, nb, R, lambda, gs, nmodes,
+                       normX2, out);
+    CPD_LAUNCH_CHECK();
+    return CPD_OK;
+}
+
+cpd_status sumsq(const float *v, int64_t n, double *out, hipStream_t s) {
+    if (!v || !out || n < 0) CPD_FAIL(CPD_EINVAL, "bad sumsq arguments");
+    const int nb = (int)std::min<int64_t>(1024, std::max<int64_t>(1, ceil_div(n, 256)));
+    DevBuf<double> part;
+    CPD_TRY(part.alloc(nb, s));
+    hipLaunchKernelGGL(k_sumsq_partial, dim3(nb), dim3(256), 0, s, v, n, part.p);
+    CPD_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(64), 0, s, (const double *)part.p, nb, out);
+    CPD_LAUNCH_CHECK();
+    return CPD_OK;
+}
+
+}  // namespace cpd
+
+extern "C" {
+
+cpd_status cpd_gram(const float *A, int64_t rows, int32_t rank, int32_t ld, double *G, void *stream) {
+    cpd::clear_error();
+    return cpd::gram_internal(A, rows, rank, ld, G, (hipStream_t)stream);
+}
+
+cpd_status cpd_solve_normalize(const double *const *grams, int32_t nmodes, int32_t mode, const float *Y,
+                               int64_t rows, int32_t rank, int32_t ldy, float *A, int32_t lda,
+                               uint16_t *A_bf16, int32_t ldb, double *lambda, double *G_new,
+                               int32_t *used_pinv, void *stream) {
+    cpd::clear_error();
+    return cpd::solve_normalize(grams, nmodes, mode, Y, rows, rank, ldy, A, lda, A_bf16, ldb, lambda, G_new,
+                                used_pinv, (hipStream_t)stream);
+}
+
+cpd_status cpd_fit(double normX2, const double *lambda, const float *A_last, int32_t lda, const float *Y_last,
+                   int32_t ldy, int64_t rows, int32_t rank, const double *const *grams, int32_t nmodes,
+                   double *fit, void *stream) {
+    cpd::clear_error();
+    return cpd::fit(normX2, lambda, A_last, lda, Y_last, ldy, rows, rank, grams, nmodes, fit, (hipStream_t)stream);
+}
+
+cpd_status cpd_sumsq(const float *vals, int64_t n, double *out, void *stream) {
+    cpd::clear_error();
+    return cpd::sumsq(vals, n, out, (hipStream_t)stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,444 @@
+// MTTKRP on a CSF tree (Algorithm 1, lines 5, 8, 11; Section III):
+//     Y(i, r) = sum over nonzeros with i_mode = i of x * prod_{m != mode} A_m(i_m, r)
+// for an output mode at any level d of the tree.
+//
+// Work split: the leaves are cut into streams of T consecutive nonzeros; each
+// stream starts from the nodes that hold its first leaf (the tile table) and
+// walks its leaves in order, advancing the node cursors of the upper levels
+// as fibers end.  Every contribution is x * (leaf row) * H, where H is the
+// Hadamard product of the rows of the non-leaf levels other than d; it changes
+// only when a fiber ends.
+//
+// Two kernel families:
+//   ROW  (levels d < N-1): one stream per lane, the whole factor row in the
+//        lane's registers (vector loads), accumulation in registers, one
+//        atomic flush per output node the stream touches.
+//   LANE (any level): one stream per group of G lanes, column r on lane r of
+//        the group; coalesced row loads and coalesced atomics.  For the leaf
+//        level each nonzero adds v*H to its row, either with global atomics or
+//        into a block-private copy of Y in LDS (the paper's privatisation,
+//        Section IV-B / V-D2) that is flushed once per block.
+#include <type_traits>
+
+#include "csf.h"
+
+namespace cpd {
+namespace {
+
+struct CsfView {
+    const int32_t *fids[CPD_MAX_MODES];
+    const int32_t *fptr[CPD_MAX_MODES];
+    const float *vals;
+    int64_t nleaves;
+};
+
+struct FacView {
+    const void *a[CPD_MAX_MODES];  // by level
+};
+
+// ------------------------------------------------------------ row loaders
+template <typename GT, int RP>
+struct Row;
+
+template <int RP>
+struct Row<float, RP> {
+    static_assert(RP % 4 == 0, "fp32 rows load as float4");
+    __device__ static __forceinline__ void load(const void *base, int64_t ld, int32_t i, float (&v)[RP]) {
+        const float4 *p = reinterpret_cast<const float4 *>(static_cast<const float *>(base) + (int64_t)i * ld);
+#pragma unroll
+        for (int c = 0; c < RP / 4; ++c) {
+            float4 q = p[c];
+            v[4 * c + 0] = q.x;
+            v[4 * c + 1] = q.y;
+            v[4 * c + 2] = q.z;
+            v[4 * c + 3] = q.w;
+        }
+    }
+};
+
+template <int RP>
+struct Row<uint16_t, RP> {
+    static_assert(RP % 8 == 0, "bf16 rows load as 8-element chunks");
+    __device__ static __forceinline__ void load(const void *base, int64_t ld, int32_t i, float (&v)[RP]) {
+        const uint4 *p = reinterpret_cast<const uint4 *>(static_cast<const uint16_t *>(base) + (int64_t)i * ld);
+#pragma unroll
+        for (int c = 0; c < RP / 8; ++c) {
+            uint4 q = p[c];
+            v[8 * c + 0] = bf16_lo(q.x);
+            v[8 * c + 1] = bf16_hi(q.x);
+            v[8 * c + 2] = bf16_lo(q.y);
+            v[8 * c + 3] = bf16_hi(q.y);
+            v[8 * c + 4] = bf16_lo(q.z);
+            v[8 * c + 5] = bf16_hi(q.z);
+            v[8 * c + 6] = bf16_lo(q.w);
+            v[8 * c + 7] = bf16_hi(q.w);
+        }
+    }
+};
+
+template <typename GT>
+__device__ __forceinline__ float load1(const void *base, int64_t off);
+template <>
+__device__ __forceinline__ float load1<float>(const void *base, int64_t off) {
+    return static_cast<const float *>(base)[off];
+}
+template <>
+__device__ __forceinline__ float load1<uint16_t>(const void *base, int64_t off) {
+    return bf16_to_f32(static_cast<const uint16_t *>(base)[off]);
+}
+
+// ------------------------------------------------------------ ROW family
+template <int N, int RP, typename GT>
+__global__ void __launch_bounds__(256)
+k_mttkrp_row(CsfView cv, FacView fv, int64_t ld, int d, const int32_t *__restrict__ starts,
+             int64_t nstreams, int32_t T, float *__restrict__ Y, int64_t ldo, int R) {
+    const int64_t sid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (sid >= nstreams) return;  // no block-level synchronisation in this kernel
+    int64_t k = sid * (int64_t)T;
+    const int64_t kend = min(k + (int64_t)T, cv.nleaves);
+    int32_t c[N - 1], e[N - 1];
+#pragma unroll
+    for (int l = 0; l < N - 1; ++l) {
+        c[l] = starts[(int64_t)l * nstreams + sid];
+        e[l] = cv.fptr[l][c[l] + 1];
+    }
+    float P[RP], H[RP], acc[RP], row[RP];
+    // P: product of the rows of levels above the fiber level, except d.
+    auto make_P = [&]() {
+#pragma unroll
+        for (int r = 0; r < RP; ++r) P[r] = 1.0f;
+#pragma unroll
+        for (int l = 0; l < N - 2; ++l) {
+            if (l == d) continue;
+            Row<GT, RP>::load(fv.a[l], ld, cv.fids[l][c[l]], row);
+#pragma unroll
+            for (int r = 0; r < RP; ++r) P[r] *= row[r];
+        }
+    };
+    auto make_H = [&]() {
+        if (d == N - 2) {
+#pragma unroll
+            for (int r = 0; r < RP; ++r) H[r] = P[r];
+        } else {
+            Row<GT, RP>::load(fv.a[N - 2], ld, cv.fids[N - 2][c[N - 2]], row);
+#pragma unroll
+            for (int r = 0; r < RP; ++r) H[r] = P[r] * row[r];
+        }
+    };
+    auto flush = [&](int32_t out_row) {
+        float *y = Y + (int64_t)out_row * ldo;
+#pragma unroll
+        for (int r = 0; r < RP; ++r)
+            if (r < R) atomicAdd(y + r, acc[r]);
+    };
+    make_P();
+    make_H();
+#pragma unroll
+    for (int r = 0; r < RP; ++r) acc[r] = 0.0f;
+    int32_t out_row = cv.fids[d][c[d]];
+    const float *__restrict__ vals = cv.vals;
+    const int32_t *__restrict__ leaf = cv.fids[N - 1];
+    for (; k < kend; ++k) {
+        if (k == e[N - 2]) {  // a fiber ends: advance the cursors
+            int lmin = N - 2;
+            c[N - 2] += 1;
+            e[N - 2] = cv.fptr[N - 2][c[N - 2] + 1];
+            int32_t child = c[N - 2];
+#pragma unroll
+            for (int l = N - 3; l >= 0; --l) {
+                if (child != e[l]) break;
+                c[l] += 1;
+                e[l] = cv.fptr[l][c[l] + 1];
+                child = c[l];
+                lmin = l;
+            }
+            if (lmin <= d) {
+                flush(out_row);
+#pragma unroll
+                for (int r = 0; r < RP; ++r) acc[r] = 0.0f;
+                out_row = cv.fids[d][c[d]];
+            }
+            if (lmin < N - 2) make_P();
+            make_H();
+        }
+        const float v = vals[k];
+        Row<GT, RP>::load(fv.a[N - 1], ld, leaf[k], row);
+#pragma unroll
+        for (int r = 0; r < RP; ++r) acc[r] = fmaf(v * row[r], H[r], acc[r]);
+    }
+    flush(out_row);
+}
+
+// ------------------------------------------------------------ LANE family
+template <int N, int G, typename GT, bool PRIV>
+__global__ void __launch_bounds__(256)
+k_mttkrp_lane(CsfView cv, FacView fv, int64_t ld, int d, const int32_t *__restrict__ starts,
+              int64_t nstreams, int32_t T, float *__restrict__ Y, int64_t ldo, int R,
+              int64_t out_rows) {
+    extern __shared__ float ypriv[];  // PRIV: out_rows x R block-private copy
+    constexpr int NG = 256 / G;       // groups per block
+    const int lig = threadIdx.x % G;
+    const bool col = lig < R;
+    if (PRIV) {
+        for (int64_t j = threadIdx.x; j < out_rows * R; j += 256) ypriv[j] = 0.0f;
+        __syncthreads();
+    }
+    // persistent over streams when privatised (one flush per block), else one
+    // stream per group
+    const int64_t g0 = (int64_t)blockIdx.x * NG + threadIdx.x / G;
+    const int64_t gstep = PRIV ? (int64_t)gridDim.x * NG : nstreams + 1;
+    for (int64_t sid = g0; sid < nstreams; sid += gstep) {
+        int64_t k = sid * (int64_t)T;
+        const int64_t kend = min(k + (int64_t)T, cv.nleaves);
+        int32_t c[N - 1], e[N - 1];
+#pragma unroll
+        for (int l = 0; l < N - 1; ++l) {
+            c[l] = starts[(int64_t)l * nstreams + sid];
+            e[l] = cv.fptr[l][c[l] + 1];
+        }
+        auto make_H = [&]() {
+            float h = 1.0f;
+#pragma unroll
+            for (int l = 0; l < N - 1; ++l) {
+                if (l == d) continue;
+                h *= col ? load1<GT>(fv.a[l], (int64_t)cv.fids[l][c[l]] * ld + lig) : 0.0f;
+            }
+            return h;
+        };
+        float H = make_H();
+        float acc = 0.0f;
+        int32_t out_row = d < N - 1 ? cv.fids[d][c[d]] : 0;
+        for (; k < kend; ++k) {
+            if (k == e[N - 2]) {
+                int lmin = N - 2;
+                c[N - 2] += 1;
+                e[N - 2] = cv.fptr[N - 2][c[N - 2] + 1];
+                int32_t child = c[N - 2];
+#pragma unroll
+                for (int l = N - 3; l >= 0; --l) {
+                    if (child != e[l]) break;
+                    c[l] += 1;
+                    e[l] = cv.fptr[l][c[l] + 1];
+                    child = c[l];
+                    lmin = l;
+                }
+                if (d < N - 1 && lmin <= d) {
+                    if (col) {
+                        if (PRIV) atomicAdd(&ypriv[(int64_t)out_row * R + lig], acc);
+                        else atomicAdd(Y + (int64_t)out_row * ldo + lig, acc);
+                    }
+                    acc = 0.0f;
+                    out_row = cv.fids[d][c[d]];
+                }
+                H = make_H();
+            }
+            const float v = cv.vals[k];
+            const int32_t i = cv.fids[N - 1][k];
+            if (d == N - 1) {
+                if (col) {
+                    if (PRIV) atomicAdd(&ypriv[(int64_t)i * R + lig], v * H);
+                    else atomicAdd(Y + (int64_t)i * ldo + lig, v * H);
+                }
+            } else {
+                float a = col ? load1<GT>(fv.a[N - 1], (int64_t)i * ld + lig) : 0.0f;
+                acc = fmaf(v * a, H, acc);
+            }
+        }
+        if (d < N - 1 && col) {
+            if (PRIV) atomicAdd(&ypriv[(int64_t)out_row * R + lig], acc);
+            else atomicAdd(Y + (int64_t)out_row * ldo + lig, acc);
+        }
+    }
+    if (PRIV) {
+        __syncthreads();
+        for (int64_t j = threadIdx.x; j < out_rows * R; j += 256) {
+            float v = ypriv[j];
+            if (v != 0.0f) atomicAdd(Y + (j / R) * ldo + (j % R), v);
+        }
+    }
+}
+
+__global__ void k_zero_rows(float *Y, int64_t rows, int64_t ldo, int R) {
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= rows * R) return;
+    Y[(j / R) * ldo + (j % R)] = 0.0f;
+}
+
+// ------------------------------------------------------------ dispatch
+// Padded row widths with a ROW kernel: fp32 rows load as float4, bf16 rows as
+// 8-element chunks.
+inline int row_width(int R, bool bf16) {
+    if (R <= 8) return 8;
+    if (R <= 16) return 16;
+    if (R <= 32) return 32;
+    if (!bf16 && R <= 36) return 36;
+    if (bf16 && R <= 40) return 40;
+    return 64;
+}
+
+template <int N, typename GT>
+cpd_status launch_row(int RP, dim3 grid, hipStream_t s, const CsfView &cv, const FacView &fv,
+                      int64_t ld, int d, const int32_t *starts, int64_t ns, int32_t T, float *Y,
+                      int64_t ldo, int R) {
+    constexpr bool F32 = std::is_same<GT, float>::value;
+    constexpr int MID = F32 ? 36 : 40;  // the width between 32 and 64
+#define CPD_ROW_CASE(rp)                                                                           \
+    case rp:                                                                                       \
+        hipLaunchKernelGGL((k_mttkrp_row<N, rp, GT>), grid, dim3(256), 0, s, cv, fv, ld, d, starts, \
+                           ns, T, Y, ldo, R);                                                      \
+        break;
+    switch (RP) {
+        CPD_ROW_CASE(8)
+        CPD_ROW_CASE(16)
+        CPD_ROW_CASE(32)
+        CPD_ROW_CASE(MID)
+        CPD_ROW_CASE(64)
+        default:
+            CPD_FAIL(CPD_EUNSUPPORTED, "no row kernel for padded rank %d", RP);
+    }
+#undef CPD_ROW_CASE
+    CPD_LAUNCH_CHECK();
+    return CPD_OK;
+}
+
+template <int N, typename GT>
+cpd_status launch_lane(int G, bool priv, dim3 grid, size_t lds, hipStream_t s, const CsfView &cv,
+                       const FacView &fv, int64_t ld, int d, const int32_t *starts, int64_t ns,
+                       int32_t T, float *Y, int64_t ldo, int R, int64_t out_rows) {
+#define CPD_LANE_CASE(g)                                                                        \
+    case g:                                                                                     \
+        if (priv)                                                                               \
+            hipLaunchKernelGGL((k_mttkrp_lane<N, g, GT, true>), grid, dim3(256), lds, s, cv, fv, ld, \
+                               d, starts, ns, T, Y, ldo, R, out_rows);                          \
+        else                                                                                    \
+            hipLaunchKernelGGL((k_mttkrp_lane<N, g, GT, false>), grid, dim3(256), 0, s, cv, fv, ld, \
+                               d, starts, ns, T, Y, ldo, R, out_rows);                          \
+        break;
+    switch (G) {
+        CPD_LANE_CASE(8)
+        CPD_LANE_CASE(16)
+        CPD_LANE_CASE(32)
+        CPD_LANE_CASE(64)
+        default:
+            CPD_FAIL(CPD_EUNSUPPORTED, "no lane kernel for group %d", G);
+    }
+#undef CPD_LANE_CASE
+    CPD_LAUNCH_CHECK();
+    return CPD_OK;
+}
+
+constexpr size_t PRIV_LDS_MAX = 64 * 1024;
+constexpr double PRIV_THRESH = 0.02;  // privatise iff rows * copies <= 0.02 * nnz
+
+}  // namespace
+
+// Internal entry (also used by the ALS driver).
+cpd_status mttkrp(cpd_csf_s *c, const void *const *factors, int32_t ld, int32_t R, int32_t mode,
+                  float *Y, int32_t ldo, const cpd_mttkrp_opts *opts, hipStream_t s) {
+    if (!c) CPD_FAIL(CPD_EINVAL, "null CSF handle");
+    const int N = c->nmodes;
+    if (R < 1 || R > CPD_MAX_RANK) CPD_FAIL(CPD_EINVAL, "rank %d not in [1, %d]", R, CPD_MAX_RANK);
+    if (mode < 0 || mode >= N) CPD_FAIL(CPD_EINVAL, "mode %d not in [0, %d)", mode, N);
+    if (!factors || !Y) CPD_FAIL(CPD_EINVAL, "null factors or output");
+    if (ld < R || ldo < R) CPD_FAIL(CPD_EINVAL, "ld %d / ldo %d below rank %d", ld, ldo, R);
+    cpd_mttkrp_opts o = opts ? *opts : cpd_mttkrp_opts{CPD_FP32, CPD_VARIANT_AUTO, CPD_KERNEL_AUTO, 0};
+    if (o.precision != CPD_FP32 && o.precision != CPD_BF16_GATHER)
+        CPD_FAIL(CPD_EINVAL, "unknown precision %d", o.precision);
+    if (o.tile_nnz < 0) CPD_FAIL(CPD_EINVAL, "tile_nnz %d < 0", o.tile_nnz);
+    const bool bf16 = o.precision == CPD_BF16_GATHER;
+    const int d = c->depth_of(mode);
+    CsfView cv{};
+    FacView fv{};
+    for (int l = 0; l < N; ++l) {
+        cv.fids[l] = c->fids[l];
+        cv.fptr[l] = c->fptr[l];
+        const int m = c->order[l];
+        fv.a[l] = factors[m];
+        if (m != mode && !factors[m]) CPD_FAIL(CPD_EINVAL, "null factor for mode %d", m);
+    }
+    cv.vals = c->vals;
+    cv.nleaves = c->counts[N - 1];
+    const int64_t out_rows = c->dims[mode];
+
+    // ROW family eligibility: vector loads need the padded row inside ld and
+    // 16-byte aligned rows.
+    const int RP = row_width(R, bf16);
+    bool row_ok = d < N - 1 && ld >= RP && (ld * (bf16 ? 2 : 4)) % 16 == 0;
+    for (int l = 0; l < N && row_ok; ++l)
+        if (c->order[l] != mode && (reinterpret_cast<uintptr_t>(factors[c->order[l]]) & 15)) row_ok = false;
+    int kernel = o.kernel;
+    if (kernel == CPD_KERNEL_AUTO) kernel = (row_ok && d == 0) ? CPD_KERNEL_ROW : CPD_KERNEL_LANE;
+    if (kernel == CPD_KERNEL_ROW && !row_ok)
+        CPD_FAIL(CPD_EUNSUPPORTED, "row kernel needs a non-leaf mode, ld >= %d, 16-byte rows", RP);
+
+    // zero the output (columns < R)
+    {
+        int64_t tot = out_rows * R;
+        hipLaunchKernelGGL(k_zero_rows, dim3((unsigned)ceil_div(tot, 256)), dim3(256), 0, s, Y, out_rows,
+                           (int64_t)ldo, R);
+        CPD_LAUNCH_CHECK();
+    }
+    if (kernel == CPD_KERNEL_ROW) {
+        int32_t T = o.tile_nnz ? o.tile_nnz : 64;
+        const int32_t *starts;
+        int64_t ns;
+        CPD_TRY(csf_tiles(c, T, &starts, &ns, s));
+        dim3 grid((unsigned)ceil_div(ns, 256));
+#define CPD_ROW_N(n)                                                                                   \
+    case n:                                                                                            \
+        return bf16 ? launch_row<n, uint16_t>(RP, grid, s, cv, fv, ld, d, starts, ns, T, Y, ldo, R)    \
+                    : launch_row<n, float>(RP, grid, s, cv, fv, ld, d, starts, ns, T, Y, ldo, R);
+        switch (N) {
+            CPD_ROW_N(3)
+            CPD_ROW_N(4)
+            CPD_ROW_N(5)
+            default:
+                CPD_FAIL(CPD_EUNSUPPORTED, "row kernel built for 3..5 modes, not %d", N);
+        }
+#undef CPD_ROW_N
+    }
+    // LANE family
+    int G = R <= 8 ? 8 : R <= 16 ? 16 : R <= 32 ? 32 : 64;
+    int32_t T = o.tile_nnz ? o.tile_nnz : 256;
+    const int32_t *starts;
+    int64_t ns;
+    CPD_TRY(csf_tiles(c, T, &starts, &ns, s));
+    const size_t lds = (size_t)out_rows * R * sizeof(float);
+    bool priv = false;
+    if (d >= 1 && lds <= PRIV_LDS_MAX) {
+        const int64_t copies = 1024;  // persistent blocks below
+        if (o.variant == CPD_VARIANT_PRIVATE) priv = true;
+        else if (o.variant == CPD_VARIANT_AUTO)
+            priv = (double)out_rows * copies <= PRIV_THRESH * (double)cv.nleaves;
+    }
+    if (o.variant == CPD_VARIANT_PRIVATE && !priv)
+        CPD_FAIL(CPD_EUNSUPPORTED, "private variant needs a non-root mode with rows*rank*4 <= %zu bytes",
+                 PRIV_LDS_MAX);
+    const int NG = 256 / G;
+    dim3 grid = priv ? dim3((unsigned)std::min<int64_t>(1024, ceil_div(ns, NG)))
+                     : dim3((unsigned)ceil_div(ns, NG));
+#define CPD_LANE_N(n)                                                                                   \
+    case n:                                                                                             \
+        return bf16 ? launch_lane<n, uint16_t>(G, priv, grid, lds, s, cv, fv, ld, d, starts, ns, T, Y, ldo, \
+                                               R, out_rows)                                             \
+                    : launch_lane<n, float>(G, priv, grid, lds, s, cv, fv, ld, d, starts, ns, T, Y, ldo, R, \
+                                            out_rows);
+    switch (N) {
+        CPD_LANE_N(2)
+        CPD_LANE_N(3)
+        CPD_LANE_N(4)
+        CPD_LANE_N(5)
+        default:
+            CPD_FAIL(CPD_EUNSUPPORTED, "MTTKRP kernels are built for 2..5 modes, not %d", N);
+    }
+#undef CPD_LANE_N
+}
+
+}  // namespace cpd
+
+extern "C" cpd_status cpd_mttkrp(cpd_csf csf, const void *const *factors, int32_t ld, int32_t rank,
+                                 int32_t mode, float *out, int32_t ldo, const cpd_mttkrp_opts *opts,
+                                 void *stream) {
+    cpd::clear_error();
+    return cpd::mttkrp(csf, factors, ld, rank, mode, out, ldo, opts, (hipStream_t)stream);
+}

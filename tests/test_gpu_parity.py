@@ -1,0 +1,353 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle, element by
+element on the same seeded inputs.
+
+Bars: CSF arrays and tile tables bit-exact; FP32 MTTKRP relative Frobenius
+error <= 1e-5 and BF16-gather <= 1e-2 against the FP64 oracle on the same
+factors; the dense FP64 steps to ~1e-10; CP-ALS final fit within 1e-4.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import als as oals
+from oracle import coo as ocoo
+from oracle import csf as ocsf
+from paper_1812_05961_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _cpd():
+    from paper_1812_05961_amd import cpd
+    cpd.lib()
+    return cpd
+
+
+def _dev(t):
+    return t.to("cuda")
+
+
+def relerr(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    den = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (den if den > 0 else 1.0)
+
+
+def _tensor(dims, nnz, alphas, seed, values="lognormal:1.0"):
+    return synth.gen_sparse(dims, nnz, alphas, values, seed, device="cpu", topup=True, fp32=True)
+
+
+def _with_dups(t, ndup, seed):
+    """Append ndup repeats of existing coordinates (new values) in shuffled order."""
+    g = torch.Generator().manual_seed(seed)
+    pick = torch.randint(0, t.nnz, (ndup,), generator=g)
+    inds = torch.cat([t.inds, t.inds[:, pick]], 1)
+    vals = torch.cat([t.vals, torch.rand(ndup, generator=g, dtype=torch.float32)])
+    perm = torch.randperm(inds.shape[1], generator=g)
+    return synth.SparseTensor(t.dims, inds[:, perm].contiguous(), vals[perm].contiguous())
+
+
+def _small3():
+    t = synth.make_config("small3")
+    return synth.SparseTensor(t.dims, t.inds, t.vals.to(torch.float32))
+
+
+CASES = {
+    "small3": _small3,
+    "zipf3": lambda: _tensor((900, 700, 1300), 300_000, (1.1, 1.1, 1.1), 5),
+    "zipf4": lambda: _tensor((500, 300, 200, 90), 250_000, (1.0, 1.0, 1.0, 1.0), 6),
+    "zipf5": lambda: _tensor((60, 50, 40, 30, 20), 150_000, (0.5, 0.8, 0.0, 1.2, 0.3), 7),
+    "dups3": lambda: _with_dups(_tensor((50, 40, 30), 5_000, (0.0, 0.0, 0.0), 8), 2_000, 9),
+    "one_nnz": lambda: synth.SparseTensor((5, 6, 7), torch.tensor([[4], [0], [6]]),
+                                          torch.tensor([2.5], dtype=torch.float32)),
+}
+
+
+@pytest.fixture(scope="module", params=list(CASES))
+def case(request):
+    t = CASES[request.param]()
+    return request.param, t
+
+
+def _orders(nm):
+    import itertools
+    allp = list(itertools.permutations(range(nm)))
+    rng = np.random.default_rng(nm)
+    pick = [allp[i] for i in rng.choice(len(allp), size=min(3, len(allp)), replace=False)]
+    return [None] + pick
+
+
+# ----------------------------------------------------------------- CSF build
+
+def test_csf_bit_exact(case):
+    cpd = _cpd()
+    name, t = case
+    inds, vals = t.numpy()
+    for order in _orders(t.nmodes):
+        c = cpd.csf_build(_dev(t.inds), _dev(t.vals), t.dims, order)
+        ref = ocsf.build(t.dims, inds, t.vals.numpy(), order or ocsf.heuristic_order(t.dims))
+        assert c.order == ref["order"]
+        assert c.counts == ref["counts"]
+        for l in range(t.nmodes):
+            fids, fptr, v = c.export(l)
+            np.testing.assert_array_equal(fids.cpu().numpy(), ref["fids"][l])
+            if l < t.nmodes - 1:
+                np.testing.assert_array_equal(fptr.cpu().numpy(), ref["fptr"][l])
+            else:
+                assert v.cpu().numpy().tobytes() == ref["vals"].tobytes()
+        for T in (1, 64, 256, 1000):
+            np.testing.assert_array_equal(c.tiles(T).cpu().numpy(), ocsf.tile_starts(ref, T))
+        c.free()
+
+
+def test_csf_build_is_deterministic():
+    cpd = _cpd()
+    t = CASES["zipf4"]()
+    outs = []
+    for _ in range(2):
+        c = cpd.csf_build(_dev(t.inds), _dev(t.vals), t.dims)
+        outs.append([x.cpu().numpy().tobytes() for l in range(4) for x in c.export(l) if x is not None])
+    assert outs[0] == outs[1]
+
+
+def test_csf_rejects_bad_input():
+    cpd = _cpd()
+    inds = torch.tensor([[0, 1], [0, 3], [0, 1]], device="cuda")
+    vals = torch.ones(2, device="cuda")
+    with pytest.raises(cpd.CpdError) as e:
+        cpd.csf_build(inds, vals, (2, 3, 2))
+    assert e.value.status == cpd.CPD_EINVAL
+    with pytest.raises(cpd.CpdError):
+        cpd.csf_build(torch.tensor([[0], [0], [-1]], device="cuda"), vals[:1], (2, 3, 2))
+
+
+# ----------------------------------------------------------------- MTTKRP
+
+def _factors(dims, R, seed, ld=None, dtype=torch.float32):
+    g = torch.Generator().manual_seed(seed)
+    out = []
+    for d in dims:
+        a = torch.rand((d, R), generator=g, dtype=torch.float64) * 2 - 0.5
+        if ld is not None and ld > R:
+            buf = torch.zeros((d, ld), dtype=torch.float64)
+            buf[:, :R] = a
+            out.append(buf)
+        else:
+            out.append(a)
+    return out
+
+
+def _run(cpd, c, facs64, mode, R, precision, kernel, variant, tile=0):
+    dt = torch.float32 if precision == "fp32" else torch.bfloat16
+    dev = [f.to(dt).to("cuda") for f in facs64]
+    dims = [f.shape[0] for f in facs64]
+    out = torch.full((dims[mode], R + 3), 7.0, device="cuda")
+    cpd.mttkrp(c, dev, mode, out=out, rank=R, precision=precision, kernel=kernel, variant=variant,
+               tile_nnz=tile)
+    torch.cuda.synchronize()
+    o = out.cpu().numpy()
+    assert (o[:, R:] == 7.0).all(), "columns beyond the rank were written"
+    return o[:, :R], [f.to(dt).to(torch.float64)[:, :R].numpy() for f in facs64]
+
+
+@pytest.mark.parametrize("R,ld", [(8, None), (16, None), (35, 36), (32, None), (3, None), (64, None)])
+def test_mttkrp_every_level(case, R, ld):
+    cpd = _cpd()
+    name, t = case
+    inds, vals = t.numpy()
+    c = cpd.csf_build(_dev(t.inds), _dev(t.vals), t.dims)
+    facs = _factors(t.dims, R, 100 + R, ld)
+    for mode in range(t.nmodes):
+        depth = c.order.index(mode)
+        kernels = ["lane"] + (["row"] if depth < t.nmodes - 1 and (ld or R) >= 8 and R in (8, 16, 32, 35, 64) and t.nmodes <= 5 else [])
+        variants = ["atomic"] + (["private"] if depth >= 1 and t.dims[mode] * R * 4 <= 65536 else [])
+        for kernel in kernels:
+            for variant in (variants if kernel == "lane" else ["auto"]):
+                for prec in ("fp32", "bf16"):
+                    if prec == "bf16" and kernel == "row" and (ld or R) % 8:
+                        continue
+                    y, used = _run(cpd, c, facs, mode, R, prec, kernel, variant)
+                    ref = ocoo.mttkrp(t.dims, inds, vals, [f[:, :R].numpy() for f in facs], mode)
+                    tol = 1e-5 if prec == "fp32" else 1e-2
+                    err = relerr(y, ref)
+                    assert err <= tol, (name, mode, kernel, variant, prec, err)
+                    if prec == "bf16":
+                        # same kernel arithmetic on the rounded rows: tight
+                        ref_b = ocoo.mttkrp(t.dims, inds, vals, used, mode)
+                        assert relerr(y, ref_b) <= 1e-5, (name, mode, kernel, variant, err)
+
+
+@pytest.mark.parametrize("tile", [1, 7, 64, 4096])
+def test_mttkrp_tile_widths(tile):
+    cpd = _cpd()
+    t = CASES["zipf3"]()
+    inds, vals = t.numpy()
+    c = cpd.csf_build(_dev(t.inds), _dev(t.vals), t.dims)
+    facs = _factors(t.dims, 16, 5)
+    for mode in range(3):
+        ref = ocoo.mttkrp(t.dims, inds, vals, [f.numpy() for f in facs], mode)
+        for kernel in (["lane", "row"] if c.order.index(mode) < 2 else ["lane"]):
+            y, _ = _run(cpd, c, facs, mode, 16, "fp32", kernel, "auto", tile)
+            assert relerr(y, ref) <= 1e-5, (mode, kernel, tile)
+
+
+def test_mttkrp_rejects_bad_arguments():
+    cpd = _cpd()
+    t = CASES["small3"]()
+    c = cpd.csf_build(_dev(t.inds), _dev(t.vals), t.dims)
+    facs = [torch.rand((d, 8), device="cuda") for d in t.dims]
+    with pytest.raises(ValueError):
+        cpd.mttkrp(c, facs, 3)
+    with pytest.raises(cpd.CpdError):
+        cpd.mttkrp(c, facs, 3, out=torch.empty((10, 8), device="cuda"))
+    with pytest.raises(cpd.CpdError):
+        cpd.mttkrp(c, facs, 0, rank=65)
+    # the row kernel is not available for the leaf level
+    leaf = c.order[-1]
+    with pytest.raises(cpd.CpdError) as e:
+        cpd.mttkrp(c, facs, leaf, kernel="row")
+    assert e.value.status == cpd.CPD_EUNSUPPORTED
+
+
+# ----------------------------------------------------------------- dense steps
+
+@pytest.mark.parametrize("rows,R", [(1, 1), (37, 5), (1000, 16), (4097, 35), (20000, 64)])
+def test_gram(rows, R):
+    cpd = _cpd()
+    g = torch.Generator().manual_seed(rows + R)
+    A = (torch.rand((rows, R), generator=g) - 0.3).to(torch.float32)
+    G = cpd.gram(A.cuda()).cpu().numpy()
+    ref = oals.gram(A.numpy().astype(np.float64))
+    np.testing.assert_allclose(G, ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
+    assert (G == G.T).all()
+
+
+@pytest.mark.parametrize("R", [1, 8, 16, 35, 64])
+def test_solve_normalize(R):
+    cpd = _cpd()
+    rng = np.random.default_rng(R)
+    dims = (300, 200, 100)
+    facs = [rng.uniform(0, 1, (d, R)) for d in dims]
+    grams = [oals.gram(f.astype(np.float32).astype(np.float64)) for f in facs]
+    Y = rng.standard_normal((dims[1], R)).astype(np.float32)
+    out = cpd.solve_normalize([torch.from_numpy(gm).cuda() for gm in grams], 1,
+                              torch.from_numpy(Y).cuda(), want_bf16=True)
+    torch.cuda.synchronize()
+    An, used = oals.normal_solve(oals.hadamard_v(grams, 1), Y.astype(np.float64))
+    Aref, lam = oals.normalize_columns(An)
+    assert int(out["used_pinv"].item()) == int(used)
+    np.testing.assert_allclose(out["lam"].cpu().numpy(), lam, rtol=1e-9)
+    assert relerr(out["A"].cpu().numpy(), Aref) <= 1e-6
+    assert torch.equal(out["A_bf16"].cpu(), out["A"].cpu().to(torch.bfloat16))
+    Gn = oals.gram(out["A"].cpu().numpy().astype(np.float64))
+    np.testing.assert_allclose(out["G"].cpu().numpy(), Gn, rtol=1e-10, atol=1e-12)
+
+
+def test_solve_normalize_singular_uses_pinv():
+    cpd = _cpd()
+    rng = np.random.default_rng(3)
+    R = 6
+    M = rng.standard_normal((40, R))
+    M[:, 4] = M[:, 2]
+    G1 = M.T @ M
+    grams = [np.ones((R, R)), G1, np.ones((R, R))]
+    Y = rng.standard_normal((25, R)).astype(np.float32)
+    out = cpd.solve_normalize([torch.from_numpy(g).cuda() for g in grams], 0, torch.from_numpy(Y).cuda())
+    torch.cuda.synchronize()
+    An, used = oals.normal_solve(oals.hadamard_v(grams, 0), Y.astype(np.float64))
+    assert used and int(out["used_pinv"].item()) == 1
+    Aref, lam = oals.normalize_columns(An)
+    assert relerr(out["A"].cpu().numpy(), Aref) <= 1e-5
+    np.testing.assert_allclose(out["lam"].cpu().numpy(), lam, rtol=1e-6)
+
+
+def test_solve_normalize_zero_column():
+    cpd = _cpd()
+    R = 4
+    G = np.eye(R)
+    Y = np.ones((10, R), dtype=np.float32)
+    Y[:, 1] = 0
+    out = cpd.solve_normalize([torch.from_numpy(G).cuda()] * 3, 2, torch.from_numpy(Y).cuda())
+    A = out["A"].cpu().numpy()
+    assert np.isfinite(A).all() and (A[:, 1] == 0).all()
+    assert out["lam"].cpu().numpy()[1] == 0.0
+
+
+def test_fit_matches_oracle():
+    cpd = _cpd()
+    t = CASES["zipf3"]()
+    inds, vals = t.numpy()
+    R = 8
+    rng = np.random.default_rng(1)
+    facs = [rng.uniform(0, 1, (d, R)).astype(np.float32).astype(np.float64) for d in t.dims]
+    lam = rng.uniform(0.5, 2, R)
+    Y = ocoo.mttkrp(t.dims, inds, vals, facs, 2)
+    grams = [oals.gram(f) for f in facs]
+    nx = ocoo.sumsq(vals)
+    ref = oals.fit_from(nx, lam, facs[2], Y, grams)
+    got = cpd.fit(nx, torch.from_numpy(lam).cuda(), torch.from_numpy(facs[2]).float().cuda(),
+                  torch.from_numpy(Y).float().cuda(), [torch.from_numpy(g).cuda() for g in grams])
+    assert abs(got.item() - ref) < 1e-6
+    s = cpd.sumsq(t.vals.cuda()).item()
+    assert abs(s - nx) <= 1e-12 * nx
+
+
+# ----------------------------------------------------------------- CP-ALS
+
+@pytest.mark.parametrize("single_csf", [False, True])
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_als_small3_matches_oracle(single_csf, precision):
+    cpd = _cpd()
+    t = synth.make_config("small3")          # float64 values, rounded to FP32 for the GPU
+    inds, vals64 = t.numpy()
+    R, iters = 8, 20
+    init = synth.init_factors(t.dims, R, 11)
+    ref = oals.cp_als(t.dims, inds, vals64, R, iters, 0.0, [a.numpy() for a in init])
+    got = cpd.als(_dev(t.inds), _dev(t.vals.float()), t.dims, R, iters, 0.0,
+                  init=[a.float().cuda() for a in init], precision=precision,
+                  single_csf=single_csf)
+    assert got["iters"] == iters
+    tol = 1e-4
+    assert abs(got["fit"] - ref["fit"]) <= tol, (got["fit"], ref["fit"])
+    if precision == "fp32":
+        np.testing.assert_allclose(got["fits"], ref["fits"], atol=1e-5)
+        np.testing.assert_allclose(got["lam"], ref["lam"], rtol=1e-3)
+        for m in range(3):
+            assert relerr(got["factors"][m].cpu().numpy(), ref["factors"][m]) <= 1e-3
+
+
+def test_als_planted_block_recovers():
+    cpd = _cpd()
+    t, _ = synth.block_planted()
+    got = None
+    for s in range(3):
+        init = synth.init_factors(t.dims, 8, 100 + s)
+        got = cpd.als(_dev(t.inds), _dev(t.vals.float()), t.dims, 8, 500, 1e-9,
+                      init=[a.float().cuda() for a in init])
+        if got["fit"] >= 1 - 1e-4:
+            break
+    # FP32 factors: the fit saturates near 1 - (float rounding), not 1 - 1e-6
+    assert got["fit"] >= 1 - 1e-4
+
+
+def test_als_4mode_and_5mode_match_oracle():
+    cpd = _cpd()
+    for name, R in (("zipf4", 8), ("zipf5", 4)):
+        t = CASES[name]()
+        inds, vals = t.numpy()
+        init = synth.init_factors(t.dims, R, 3)
+        ref = oals.cp_als(t.dims, inds, vals, R, 5, 0.0, [a.numpy() for a in init])
+        got = cpd.als(_dev(t.inds), _dev(t.vals), t.dims, R, 5, 0.0, init=[a.float().cuda() for a in init])
+        np.testing.assert_allclose(got["fits"], ref["fits"], atol=1e-4)
+
+
+def test_als_convergence_stop_and_seeded_init():
+    cpd = _cpd()
+    t = synth.make_config("small3")
+    got = cpd.als(_dev(t.inds), _dev(t.vals.float()), t.dims, 4, 50, 1.0, seed=5, timing=True)
+    assert got["iters"] == 2
+    assert got["timing_ms"]["total"] > 0
+    again = cpd.als(_dev(t.inds), _dev(t.vals.float()), t.dims, 4, 3, 0.0, seed=5)
+    same = cpd.als(_dev(t.inds), _dev(t.vals.float()), t.dims, 4, 3, 0.0, seed=5)
+    assert abs(again["fit"] - same["fit"]) < 1e-6
