@@ -1,0 +1,226 @@
+#!/usr/bin/env python3
+"""Benchmark of the sparse CP-ALS hot path on one MI355X.
+
+A step is one whole CP-ALS job on a tensor already resident in HBM: index
+check, sort and CSF construction (one tree rooted at each mode), then the
+ALS sweeps (per mode: V, MTTKRP, solve, normalise, Gram) with the fit after
+each sweep.  The default workload is the NELL-2-shaped synthetic tensor
+(12,000 x 9,000 x 29,000, 76M distinct nonzeros, Zipf(1.1) per mode,
+lognormal values, rank 35, 10 sweeps).
+
+Prints one JSON line: value = CP-ALS seconds per sweep (whole step / sweeps),
+plus the MTTKRP ns/nnz per mode, the HBM-roofline fraction of the MTTKRP
+kernel (algorithmic bytes / measured kernel time), the oracle timed on a
+bounded sample on the host (cpu_baseline), and the BF16-gather vs FP32
+comparison on the NETFLIX-shaped tensor.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "MTTKRP ns/nnz & HBM-roofline %; CP-ALS s/iter, BF16 vs FP32 at fit±1e-4"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def root_orders(dims):
+    """The mode order of each per-mode CSF: the mode first, then the others by
+    ascending length (ties to the lower mode)."""
+    nm = len(dims)
+    out = []
+    for m in range(nm):
+        rest = sorted([q for q in range(nm) if q != m], key=lambda q: (dims[q], q))
+        out.append([m] + rest)
+    return out
+
+
+def root_kernel_name(nmodes, R, precision):
+    """Template instance of the root-level MTTKRP kernel used for rank R: G
+    lanes per leaf, one 16-byte chunk each, over the padded row."""
+    if precision == "fp32":
+        width = next(w for w in (8, 16, 32, 36, 64) if w >= R)
+        return "k_mttkrp_root<%d, %d, float>" % (nmodes, width // 4)
+    width = next(w for w in (16, 16, 32, 40, 64) if w >= R)
+    return "k_mttkrp_root<%d, %d, unsigned short>" % (nmodes, width // 8)
+
+
+def alg_bytes(counts, dims, mode, R):
+    """Compulsory HBM bytes of one MTTKRP on a CSF with level counts `counts`:
+    the tree once (int32 ids, int32 pointers, float values), every input
+    factor once and the output once (float rows of R entries)."""
+    nm = len(dims)
+    b = sum(4 * counts[l] + 4 * (counts[l] + 1) for l in range(nm - 1))
+    b += 8 * counts[nm - 1]
+    b += sum(4 * dims[m] * R for m in range(nm) if m != mode)
+    b += 4 * dims[mode] * R
+    return b
+
+
+def run_steps(cpd, x, R, iters, steps, warmup, precision, seed=7):
+    import torch
+    inds, vals = x.inds, x.vals
+    res = None
+    for _ in range(warmup):
+        res = cpd.als(inds, vals, x.dims, R, iters, 0.0, precision=precision, seed=seed, timing=True)
+    torch.cuda.synchronize()
+    runs = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        runs.append(cpd.als(inds, vals, x.dims, R, iters, 0.0, precision=precision, seed=seed,
+                            timing=True))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return wall, runs
+
+
+def summarize(runs, nm):
+    import statistics as st
+    csf = st.mean(r["timing_ms"]["csf_build"] for r in runs)
+    # sweeps 2..K: the first sweep also builds the tile tables
+    iters = [row[nm] for r in runs for row in r["timing_ms"]["per_iter"][1:]]
+    mt = [[row[n] for r in runs for row in r["timing_ms"]["per_iter"][1:]] for n in range(nm)]
+    return dict(csf_build_ms=csf, iter_ms=st.mean(iters), mttkrp_ms=[st.mean(v) for v in mt])
+
+
+def cpu_baseline(x, R, sample_nnz, seed=11):
+    """The oracle (single-threaded C MTTKRP + numpy ALS steps, BLAS limited to
+    one thread) on the first sample_nnz nonzeros, one sweep; scaled to the
+    full tensor by the nonzero ratio."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import als as oals
+    from oracle import coo as ocoo
+    from paper_1812_05961_amd import synth
+
+    S = min(sample_nnz, x.nnz)
+    inds = x.inds[:, :S].cpu().numpy().astype(np.int64)
+    vals = x.vals[:S].cpu().double().numpy()
+    init = [a.numpy() for a in synth.init_factors(x.dims, R, seed)]
+    ocoo.build()
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        oals.cp_als(x.dims, inds, vals, R, 1, 0.0, init)
+        t = time.perf_counter() - t0
+    return dict(value=t * x.nnz / S, unit="s/iter", cores=1, kind="oracle",
+                sample="first %d of %d nonzeros (a uniform random subset: the generator emits "
+                       "coordinates in seeded random order), one CP-ALS sweep of the FP64 oracle "
+                       "(C MTTKRP loop, numpy solve), %.2f s measured, scaled by the nonzero ratio"
+                       % (S, x.nnz, t))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="nell2")
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16"])
+    ap.add_argument("--cpu-sample-nnz", type=int, default=16_000_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the BF16-vs-FP32 comparison on the NETFLIX-shaped tensor")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the hot path is built and measured on a single "
+              "MI355X (--gpus %d was requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1812_05961_amd import cpd, synth
+    cpd.lib()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    cfg = synth.CONFIGS[args.workload]
+    R, iters = cfg["rank"], cfg["iters"]
+
+    t0 = time.perf_counter()
+    x = synth.make_config(args.workload, device=dev)
+    x.inds = x.inds.to(torch.int32)
+    torch.cuda.synchronize()
+    log("generated %s: %d nnz in %.1f s" % (args.workload, x.nnz, time.perf_counter() - t0))
+
+    wall, runs = run_steps(cpd, x, R, iters, args.steps, args.warmup, args.precision)
+    s = summarize(runs, x.nmodes)
+    log("steps done: %.3f s wall for %d steps" % (wall, args.steps))
+
+    # level counts of the per-mode trees, for the algorithmic bytes
+    counts = []
+    for m, order in enumerate(root_orders(x.dims)):
+        c = cpd.csf_build(x.inds, x.vals, x.dims, order)
+        counts.append(c.counts)
+        c.free()
+    nnz_csf = counts[0][-1]
+    bytes_mode = [alg_bytes(counts[m], x.dims, m, R) for m in range(x.nmodes)]
+    avg_bytes = sum(bytes_mode) / len(bytes_mode)
+    avg_ms = sum(s["mttkrp_ms"]) / len(s["mttkrp_ms"])
+    achieved = avg_bytes / (avg_ms * 1e-3) / 1e9
+    kernel = root_kernel_name(x.nmodes, R, args.precision)
+    roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None, kernel=kernel,
+                    bytes_per_launch=int(avg_bytes), avg_launch_us=round(avg_ms * 1e3, 2))
+
+    ms_per_step = wall / args.steps * 1e3
+    out = dict(
+        metric=METRIC, value=round(ms_per_step / 1e3 / iters, 6), unit="s/iter", n_gpus=1,
+        steps=args.steps, warmup=args.warmup, ms_per_step=round(ms_per_step, 3),
+        higher_is_better=False, scaling="weak", vs_baseline=None,
+        dtype="f32" if args.precision == "fp32" else "bf16-gather/f32",
+        data="synthetic",
+        config=dict(workload="%s: %s, %d distinct nonzeros, Zipf alphas %s, %s values, rank %d, "
+                             "%d CP-ALS sweeps from COO in HBM (CSF build included), one CSF "
+                             "per mode" % (args.workload, "x".join(map(str, x.dims)), nnz_csf,
+                                           cfg["alphas"], cfg["values"], R, iters),
+                    dims=list(x.dims), nnz=nnz_csf, rank=R, iters=iters,
+                    precision=args.precision),
+        breakdown=dict(csf_build_ms=round(s["csf_build_ms"], 3), als_iter_ms=round(s["iter_ms"], 4),
+                       mttkrp_ms=[round(v, 4) for v in s["mttkrp_ms"]],
+                       mttkrp_ns_per_nnz=[round(v * 1e6 / nnz_csf, 4) for v in s["mttkrp_ms"]],
+                       mttkrp_alg_bytes=bytes_mode,
+                       mttkrp_roofline_frac=[round(b / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+                                             for b, t in zip(bytes_mode, s["mttkrp_ms"])],
+                       fit=runs[-1]["fit"]),
+        roofline=roofline,
+    )
+    log("main line ready; value %.5f s/iter" % out["value"])
+
+    if not args.no_compare and args.workload == "nell2":
+        cmp = {}
+        y = synth.make_config("netflix", device=dev)
+        y.inds = y.inds.to(torch.int32)
+        torch.cuda.synchronize()
+        ycfg = synth.CONFIGS["netflix"]
+        for prec in ("fp32", "bf16"):
+            w, rr = run_steps(cpd, y, ycfg["rank"], ycfg["iters"], 1, 1, prec)
+            ss = summarize(rr, y.nmodes)
+            cmp[prec] = dict(s_per_iter=round(ss["iter_ms"] / 1e3, 6),
+                             mttkrp_ms=[round(v, 4) for v in ss["mttkrp_ms"]],
+                             fit=rr[-1]["fit"])
+        cmp["fit_diff"] = abs(cmp["fp32"]["fit"] - cmp["bf16"]["fit"])
+        cmp["bf16_speedup_mttkrp"] = round(sum(cmp["fp32"]["mttkrp_ms"]) / sum(cmp["bf16"]["mttkrp_ms"]), 3)
+        cmp["workload"] = "netflix: %s, %d nnz, rank %d, %d sweeps" % (
+            "x".join(map(str, y.dims)), y.nnz, ycfg["rank"], ycfg["iters"])
+        out["precision_compare"] = cmp
+        del y
+        log("precision comparison done")
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(x, R, args.cpu_sample_nnz)
+        log("cpu baseline done")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -23,7 +23,7 @@ void set_error(const char *fmt, ...) {
 void clear_error() { g_err[0] = 0; }
 
 cpd_status mttkrp(cpd_csf_s *c, const void *const *factors, int32_t ld, int32_t R, int32_t mode, float *Y,
-                  int32_t ldo, const cpd_mttkrp_opts *opts, hipStream_t s);
+                  int32_t ldo, const cpd_mttkrp_opts *opts, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
 cpd_status gram_internal(const float *A, int64_t rows, int R, int64_t ld, double *G, hipStream_t s);
 cpd_status solve_normalize(const double *const *grams, int nmodes, int mode, const float *Y, int64_t rows,
                            int R, int64_t ldy, float *A, int64_t lda, uint16_t *Ab, int64_t ldb,
@@ -70,7 +70,7 @@ __global__ void k_fill_zero_u16(uint16_t *p, int64_t n) {
 }
 
 inline int pad_width(int R, bool bf16) {
-    if (R <= 8) return 8;
+    if (R <= 8) return bf16 ? 16 : 8;  // rows of at least two 16-byte chunks
     if (R <= 16) return 16;
     if (R <= 32) return 32;
     if (!bf16 && R <= 36) return 36;
@@ -231,9 +231,7 @@ cpd_status als(int nm, const int64_t *dims, int64_t nnz, const int32_t *const *i
     for (it = 1; it <= max_iters; ++it) {
         for (int n = 0; n < nm; ++n) {
             hipEvent_t e0 = timing ? evs.make() : nullptr, e1 = timing ? evs.make() : nullptr;
-            if (timing) CPD_HIP(hipEventRecord(e0, s));
-            CPD_TRY(mttkrp(csf_of[n], fac_ptrs, fld, R, n, Y, ldf, &mo, s));
-            if (timing) CPD_HIP(hipEventRecord(e1, s));
+            CPD_TRY(mttkrp(csf_of[n], fac_ptrs, fld, R, n, Y, ldf, &mo, s, e0, e1));
             ev_mt0.push_back(e0);
             ev_mt1.push_back(e1);
             CPD_TRY(solve_normalize(gptr, nm, n, Y, dims[n], R, ldf, A[n], ldf, bf16 ? Ab[n] : nullptr, ldb,
@@ -260,7 +258,7 @@ cpd_status als(int nm, const int64_t *dims, int64_t nnz, const int32_t *const *i
         for (int m = 0; m < nm; ++m) f32_ptrs[m] = A[m];
         cpd_mttkrp_opts mf = mo;
         mf.precision = CPD_FP32;
-        CPD_TRY(mttkrp(csf_of[nm - 1], f32_ptrs, ldf, R, nm - 1, Y, ldf, &mf, s));
+        CPD_TRY(mttkrp(csf_of[nm - 1], f32_ptrs, ldf, R, nm - 1, Y, ldf, &mf, s, nullptr, nullptr));
         CPD_TRY(fit(h_normX2, lambda, A[nm - 1], ldf, Y, ldf, dims[nm - 1], R, gptr, nm, d_fit + max_iters, s));
     }
     hipEvent_t t_end = timing ? evs.make() : nullptr;

@@ -15,6 +15,17 @@ struct cpd_csf_s {
     int32_t *fids[CPD_MAX_MODES] = {};    // per level
     int32_t *fptr[CPD_MAX_MODES] = {};    // per level < N-1
     float *vals = nullptr;
+    // Leaf words for the MTTKRP kernels: leafw[k] = (lvl << 29) | rank of
+    // fids[N-1][k], lvl = the highest level at which leaf k starts a new node
+    // (0 = a new root node, N-1 = same fiber as leaf k-1), rank = position of
+    // the leaf index when the indices are ordered by how often they occur
+    // (leaf_perm[rank] = index).  Null when a leaf index does not fit in 29 bits.
+    int32_t *leafw = nullptr;
+    int32_t *leaf_perm = nullptr;
+    // Per-leaf row ids of the internal levels 1..N-2 (uprow[l][k] = the index
+    // i_order[l] of leaf k), so a kernel can gather every leaf's internal rows
+    // without walking fiber pointers.  Allocated with leafw.
+    int32_t *uprow[CPD_MAX_MODES] = {};
 
     struct Tiles {
         int32_t tile;

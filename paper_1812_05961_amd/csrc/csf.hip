@@ -136,6 +136,77 @@ struct HistAt {
     __device__ int32_t operator()(int64_t i) const { return h[i]; }
 };
 
+// Stable LSD radix sort of n keys (one or two 64-bit words, `bits` significant
+// bits) with an int32 payload, 8 bits per pass, ping-ponging between the
+// (k*, p*) and (o*, op*) buffers; on return k*, kp point at the sorted data.
+cpd_status radix_sort(uint64_t *&klo, uint64_t *&khi, int32_t *&kp, uint64_t *&olo, uint64_t *&ohi, int32_t *&op,
+                      int64_t n, int bits, hipStream_t s) {
+    const int64_t ntiles = ceil_div(n, RS_TILE);
+    if (ntiles == 0) return CPD_OK;
+    DevBuf<int32_t> hist;
+    CPD_TRY(hist.alloc((size_t)256 * ntiles, s));
+    const int passes = (bits + 7) / 8;
+    for (int d = 0; d < passes; ++d) {
+        int word = (8 * d) / 64, shift = (8 * d) % 64;
+        const uint64_t *src = word ? khi : klo;
+        hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)ntiles), dim3(RS_THREADS), 0, s, src, n, shift, hist.p, ntiles);
+        CPD_LAUNCH_CHECK();
+        CPD_TRY(exclusive_scan(HistAt{hist.p}, 256 * ntiles, hist.p, (int32_t *)nullptr, s));
+        hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)ntiles), dim3(RS_THREADS), 0, s, klo, khi, kp, olo, ohi, op,
+                           (const int32_t *)hist.p, n, ntiles, word, shift);
+        CPD_LAUNCH_CHECK();
+        std::swap(klo, olo);
+        std::swap(khi, ohi);
+        std::swap(kp, op);
+    }
+    return CPD_OK;
+}
+
+// ---- leaf ranking: leaf ids ordered by how often a strided sample of the
+// leaves holds them (descending, ties by id); only the MTTKRP kernels' cache
+// of hot rows depends on it, never a result.
+__global__ void k_sample(const int32_t *ids, int64_t stride, int64_t ns, uint64_t *key, int32_t *pay) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ns) return;
+    key[i] = (uint64_t)(uint32_t)ids[i * stride];
+    pay[i] = 0;
+}
+
+struct RunStart {
+    const uint64_t *key;
+    __device__ int32_t operator()(int64_t i) const { return (i == 0 || key[i] != key[i - 1]) ? 1 : 0; }
+};
+
+__global__ void k_run_starts(const uint64_t *key, const int32_t *pos, int64_t ns, int32_t *starts) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ns || !(i == 0 || key[i] != key[i - 1])) return;
+    starts[pos[i]] = (int32_t)i;
+}
+
+__global__ void k_run_counts(const uint64_t *key, const int32_t *starts, const int32_t *nruns, int64_t ns,
+                             int32_t *cnt) {
+    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t nr = *nruns;
+    if (r >= nr) return;
+    const int32_t b = starts[r], e = (r + 1 < nr) ? starts[r + 1] : (int32_t)ns;
+    cnt[key[b]] = e - b;
+}
+
+__global__ void k_rank_keys(const int32_t *cnt, int64_t nid, uint64_t *key, int32_t *pay) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nid) return;
+    key[i] = ((uint64_t)(0x7fffffff - cnt[i]) << 32) | (uint64_t)i;
+    pay[i] = 0;
+}
+
+__global__ void k_rank_scatter(const uint64_t *key, int64_t nid, int32_t *perm, int32_t *rank) {
+    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nid) return;
+    const int32_t id = (int32_t)(key[r] & 0xffffffffull);
+    perm[r] = id;
+    rank[id] = (int32_t)r;
+}
+
 // First level at which sorted key k differs from key k-1 (0 for k = 0, nl for
 // an exact duplicate).
 __global__ void k_first_diff(const uint64_t *lo, const uint64_t *hi, KeyLayout kl, int64_t n,
@@ -200,6 +271,18 @@ __global__ void k_leaf(const uint64_t *lo, const uint64_t *hi, KeyLayout kl, int
     fids[k] = (int32_t)key_field(lo[k], hi ? hi[k] : 0ull, kl.shift[l], kl.bits[l]);
 }
 
+__global__ void k_leafw(const uint8_t *dl, const int32_t *fids, const int32_t *rank, int64_t n, int32_t *leafw) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    leafw[k] = (int32_t)(((uint32_t)dl[k] << 29) | (uint32_t)rank[fids[k]]);
+}
+
+__global__ void k_uprow(const uint64_t *lo, const uint64_t *hi, KeyLayout kl, int64_t n, int l, int32_t *out) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    out[k] = (int32_t)key_field(lo[k], hi ? hi[k] : 0ull, kl.shift[l], kl.bits[l]);
+}
+
 __global__ void k_set_last(int32_t *fptr, int64_t at, const int32_t *value) {
     fptr[at] = *value;
 }
@@ -240,6 +323,10 @@ void free_csf(cpd_csf_s *c) {
         if (c->fptr[l]) (void)hipFree(c->fptr[l]);
     }
     if (c->vals) (void)hipFree(c->vals);
+    if (c->leafw) (void)hipFree(c->leafw);
+    if (c->leaf_perm) (void)hipFree(c->leaf_perm);
+    for (int l = 0; l < CPD_MAX_MODES; ++l)
+        if (c->uprow[l]) (void)hipFree(c->uprow[l]);
     for (auto &t : c->tiles) (void)hipFree(t.starts);
     delete c;
 }
@@ -310,27 +397,9 @@ cpd_status build(int nm, const int64_t *dims, int64_t nnz, const int32_t *const 
     CPD_TRY(p1.alloc(nnz, s));
     hipLaunchKernelGGL(k_pack, dim3(grid1(nnz)), dim3(256), 0, s, li, kl, nnz, lo0.p, hi0.p, p0.p);
     CPD_LAUNCH_CHECK();
-    const int64_t ntiles = ceil_div(nnz, RS_TILE);
-    DevBuf<int32_t> hist;
-    CPD_TRY(hist.alloc((size_t)256 * ntiles, s));
     uint64_t *klo = lo0.p, *khi = hi0.p, *olo = lo1.p, *ohi = hi1.p;
     int32_t *kp = p0.p, *op = p1.p;
-    const int passes = (total_bits + 7) / 8;
-    for (int d = 0; d < passes; ++d) {
-        int word = (8 * d) / 64, shift = (8 * d) % 64;
-        const uint64_t *src = word ? khi : klo;
-        hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)ntiles), dim3(RS_THREADS), 0, s, src, nnz,
-                           shift, hist.p, ntiles);
-        CPD_LAUNCH_CHECK();
-        CPD_TRY(exclusive_scan(HistAt{hist.p}, 256 * ntiles, hist.p, (int32_t *)nullptr, s));
-        hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)ntiles), dim3(RS_THREADS), 0, s, klo, khi,
-                           kp, olo, ohi, op, (const int32_t *)hist.p, nnz, ntiles, word, shift);
-        CPD_LAUNCH_CHECK();
-        std::swap(klo, olo);
-        std::swap(khi, ohi);
-        std::swap(kp, op);
-    }
-    hist.release();
+    CPD_TRY(radix_sort(klo, khi, kp, olo, ohi, op, nnz, total_bits, s));
 
     // a4: duplicate merge
     DevBuf<uint8_t> dl;
@@ -395,6 +464,10 @@ cpd_status build(int nm, const int64_t *dims, int64_t nnz, const int32_t *const 
         if (ok && l < nm - 1) ok = alloc_arr((void **)&c->fptr[l], sizeof(int32_t) * (c->counts[l] + 1));
     }
     if (ok) ok = alloc_arr((void **)&c->vals, sizeof(float) * n);
+    const bool want_leafw = dims[order[nm - 1]] <= (1ll << 29);
+    if (ok && want_leafw) ok = alloc_arr((void **)&c->leafw, sizeof(int32_t) * n);
+    if (ok && want_leafw) ok = alloc_arr((void **)&c->leaf_perm, sizeof(int32_t) * dims[order[nm - 1]]);
+    for (int l = 1; l < nm - 1 && ok && want_leafw; ++l) ok = alloc_arr((void **)&c->uprow[l], sizeof(int32_t) * n);
     if (!ok) {
         free_csf(c);
         CPD_FAIL(CPD_ENOMEM, "device allocation for the CSF failed");
@@ -409,6 +482,55 @@ cpd_status build(int nm, const int64_t *dims, int64_t nnz, const int32_t *const 
     }
     hipLaunchKernelGGL(k_leaf, dim3(grid1(n)), dim3(256), 0, s, klo, khi, kl, n, c->fids[nm - 1]);
     if (st == CPD_OK && hipGetLastError() != hipSuccess) st = CPD_EHIP;
+    if (c->leafw && st == CPD_OK) {
+        // rank the leaf ids by frequency in a strided sample of the leaves
+        const int64_t nid = dims[order[nm - 1]];
+        const int64_t stride = std::max<int64_t>(1, n / (1 << 22));
+        const int64_t ns = ceil_div(n, stride);
+        int ibits = 0;
+        while ((1ll << ibits) < nid) ++ibits;
+        DevBuf<uint64_t> sk0, sk1;
+        DevBuf<int32_t> sp0, sp1, spos, sstart, cnt, rank;
+        const int64_t m = std::max(ns, nid);
+        cpd_status rs = CPD_OK;
+        if (rs == CPD_OK) rs = sk0.alloc(m, s);
+        if (rs == CPD_OK) rs = sk1.alloc(m, s);
+        if (rs == CPD_OK) rs = sp0.alloc(m, s);
+        if (rs == CPD_OK) rs = sp1.alloc(m, s);
+        if (rs == CPD_OK) rs = spos.alloc(ns, s);
+        if (rs == CPD_OK) rs = sstart.alloc(ns, s);
+        if (rs == CPD_OK) rs = cnt.alloc(nid, s);
+        if (rs == CPD_OK) rs = rank.alloc(nid, s);
+        if (rs == CPD_OK && hipMemsetAsync(cnt.p, 0, sizeof(int32_t) * nid, s) != hipSuccess) rs = CPD_EHIP;
+        uint64_t *a = sk0.p, *ah = nullptr, *b = sk1.p, *bh = nullptr;
+        int32_t *ap = sp0.p, *bp = sp1.p;
+        if (rs == CPD_OK) {
+            hipLaunchKernelGGL(k_sample, dim3(grid1(ns)), dim3(256), 0, s, (const int32_t *)c->fids[nm - 1], stride,
+                               ns, a, ap);
+            rs = radix_sort(a, ah, ap, b, bh, bp, ns, std::max(ibits, 1), s);
+        }
+        if (rs == CPD_OK) rs = exclusive_scan(RunStart{a}, ns, spos.p, d_flag.p + 1, s);
+        if (rs == CPD_OK) {
+            hipLaunchKernelGGL(k_run_starts, dim3(grid1(ns)), dim3(256), 0, s, (const uint64_t *)a,
+                               (const int32_t *)spos.p, ns, sstart.p);
+            hipLaunchKernelGGL(k_run_counts, dim3(grid1(ns)), dim3(256), 0, s, (const uint64_t *)a,
+                               (const int32_t *)sstart.p, (const int32_t *)(d_flag.p + 1), ns, cnt.p);
+            hipLaunchKernelGGL(k_rank_keys, dim3(grid1(nid)), dim3(256), 0, s, (const int32_t *)cnt.p, nid, a, ap);
+            rs = radix_sort(a, ah, ap, b, bh, bp, nid, 64, s);
+        }
+        if (rs == CPD_OK) {
+            hipLaunchKernelGGL(k_rank_scatter, dim3(grid1(nid)), dim3(256), 0, s, (const uint64_t *)a, nid,
+                               c->leaf_perm, rank.p);
+            hipLaunchKernelGGL(k_leafw, dim3(grid1(n)), dim3(256), 0, s, (const uint8_t *)udl.p,
+                               (const int32_t *)c->fids[nm - 1], (const int32_t *)rank.p, n, c->leafw);
+            if (hipGetLastError() != hipSuccess) rs = CPD_EHIP;
+        }
+        if (rs != CPD_OK) st = rs;
+        for (int l = 1; l < nm - 1; ++l) {
+            hipLaunchKernelGGL(k_uprow, dim3(grid1(n)), dim3(256), 0, s, klo, khi, kl, n, l, c->uprow[l]);
+            if (st == CPD_OK && hipGetLastError() != hipSuccess) st = CPD_EHIP;
+        }
+    }
     if (st == CPD_OK && hipMemcpyAsync(c->vals, uval.p, sizeof(float) * n, hipMemcpyDeviceToDevice, s) != hipSuccess)
         st = CPD_EHIP;
     if (st == CPD_OK && hipStreamSynchronize(s) != hipSuccess) st = CPD_EHIP;

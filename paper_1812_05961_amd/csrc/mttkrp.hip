@@ -268,7 +268,7 @@ __global__ void k_zero_rows(float *Y, int64_t rows, int64_t ldo, int R) {
 // Padded row widths with a ROW kernel: fp32 rows load as float4, bf16 rows as
 // 8-element chunks.
 inline int row_width(int R, bool bf16) {
-    if (R <= 8) return 8;
+    if (R <= 8) return bf16 ? 16 : 8;  // rows of at least two 16-byte chunks
     if (R <= 16) return 16;
     if (R <= 32) return 32;
     if (!bf16 && R <= 36) return 36;
@@ -332,9 +332,16 @@ constexpr double PRIV_THRESH = 0.02;  // privatise iff rows * copies <= 0.02 * n
 
 }  // namespace
 
+cpd_status launch_root(int N, bool bf16, int RP, const int32_t *const *fids, const int32_t *const *fptr,
+                       const float *vals, const int32_t *leafw, const int32_t *leaf_perm, const int32_t *const *uprow,
+                       const int64_t *counts, const int64_t *dims_by_level, const void *const *fac_by_level,
+                       int64_t ld, const int32_t *starts, int64_t ntiles, int32_t T, float *Y, int64_t ldo, int R,
+                       hipStream_t s);
+
 // Internal entry (also used by the ALS driver).
 cpd_status mttkrp(cpd_csf_s *c, const void *const *factors, int32_t ld, int32_t R, int32_t mode,
-                  float *Y, int32_t ldo, const cpd_mttkrp_opts *opts, hipStream_t s) {
+                  float *Y, int32_t ldo, const cpd_mttkrp_opts *opts, hipStream_t s, hipEvent_t ev0,
+                  hipEvent_t ev1) {
     if (!c) CPD_FAIL(CPD_EINVAL, "null CSF handle");
     const int N = c->nmodes;
     if (R < 1 || R > CPD_MAX_RANK) CPD_FAIL(CPD_EINVAL, "rank %d not in [1, %d]", R, CPD_MAX_RANK);
@@ -363,7 +370,10 @@ cpd_status mttkrp(cpd_csf_s *c, const void *const *factors, int32_t ld, int32_t 
     // ROW family eligibility: vector loads need the padded row inside ld and
     // 16-byte aligned rows.
     const int RP = row_width(R, bf16);
-    bool row_ok = d < N - 1 && ld >= RP && (ld * (bf16 ? 2 : 4)) % 16 == 0;
+    bool row_ok = d < N - 1 && ld >= RP && (ld * (bf16 ? 2 : 4)) % 16 == 0 && (d > 0 || c->leafw);
+    // the root kernel addresses rows with 24-bit products: row ids below 2^24
+    for (int l = 1; l < N && row_ok && d == 0; ++l)
+        if (c->dims[c->order[l]] >= (1 << 24)) row_ok = false;
     for (int l = 0; l < N && row_ok; ++l)
         if (c->order[l] != mode && (reinterpret_cast<uintptr_t>(factors[c->order[l]]) & 15)) row_ok = false;
     int kernel = o.kernel;
@@ -378,24 +388,44 @@ cpd_status mttkrp(cpd_csf_s *c, const void *const *factors, int32_t ld, int32_t 
                            (int64_t)ldo, R);
         CPD_LAUNCH_CHECK();
     }
+    if (kernel == CPD_KERNEL_ROW && d == 0) {
+        const int32_t T = o.tile_nnz ? o.tile_nnz : 64;
+
+        const int32_t *starts;
+        int64_t ns;
+        CPD_TRY(csf_tiles(c, T, &starts, &ns, s));
+        const void *fac_by_level[CPD_MAX_MODES];
+        for (int l = 0; l < N; ++l) fac_by_level[l] = fv.a[l];
+        if (ev0) CPD_HIP(hipEventRecord(ev0, s));
+        int64_t dims_by_level[CPD_MAX_MODES];
+        for (int l = 0; l < N; ++l) dims_by_level[l] = c->dims[c->order[l]];
+        cpd_status st = launch_root(N, bf16, RP, cv.fids, cv.fptr, cv.vals, c->leafw, c->leaf_perm, c->uprow,
+                                    c->counts, dims_by_level, fac_by_level, ld, starts, ns, T, Y, ldo, R, s);
+        if (st == CPD_OK && ev1) CPD_HIP(hipEventRecord(ev1, s));
+        return st;
+    }
     if (kernel == CPD_KERNEL_ROW) {
         int32_t T = o.tile_nnz ? o.tile_nnz : 64;
         const int32_t *starts;
         int64_t ns;
         CPD_TRY(csf_tiles(c, T, &starts, &ns, s));
         dim3 grid((unsigned)ceil_div(ns, 256));
+        if (N < 3 || N > 5) CPD_FAIL(CPD_EUNSUPPORTED, "row kernel built for 3..5 modes, not %d", N);
+        if (ev0) CPD_HIP(hipEventRecord(ev0, s));
+        cpd_status st = CPD_OK;
 #define CPD_ROW_N(n)                                                                                   \
     case n:                                                                                            \
-        return bf16 ? launch_row<n, uint16_t>(RP, grid, s, cv, fv, ld, d, starts, ns, T, Y, ldo, R)    \
-                    : launch_row<n, float>(RP, grid, s, cv, fv, ld, d, starts, ns, T, Y, ldo, R);
+        st = bf16 ? launch_row<n, uint16_t>(RP, grid, s, cv, fv, ld, d, starts, ns, T, Y, ldo, R)      \
+                  : launch_row<n, float>(RP, grid, s, cv, fv, ld, d, starts, ns, T, Y, ldo, R);        \
+        break;
         switch (N) {
             CPD_ROW_N(3)
             CPD_ROW_N(4)
             CPD_ROW_N(5)
-            default:
-                CPD_FAIL(CPD_EUNSUPPORTED, "row kernel built for 3..5 modes, not %d", N);
         }
 #undef CPD_ROW_N
+        if (st == CPD_OK && ev1) CPD_HIP(hipEventRecord(ev1, s));
+        return st;
     }
     // LANE family
     int G = R <= 8 ? 8 : R <= 16 ? 16 : R <= 32 ? 32 : 64;
@@ -417,21 +447,25 @@ cpd_status mttkrp(cpd_csf_s *c, const void *const *factors, int32_t ld, int32_t 
     const int NG = 256 / G;
     dim3 grid = priv ? dim3((unsigned)std::min<int64_t>(1024, ceil_div(ns, NG)))
                      : dim3((unsigned)ceil_div(ns, NG));
+    if (N < 2 || N > 5) CPD_FAIL(CPD_EUNSUPPORTED, "MTTKRP kernels are built for 2..5 modes, not %d", N);
+    if (ev0) CPD_HIP(hipEventRecord(ev0, s));
+    cpd_status st = CPD_OK;
 #define CPD_LANE_N(n)                                                                                   \
     case n:                                                                                             \
-        return bf16 ? launch_lane<n, uint16_t>(G, priv, grid, lds, s, cv, fv, ld, d, starts, ns, T, Y, ldo, \
-                                               R, out_rows)                                             \
-                    : launch_lane<n, float>(G, priv, grid, lds, s, cv, fv, ld, d, starts, ns, T, Y, ldo, R, \
-                                            out_rows);
+        st = bf16 ? launch_lane<n, uint16_t>(G, priv, grid, lds, s, cv, fv, ld, d, starts, ns, T, Y, ldo, R, \
+                                             out_rows)                                                  \
+                  : launch_lane<n, float>(G, priv, grid, lds, s, cv, fv, ld, d, starts, ns, T, Y, ldo, R,  \
+                                          out_rows);                                                    \
+        break;
     switch (N) {
         CPD_LANE_N(2)
         CPD_LANE_N(3)
         CPD_LANE_N(4)
         CPD_LANE_N(5)
-        default:
-            CPD_FAIL(CPD_EUNSUPPORTED, "MTTKRP kernels are built for 2..5 modes, not %d", N);
     }
 #undef CPD_LANE_N
+    if (st == CPD_OK && ev1) CPD_HIP(hipEventRecord(ev1, s));
+    return st;
 }
 
 }  // namespace cpd
@@ -440,5 +474,5 @@ extern "C" cpd_status cpd_mttkrp(cpd_csf csf, const void *const *factors, int32_
                                  int32_t mode, float *out, int32_t ldo, const cpd_mttkrp_opts *opts,
                                  void *stream) {
     cpd::clear_error();
-    return cpd::mttkrp(csf, factors, ld, rank, mode, out, ldo, opts, (hipStream_t)stream);
+    return cpd::mttkrp(csf, factors, ld, rank, mode, out, ldo, opts, (hipStream_t)stream, nullptr, nullptr);
 }

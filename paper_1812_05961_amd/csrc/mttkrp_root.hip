@@ -1,0 +1,429 @@
+// Root-level MTTKRP on a CSF tree (the output mode is the tree's root, as in
+// every MTTKRP of a CSF rooted at its own mode; Section III, Algorithm 1):
+//     Y(i, :) = sum over leaves k below root node i of x_k * A_leaf(j_k, :) * H_k,
+// H_k = Hadamard product of the rows of the internal levels above leaf k.
+//
+// Lane layout: a group of G lanes handles one leaf at a time, lane j of the
+// group holding 16-byte chunks j, j+G, ... of the factor rows, so each load
+// instruction reads whole rows as contiguous runs (G = padded rank / 4 for
+// FP32, / 8 for BF16) and a wave walks 64/G leaves per step.
+//
+// Work split, aimed at Zipf-skewed root rows whose leaves span thousands of
+// work units: every wave owns a contiguous range of leaves and walks it in
+// tile steps of (64/G)*T leaves, group g taking the g-th run of T leaves.
+// Partial rows are combined without contention:
+//   - a row that starts and ends inside one group's run is stored directly;
+//   - the partial of the row open at the end of each run is combined across
+//     the wave's groups by a segmented scan (rows are sorted, so equal rows
+//     are adjacent groups); a row closed inside the wave's range is stored
+//     directly, the row still open after the last group is carried to the
+//     next tile step in group 0's accumulator;
+//   - only rows that cross the wave's range boundary, and the closing part of
+//     a row that began in an earlier group, use atomic adds -- a few per row.
+// Every leaf carries the row ids of its internal levels (per-leaf arrays built
+// with the tree), so the rows of a block of leaves -- leaf rows and internal
+// rows alike -- are gathered together with no pointer chasing; only root-row
+// boundaries, read from the leaf words (level << 29 | leaf id), change the
+// control flow.  Leaf words, values and internal ids are staged through LDS
+// with coalesced loads.
+#include <type_traits>
+
+#include "csf.h"
+
+namespace cpd {
+namespace {
+
+struct CsfView {
+    const int32_t *fids[CPD_MAX_MODES];
+    const int32_t *fptr[CPD_MAX_MODES];
+    const int32_t *uprow[CPD_MAX_MODES];  // per-leaf ids of levels 1..N-2
+    const float *vals;
+    const int32_t *leafw;  // (level << 29) | leaf id
+    int64_t nleaves;
+};
+
+struct FacView {
+    const void *a[CPD_MAX_MODES];  // by level
+};
+
+// One 16-byte chunk of a factor row: 4 floats, or 8 bfloat16 widened to float.
+// Rows are addressed by a 32-bit byte offset from a uniform base (row id times
+// row bytes, both below 2^24), which keeps address arithmetic at one 24-bit
+// multiply per row.
+template <typename GT>
+struct Chunk;
+
+template <>
+struct Chunk<float> {
+    static constexpr int W = 4;
+    __device__ static __forceinline__ void load(const char *base, uint32_t off, float *v) {
+        const float4 x = *reinterpret_cast<const float4 *>(base + off);
+        v[0] = x.x;
+        v[1] = x.y;
+        v[2] = x.z;
+        v[3] = x.w;
+    }
+};
+
+template <>
+struct Chunk<uint16_t> {
+    static constexpr int W = 8;
+    __device__ static __forceinline__ void load(const char *base, uint32_t off, float *v) {
+        const uint4 x = *reinterpret_cast<const uint4 *>(base + off);
+        v[0] = bf16_lo(x.x);
+        v[1] = bf16_hi(x.x);
+        v[2] = bf16_lo(x.y);
+        v[3] = bf16_hi(x.y);
+        v[4] = bf16_lo(x.z);
+        v[5] = bf16_hi(x.z);
+        v[6] = bf16_lo(x.w);
+        v[7] = bf16_hi(x.w);
+    }
+};
+
+// Leaves per LDS staging chunk (per group): fewer when a wave has many groups.
+template <int NG>
+constexpr int root_chunk() {
+    return NG >= 32 ? 8 : 16;
+}
+constexpr int ROOT_C = 32;      // tile widths must be multiples of this
+constexpr int ROOT_WAVES = 4;   // waves per block
+
+// Leaves per block whose rows are gathered together: keeps the block's rows
+// (leaf row and the N-2 internal rows per leaf) near 64 registers.
+template <int N, typename GT>
+constexpr int root_unroll() {
+    constexpr int per = Chunk<GT>::W * (N - 1);
+    return per <= 16 ? 4 : 2;
+}
+
+// a_leaf: the leaf factor with rows in rank order (row r = factor row
+// leaf_perm[r]), so the most used rows share cache lines and pages.
+template <int N, int G, typename GT>
+__global__ void __launch_bounds__(64 * ROOT_WAVES)
+k_mttkrp_root(CsfView cv, FacView fv, const char *__restrict__ a_leaf, uint32_t rowb,
+              const int32_t *__restrict__ starts, int64_t ntiles, int32_t T, int64_t nsteps, int64_t nwaves,
+              float *__restrict__ Y, int64_t ldo, int R) {
+    constexpr int NG = 64 / G;  // groups per wave
+    constexpr int C = root_chunk<NG>(), U = root_unroll<N, GT>();
+    static_assert(C % U == 0 && ROOT_C % C == 0, "staging chunk must hold whole blocks");
+    constexpr int W = Chunk<GT>::W;
+    constexpr int E = W;        // row elements per lane
+    constexpr int NU = N - 2;   // internal levels
+    constexpr int SS = NG * (C + 1);
+    constexpr int32_t IDMASK = (1 << 29) - 1;
+    __shared__ int32_t s_w[ROOT_WAVES][SS];
+    __shared__ float s_v[ROOT_WAVES][SS];
+    __shared__ int32_t s_u[ROOT_WAVES][NU][SS];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int g = lane / G, lig = lane % G;  // g == NG: idle lane
+    const int64_t gw = (int64_t)blockIdx.x * ROOT_WAVES + wave;
+    if (gw >= nwaves) return;  // waves are independent: no block barriers below
+    const int64_t nleaves = cv.nleaves;
+    const int64_t s_begin = gw * nsteps / nwaves, s_end = (gw + 1) * nsteps / nwaves;
+    const int64_t span = NG * (int64_t)T;
+    const int64_t W0 = s_begin * span;  // first leaf of this wave's range
+    const int32_t *__restrict__ leafw = cv.leafw;
+    const float *__restrict__ vals = cv.vals;
+    const int32_t *__restrict__ root_ids = cv.fids[0];
+    int32_t *sw = s_w[wave];
+    float *sv = s_v[wave];
+    const int gs = g < NG ? g : NG - 1;  // staged slot this lane reads (idle lanes never do)
+    auto col_of = [&](int e) { return (lig * W) + e; };
+    const uint32_t lane_off = (uint32_t)lig * 16u;  // this lane's chunk within a row
+    const char *a_up[NU];
+#pragma unroll
+    for (int l = 0; l < NU; ++l) a_up[l] = static_cast<const char *>(fv.a[l + 1]);
+
+    float acc[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) acc[e] = 0.0f;
+    int32_t carry_row = -1;  // row carried into group 0 of the next tile step
+
+    for (int64_t st = s_begin; st < s_end; ++st) {
+        const int64_t base = st * span;
+        const int64_t k0 = base + (int64_t)gs * T;
+        const bool active = g < NG && k0 < nleaves;
+        const int64_t kend = active ? min(k0 + (int64_t)T, nleaves) : k0;
+        const int64_t tile = active ? (base / T + g) : (ntiles - 1);
+        int32_t c0 = starts[tile];  // root node of the run's first leaf
+        const int32_t w_first = active ? leafw[k0] : 0;
+        const int32_t w_next = (active && kend < nleaves) ? leafw[kend] : 0;
+        const bool first_here = active && ((uint32_t)w_first >> 29) == 0;  // a root row starts at k0
+        bool first_in_range = true;
+        if (active && !first_here) {  // first leaf of the current root node
+            int64_t fl = c0;
+#pragma unroll
+            for (int l = 0; l < N - 1; ++l) fl = cv.fptr[l][fl];
+            first_in_range = fl >= W0;
+        }
+        const bool closes_at_end = !active || kend == nleaves || ((uint32_t)w_next >> 29) == 0;
+        int32_t cur_row = root_ids[c0];
+        bool is_first = true;
+        if (g != 0 || carry_row < 0) {
+#pragma unroll
+            for (int e = 0; e < E; ++e) acc[e] = 0.0f;
+        }
+        // internal rows of the previous leaf (reused while the ids repeat)
+        int32_t last_up[NU];
+        float Hl[NU][E];
+#pragma unroll
+        for (int l = 0; l < NU; ++l) last_up[l] = -1;
+        for (int t0 = 0; t0 < T; t0 += C) {
+            // stage leaf words, values and internal ids: run s, positions t0..t0+C-1
+            for (int e2 = lane; e2 < NG * C; e2 += 64) {
+                const int s = e2 / C, j = e2 % C;
+                const int64_t k = base + (int64_t)s * T + t0 + j;
+                const bool in = k < nleaves;
+                sw[s * (C + 1) + j] = in ? leafw[k] : 0;
+                sv[s * (C + 1) + j] = in ? vals[k] : 0.0f;
+#pragma unroll
+                for (int l = 0; l < NU; ++l) s_u[wave][l][s * (C + 1) + j] = in ? cv.uprow[l + 1][k] : 0;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const int len = (int)(kend - k0) - t0;  // leaves of this run left in the chunk
+            for (int j0 = 0; j0 < C; j0 += U) {
+                if (j0 >= len) break;
+                // a block of U leaves: every row of the block is in flight before any use
+                int32_t wu[U];
+                float vu[U], rowu[U][E], hu[U][NU][E];
+                bool need[U][NU];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int at = gs * (C + 1) + j0 + u;
+                    wu[u] = sw[at];
+                    vu[u] = sv[at];
+                    Chunk<GT>::load(a_leaf, __umul24((uint32_t)wu[u] & IDMASK, rowb) + lane_off, rowu[u]);
+#pragma unroll
+                    for (int l = 0; l < NU; ++l) {
+                        const int32_t id = s_u[wave][l][at];
+                        need[u][l] = id != last_up[l];
+                        last_up[l] = id;
+                        if (need[u][l]) Chunk<GT>::load(a_up[l], __umul24((uint32_t)id, rowb) + lane_off, hu[u][l]);
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int jr = j0 + u;  // position in the chunk
+                    if (jr < len) {
+                        if (((uint32_t)wu[u] >> 29) == 0 && (t0 | jr) != 0) {  // a new root row starts here
+                            float *y = Y + (int64_t)cur_row * ldo;
+                            if (is_first && !first_here) {
+                                // began in an earlier run: add this part now, the
+                                // earlier groups' part after the scan
+#pragma unroll
+                                for (int e = 0; e < E; ++e)
+                                    if (col_of(e) < R) atomicAdd(y + col_of(e), acc[e]);
+                            } else {
+                                // began and ended in this run: exclusive
+#pragma unroll
+                                for (int e = 0; e < E; ++e)
+                                    if (col_of(e) < R) y[col_of(e)] = acc[e];
+                            }
+#pragma unroll
+                            for (int e = 0; e < E; ++e) acc[e] = 0.0f;
+                            is_first = false;
+                            c0 += 1;
+                            cur_row = root_ids[c0];
+                        }
+#pragma unroll
+                        for (int l = 0; l < NU; ++l)
+                            if (need[u][l]) {
+#pragma unroll
+                                for (int e = 0; e < E; ++e) Hl[l][e] = hu[u][l][e];
+                            }
+#pragma unroll
+                        for (int e = 0; e < E; ++e) {
+                            float h = Hl[0][e];
+#pragma unroll
+                            for (int l = 1; l < NU; ++l) h *= Hl[l][e];
+                            acc[e] = fmaf(vu[u] * rowu[u][e], h, acc[e]);
+                        }
+                    }
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+        // --- end of the run: classify the open row
+        const bool head_closed = !is_first && !first_here;  // row that began earlier closed inside
+        const bool open_here = !is_first || first_here;     // open row began in this run
+        const bool open_in_range = is_first ? first_in_range : true;
+        const int32_t key = active ? cur_row : INT32_MAX;
+        if (active && closes_at_end && open_here) {
+            float *y = Y + (int64_t)cur_row * ldo;
+#pragma unroll
+            for (int e = 0; e < E; ++e)
+                if (col_of(e) < R) y[col_of(e)] = acc[e];
+#pragma unroll
+            for (int e = 0; e < E; ++e) acc[e] = 0.0f;
+        }
+        // segment heads: first group of each run of equal keys (rows are sorted)
+        const int32_t key_prev = __shfl_up(key, G, 64);
+        const bool seg_head = g == 0 || key_prev != key;
+        int head_group = seg_head ? g : 0;
+#pragma unroll
+        for (int o = 1; o < NG; o <<= 1) {
+            const int h = __shfl_up(head_group, o * G, 64);
+            if (g >= o) head_group = max(head_group, h);
+        }
+        const bool seg_in_range =
+            __shfl(open_in_range ? 1 : 0, min(head_group, NG - 1) * G + lig, 64) != 0;
+        // inclusive segmented scan of the open partials over groups
+#pragma unroll
+        for (int o = 1; o < NG; o <<= 1) {
+            const int32_t ko = __shfl_up(key, o * G, 64);
+            const bool take = g >= o && ko == key;
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const float x = __shfl_up(acc[e], o * G, 64);
+                if (take) acc[e] += x;
+            }
+        }
+        // a row that began in earlier groups and closed inside this group's run:
+        // add the earlier groups' part (group g-1's segment total)
+        const bool add_prev = active && head_closed && g > 0;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const float x = __shfl_up(acc[e], G, 64);
+            if (add_prev && col_of(e) < R) atomicAdd(Y + (int64_t)key_prev * ldo + col_of(e), x);
+        }
+        // open row closing exactly at the end of this run (not exclusive)
+        if (active && closes_at_end && !open_here) {
+            float *y = Y + (int64_t)cur_row * ldo;
+            if (seg_in_range) {
+#pragma unroll
+                for (int e = 0; e < E; ++e)
+                    if (col_of(e) < R) y[col_of(e)] = acc[e];
+            } else {
+#pragma unroll
+                for (int e = 0; e < E; ++e)
+                    if (col_of(e) < R) atomicAdd(y + col_of(e), acc[e]);
+            }
+        }
+        // carry: the last group's open segment, if it stays open, moves to group 0
+        const int src = (NG - 1) * G + lig;
+        const bool last_open = __shfl(active && !closes_at_end ? 1 : 0, src, 64) != 0;
+        const int32_t last_key = __shfl(key, src, 64);
+#pragma unroll
+        for (int e = 0; e < E; ++e) acc[e] = __shfl(acc[e], src, 64);
+        carry_row = last_open ? last_key : -1;
+        if (g != 0 || !last_open) {
+#pragma unroll
+            for (int e = 0; e < E; ++e) acc[e] = 0.0f;
+        }
+    }
+    // the row still open at the end of the range continues in the next wave
+    if (g == 0 && carry_row >= 0) {
+        float *y = Y + (int64_t)carry_row * ldo;
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+            if (col_of(e) < R) atomicAdd(y + col_of(e), acc[e]);
+    }
+}
+
+// Rows of the leaf factor in rank order: dst row r = src row perm[r] (16-byte chunks).
+__global__ void k_permute_rows(const uint4 *__restrict__ src, const int32_t *__restrict__ perm, int64_t rows,
+                               int chunks, uint4 *__restrict__ dst) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= rows * chunks) return;
+    const int64_t r = t / chunks, q = t % chunks;
+    dst[t] = src[(int64_t)perm[r] * chunks + q];
+}
+
+}  // namespace
+
+// Launch the root kernel (FP32 rows when GT = float, bf16 when uint16_t):
+// G lanes per leaf, one 16-byte chunk each, cover the padded row; one wave
+// range per resident wave.
+template <int N, int G, typename GT>
+static cpd_status launch_root_g(const CsfView &cv, const FacView &fv, const char *a_leaf, uint32_t rowb,
+                                const int32_t *starts, int64_t ntiles, int32_t T, float *Y, int64_t ldo, int R,
+                                hipStream_t s) {
+    constexpr int NG = 64 / G;
+    auto kern = k_mttkrp_root<N, G, GT>;
+    const int64_t nsteps = ceil_div(cv.nleaves, NG * (int64_t)T);
+    int dev = 0, ncu = 256;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) ncu = v;
+    }
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64 * ROOT_WAVES, 0) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    const int64_t nwaves = std::max<int64_t>(1, std::min<int64_t>(nsteps, (int64_t)ncu * per_cu * ROOT_WAVES));
+    hipLaunchKernelGGL(kern, dim3((unsigned)ceil_div(nwaves, ROOT_WAVES)), dim3(64 * ROOT_WAVES), 0, s, cv, fv, a_leaf,
+                       rowb, starts, ntiles, T, nsteps, nwaves, Y, ldo, R);
+    CPD_LAUNCH_CHECK();
+    return CPD_OK;
+}
+
+template <int N, typename GT>
+static cpd_status launch_root_n(int RP, const CsfView &cv, const FacView &fv, const char *a_leaf, int64_t ld,
+                                const int32_t *starts, int64_t ntiles, int32_t T, float *Y, int64_t ldo, int R,
+                                hipStream_t s) {
+    constexpr int W = Chunk<GT>::W;
+    const uint32_t rowb = (uint32_t)(ld * (int64_t)sizeof(GT));
+    switch (RP / W) {
+#define CPD_ROOT_G(g) \
+    case g: return launch_root_g<N, g, GT>(cv, fv, a_leaf, rowb, starts, ntiles, T, Y, ldo, R, s);
+        CPD_ROOT_G(2)
+        CPD_ROOT_G(4)
+        CPD_ROOT_G(5)
+        CPD_ROOT_G(8)
+        CPD_ROOT_G(9)
+        CPD_ROOT_G(16)
+#undef CPD_ROOT_G
+        default: CPD_FAIL(CPD_EUNSUPPORTED, "no root kernel for padded rank %d", RP);
+    }
+}
+
+cpd_status launch_root(int N, bool bf16, int RP, const int32_t *const *fids, const int32_t *const *fptr,
+                       const float *vals, const int32_t *leafw, const int32_t *leaf_perm, const int32_t *const *uprow,
+                       const int64_t *counts, const int64_t *dims_by_level, const void *const *fac_by_level,
+                       int64_t ld, const int32_t *starts, int64_t ntiles, int32_t T, float *Y, int64_t ldo, int R,
+                       hipStream_t s) {
+    if (!leafw || !leaf_perm) CPD_FAIL(CPD_EUNSUPPORTED, "root kernel needs leaf ids below 2^29");
+    const int64_t rowb = ld * (bf16 ? 2 : 4);
+    if (rowb >= (1 << 24) || rowb % 16) CPD_FAIL(CPD_EUNSUPPORTED, "root kernel needs 16-byte rows below 16 MiB");
+    if (T < ROOT_C || T % ROOT_C)
+        CPD_FAIL(CPD_EINVAL, "root kernel tile width %d must be a multiple of %d", T, ROOT_C);
+    CsfView cv{};
+    FacView fv{};
+    for (int l = 0; l < N; ++l) {
+        cv.fids[l] = fids[l];
+        cv.fptr[l] = fptr[l];
+        fv.a[l] = fac_by_level[l];
+    }
+    cv.vals = vals;
+    cv.leafw = leafw;
+    cv.nleaves = counts[N - 1];
+    for (int l = 1; l < N - 1; ++l) {
+        if (!uprow[l]) CPD_FAIL(CPD_EUNSUPPORTED, "root kernel needs the per-leaf internal ids");
+        cv.uprow[l] = uprow[l];
+    }
+    // the leaf factor in rank order (hot rows first)
+    const int64_t leaf_rows = dims_by_level[N - 1];
+    DevBuf<uint4> perm;
+    CPD_TRY(perm.alloc((size_t)leaf_rows * (rowb / 16), s));
+    {
+        const int chunks = (int)(rowb / 16);
+        const int64_t tot = leaf_rows * chunks;
+        hipLaunchKernelGGL(k_permute_rows, dim3((unsigned)ceil_div(tot, 256)), dim3(256), 0, s,
+                           static_cast<const uint4 *>(fac_by_level[N - 1]), leaf_perm, leaf_rows, chunks, perm.p);
+        CPD_LAUNCH_CHECK();
+    }
+    const char *a_leaf = reinterpret_cast<const char *>(perm.p);
+    switch (N) {
+        case 3: return bf16 ? launch_root_n<3, uint16_t>(RP, cv, fv, a_leaf, ld, starts, ntiles, T, Y, ldo, R, s)
+                            : launch_root_n<3, float>(RP, cv, fv, a_leaf, ld, starts, ntiles, T, Y, ldo, R, s);
+        case 4: return bf16 ? launch_root_n<4, uint16_t>(RP, cv, fv, a_leaf, ld, starts, ntiles, T, Y, ldo, R, s)
+                            : launch_root_n<4, float>(RP, cv, fv, a_leaf, ld, starts, ntiles, T, Y, ldo, R, s);
+        case 5: return bf16 ? launch_root_n<5, uint16_t>(RP, cv, fv, a_leaf, ld, starts, ntiles, T, Y, ldo, R, s)
+                            : launch_root_n<5, float>(RP, cv, fv, a_leaf, ld, starts, ntiles, T, Y, ldo, R, s);
+        default: CPD_FAIL(CPD_EUNSUPPORTED, "root kernel built for 3..5 modes, not %d", N);
+    }
+}
+
+}  // namespace cpd

@@ -138,6 +138,16 @@ def _factors(dims, R, seed, ld=None, dtype=torch.float32):
     return out
 
 
+def _row_ok(R, ld, prec):
+    """Whether the row/root kernel takes this rank and row stride: the padded
+    width (fp32 8/16/32/36/64, bf16 16/16/32/40/64) must fit in ld and rows must
+    be 16-byte multiples."""
+    widths = (8, 16, 32, 36, 64) if prec == "fp32" else (16, 16, 32, 40, 64)
+    w = next(x for x in widths if x >= R)
+    esize = 4 if prec == "fp32" else 2
+    return ld >= w and (ld * esize) % 16 == 0
+
+
 def _run(cpd, c, facs64, mode, R, precision, kernel, variant, tile=0):
     dt = torch.float32 if precision == "fp32" else torch.bfloat16
     dev = [f.to(dt).to("cuda") for f in facs64]
@@ -165,7 +175,7 @@ def test_mttkrp_every_level(case, R, ld):
         for kernel in kernels:
             for variant in (variants if kernel == "lane" else ["auto"]):
                 for prec in ("fp32", "bf16"):
-                    if prec == "bf16" and kernel == "row" and (ld or R) % 8:
+                    if kernel == "row" and not _row_ok(R, ld or R, prec):
                         continue
                     y, used = _run(cpd, c, facs, mode, R, prec, kernel, variant)
                     ref = ocoo.mttkrp(t.dims, inds, vals, [f[:, :R].numpy() for f in facs], mode)
@@ -178,7 +188,7 @@ def test_mttkrp_every_level(case, R, ld):
                         assert relerr(y, ref_b) <= 1e-5, (name, mode, kernel, variant, err)
 
 
-@pytest.mark.parametrize("tile", [1, 7, 64, 4096])
+@pytest.mark.parametrize("tile", [1, 7, 32, 64, 96, 4096])
 def test_mttkrp_tile_widths(tile):
     cpd = _cpd()
     t = CASES["zipf3"]()
@@ -187,9 +197,36 @@ def test_mttkrp_tile_widths(tile):
     facs = _factors(t.dims, 16, 5)
     for mode in range(3):
         ref = ocoo.mttkrp(t.dims, inds, vals, [f.numpy() for f in facs], mode)
-        for kernel in (["lane", "row"] if c.order.index(mode) < 2 else ["lane"]):
+        depth = c.order.index(mode)
+        # the root kernel takes tile widths in multiples of 32
+        row_ok = depth < 2 and (depth > 0 or tile % 32 == 0)
+        for kernel in (["lane", "row"] if row_ok else ["lane"]):
             y, _ = _run(cpd, c, facs, mode, 16, "fp32", kernel, "auto", tile)
             assert relerr(y, ref) <= 1e-5, (mode, kernel, tile)
+    if tile % 32:
+        with pytest.raises(cpd.CpdError):
+            _run(cpd, c, facs, c.order[0], 16, "fp32", "row", "auto", tile)
+
+
+@pytest.mark.parametrize("dims,alphas,nnz", [((50, 40, 3000), (2.0, 0.0, 0.0), 200_000),
+                                             ((3, 500, 400), (0.0, 0.5, 0.5), 150_000),
+                                             ((1, 700, 900), (0.0, 1.0, 1.0), 120_000),
+                                             ((20, 30, 40, 50), (1.5, 1.0, 0.0, 0.0), 150_000)])
+def test_mttkrp_root_hot_rows(dims, alphas, nnz):
+    """Root rows spanning many lanes, tile steps and wave ranges (one root row
+    holds most nonzeros), checked for every mode rooted at its own tree."""
+    cpd = _cpd()
+    t = _tensor(dims, nnz, alphas, 21)
+    inds, vals = t.numpy()
+    facs = _factors(t.dims, 8, 3)
+    for mode in range(t.nmodes):
+        order = [mode] + [m for m in range(t.nmodes) if m != mode]
+        c = cpd.csf_build(_dev(t.inds), _dev(t.vals), t.dims, order)
+        ref = ocoo.mttkrp(t.dims, inds, vals, [f.numpy() for f in facs], mode)
+        for tile in (32, 64, 256):
+            y, _ = _run(cpd, c, facs, mode, 8, "fp32", "row", "auto", tile)
+            assert relerr(y, ref) <= 1e-5, (mode, tile)
+        c.free()
 
 
 def test_mttkrp_rejects_bad_arguments():
