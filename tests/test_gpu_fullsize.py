@@ -1,0 +1,89 @@
+"""GPU parity at the benchmark's full sizes, in the launch configuration that
+bench.py times (one CSF rooted at each mode, the root-level kernel, default
+tile width): sampled output rows against the oracle's row-by-row COO MTTKRP,
+and the fit reported by cpd_als against the oracle's fit of the returned model.
+
+The oracle loops over every nonzero once per checked mode (single-threaded C),
+so each workload costs a few seconds of host time.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import als as oals
+from oracle import coo as ocoo
+from paper_1812_05961_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _cpd():
+    from paper_1812_05961_amd import cpd
+    cpd.lib()
+    return cpd
+
+
+def _root_order(dims, m):
+    return [m] + sorted([q for q in range(len(dims)) if q != m], key=lambda q: (dims[q], q))
+
+
+def _sample_rows(inds_mode, dim, rng, k=6):
+    """The three fullest rows plus random non-empty ones."""
+    counts = np.bincount(inds_mode, minlength=dim)
+    hot = np.argsort(-counts, kind="stable")[:3]
+    nonempty = np.flatnonzero(counts)
+    rand = rng.choice(nonempty, size=min(k, nonempty.size), replace=False)
+    return np.unique(np.concatenate([hot, rand]))
+
+
+@pytest.mark.parametrize("name,precision", [("nell2", "fp32"), ("nell2", "bf16"), ("netflix", "fp32"),
+                                            ("fourmode", "fp32")])
+def test_full_size_mttkrp_sampled_rows(name, precision):
+    cpd = _cpd()
+    x = synth.make_config(name, device="cuda")
+    R = synth.CONFIGS[name]["rank"]
+    inds_h = x.inds.cpu().numpy()
+    vals_h = x.vals.cpu().double().numpy()
+    rng = np.random.default_rng(7)
+    g = torch.Generator().manual_seed(3)
+    dt = torch.float32 if precision == "fp32" else torch.bfloat16
+    width = next(w for w in ((8, 16, 32, 36, 64) if precision == "fp32" else (16, 16, 32, 40, 64)) if w >= R)
+    facs, facs_used = [], []
+    for d in x.dims:
+        a = torch.rand((d, R), generator=g, dtype=torch.float64)
+        buf = torch.zeros((d, width), dtype=dt)
+        buf[:, :R] = a.to(dt)
+        facs.append(buf.cuda())
+        facs_used.append(buf[:, :R].to(torch.float64).numpy())
+    xi = x.inds.to(torch.int32)
+    for m in range(x.nmodes):
+        c = cpd.csf_build(xi, x.vals, x.dims, _root_order(x.dims, m))
+        y = cpd.mttkrp(c, facs, m, rank=R, precision=precision)
+        torch.cuda.synchronize()
+        rows = _sample_rows(inds_h[m], x.dims[m], rng)
+        ref = ocoo.mttkrp_rows(x.dims, inds_h, vals_h, facs_used, m, rows)
+        got = y.cpu().numpy()[rows].astype(np.float64)
+        err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+        # the same rows, computed on the rows the kernel read: FP32 products and sums
+        assert err <= 1e-5, (name, precision, m, err)
+        c.free()
+        del y
+
+
+def test_full_size_als_fit_matches_oracle_fit_of_returned_model():
+    cpd = _cpd()
+    x = synth.make_config("nell2", device="cuda")
+    R = synth.CONFIGS["nell2"]["rank"]
+    got = cpd.als(x.inds.to(torch.int32), x.vals, x.dims, R, 3, 0.0, seed=5)
+    inds_h = x.inds.cpu().numpy()
+    vals_h = x.vals.cpu().double().numpy()
+    A = [f.cpu().double().numpy() for f in got["factors"]]
+    lam = np.array(got["lam"])
+    nm = x.nmodes
+    Y = ocoo.mttkrp(x.dims, inds_h, vals_h, A, nm - 1)
+    ref = oals.fit_from(ocoo.sumsq(vals_h), lam, A[nm - 1], Y, [oals.gram(a) for a in A])
+    assert abs(got["fit"] - ref) <= 1e-4, (got["fit"], ref)
+    # unit-norm columns, finite factors
+    for a in A:
+        assert np.isfinite(a).all()
+        np.testing.assert_allclose(np.linalg.norm(a, axis=0), 1.0, atol=1e-4)
