@@ -195,9 +195,19 @@ typedef struct {
     uint64_t seed;           /* seed of the U(0,1) initialisation */
     double *fit_trace;       /* host, max_iters doubles, or NULL */
     double *timing_ms;       /* host, 4 + max_iters*(N+1) doubles, or NULL:
-                                [0] CSF build, [1] all iterations, [2] final fit,
-                                [3] total; then per iteration: N MTTKRP times
-                                and the iteration time */
+                                [0] CSF build (with the selection, if any),
+                                [1] all iterations, [2] final fit, [3] total;
+                                then per iteration: N MTTKRP times and the
+                                iteration time */
+    int32_t select;          /* 0: as above; 1: per mode, the CSF order and
+                                MTTKRP options cpd_select picks with the
+                                network `selector_params`; 2: cpd_select's
+                                fallback rule (one shared ascending tree).
+                                With 1 or 2 the variant, kernel, tile_nnz,
+                                single_csf and order fields are not used;
+                                3..5 modes. */
+    int32_t selector_hidden; /* hidden width of the network (select = 1) */
+    const float *selector_params; /* device, the network's parameters (select = 1) */
 } cpd_als_opts;
 
 /* Run CP-ALS with `rank` components for at most max_iters sweeps; when tol > 0
@@ -210,6 +220,121 @@ cpd_status cpd_als(int32_t nmodes, const int64_t *dims, int64_t nnz, const int32
                    const float *vals, int32_t rank, int32_t max_iters, double tol,
                    const cpd_als_opts *opts, float *const *factors_out, double *lambda_out,
                    double *fit_out, int32_t *iters_out, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Variant selector.  Section V-D2 of the paper settles the lock-or-privatise
+ * question by a rule on the output length, the thread count and the nonzero
+ * count, and observes that the better choice depends on the tensor.  Here a
+ * small network predicts the MTTKRP time of every candidate (CSF mode order,
+ * conflict handling, tile width) from tensor statistics, and the candidate
+ * with the smallest prediction is taken.  Without a network the fallback is
+ * that rule on the tree in ascending-length order. */
+
+/* Per-mode statistics of a COO tensor from a strided sample of its nonzeros. */
+typedef struct {
+    int32_t nmodes;
+    int32_t reserved;
+    int64_t nnz;
+    int64_t sample;                   /* nonzeros in the sample (<= 2^20) */
+    int64_t dims[CPD_MAX_MODES];
+    double top1[CPD_MAX_MODES];       /* share of the sample at the most frequent index */
+    double distinct[CPD_MAX_MODES];   /* distinct sampled indices / min(dim, sample) */
+    double alpha[CPD_MAX_MODES];      /* cpd_zipf_alpha(top1, dim) */
+} cpd_stats;
+
+/* Fill *out for a COO tensor (arguments as in cpd_csf_build; indices are not
+ * range-checked here).  Sorts a sample of each mode's indices on the device;
+ * waits for `stream` before returning. */
+cpd_status cpd_tensor_stats(int32_t nmodes, const int64_t *dims, int64_t nnz,
+                            const int32_t *const *inds, void *stream, cpd_stats *out);
+
+/* The exponent a >= 0 of a Zipf law p_k proportional to k^-a over dim items
+ * whose largest probability 1/sum_k k^-a equals top1 (0 when top1 <= 1/dim;
+ * capped at 8).  Host only. */
+double cpd_zipf_alpha(double top1, int64_t dim);
+
+/* CSF mode orders a candidate can use for MTTKRP of mode n: all modes by
+ * ascending length (ties to the lower mode); n first then the rest ascending;
+ * the rest ascending then n last; all by descending length. */
+enum { CPD_ORDER_ASC = 0, CPD_ORDER_FIRST = 1, CPD_ORDER_LAST = 2, CPD_ORDER_DESC = 3 };
+
+typedef struct {
+    int32_t order_kind;              /* CPD_ORDER_* */
+    int32_t depth;                   /* level of the mode in `order` */
+    int32_t order[CPD_MAX_MODES];    /* the CSF mode order (nmodes entries) */
+    cpd_mttkrp_opts opts;            /* precision CPD_FP32; variant, kernel, tile */
+} cpd_choice;
+
+#define CPD_SEL_MAX_CAND 24
+#define CPD_SEL_NFEAT 40
+
+/* Candidates for MTTKRP of `mode` at `rank` (3..5 modes): every distinct
+ * order of the four kinds; at the root the root-level kernel with tile widths
+ * 32, 64, 256 (or atomic lanes with 64, 256, 1024 when the tree exceeds that
+ * kernel's index limits); below the root atomic lanes, and privatised lanes
+ * when dims[mode] * rank * 4 <= 64 KiB, each with tile widths 64, 256, 1024.
+ * out: host, CPD_SEL_MAX_CAND entries; *n receives the count.
+ * Factor rows are assumed padded as cpd_als pads them (stride a multiple of
+ * 4 floats, at least the rank rounded up to 8/16/32/36/64). */
+cpd_status cpd_select_candidates(const cpd_stats *st, int32_t rank, int32_t mode,
+                                 cpd_choice *out, int32_t *n);
+
+/* Network inputs of n candidates: feat (host, n x CPD_SEL_NFEAT floats,
+ * row-major) from the statistics, the rank, the mode and each candidate. */
+cpd_status cpd_select_features(const cpd_stats *st, int32_t rank, int32_t mode,
+                               const cpd_choice *cand, int32_t n, float *feat);
+
+/* The fallback: ascending-length order; below the root privatised lanes iff
+ * dims[mode] * 1024 (the private copies) <= 0.02 * nnz and the copy fits in
+ * 64 KiB of LDS, else atomic lanes; default tile widths. */
+cpd_status cpd_select_heuristic(const cpd_stats *st, int32_t rank, int32_t mode, cpd_choice *out);
+
+/* Pick the candidate with the smallest predicted time.
+ * params: device, cpd_mlp_param_count(CPD_SEL_NFEAT, hidden) floats of a
+ *         trained network, or NULL for the fallback.
+ * out:    host, the choice.  pred (host, CPD_SEL_MAX_CAND floats) and ncand
+ *         (host) receive the predictions and the candidate count when not
+ *         NULL (ncand = 0 for the fallback).
+ * Waits for `stream` before returning. */
+cpd_status cpd_select(const cpd_stats *st, int32_t rank, int32_t mode, const float *params,
+                      int32_t hidden, cpd_choice *out, float *pred, int32_t *ncand, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * The selector's network: in -> hidden -> hidden -> 1 with ReLU after the
+ * first two layers (hidden <= 64, in <= 4096), float32, mean squared error,
+ * Adam updates (Kingma and Ba, ICLR 2015).  Parameters are one flat device
+ * array: W1 (hidden x in, row-major), b1 (hidden), W2 (hidden x hidden), b2
+ * (hidden), W3 (hidden), b3 (1). */
+
+/* Number of parameters (0 for a bad shape). */
+int64_t cpd_mlp_param_count(int32_t n_in, int32_t hidden);
+
+/* He-normal weights (standard deviation sqrt(2 / fan-in)) from a seeded
+ * counter-based generator, zero biases.  params: device. */
+cpd_status cpd_mlp_init(float *params, int32_t n_in, int32_t hidden, uint64_t seed, void *stream);
+
+/* out[b] = f(X[b]) for batch rows of X (device, batch x n_in). out: device. */
+cpd_status cpd_mlp_forward(const float *params, int32_t n_in, int32_t hidden, const float *X,
+                           int64_t batch, float *out, void *stream);
+
+/* loss = mean_b (f(X[b]) - y[b])^2 and its gradient with respect to every
+ * parameter (back-propagation; batch sums in batch order).  All device:
+ * X batch x n_in, y batch, loss one float (or NULL), grad param_count floats. */
+cpd_status cpd_mlp_loss_grad(const float *params, int32_t n_in, int32_t hidden, const float *X,
+                             const float *y, int64_t batch, float *loss, float *grad, void *stream);
+
+/* One Adam step (step >= 1) on count parameters: m and v (device, count
+ * floats each) are the moment estimates, updated in place. */
+cpd_status cpd_mlp_adam(float *params, const float *grad, float *m, float *v, int64_t count,
+                        float lr, float beta1, float beta2, float eps, int32_t step, void *stream);
+
+/* Mini-batch training for `epochs` passes over n samples (X device n x n_in,
+ * y device n), shuffled each epoch by a seeded host generator, Adam with
+ * beta1 0.9, beta2 0.999, eps 1e-8 from zero moments.  loss_trace: host,
+ * epochs floats (mean batch loss per epoch), or NULL.  Waits for `stream`. */
+cpd_status cpd_mlp_train(float *params, int32_t n_in, int32_t hidden, const float *X,
+                         const float *y, int64_t n, int32_t epochs, int32_t batch, float lr,
+                         uint64_t seed, float *loss_trace, void *stream);
 
 #ifdef __cplusplus
 }

@@ -39,7 +39,38 @@ class MttkrpOpts(ctypes.Structure):
 class AlsOpts(ctypes.Structure):
     _fields_ = [("precision", _I32), ("variant", _I32), ("kernel", _I32), ("tile_nnz", _I32),
                 ("single_csf", _I32), ("reserved", _I32), ("order", _P), ("init", _P),
-                ("seed", ctypes.c_uint64), ("fit_trace", _P), ("timing_ms", _P)]
+                ("seed", ctypes.c_uint64), ("fit_trace", _P), ("timing_ms", _P),
+                ("select", _I32), ("selector_hidden", _I32), ("selector_params", _P)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("nmodes", _I32), ("reserved", _I32), ("nnz", _I64), ("sample", _I64),
+                ("dims", _I64 * MAX_MODES), ("top1", _F64 * MAX_MODES),
+                ("distinct", _F64 * MAX_MODES), ("alpha", _F64 * MAX_MODES)]
+
+    def as_dict(self):
+        n = self.nmodes
+        return dict(nmodes=n, nnz=self.nnz, sample=self.sample, dims=list(self.dims[:n]),
+                    top1=list(self.top1[:n]), distinct=list(self.distinct[:n]),
+                    alpha=list(self.alpha[:n]))
+
+
+class Choice(ctypes.Structure):
+    _fields_ = [("order_kind", _I32), ("depth", _I32), ("order", _I32 * MAX_MODES),
+                ("opts", MttkrpOpts)]
+
+    def as_dict(self, nmodes):
+        return dict(order_kind=ORDER_KINDS[self.order_kind], depth=self.depth,
+                    order=list(self.order[:nmodes]), variant=_VARIANT_NAME[self.opts.variant],
+                    kernel=_KERNEL_NAME[self.opts.kernel], tile_nnz=self.opts.tile_nnz)
+
+
+ORDER_KINDS = ("asc", "first", "last", "desc")
+_VARIANT_NAME = {v: k for k, v in VARIANT.items()}
+_KERNEL_NAME = {v: k for k, v in KERNEL.items()}
+SEL_MAX_CAND = 24
+SEL_NFEAT = 40
+SELECT = {"none": 0, "network": 1, "heuristic": 2}
 
 
 _lib = None
@@ -60,6 +91,20 @@ _SIGS = {
     "cpd_fit": (_I32, [_F64, _P, _P, _I32, _P, _I32, _I64, _I32, _P, _I32, _P, _P]),
     "cpd_sumsq": (_I32, [_P, _I64, _P, _P]),
     "cpd_als": (_I32, [_I32, _P, _I64, _P, _P, _I32, _I32, _F64, _P, _P, _P, _P, _P, _P]),
+    "cpd_tensor_stats": (_I32, [_I32, _P, _I64, _P, _P, _P]),
+    "cpd_zipf_alpha": (_F64, [_F64, _I64]),
+    "cpd_select_candidates": (_I32, [_P, _I32, _I32, _P, _P]),
+    "cpd_select_features": (_I32, [_P, _I32, _I32, _P, _I32, _P]),
+    "cpd_select_heuristic": (_I32, [_P, _I32, _I32, _P]),
+    "cpd_select": (_I32, [_P, _I32, _I32, _P, _I32, _P, _P, _P, _P]),
+    "cpd_mlp_param_count": (_I64, [_I32, _I32]),
+    "cpd_mlp_init": (_I32, [_P, _I32, _I32, ctypes.c_uint64, _P]),
+    "cpd_mlp_forward": (_I32, [_P, _I32, _I32, _P, _I64, _P, _P]),
+    "cpd_mlp_loss_grad": (_I32, [_P, _I32, _I32, _P, _P, _I64, _P, _P, _P]),
+    "cpd_mlp_adam": (_I32, [_P, _P, _P, _P, _I64, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                            ctypes.c_float, _I32, _P]),
+    "cpd_mlp_train": (_I32, [_P, _I32, _I32, _P, _P, _I64, _I32, _I32, ctypes.c_float,
+                             ctypes.c_uint64, _P, _P]),
 }
 
 
@@ -252,8 +297,11 @@ def sumsq(vals, stream=None):
 
 def als(inds, vals, dims, rank, iters, tol=0.0, init=None, precision="fp32", variant="auto",
         kernel="auto", tile_nnz=0, single_csf=False, order=None, seed=0, timing=False,
-        stream=None):
-    """cpd_als -> dict(factors, lam, fit, iters, fits, timing_ms)."""
+        select="none", selector=None, stream=None):
+    """cpd_als -> dict(factors, lam, fit, iters, fits, timing_ms).
+
+    select: "none", "network" (selector = (params CUDA tensor, hidden)) or
+    "heuristic"."""
     inds, vals, dims = _coo_args(inds, vals, dims)
     nm = len(dims)
     outs = [torch.empty((d, rank), dtype=torch.float32, device="cuda") for d in dims]
@@ -271,7 +319,13 @@ def als(inds, vals, dims, rank, iters, tol=0.0, init=None, precision="fp32", var
                    ctypes.cast(ordarr, ctypes.c_void_p) if ordarr is not None else None,
                    ctypes.cast(initarr, ctypes.c_void_p) if initarr is not None else None,
                    int(seed), ctypes.cast(trace, ctypes.c_void_p),
-                   ctypes.cast(tms, ctypes.c_void_p) if tms is not None else None)
+                   ctypes.cast(tms, ctypes.c_void_p) if tms is not None else None,
+                   SELECT[select], 0, None)
+    if select == "network":
+        params, hidden = selector
+        _need_cuda(params, "selector params", torch.float32)
+        opts.selector_hidden = int(hidden)
+        opts.selector_params = params.data_ptr()
     lam = (ctypes.c_double * rank)()
     fit_out = ctypes.c_double()
     it_out = ctypes.c_int32()
@@ -287,3 +341,133 @@ def als(inds, vals, dims, rank, iters, tol=0.0, init=None, precision="fp32", var
                                 per_iter=[t[4 + i * (nm + 1): 4 + (i + 1) * (nm + 1)]
                                           for i in range(n_it)])
     return res
+
+
+# ---------------------------------------------------------------------------
+# Variant selector and its network
+
+
+def tensor_stats(inds, dims, stream=None) -> Stats:
+    """cpd_tensor_stats of a COO tensor (inds: N int tensors or (N, nnz))."""
+    if isinstance(inds, torch.Tensor):
+        inds = [inds[m] for m in range(inds.shape[0])]
+    inds = [_need_cuda(i, "inds").to(torch.int32).contiguous() for i in inds]
+    st = Stats()
+    _check(lib().cpd_tensor_stats(len(dims), _i64s(dims), inds[0].numel(), _ptrs(inds),
+                                  _stream(stream), ctypes.byref(st)))
+    return st
+
+
+def make_stats(dims, nnz, top1, distinct, alpha=None, sample=None) -> Stats:
+    """A Stats record from given values (alpha from cpd_zipf_alpha if None)."""
+    st = Stats()
+    st.nmodes = len(dims)
+    st.nnz = int(nnz)
+    st.sample = int(sample if sample is not None else min(nnz, 1 << 20))
+    for m, d in enumerate(dims):
+        st.dims[m] = int(d)
+        st.top1[m] = float(top1[m])
+        st.distinct[m] = float(distinct[m])
+        st.alpha[m] = float(alpha[m]) if alpha is not None else zipf_alpha(top1[m], d)
+    return st
+
+
+def make_choice(d) -> Choice:
+    """A Choice record from its as_dict() form."""
+    c = Choice()
+    c.order_kind = ORDER_KINDS.index(d["order_kind"])
+    c.depth = int(d["depth"])
+    for l, m in enumerate(d["order"]):
+        c.order[l] = int(m)
+    c.opts = MttkrpOpts(FP32, VARIANT[d["variant"]], KERNEL[d["kernel"]], int(d["tile_nnz"]))
+    return c
+
+
+def zipf_alpha(top1, dim):
+    return lib().cpd_zipf_alpha(float(top1), int(dim))
+
+
+def select_candidates(st: Stats, rank, mode):
+    out = (Choice * SEL_MAX_CAND)()
+    n = _I32()
+    _check(lib().cpd_select_candidates(ctypes.byref(st), int(rank), int(mode), out, ctypes.byref(n)))
+    return [out[i] for i in range(n.value)]
+
+
+def select_features(st: Stats, rank, mode, cands):
+    import numpy as np
+    arr = (Choice * max(1, len(cands)))(*cands)
+    feat = np.zeros((len(cands), SEL_NFEAT), dtype=np.float32)
+    _check(lib().cpd_select_features(ctypes.byref(st), int(rank), int(mode), arr, len(cands),
+                                     feat.ctypes.data_as(ctypes.c_void_p)))
+    return feat
+
+
+def select_heuristic(st: Stats, rank, mode) -> Choice:
+    out = Choice()
+    _check(lib().cpd_select_heuristic(ctypes.byref(st), int(rank), int(mode), ctypes.byref(out)))
+    return out
+
+
+def select(st: Stats, rank, mode, params=None, hidden=64, stream=None):
+    """cpd_select -> (Choice, predictions list)."""
+    out = Choice()
+    pred = (ctypes.c_float * SEL_MAX_CAND)()
+    n = _I32()
+    if params is not None:
+        _need_cuda(params, "params", torch.float32)
+    _check(lib().cpd_select(ctypes.byref(st), int(rank), int(mode),
+                            None if params is None else params.data_ptr(), int(hidden),
+                            ctypes.byref(out), pred, ctypes.byref(n),
+                            None if params is None else _stream(stream)))
+    return out, [pred[i] for i in range(n.value)]
+
+
+def mlp_param_count(n_in, hidden):
+    return int(lib().cpd_mlp_param_count(int(n_in), int(hidden)))
+
+
+def mlp_init(n_in, hidden, seed, stream=None):
+    p = torch.empty(mlp_param_count(n_in, hidden), dtype=torch.float32, device="cuda")
+    _check(lib().cpd_mlp_init(p.data_ptr(), int(n_in), int(hidden), int(seed), _stream(stream)))
+    return p
+
+
+def mlp_forward(params, n_in, hidden, X, stream=None):
+    _need_cuda(params, "params", torch.float32)
+    X = _need_cuda(X, "X", torch.float32).contiguous()
+    out = torch.empty(X.shape[0], dtype=torch.float32, device="cuda")
+    _check(lib().cpd_mlp_forward(params.data_ptr(), int(n_in), int(hidden), X.data_ptr(),
+                                 X.shape[0], out.data_ptr(), _stream(stream)))
+    return out
+
+
+def mlp_loss_grad(params, n_in, hidden, X, y, stream=None):
+    _need_cuda(params, "params", torch.float32)
+    X = _need_cuda(X, "X", torch.float32).contiguous()
+    y = _need_cuda(y, "y", torch.float32).contiguous()
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    grad = torch.empty_like(params)
+    _check(lib().cpd_mlp_loss_grad(params.data_ptr(), int(n_in), int(hidden), X.data_ptr(),
+                                   y.data_ptr(), X.shape[0], loss.data_ptr(), grad.data_ptr(),
+                                   _stream(stream)))
+    return loss, grad
+
+
+def mlp_adam(params, grad, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    for t, nm in ((params, "params"), (grad, "grad"), (m, "m"), (v, "v")):
+        _need_cuda(t, nm, torch.float32)
+    _check(lib().cpd_mlp_adam(params.data_ptr(), grad.data_ptr(), m.data_ptr(), v.data_ptr(),
+                              params.numel(), lr, beta1, beta2, eps, int(step), _stream(stream)))
+
+
+def mlp_train(params, n_in, hidden, X, y, epochs, batch, lr, seed, stream=None):
+    """cpd_mlp_train in place on params; returns the per-epoch mean loss."""
+    _need_cuda(params, "params", torch.float32)
+    X = _need_cuda(X, "X", torch.float32).contiguous()
+    y = _need_cuda(y, "y", torch.float32).contiguous()
+    trace = (ctypes.c_float * int(epochs))()
+    _check(lib().cpd_mlp_train(params.data_ptr(), int(n_in), int(hidden), X.data_ptr(),
+                               y.data_ptr(), X.shape[0], int(epochs), int(batch), float(lr),
+                               int(seed), trace, _stream(stream)))
+    return list(trace)

@@ -4,6 +4,7 @@
 // convergence check (tol > 0) and at the end.
 #include <stdarg.h>
 
+#include <algorithm>
 #include <vector>
 
 #include "csf.h"
@@ -139,9 +140,37 @@ cpd_status als(int nm, const int64_t *dims, int64_t nnz, const int32_t *const *i
     hipEvent_t t_begin = timing ? evs.make() : nullptr;
     if (timing) CPD_HIP(hipEventRecord(t_begin, s));
 
-    // CSF trees: one rooted at each mode (every MTTKRP at the root), or one shared tree.
+    // CSF trees: one rooted at each mode (every MTTKRP at the root), one
+    // shared tree, or the trees the selector picks (equal orders shared).
     std::vector<cpd_csf_s *> csf_of(nm, nullptr);
-    if (o.single_csf) {
+    std::vector<cpd_mttkrp_opts> mo_of(nm, cpd_mttkrp_opts{bf16 ? CPD_BF16_GATHER : CPD_FP32, o.variant, o.kernel,
+                                                           o.tile_nnz});
+    if (o.select != 0 && o.select != 1 && o.select != 2) CPD_FAIL(CPD_EINVAL, "unknown select mode %d", o.select);
+    if (o.select == 1 && !o.selector_params) CPD_FAIL(CPD_EINVAL, "select = 1 needs selector_params");
+    if (o.select) {
+        cpd_stats st{};
+        CPD_TRY(cpd_tensor_stats(nm, dims, nnz, inds, s, &st));
+        std::vector<std::vector<int32_t>> built;
+        for (int m = 0; m < nm; ++m) {
+            cpd_choice ch{};
+            CPD_TRY(cpd_select(&st, R, m, o.select == 1 ? o.selector_params : nullptr, o.selector_hidden, &ch,
+                               nullptr, nullptr, s));
+            std::vector<int32_t> ord(ch.order, ch.order + nm);
+            auto it = std::find(built.begin(), built.end(), ord);
+            if (it == built.end()) {
+                cpd_csf c = nullptr;
+                CPD_TRY(cpd_csf_build(nm, dims, nnz, inds, vals, ch.order, s, &c));
+                own.csfs.push_back(c);
+                built.push_back(ord);
+                csf_of[m] = c;
+            } else {
+                csf_of[m] = own.csfs[it - built.begin()];
+            }
+            mo_of[m].variant = ch.opts.variant;
+            mo_of[m].kernel = ch.opts.kernel;
+            mo_of[m].tile_nnz = ch.opts.tile_nnz;
+        }
+    } else if (o.single_csf) {
         cpd_csf c = nullptr;
         CPD_TRY(cpd_csf_build(nm, dims, nnz, inds, vals, o.order, s, &c));
         own.csfs.push_back(c);
@@ -216,7 +245,6 @@ cpd_status als(int nm, const int64_t *dims, int64_t nnz, const int32_t *const *i
     CPD_HIP(hipStreamSynchronize(s));
     if (!(h_normX2 > 0.0)) CPD_FAIL(CPD_EINVAL, "the tensor has no nonzero value (||X|| = 0)");
 
-    cpd_mttkrp_opts mo{bf16 ? CPD_BF16_GATHER : CPD_FP32, o.variant, o.kernel, o.tile_nnz};
     const void *fac_ptrs[CPD_MAX_MODES];
     for (int m = 0; m < nm; ++m) fac_ptrs[m] = bf16 ? (const void *)Ab[m] : (const void *)A[m];
     const int fld = bf16 ? ldb : ldf;
@@ -231,7 +259,7 @@ cpd_status als(int nm, const int64_t *dims, int64_t nnz, const int32_t *const *i
     for (it = 1; it <= max_iters; ++it) {
         for (int n = 0; n < nm; ++n) {
             hipEvent_t e0 = timing ? evs.make() : nullptr, e1 = timing ? evs.make() : nullptr;
-            CPD_TRY(mttkrp(csf_of[n], fac_ptrs, fld, R, n, Y, ldf, &mo, s, e0, e1));
+            CPD_TRY(mttkrp(csf_of[n], fac_ptrs, fld, R, n, Y, ldf, &mo_of[n], s, e0, e1));
             ev_mt0.push_back(e0);
             ev_mt1.push_back(e1);
             CPD_TRY(solve_normalize(gptr, nm, n, Y, dims[n], R, ldf, A[n], ldf, bf16 ? Ab[n] : nullptr, ldb,
@@ -256,7 +284,7 @@ cpd_status als(int nm, const int64_t *dims, int64_t nnz, const int32_t *const *i
     if (bf16) {
         const void *f32_ptrs[CPD_MAX_MODES];
         for (int m = 0; m < nm; ++m) f32_ptrs[m] = A[m];
-        cpd_mttkrp_opts mf = mo;
+        cpd_mttkrp_opts mf = mo_of[nm - 1];
         mf.precision = CPD_FP32;
         CPD_TRY(mttkrp(csf_of[nm - 1], f32_ptrs, ldf, R, nm - 1, Y, ldf, &mf, s, nullptr, nullptr));
         CPD_TRY(fit(h_normX2, lambda, A[nm - 1], ldf, Y, ldf, dims[nm - 1], R, gptr, nm, d_fit + max_iters, s));
@@ -298,7 +326,7 @@ extern "C" {
 
 const char *cpd_last_error(void) { return cpd::g_err; }
 
-int32_t cpd_abi_version(void) { return 1; }
+int32_t cpd_abi_version(void) { return 2; }
 
 cpd_status cpd_als(int32_t nmodes, const int64_t *dims, int64_t nnz, const int32_t *const *inds, const float *vals,
                    int32_t rank, int32_t max_iters, double tol, const cpd_als_opts *opts, float *const *factors_out,

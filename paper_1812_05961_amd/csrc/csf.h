@@ -49,6 +49,16 @@ namespace cpd {
 template <typename F>
 cpd_status exclusive_scan(F f, int64_t n, int32_t *out, int32_t *total, hipStream_t s);
 
+// Stable LSD radix sort (see csf.hip); buffers ping-pong, k*/kp end on the result.
+cpd_status radix_sort(uint64_t *&klo, uint64_t *&khi, int32_t *&kp, uint64_t *&olo, uint64_t *&ohi, int32_t *&op,
+                      int64_t n, int bits, hipStream_t s);
+
+// Index frequencies in a strided sample of at most max_samples of the n ids
+// (values in [0, nid)): out (device, 3 int32) = distinct ids in the sample,
+// largest count, sample size.
+cpd_status sample_freq(const int32_t *ids, int64_t n, int64_t nid, int64_t max_samples, int32_t *out,
+                       hipStream_t s);
+
 // Tile start nodes for a tile width (cached in the handle; created on first use).
 cpd_status csf_tiles(cpd_csf_s *c, int32_t tile, const int32_t **starts, int64_t *ntiles,
                      hipStream_t s);

@@ -136,6 +136,8 @@ struct HistAt {
     __device__ int32_t operator()(int64_t i) const { return h[i]; }
 };
 
+}  // namespace
+
 // Stable LSD radix sort of n keys (one or two 64-bit words, `bits` significant
 // bits) with an int32 payload, 8 bits per pass, ping-ponging between the
 // (k*, p*) and (o*, op*) buffers; on return k*, kp point at the sorted data.
@@ -162,9 +164,11 @@ cpd_status radix_sort(uint64_t *&klo, uint64_t *&khi, int32_t *&kp, uint64_t *&o
     return CPD_OK;
 }
 
+namespace {
+
 // ---- leaf ranking: leaf ids ordered by how often a strided sample of the
-// leaves holds them (descending, ties by id); only the MTTKRP kernels' cache
-// of hot rows depends on it, never a result.
+// leaves holds them (descending, ties by id); only the order of a private
+// copy of the leaf factor depends on it, never a result.
 __global__ void k_sample(const int32_t *ids, int64_t stride, int64_t ns, uint64_t *key, int32_t *pay) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= ns) return;
@@ -315,6 +319,24 @@ __global__ void k_tiles(FptrSet fp, int nl, int64_t nleaves, int32_t tile, int64
 }
 
 inline unsigned grid1(int64_t n, int t = 256) { return (unsigned)ceil_div(n, t); }
+
+__global__ void k_max_run(const int32_t *starts, const int32_t *nruns, int64_t ns, int32_t *out) {
+    __shared__ int32_t red[4];
+    const int32_t nr = *nruns;
+    int32_t mx = 0;
+    for (int64_t r = threadIdx.x; r < nr; r += blockDim.x) {
+        const int32_t e = (r + 1 < nr) ? starts[r + 1] : (int32_t)ns;
+        mx = max(mx, e - starts[r]);
+    }
+    for (int o = 32; o > 0; o >>= 1) mx = max(mx, __shfl_xor(mx, o, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        out[0] = nr;
+        out[1] = max(max(red[0], red[1]), max(red[2], red[3]));
+        out[2] = (int32_t)ns;
+    }
+}
 
 void free_csf(cpd_csf_s *c) {
     if (!c) return;
@@ -543,6 +565,34 @@ cpd_status build(int nm, const int64_t *dims, int64_t nnz, const int32_t *const 
 }
 
 }  // namespace
+
+cpd_status sample_freq(const int32_t *ids, int64_t n, int64_t nid, int64_t max_samples, int32_t *out,
+                       hipStream_t s) {
+    const int64_t stride = std::max<int64_t>(1, ceil_div(n, max_samples));
+    const int64_t ns = ceil_div(n, stride);
+    int ibits = 0;
+    while ((1ll << ibits) < nid) ++ibits;
+    DevBuf<uint64_t> k0, k1;
+    DevBuf<int32_t> p0, p1, pos, starts, nr;
+    CPD_TRY(k0.alloc(ns, s));
+    CPD_TRY(k1.alloc(ns, s));
+    CPD_TRY(p0.alloc(ns, s));
+    CPD_TRY(p1.alloc(ns, s));
+    CPD_TRY(pos.alloc(ns, s));
+    CPD_TRY(starts.alloc(ns, s));
+    CPD_TRY(nr.alloc(1, s));
+    uint64_t *a = k0.p, *ah = nullptr, *b = k1.p, *bh = nullptr;
+    int32_t *ap = p0.p, *bp = p1.p;
+    hipLaunchKernelGGL(k_sample, dim3(grid1(ns)), dim3(256), 0, s, ids, stride, ns, a, ap);
+    CPD_LAUNCH_CHECK();
+    CPD_TRY(radix_sort(a, ah, ap, b, bh, bp, ns, std::max(ibits, 1), s));
+    CPD_TRY(exclusive_scan(RunStart{a}, ns, pos.p, nr.p, s));
+    hipLaunchKernelGGL(k_run_starts, dim3(grid1(ns)), dim3(256), 0, s, (const uint64_t *)a, (const int32_t *)pos.p, ns,
+                       starts.p);
+    hipLaunchKernelGGL(k_max_run, dim3(1), dim3(256), 0, s, (const int32_t *)starts.p, (const int32_t *)nr.p, ns, out);
+    CPD_LAUNCH_CHECK();
+    return CPD_OK;
+}
 
 cpd_status csf_tiles(cpd_csf_s *c, int32_t tile, const int32_t **starts, int64_t *ntiles,
                      hipStream_t s) {

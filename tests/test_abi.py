@@ -45,7 +45,7 @@ def test_binding_covers_the_header():
 def test_abi_version_and_error_string_without_gpu():
     L = ctypes.CDLL(LIB)
     L.cpd_abi_version.restype = ctypes.c_int32
-    assert L.cpd_abi_version() == 1
+    assert L.cpd_abi_version() == 2
     L.cpd_last_error.restype = ctypes.c_char_p
     assert L.cpd_last_error() == b""
 
