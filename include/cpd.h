@@ -144,9 +144,10 @@ cpd_status cpd_gram(const float *A, int64_t rows, int32_t rank, int32_t ld, doub
 
 /* One mode update after its MTTKRP (Algorithm 1, lines 4-6 and 7-9, ...):
  *   V = Hadamard product of grams[m] over m != mode;
- *   A = Y V^+, by Cholesky when every pivot exceeds rank*eps*max(diag V),
- *       else by the Moore-Penrose inverse from a Jacobi eigendecomposition
- *       dropping eigenvalues <= rank*eps*max eigenvalue;
+ *   A = Y V^+, with V^+ = V^{-1} by symmetric Gauss-Jordan elimination when
+ *       every pivot (the square of Cholesky's diagonal) exceeds
+ *       rank*eps*max(diag V), else the Moore-Penrose inverse from a Jacobi
+ *       eigendecomposition dropping eigenvalues <= rank*eps*max eigenvalue;
  *   lambda_r = 2-norm of column r of A; A(:, r) /= lambda_r when > 0.
  * grams:    host array of nmodes device pointers to rank x rank doubles.
  * Y:        device, rows x rank floats (stride ldy).

@@ -36,25 +36,18 @@ __device__ __forceinline__ uint32_t key_field(uint64_t lo, uint64_t hi, int s, i
     return (uint32_t)(((lo >> s) | (hi << (64 - s))) & mask);
 }
 
-__global__ void k_validate(LevelInds in, KeyLayout kl, const int64_t *dims_by_level, int64_t n,
-                           int32_t *bad) {
-    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
-    bool ok = true;
-    for (int l = 0; l < kl.nl; ++l) {
-        int32_t v = in.p[l][k];
-        ok = ok && v >= 0 && (int64_t)v < dims_by_level[l];
-    }
-    if (!ok) atomicOr(bad, 1);
-}
-
-__global__ void k_pack(LevelInds in, KeyLayout kl, int64_t n, uint64_t *lo, uint64_t *hi,
-                       int32_t *pay) {
+// Packed key of nonzero k (root index most significant) and its value as the
+// sort payload (bits of the float), with the index check of every level.
+__global__ void k_pack(LevelInds in, KeyLayout kl, const int64_t *dims_by_level, const float *vals, int64_t n,
+                       uint64_t *lo, uint64_t *hi, int32_t *pay, int32_t *bad) {
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
     uint64_t a = 0, b = 0;
+    bool ok = true;
     for (int l = 0; l < kl.nl; ++l) {
-        uint64_t x = (uint64_t)(uint32_t)in.p[l][k];
+        const int32_t v = in.p[l][k];
+        ok = ok && v >= 0 && (int64_t)v < dims_by_level[l];
+        uint64_t x = (uint64_t)(uint32_t)v;
         int s = kl.shift[l];
         if (kl.bits[l] == 0) continue;
         if (s >= 64) {
@@ -64,9 +57,10 @@ __global__ void k_pack(LevelInds in, KeyLayout kl, int64_t n, uint64_t *lo, uint
             if (s > 0 && s + kl.bits[l] > 64) b |= x >> (64 - s);
         }
     }
+    if (!ok) atomicOr(bad, 1);
     lo[k] = a;
     if (hi) hi[k] = b;
-    pay[k] = (int32_t)k;
+    pay[k] = __float_as_int(vals[k]);
 }
 
 // ---- radix sort: per-tile digit histogram (digit-major output)
@@ -131,6 +125,91 @@ k_radix_scatter(const uint64_t *klo, const uint64_t *khi, const int32_t *pay, ui
     }
 }
 
+// ---- radix sort: stable scatter of one-word keys through LDS.  The tile is
+// ranked as above, reordered by digit in LDS, and written out run by run, so
+// consecutive threads store to consecutive addresses.
+__global__ void __launch_bounds__(RS_THREADS)
+k_radix_scatter1(const uint64_t *__restrict__ keys, const int32_t *__restrict__ pay, uint64_t *__restrict__ okeys,
+                 int32_t *__restrict__ opay, const int32_t *__restrict__ offsets, int64_t n, int64_t ntiles,
+                 int shift) {
+    __shared__ uint64_t s_key[RS_TILE];
+    __shared__ int32_t s_pay[RS_TILE];
+    __shared__ int32_t s_run[256];      // counts of earlier rounds, then the tile's digit starts
+    __shared__ int32_t s_off[256];      // global start minus tile start, per digit
+    __shared__ int32_t wcnt[2][4][256];  // per-wave digit counts, two rounds in flight
+    __shared__ int32_t s_wsum[4];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    s_run[tid] = 0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) wcnt[0][w][tid] = wcnt[1][w][tid] = 0;
+    const int64_t tbase = (int64_t)blockIdx.x * RS_TILE;
+    const int tn = (int)min<int64_t>(RS_TILE, n - tbase);
+    uint64_t k[RS_ITEMS];
+    int32_t p[RS_ITEMS], rk[RS_ITEMS];
+#pragma unroll
+    for (int r = 0; r < RS_ITEMS; ++r) {
+        const int j = r * RS_THREADS + tid;
+        k[r] = j < tn ? keys[tbase + j] : 0ull;
+        p[r] = j < tn ? pay[tbase + j] : 0;
+    }
+    __syncthreads();
+    const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+#pragma unroll
+    for (int r = 0; r < RS_ITEMS; ++r) {
+        const bool valid = r * RS_THREADS + tid < tn;
+        const uint32_t d = (uint32_t)((k[r] >> shift) & 255u);
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int bit = 0; bit < 8; ++bit) {
+            const bool set = (d >> bit) & 1u;
+            const uint64_t m = __ballot(set);
+            peers &= set ? m : ~m;
+        }
+        const int rank_w = __popcll(peers & lt);
+        const int b = r & 1;
+        if (valid && rank_w == 0) wcnt[b][wave][d] = __popcll(peers);
+        __syncthreads();
+        int x = s_run[d] + rank_w;
+        for (int w = 0; w < wave; ++w) x += wcnt[b][w][d];
+        rk[r] = x;
+        __syncthreads();
+        s_run[tid] += wcnt[b][0][tid] + wcnt[b][1][tid] + wcnt[b][2][tid] + wcnt[b][3][tid];
+        wcnt[b][0][tid] = wcnt[b][1][tid] = wcnt[b][2][tid] = wcnt[b][3][tid] = 0;
+    }
+    __syncthreads();
+    // exclusive scan of the tile's digit counts
+    const int c = s_run[tid];
+    int incl = c;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += y;
+    }
+    if (lane == 63) s_wsum[wave] = incl;
+    __syncthreads();
+    int excl = incl - c;
+    for (int w = 0; w < wave; ++w) excl += s_wsum[w];
+    s_run[tid] = excl;
+    s_off[tid] = offsets[(int64_t)tid * ntiles + blockIdx.x] - excl;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < RS_ITEMS; ++r) {
+        if (r * RS_THREADS + tid < tn) {
+            const uint32_t d = (uint32_t)((k[r] >> shift) & 255u);
+            const int at = s_run[d] + rk[r];
+            s_key[at] = k[r];
+            s_pay[at] = p[r];
+        }
+    }
+    __syncthreads();
+    for (int e = tid; e < tn; e += RS_THREADS) {
+        const uint64_t key = s_key[e];
+        const int64_t g = (int64_t)s_off[(key >> shift) & 255u] + e;
+        okeys[g] = key;
+        opay[g] = s_pay[e];
+    }
+}
+
 struct HistAt {
     const int32_t *h;
     __device__ int32_t operator()(int64_t i) const { return h[i]; }
@@ -154,8 +233,12 @@ cpd_status radix_sort(uint64_t *&klo, uint64_t *&khi, int32_t *&kp, uint64_t *&o
         hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)ntiles), dim3(RS_THREADS), 0, s, src, n, shift, hist.p, ntiles);
         CPD_LAUNCH_CHECK();
         CPD_TRY(exclusive_scan(HistAt{hist.p}, 256 * ntiles, hist.p, (int32_t *)nullptr, s));
-        hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)ntiles), dim3(RS_THREADS), 0, s, klo, khi, kp, olo, ohi, op,
-                           (const int32_t *)hist.p, n, ntiles, word, shift);
+        if (khi)
+            hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)ntiles), dim3(RS_THREADS), 0, s, klo, khi, kp, olo,
+                               ohi, op, (const int32_t *)hist.p, n, ntiles, word, shift);
+        else
+            hipLaunchKernelGGL(k_radix_scatter1, dim3((unsigned)ntiles), dim3(RS_THREADS), 0, s, klo, kp, olo, op,
+                               (const int32_t *)hist.p, n, ntiles, shift);
         CPD_LAUNCH_CHECK();
         std::swap(klo, olo);
         std::swap(khi, ohi);
@@ -243,13 +326,13 @@ struct AtLevel {
 
 // One thread per run of equal keys: the float sum of the run in input order
 // (the sort is stable, so the run is in input order).
-__global__ void k_merge(const uint64_t *lo, const uint64_t *hi, const int32_t *pay,
-                        const float *vals, const uint8_t *dl, const int32_t *pos, int64_t n,
-                        int nl, uint64_t *ulo, uint64_t *uhi, float *uval, uint8_t *udl) {
+__global__ void k_merge(const uint64_t *lo, const uint64_t *hi, const int32_t *pay, const uint8_t *dl,
+                        const int32_t *pos, int64_t n, int nl, uint64_t *ulo, uint64_t *uhi, float *uval,
+                        uint8_t *udl) {
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n || dl[k] >= nl) return;
-    float s = vals[pay[k]];
-    for (int64_t j = k + 1; j < n && dl[j] >= nl; ++j) s += vals[pay[j]];
+    float s = __int_as_float(pay[k]);
+    for (int64_t j = k + 1; j < n && dl[j] >= nl; ++j) s += __int_as_float(pay[j]);
     int32_t p = pos[k];
     ulo[p] = lo[k];
     if (uhi) uhi[p] = hi[k];
@@ -402,9 +485,6 @@ cpd_status build(int nm, const int64_t *dims, int64_t nnz, const int32_t *const 
     CPD_TRY(d_flag.alloc(1 + CPD_MAX_MODES, s));
     CPD_HIP(hipMemcpyAsync(d_dims.p, dims_l, sizeof(int64_t) * nm, hipMemcpyHostToDevice, s));
     CPD_HIP(hipMemsetAsync(d_flag.p, 0, sizeof(int32_t) * (1 + CPD_MAX_MODES), s));
-    hipLaunchKernelGGL(k_validate, dim3(grid1(nnz)), dim3(256), 0, s, li, kl, (const int64_t *)d_dims.p,
-                       nnz, d_flag.p);
-    CPD_LAUNCH_CHECK();
 
     // a3: keys and stable LSD radix sort
     DevBuf<uint64_t> lo0, lo1, hi0, hi1;
@@ -417,7 +497,8 @@ cpd_status build(int nm, const int64_t *dims, int64_t nnz, const int32_t *const 
     }
     CPD_TRY(p0.alloc(nnz, s));
     CPD_TRY(p1.alloc(nnz, s));
-    hipLaunchKernelGGL(k_pack, dim3(grid1(nnz)), dim3(256), 0, s, li, kl, nnz, lo0.p, hi0.p, p0.p);
+    hipLaunchKernelGGL(k_pack, dim3(grid1(nnz)), dim3(256), 0, s, li, kl, (const int64_t *)d_dims.p, vals, nnz,
+                       lo0.p, hi0.p, p0.p, d_flag.p);
     CPD_LAUNCH_CHECK();
     uint64_t *klo = lo0.p, *khi = hi0.p, *olo = lo1.p, *ohi = hi1.p;
     int32_t *kp = p0.p, *op = p1.p;
@@ -437,8 +518,8 @@ cpd_status build(int nm, const int64_t *dims, int64_t nnz, const int32_t *const 
     DevBuf<float> uval;
     CPD_TRY(udl.alloc(nnz, s));
     CPD_TRY(uval.alloc(nnz, s));
-    hipLaunchKernelGGL(k_merge, dim3(grid1(nnz)), dim3(256), 0, s, klo, khi, kp, vals, dl.p, pos.p,
-                       nnz, nm, olo, ohi, uval.p, udl.p);
+    hipLaunchKernelGGL(k_merge, dim3(grid1(nnz)), dim3(256), 0, s, klo, khi, kp, dl.p, pos.p, nnz, nm, olo, ohi,
+                       uval.p, udl.p);
     CPD_LAUNCH_CHECK();
     std::swap(klo, olo);
     std::swap(khi, ohi);

@@ -13,7 +13,7 @@ namespace {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-constexpr int GRAM_MAX_BLOCKS = 1024;
+constexpr int GRAM_MAX_BLOCKS = 512;
 constexpr double EPS64 = 2.220446049250313080847e-16;
 
 struct GramSet {
@@ -75,7 +75,20 @@ k_gram(const float *__restrict__ A, int64_t rows, int R, int64_t ld, double *__r
     }
 }
 
-// Sum the per-block partials in block order; fill both triangles.
+// sum over b < nb of p[b * stride]: eight interleaved chains (b mod 8),
+// combined in a fixed order, so loads overlap and the result is deterministic
+__device__ inline double sum_strided(const double *__restrict__ p, int nb, int64_t stride) {
+    double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int b = 0;
+    for (; b + 7 < nb; b += 8) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) a[q] += p[(int64_t)(b + q) * stride];
+    }
+    for (int q = 0; b < nb; ++b, ++q) a[q] += p[(int64_t)b * stride];
+    return ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+}
+
+// Sum the per-block partials; fill both triangles.
 __global__ void k_gram_reduce(const double *__restrict__ partial, int nblocks, int P, int R,
                               double *__restrict__ G) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -84,9 +97,7 @@ __global__ void k_gram_reduce(const double *__restrict__ partial, int nblocks, i
     const int rr = min(r, c), cc = max(r, c);
     // within a diagonal block both triangles were computed; outside, use the upper block
     const int src = ((rr >> 4) == (cc >> 4)) ? (r * P + c) : (rr * P + cc);
-    double s = 0.0;
-    for (int b = 0; b < nblocks; ++b) s += partial[(int64_t)b * P * P + src];
-    G[t] = s;
+    G[t] = sum_strided(partial + src, nblocks, (int64_t)P * P);
 }
 
 cpd_status gram(const float *A, int64_t rows, int R, int64_t ld, double *G, hipStream_t s) {
@@ -110,9 +121,10 @@ cpd_status gram(const float *A, int64_t rows, int R, int64_t ld, double *G, hipS
 }
 
 // ------------------------------------------------------------------ W = V^+
-// One block of 256 threads.  V (R x R, FP64) lives in LDS; work matrices in
-// global scratch `wk` (2 R^2 doubles).  Writes W = V^{-1} (Cholesky) or V^+
-// (Jacobi eigendecomposition) to W, and the fallback flag.
+// One block of 256 threads.  V (R x R, FP64) lives in LDS; the fallback's
+// eigenvectors in global scratch `wk` (R^2 doubles).  Writes W = V^{-1}
+// (symmetric Gauss-Jordan) or V^+ (Jacobi eigendecomposition) to W, and the
+// fallback flag.
 __global__ void __launch_bounds__(256)
 k_make_w(GramSet gs, int nmodes, int mode, int R, double *__restrict__ W, double *__restrict__ wk,
          int32_t *__restrict__ used_pinv) {
@@ -138,41 +150,36 @@ k_make_w(GramSet gs, int nmodes, int mode, int R, double *__restrict__ W, double
     }
     __syncthreads();
     const double thresh = sh[0];
-    // Cholesky-Banachiewicz in place (lower triangle of V becomes L)
+    // W = V^{-1} by symmetric Gauss-Jordan elimination in place (the sweep
+    // operator, Goodnight 1979; no pivoting, as for Cholesky on an SPD matrix).
+    // Pivot j is the j-th diagonal of the Schur complement, the square of
+    // Cholesky's L(j, j), so the same threshold decides between the inverse
+    // and the fallback.  Sweeping every index leaves -V^{-1}; the update is
+    // symmetric term by term, so W is exactly symmetric.
+    __shared__ double colj[CPD_MAX_RANK];
+    bool ok = true;
     for (int j = 0; j < R; ++j) {
-        if (tid == 0) {
-            double d = V[j * R + j];
-            for (int k = 0; k < j; ++k) d -= V[j * R + k] * V[j * R + k];
-            if (!(d > thresh)) fail = 1;
-            else V[j * R + j] = sqrt(d);
+        const double d = V[j * R + j];
+        if (!(d > thresh)) {
+            ok = false;  // every thread reads the same d
+            break;
         }
+        if (tid < R) colj[tid] = V[tid * R + j];
         __syncthreads();
-        if (fail) break;
-        for (int i = j + 1 + tid; i < R; i += 256) {
-            double x = V[i * R + j];
-            for (int k = 0; k < j; ++k) x -= V[i * R + k] * V[j * R + k];
-            V[i * R + j] = x / V[j * R + j];
+        const double inv = 1.0 / d;
+        for (int t = tid; t < R * R; t += 256) {
+            const int r = t / R, c = t % R;
+            double x;
+            if (r == j && c == j) x = -inv;
+            else if (r == j) x = colj[c] * inv;
+            else if (c == j) x = colj[r] * inv;
+            else x = V[t] - colj[r] * colj[c] * inv;
+            V[t] = x;
         }
         __syncthreads();
     }
-    if (!fail) {
-        // Linv (lower) column by column into wk, then W = Linv^T Linv
-        double *Li = wk;
-        for (int c = tid; c < R; c += 256) {
-            for (int i = 0; i < R; ++i) {
-                if (i < c) { Li[i * R + c] = 0.0; continue; }
-                double x = (i == c) ? 1.0 : 0.0;
-                for (int k = c; k < i; ++k) x -= V[i * R + k] * Li[k * R + c];
-                Li[i * R + c] = x / V[i * R + i];
-            }
-        }
-        __syncthreads();
-        for (int t = tid; t < R * R; t += 256) {
-            const int r = t / R, c = t % R;
-            double x = 0.0;
-            for (int k = max(r, c); k < R; ++k) x += Li[k * R + r] * Li[k * R + c];
-            W[t] = x;
-        }
+    if (ok) {
+        for (int t = tid; t < R * R; t += 256) W[t] = -V[t];
         if (tid == 0 && used_pinv) *used_pinv = 0;
         return;
     }
@@ -300,9 +307,7 @@ k_apply_w(const float *__restrict__ Y, int64_t rows, int R, int64_t ldy, const d
 __global__ void k_lambda(const double *__restrict__ partial, int nblocks, int R, double *__restrict__ lambda) {
     const int c = threadIdx.x;
     if (c >= R) return;
-    double s = 0.0;
-    for (int b = 0; b < nblocks; ++b) s += partial[(int64_t)b * R + c];
-    lambda[c] = sqrt(s);
+    lambda[c] = sqrt(sum_strided(partial + c, nblocks, R));
 }
 
 // ------------------------------------------------------------------ fit
@@ -329,9 +334,7 @@ __global__ void k_fit_final(const double *__restrict__ partial, int nblocks, int
     __shared__ double inner_r[CPD_MAX_RANK], quad_r[CPD_MAX_RANK];
     const int r = threadIdx.x;
     if (r < R) {
-        double s = 0.0;
-        for (int b = 0; b < nblocks; ++b) s += partial[(int64_t)b * R + r];
-        inner_r[r] = lambda[r] * s;
+        inner_r[r] = lambda[r] * sum_strided(partial + r, nblocks, R);
         double q = 0.0;
         for (int c = 0; c < R; ++c) {
             double h = 1.0;
@@ -438,7 +441,7 @@ cpd_status fit(double normX2, const double *lambda, const float *A, int64_t lda,
         if (!grams[m]) CPD_FAIL(CPD_EINVAL, "null gram for mode %d", m);
         gs.g[m] = grams[m];
     }
-    const int nb = (int)std::min<int64_t>(1024, std::max<int64_t>(1, ceil_div(rows, 64)));
+    const int nb = (int)std::min<int64_t>(256, std::max<int64_t>(1, ceil_div(rows, 64)));
     DevBuf<double> part;
     CPD_TRY(part.alloc((size_t)nb * R, s));
     hipLaunchKernelGGL(k_fit_partial, dim3(nb), dim3(256), 0, s, A, lda, Y, ldy, rows, R, part.p);

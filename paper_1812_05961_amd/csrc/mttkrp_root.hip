@@ -46,16 +46,19 @@ struct FacView {
     const void *a[CPD_MAX_MODES];  // by level
 };
 
-// One 16-byte chunk of a factor row: 4 floats, or 8 bfloat16 widened to float.
-// Rows are addressed by a 32-bit byte offset from a uniform base (row id times
-// row bytes, both below 2^24), which keeps address arithmetic at one 24-bit
-// multiply per row.
+// One lane's chunk of a factor row: 4 floats (16 bytes), 8 bfloat16 (16
+// bytes) or 4 bfloat16 (8 bytes: the lane layout of the float rows at half
+// the bytes), widened to float.  Rows are addressed by a 32-bit byte offset
+// from a uniform base (row id times row bytes, both below 2^24), which keeps
+// address arithmetic at one 24-bit multiply per row.
+struct bf16x4;  // tag: 4 bfloat16 per lane
+
 template <typename GT>
 struct Chunk;
 
 template <>
 struct Chunk<float> {
-    static constexpr int W = 4;
+    static constexpr int W = 4, BYTES = 16, ELEM = 4;
     __device__ static __forceinline__ void load(const char *base, uint32_t off, float *v) {
         const float4 x = *reinterpret_cast<const float4 *>(base + off);
         v[0] = x.x;
@@ -67,7 +70,7 @@ struct Chunk<float> {
 
 template <>
 struct Chunk<uint16_t> {
-    static constexpr int W = 8;
+    static constexpr int W = 8, BYTES = 16, ELEM = 2;
     __device__ static __forceinline__ void load(const char *base, uint32_t off, float *v) {
         const uint4 x = *reinterpret_cast<const uint4 *>(base + off);
         v[0] = bf16_lo(x.x);
@@ -81,12 +84,25 @@ struct Chunk<uint16_t> {
     }
 };
 
+template <>
+struct Chunk<bf16x4> {
+    static constexpr int W = 4, BYTES = 8, ELEM = 2;
+    __device__ static __forceinline__ void load(const char *base, uint32_t off, float *v) {
+        const uint2 x = *reinterpret_cast<const uint2 *>(base + off);
+        v[0] = bf16_lo(x.x);
+        v[1] = bf16_hi(x.x);
+        v[2] = bf16_lo(x.y);
+        v[3] = bf16_hi(x.y);
+    }
+};
+
 // Leaves per LDS staging chunk (per group): fewer when a wave has many groups.
 template <int NG>
 constexpr int root_chunk() {
     return NG >= 32 ? 8 : 16;
 }
 constexpr int ROOT_C = 32;      // tile widths must be multiples of this
+constexpr int BF16_NARROW_MAX = 16;
 constexpr int ROOT_WAVES = 4;   // waves per block
 
 // Leaves per block whose rows are gathered together: keeps the block's rows
@@ -130,7 +146,7 @@ k_mttkrp_root(CsfView cv, FacView fv, const char *__restrict__ a_leaf, uint32_t 
     float *sv = s_v[wave];
     const int gs = g < NG ? g : NG - 1;  // staged slot this lane reads (idle lanes never do)
     auto col_of = [&](int e) { return (lig * W) + e; };
-    const uint32_t lane_off = (uint32_t)lig * 16u;  // this lane's chunk within a row
+    const uint32_t lane_off = (uint32_t)lig * Chunk<GT>::BYTES;  // this lane's chunk within a row
     const char *a_up[NU];
 #pragma unroll
     for (int l = 0; l < NU; ++l) a_up[l] = static_cast<const char *>(fv.a[l + 1]);
@@ -364,7 +380,7 @@ static cpd_status launch_root_n(int RP, const CsfView &cv, const FacView &fv, co
                                 const int32_t *starts, int64_t ntiles, int32_t T, float *Y, int64_t ldo, int R,
                                 hipStream_t s) {
     constexpr int W = Chunk<GT>::W;
-    const uint32_t rowb = (uint32_t)(ld * (int64_t)sizeof(GT));
+    const uint32_t rowb = (uint32_t)(ld * (int64_t)Chunk<GT>::ELEM);
     switch (RP / W) {
 #define CPD_ROOT_G(g) \
     case g: return launch_root_g<N, g, GT>(cv, fv, a_leaf, rowb, starts, ntiles, T, Y, ldo, R, s);
@@ -415,15 +431,21 @@ cpd_status launch_root(int N, bool bf16, int RP, const int32_t *const *fids, con
         CPD_LAUNCH_CHECK();
     }
     const char *a_leaf = reinterpret_cast<const char *>(perm.p);
+    // bfloat16 rows: 8-byte chunks (the float layout at half the bytes) up to
+    // a padded rank of BF16_NARROW_MAX, 16-byte chunks above
+    const bool narrow = bf16 && RP <= BF16_NARROW_MAX;
+#define CPD_ROOT_N(n)                                                                                      \
+    case n:                                                                                                \
+        if (narrow) return launch_root_n<n, bf16x4>(RP, cv, fv, a_leaf, ld, starts, ntiles, T, Y, ldo, R, s); \
+        return bf16 ? launch_root_n<n, uint16_t>(RP, cv, fv, a_leaf, ld, starts, ntiles, T, Y, ldo, R, s)   \
+                    : launch_root_n<n, float>(RP, cv, fv, a_leaf, ld, starts, ntiles, T, Y, ldo, R, s);
     switch (N) {
-        case 3: return bf16 ? launch_root_n<3, uint16_t>(RP, cv, fv, a_leaf, ld, starts, ntiles, T, Y, ldo, R, s)
-                            : launch_root_n<3, float>(RP, cv, fv, a_leaf, ld, starts, ntiles, T, Y, ldo, R, s);
-        case 4: return bf16 ? launch_root_n<4, uint16_t>(RP, cv, fv, a_leaf, ld, starts, ntiles, T, Y, ldo, R, s)
-                            : launch_root_n<4, float>(RP, cv, fv, a_leaf, ld, starts, ntiles, T, Y, ldo, R, s);
-        case 5: return bf16 ? launch_root_n<5, uint16_t>(RP, cv, fv, a_leaf, ld, starts, ntiles, T, Y, ldo, R, s)
-                            : launch_root_n<5, float>(RP, cv, fv, a_leaf, ld, starts, ntiles, T, Y, ldo, R, s);
+        CPD_ROOT_N(3)
+        CPD_ROOT_N(4)
+        CPD_ROOT_N(5)
         default: CPD_FAIL(CPD_EUNSUPPORTED, "root kernel built for 3..5 modes, not %d", N);
     }
+#undef CPD_ROOT_N
 }
 
 }  // namespace cpd
