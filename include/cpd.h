@@ -271,7 +271,7 @@ typedef struct {
 
 /* Candidates for MTTKRP of `mode` at `rank` (3..5 modes): every distinct
  * order of the four kinds; at the root the root-level kernel with tile widths
- * 32, 64, 256 (or atomic lanes with 64, 256, 1024 when the tree exceeds that
+ * 32, 128, 512 (or atomic lanes with 64, 256, 1024 when the tree exceeds that
  * kernel's index limits); below the root atomic lanes, and privatised lanes
  * when dims[mode] * rank * 4 <= 64 KiB, each with tile widths 64, 256, 1024.
  * out: host, CPD_SEL_MAX_CAND entries; *n receives the count.

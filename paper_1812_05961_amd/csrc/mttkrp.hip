@@ -389,7 +389,7 @@ cpd_status mttkrp(cpd_csf_s *c, const void *const *factors, int32_t ld, int32_t 
         CPD_LAUNCH_CHECK();
     }
     if (kernel == CPD_KERNEL_ROW && d == 0) {
-        const int32_t T = o.tile_nnz ? o.tile_nnz : 64;
+        const int32_t T = o.tile_nnz ? o.tile_nnz : 128;
 
         const int32_t *starts;
         int64_t ns;

@@ -105,18 +105,26 @@ constexpr int ROOT_C = 32;      // tile widths must be multiples of this
 constexpr int BF16_NARROW_MAX = 16;
 constexpr int ROOT_WAVES = 4;   // waves per block
 
-// Leaves per block whose rows are gathered together: keeps the block's rows
-// (leaf row and the N-2 internal rows per leaf) near 64 registers.
+// Leaves per block whose rows are gathered together.  Two: measured faster
+// than four or eight on every workload (fewer registers, more resident waves
+// to cover the gather latency).
 template <int N, typename GT>
 constexpr int root_unroll() {
-    constexpr int per = Chunk<GT>::W * (N - 1);
-    return per <= 16 ? 4 : 2;
+    return 2;
+}
+
+// Minimum resident waves per SIMD asked of the compiler: 6 for 16-byte
+// bfloat16 chunks on 3 modes (measured faster, despite a few spilled
+// registers), no constraint otherwise.
+template <int N, typename GT>
+constexpr int root_min_waves() {
+    return (N == 3 && std::is_same<GT, uint16_t>::value) ? 6 : 1;
 }
 
 // a_leaf: the leaf factor with rows in rank order (row r = factor row
 // leaf_perm[r]), so the most used rows share cache lines and pages.
 template <int N, int G, typename GT>
-__global__ void __launch_bounds__(64 * ROOT_WAVES)
+__global__ void __launch_bounds__(64 * ROOT_WAVES, (root_min_waves<N, GT>()))
 k_mttkrp_root(CsfView cv, FacView fv, const char *__restrict__ a_leaf, uint32_t rowb,
               const int32_t *__restrict__ starts, int64_t ntiles, int32_t T, int64_t nsteps, int64_t nwaves,
               float *__restrict__ Y, int64_t ldo, int R) {

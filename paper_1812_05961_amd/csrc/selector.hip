@@ -171,7 +171,7 @@ cpd_status cpd_select_candidates(const cpd_stats *st, int32_t rank, int32_t mode
             out[cnt++] = c;
         };
         if (b.depth == 0 && root_kernel_fits(*st, b.order)) {
-            for (int t : {32, 64, 256}) push(CPD_VARIANT_AUTO, CPD_KERNEL_ROW, t);
+            for (int t : {32, 128, 512}) push(CPD_VARIANT_AUTO, CPD_KERNEL_ROW, t);
         } else {
             for (int t : {64, 256, 1024}) push(CPD_VARIANT_ATOMIC, CPD_KERNEL_LANE, t);
             if (b.depth > 0 && priv_fits(*st, mode, rank))
@@ -234,7 +234,7 @@ cpd_status cpd_select_heuristic(const cpd_stats *st, int32_t rank, int32_t mode,
     if (c.depth == 0 && root_kernel_fits(*st, c.order)) {
         c.opts.variant = CPD_VARIANT_AUTO;
         c.opts.kernel = CPD_KERNEL_ROW;
-        c.opts.tile_nnz = 64;
+        c.opts.tile_nnz = 128;
     } else {
         const bool priv = c.depth > 0 && priv_fits(*st, mode, rank) &&
                           (double)st->dims[mode] * kPrivCopies <= kPrivThresh * (double)st->nnz;

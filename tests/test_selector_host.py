@@ -55,7 +55,7 @@ def test_candidates_three_modes():
     assert len(c1) == 12
     for c in c1:
         if c["depth"] == 0:
-            assert c["kernel"] == "row" and c["variant"] == "auto" and c["tile_nnz"] in (32, 64, 256)
+            assert c["kernel"] == "row" and c["variant"] == "auto" and c["tile_nnz"] in (32, 128, 512)
         else:
             assert c["kernel"] == "lane" and c["variant"] == "atomic" and c["tile_nnz"] in (64, 256, 1024)
     # mode 0 is the shortest: "first" equals "asc" and is listed once; 100 x 16 x 4 B fits LDS
