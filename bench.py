@@ -84,6 +84,65 @@ def run_steps(cpd, x, R, iters, steps, warmup, precision, seed=7):
     return wall, runs
 
 
+def gather_bytes(counts, R, precision):
+    """Factor-row bytes a root-level MTTKRP reads through the caches: one
+    padded row per leaf and per internal node (the ALS layout)."""
+    nm = len(counts)
+    if precision == "fp32":
+        width, esz = next(w for w in (8, 16, 32, 36, 64) if w >= R), 4
+    else:
+        width, esz = next(w for w in (16, 16, 32, 40, 64) if w >= R), 2
+    return (counts[nm - 1] + sum(counts[l] for l in range(1, nm - 1))) * width * esz
+
+
+def time_mttkrp(cpd, csf, facs, mode, R, variant, reps=10):
+    import statistics as st
+
+    import torch
+    out = torch.empty((csf.dims[mode], R), dtype=torch.float32, device="cuda")
+    cpd.mttkrp(csf, facs, mode, out=out, rank=R, variant=variant)
+    ts = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        cpd.mttkrp(csf, facs, mode, out=out, rank=R, variant=variant)
+        e1.record()
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    return st.median(ts)
+
+
+def single_tree(cpd, x, R):
+    """Every mode's MTTKRP on one tree in ascending-length order: the root,
+    internal and leaf kernels, each conflict-handling variant that applies,
+    timed around the whole call (median of 10)."""
+    import torch
+    c = cpd.csf_build(x.inds, x.vals, x.dims, None)
+    ld = next(w for w in (8, 16, 32, 36, 64) if w >= R)
+    g = torch.Generator(device="cuda").manual_seed(3)
+    facs = []
+    for d in x.dims:
+        f = torch.zeros((d, ld), dtype=torch.float32, device="cuda")
+        f[:, :R] = torch.rand((d, R), device="cuda", generator=g)
+        facs.append(f)
+    res = dict(order=c.order, counts=c.counts, modes=[])
+    nnz = c.counts[-1]
+    for depth, mode in enumerate(c.order):
+        level = "root" if depth == 0 else ("leaf" if depth == x.nmodes - 1 else "internal")
+        b = alg_bytes(c.counts, x.dims, mode, R)
+        variants = ["auto"] if depth == 0 else ["atomic"]
+        if depth > 0 and x.dims[mode] * R * 4 <= 64 * 1024:
+            variants.append("private")
+        for v in variants:
+            ms = time_mttkrp(cpd, c, facs, mode, R, v)
+            res["modes"].append(dict(mode=mode, level=level, variant=v, ms=round(ms, 4),
+                                     ns_per_nnz=round(ms * 1e6 / nnz, 4), alg_bytes=b,
+                                     roofline_frac=round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)))
+    c.free()
+    return res
+
+
 def summarize(runs, nm):
     import statistics as st
     csf = st.mean(r["timing_ms"]["csf_build"] for r in runs)
@@ -91,6 +150,28 @@ def summarize(runs, nm):
     iters = [row[nm] for r in runs for row in r["timing_ms"]["per_iter"][1:]]
     mt = [[row[n] for r in runs for row in r["timing_ms"]["per_iter"][1:]] for n in range(nm)]
     return dict(csf_build_ms=csf, iter_ms=st.mean(iters), mttkrp_ms=[st.mean(v) for v in mt])
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_mttkrp_root_nell2_r35_fp32.json")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1812_05961_amd", "csrc", "mttkrp_root.hip")
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch (read + write, averaged over the three modes) of
+    the root kernel from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
+    counters, scaled by the copy calibration; None when the counters were
+    taken on another version of the kernel source or another kernel."""
+    import hashlib
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+        with open(KERNEL_SOURCE, "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+    except OSError:
+        return None
+    if t.get("source_sha256") != sha or t.get("kernel") != kernel:
+        return None
+    return int(t["hbm_bytes_per_launch"])
 
 
 def cpu_baseline(x, R, sample_nnz, seed=11):
@@ -169,8 +250,13 @@ def main():
     achieved = avg_bytes / (avg_ms * 1e-3) / 1e9
     kernel = root_kernel_name(x.nmodes, R, args.precision)
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None, kernel=kernel,
+                    frac=round(achieved / HBM_PEAK_GBS, 4),
+                    traffic=measured_traffic(kernel) if args.precision == "fp32" else None, kernel=kernel,
                     bytes_per_launch=int(avg_bytes), avg_launch_us=round(avg_ms * 1e3, 2))
+
+    gathered = [gather_bytes(counts[m], R, args.precision) for m in range(x.nmodes)]
+    one_tree = single_tree(cpd, x, R)
+    log("single-tree timings done")
 
     ms_per_step = wall / args.steps * 1e3
     out = dict(
@@ -191,7 +277,10 @@ def main():
                        mttkrp_alg_bytes=bytes_mode,
                        mttkrp_roofline_frac=[round(b / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
                                              for b, t in zip(bytes_mode, s["mttkrp_ms"])],
-                       fit=runs[-1]["fit"]),
+                       mttkrp_gather_bytes=gathered,
+                       mttkrp_gather_inclusive_gbs=[round((b + gb) / (t * 1e-3) / 1e9, 1)
+                                                    for b, gb, t in zip(bytes_mode, gathered, s["mttkrp_ms"])],
+                       fit=runs[-1]["fit"], single_tree=one_tree),
         roofline=roofline,
     )
     log("main line ready; value %.5f s/iter" % out["value"])

@@ -338,6 +338,9 @@ cpd_status launch_root(int N, bool bf16, int RP, const int32_t *const *fids, con
                        int64_t ld, const int32_t *starts, int64_t ntiles, int32_t T, float *Y, int64_t ldo, int R,
                        hipStream_t s);
 
+// Lanes the root kernel gives one leaf for a padded rank RP.
+int root_lanes_per_leaf(int RP, bool bf16);
+
 // Internal entry (also used by the ALS driver).
 cpd_status mttkrp(cpd_csf_s *c, const void *const *factors, int32_t ld, int32_t R, int32_t mode,
                   float *Y, int32_t ldo, const cpd_mttkrp_opts *opts, hipStream_t s, hipEvent_t ev0,
@@ -389,7 +392,14 @@ cpd_status mttkrp(cpd_csf_s *c, const void *const *factors, int32_t ld, int32_t 
         CPD_LAUNCH_CHECK();
     }
     if (kernel == CPD_KERNEL_ROW && d == 0) {
-        const int32_t T = o.tile_nnz ? o.tile_nnz : 128;
+        // default tile: 128 leaves per group run, halved (down to 32) while
+        // the tile steps would not give every resident wave two of them
+        int32_t T = o.tile_nnz;
+        if (!T) {
+            const int64_t groups = 64 / root_lanes_per_leaf(RP, bf16), waves = 256 * 16;
+            T = 128;
+            while (T > 32 && cv.nleaves < groups * T * 2 * waves) T /= 2;
+        }
 
         const int32_t *starts;
         int64_t ns;

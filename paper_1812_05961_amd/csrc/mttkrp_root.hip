@@ -403,6 +403,11 @@ static cpd_status launch_root_n(int RP, const CsfView &cv, const FacView &fv, co
     }
 }
 
+int root_lanes_per_leaf(int RP, bool bf16) {
+    if (!bf16) return RP / Chunk<float>::W;
+    return RP <= BF16_NARROW_MAX ? RP / Chunk<bf16x4>::W : RP / Chunk<uint16_t>::W;
+}
+
 cpd_status launch_root(int N, bool bf16, int RP, const int32_t *const *fids, const int32_t *const *fptr,
                        const float *vals, const int32_t *leafw, const int32_t *leaf_perm, const int32_t *const *uprow,
                        const int64_t *counts, const int64_t *dims_by_level, const void *const *fac_by_level,

@@ -136,3 +136,39 @@ def test_selector_rejects_bad_requests():
         with pytest.raises(cpd.CpdError) as e:
             cpd.select_candidates(st, rank, mode)
         assert e.value.status == cpd.CPD_EINVAL
+
+
+def test_committed_network_matches_the_library_shape():
+    import json
+    import os
+
+    from paper_1812_05961_amd import selector_train as st
+    with open(st.PARAMS_PATH) as f:
+        d = json.load(f)
+    assert d["n_in"] == cpd.SEL_NFEAT and 1 <= d["hidden"] <= 64
+    p = np.asarray(d["params"], dtype=np.float64)
+    assert p.size == cpd.mlp_param_count(d["n_in"], d["hidden"]) and np.isfinite(p).all()
+    # trained on the first 1600 corpus tensors, evaluated on the other 400
+    rep = d["report"]
+    assert rep["train_tensors"] >= 1500 and rep["heldout_tensors"] >= 350
+
+
+def test_committed_corpus_is_consistent():
+    import glob
+    import gzip
+    import json
+    import os
+
+    from paper_1812_05961_amd import selector_train as st
+    files = sorted(glob.glob(os.path.join(os.path.dirname(st.PARAMS_PATH), "selector_corpus", "*.jsonl.gz")))
+    assert files
+    with gzip.open(files[0], "rt") as f:
+        recs = [json.loads(next(f)) for _ in range(20)]
+    for r in recs:
+        s = r["stats"]
+        stt = cpd.make_stats(s["dims"], s["nnz"], s["top1"], s["distinct"], s["alpha"], s["sample"])
+        # the candidates recorded are the ones the library enumerates today
+        now = [c.as_dict(s["nmodes"]) for c in cpd.select_candidates(stt, r["rank"], r["mode"])]
+        assert now == r["cands"]
+        assert now[r["heur"]] == cpd.select_heuristic(stt, r["rank"], r["mode"]).as_dict(s["nmodes"])
+        assert len(r["ms"]) == len(now) and min(r["ms"]) > 0
