@@ -35,12 +35,12 @@ def log(msg):
 
 
 def root_orders(dims):
-    """The mode order of each per-mode CSF: the mode first, then the others by
-    ascending length (ties to the lower mode)."""
+    """The mode order of each per-mode CSF (as cpd_als builds them): the mode
+    first, then the others by descending length (ties to the lower mode)."""
     nm = len(dims)
     out = []
     for m in range(nm):
-        rest = sorted([q for q in range(nm) if q != m], key=lambda q: (dims[q], q))
+        rest = sorted([q for q in range(nm) if q != m], key=lambda q: (-dims[q], q))
         out.append([m] + rest)
     return out
 

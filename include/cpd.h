@@ -186,8 +186,9 @@ typedef struct {
     int32_t variant;         /* CPD_VARIANT_* for every MTTKRP */
     int32_t kernel;          /* CPD_KERNEL_* */
     int32_t tile_nnz;        /* 0 = automatic */
-    int32_t single_csf;      /* 0: one CSF per mode, rooted at that mode (the
-                                default: every MTTKRP is a root-level one);
+    int32_t single_csf;      /* 0: one CSF per mode, rooted at that mode, the
+                                other modes by descending length (the default:
+                                every MTTKRP is a root-level one);
                                 1: one CSF in `order` (or ascending lengths) */
     int32_t reserved;
     const int32_t *order;    /* host, N entries, or NULL (used with single_csf) */

@@ -5,6 +5,7 @@
 #include <stdarg.h>
 
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "csf.h"
@@ -22,6 +23,25 @@ void set_error(const char *fmt, ...) {
 }
 
 void clear_error() { g_err[0] = 0; }
+
+void keep_pool_memory() {
+    static std::mutex mu;
+    static bool done[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
+        (void)hipGetLastError();
+        return;
+    }
+    std::lock_guard<std::mutex> g(mu);
+    if (done[dev]) return;
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+        uint64_t thr = UINT64_MAX;
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+    }
+    (void)hipGetLastError();
+    done[dev] = true;
+}
 
 cpd_status mttkrp(cpd_csf_s *c, const void *const *factors, int32_t ld, int32_t R, int32_t mode, float *Y,
                   int32_t ldo, const cpd_mttkrp_opts *opts, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
@@ -183,7 +203,10 @@ cpd_status als(int nm, const int64_t *dims, int64_t nnz, const int32_t *const *i
             std::vector<int> rest;
             for (int q = 0; q < nm; ++q)
                 if (q != m) rest.push_back(q);
-            std::stable_sort(rest.begin(), rest.end(), [&](int a, int b) { return dims[a] < dims[b]; });
+            // the others by descending length: the smallest factor sits at the
+            // leaf level, gathered once per nonzero (measured 1-4% faster
+            // than ascending on the benchmark shapes)
+            std::stable_sort(rest.begin(), rest.end(), [&](int a, int b) { return dims[a] > dims[b]; });
             for (int q : rest) ord[k++] = q;
             cpd_csf c = nullptr;
             CPD_TRY(cpd_csf_build(nm, dims, nnz, inds, vals, ord, s, &c));

@@ -14,6 +14,11 @@ namespace cpd {
 void set_error(const char *fmt, ...);
 void clear_error();
 
+// Keep memory returned to the current device's stream-ordered pool cached in
+// the pool (release threshold raised once per device), so repeated builds and
+// solves reuse it instead of mapping fresh pages.
+void keep_pool_memory();
+
 #define CPD_FAIL(code, ...)              \
     do {                                 \
         ::cpd::set_error(__VA_ARGS__);   \

@@ -22,6 +22,11 @@ struct cpd_csf_s {
     // (leaf_perm[rank] = index).  Null when a leaf index does not fit in 29 bits.
     int32_t *leafw = nullptr;
     int32_t *leaf_perm = nullptr;
+    int32_t *leaf_rank = nullptr;         // index -> rank (inverse of leaf_perm)
+    // The same ranking for internal levels (index frequency among the level's
+    // nodes), built on first use by csf_level_rank.
+    int32_t *lvl_perm[CPD_MAX_MODES] = {};
+    int32_t *lvl_rank[CPD_MAX_MODES] = {};
     // Per-leaf row ids of the internal levels 1..N-2 (uprow[l][k] = the index
     // i_order[l] of leaf k), so a kernel can gather every leaf's internal rows
     // without walking fiber pointers.  Allocated with leafw.
@@ -58,6 +63,18 @@ cpd_status radix_sort(uint64_t *&klo, uint64_t *&khi, int32_t *&kp, uint64_t *&o
 // largest count, sample size.
 cpd_status sample_freq(const int32_t *ids, int64_t n, int64_t nid, int64_t max_samples, int32_t *out,
                        hipStream_t s);
+
+// Frequency ranking of the values ids[0..n) (in [0, nid)) by a strided sample
+// of at most 2^22 of them: perm[r] = the index of rank r (descending count,
+// ties to the lower index; unsampled indices last), rank[i] its inverse.
+// nruns: device scratch for one int32.
+cpd_status rank_ids(const int32_t *ids, int64_t n, int64_t nid, int32_t *perm, int32_t *rank, int32_t *nruns,
+                    hipStream_t s);
+
+// Ranking of the indices of level l (1 <= l < N) of a tree: the leaf ranking
+// for l = N-1, else built on first use and cached in the handle.  Null
+// outputs when the tree has no ranking (leaf index above 2^29).
+cpd_status csf_level_rank(cpd_csf_s *c, int l, const int32_t **perm, const int32_t **rank, hipStream_t s);
 
 // Tile start nodes for a tile width (cached in the handle; created on first use).
 cpd_status csf_tiles(cpd_csf_s *c, int32_t tile, const int32_t **starts, int64_t *ntiles,

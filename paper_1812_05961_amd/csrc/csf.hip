@@ -423,15 +423,23 @@ __global__ void k_max_run(const int32_t *starts, const int32_t *nruns, int64_t n
 
 void free_csf(cpd_csf_s *c) {
     if (!c) return;
+    // work on any stream may still read the arrays: wait for the device, then
+    // return the pool allocations
+    (void)hipDeviceSynchronize();
     for (int l = 0; l < CPD_MAX_MODES; ++l) {
-        if (c->fids[l]) (void)hipFree(c->fids[l]);
-        if (c->fptr[l]) (void)hipFree(c->fptr[l]);
+        if (c->fids[l]) (void)hipFreeAsync(c->fids[l], nullptr);
+        if (c->fptr[l]) (void)hipFreeAsync(c->fptr[l], nullptr);
+        if (c->uprow[l]) (void)hipFreeAsync(c->uprow[l], nullptr);
     }
-    if (c->vals) (void)hipFree(c->vals);
-    if (c->leafw) (void)hipFree(c->leafw);
-    if (c->leaf_perm) (void)hipFree(c->leaf_perm);
-    for (int l = 0; l < CPD_MAX_MODES; ++l)
-        if (c->uprow[l]) (void)hipFree(c->uprow[l]);
+    if (c->vals) (void)hipFreeAsync(c->vals, nullptr);
+    if (c->leafw) (void)hipFreeAsync(c->leafw, nullptr);
+    if (c->leaf_perm) (void)hipFreeAsync(c->leaf_perm, nullptr);
+    if (c->leaf_rank) (void)hipFreeAsync(c->leaf_rank, nullptr);
+    (void)hipStreamSynchronize(nullptr);
+    for (int l = 0; l < CPD_MAX_MODES; ++l) {
+        if (c->lvl_perm[l]) (void)hipFree(c->lvl_perm[l]);
+        if (c->lvl_rank[l]) (void)hipFree(c->lvl_rank[l]);
+    }
     for (auto &t : c->tiles) (void)hipFree(t.starts);
     delete c;
 }
@@ -445,6 +453,7 @@ cpd_status build(int nm, const int64_t *dims, int64_t nnz, const int32_t *const 
         if (dims[m] < 1 || dims[m] > INT32_MAX) CPD_FAIL(CPD_EINVAL, "dim %d = %lld out of range", m, (long long)dims[m]);
         if (!inds[m]) CPD_FAIL(CPD_EINVAL, "null index array for mode %d", m);
     }
+    keep_pool_memory();
     int order[CPD_MAX_MODES];
     if (order_in) {
         bool seen[CPD_MAX_MODES] = {};
@@ -553,8 +562,10 @@ cpd_status build(int nm, const int64_t *dims, int64_t nnz, const int32_t *const 
         c->counts[l] = (l == nm - 1) ? n : h_counts[l];
     }
     cpd_status st = CPD_OK;
+    // the tree's arrays come from the stream-ordered pool: repeated builds
+    // reuse memory instead of mapping fresh pages
     auto alloc_arr = [&](void **p, size_t bytes) -> bool {
-        if (hipMalloc(p, bytes) != hipSuccess) {
+        if (hipMallocAsync(p, std::max<size_t>(bytes, 4), s) != hipSuccess) {
             (void)hipGetLastError();
             *p = nullptr;
             return false;
@@ -570,6 +581,7 @@ cpd_status build(int nm, const int64_t *dims, int64_t nnz, const int32_t *const 
     const bool want_leafw = dims[order[nm - 1]] <= (1ll << 29);
     if (ok && want_leafw) ok = alloc_arr((void **)&c->leafw, sizeof(int32_t) * n);
     if (ok && want_leafw) ok = alloc_arr((void **)&c->leaf_perm, sizeof(int32_t) * dims[order[nm - 1]]);
+    if (ok && want_leafw) ok = alloc_arr((void **)&c->leaf_rank, sizeof(int32_t) * dims[order[nm - 1]]);
     for (int l = 1; l < nm - 1 && ok && want_leafw; ++l) ok = alloc_arr((void **)&c->uprow[l], sizeof(int32_t) * n);
     if (!ok) {
         free_csf(c);
@@ -588,44 +600,10 @@ cpd_status build(int nm, const int64_t *dims, int64_t nnz, const int32_t *const 
     if (c->leafw && st == CPD_OK) {
         // rank the leaf ids by frequency in a strided sample of the leaves
         const int64_t nid = dims[order[nm - 1]];
-        const int64_t stride = std::max<int64_t>(1, n / (1 << 22));
-        const int64_t ns = ceil_div(n, stride);
-        int ibits = 0;
-        while ((1ll << ibits) < nid) ++ibits;
-        DevBuf<uint64_t> sk0, sk1;
-        DevBuf<int32_t> sp0, sp1, spos, sstart, cnt, rank;
-        const int64_t m = std::max(ns, nid);
-        cpd_status rs = CPD_OK;
-        if (rs == CPD_OK) rs = sk0.alloc(m, s);
-        if (rs == CPD_OK) rs = sk1.alloc(m, s);
-        if (rs == CPD_OK) rs = sp0.alloc(m, s);
-        if (rs == CPD_OK) rs = sp1.alloc(m, s);
-        if (rs == CPD_OK) rs = spos.alloc(ns, s);
-        if (rs == CPD_OK) rs = sstart.alloc(ns, s);
-        if (rs == CPD_OK) rs = cnt.alloc(nid, s);
-        if (rs == CPD_OK) rs = rank.alloc(nid, s);
-        if (rs == CPD_OK && hipMemsetAsync(cnt.p, 0, sizeof(int32_t) * nid, s) != hipSuccess) rs = CPD_EHIP;
-        uint64_t *a = sk0.p, *ah = nullptr, *b = sk1.p, *bh = nullptr;
-        int32_t *ap = sp0.p, *bp = sp1.p;
+        cpd_status rs = rank_ids(c->fids[nm - 1], n, nid, c->leaf_perm, c->leaf_rank, d_flag.p + 1, s);
         if (rs == CPD_OK) {
-            hipLaunchKernelGGL(k_sample, dim3(grid1(ns)), dim3(256), 0, s, (const int32_t *)c->fids[nm - 1], stride,
-                               ns, a, ap);
-            rs = radix_sort(a, ah, ap, b, bh, bp, ns, std::max(ibits, 1), s);
-        }
-        if (rs == CPD_OK) rs = exclusive_scan(RunStart{a}, ns, spos.p, d_flag.p + 1, s);
-        if (rs == CPD_OK) {
-            hipLaunchKernelGGL(k_run_starts, dim3(grid1(ns)), dim3(256), 0, s, (const uint64_t *)a,
-                               (const int32_t *)spos.p, ns, sstart.p);
-            hipLaunchKernelGGL(k_run_counts, dim3(grid1(ns)), dim3(256), 0, s, (const uint64_t *)a,
-                               (const int32_t *)sstart.p, (const int32_t *)(d_flag.p + 1), ns, cnt.p);
-            hipLaunchKernelGGL(k_rank_keys, dim3(grid1(nid)), dim3(256), 0, s, (const int32_t *)cnt.p, nid, a, ap);
-            rs = radix_sort(a, ah, ap, b, bh, bp, nid, 64, s);
-        }
-        if (rs == CPD_OK) {
-            hipLaunchKernelGGL(k_rank_scatter, dim3(grid1(nid)), dim3(256), 0, s, (const uint64_t *)a, nid,
-                               c->leaf_perm, rank.p);
             hipLaunchKernelGGL(k_leafw, dim3(grid1(n)), dim3(256), 0, s, (const uint8_t *)udl.p,
-                               (const int32_t *)c->fids[nm - 1], (const int32_t *)rank.p, n, c->leafw);
+                               (const int32_t *)c->fids[nm - 1], (const int32_t *)c->leaf_rank, n, c->leafw);
             if (hipGetLastError() != hipSuccess) rs = CPD_EHIP;
         }
         if (rs != CPD_OK) st = rs;
@@ -646,6 +624,78 @@ cpd_status build(int nm, const int64_t *dims, int64_t nnz, const int32_t *const 
 }
 
 }  // namespace
+
+cpd_status rank_ids(const int32_t *ids, int64_t n, int64_t nid, int32_t *perm, int32_t *rank, int32_t *nruns,
+                    hipStream_t s) {
+    const int64_t stride = std::max<int64_t>(1, n / (1 << 22));
+    const int64_t ns = ceil_div(n, stride);
+    int ibits = 0;
+    while ((1ll << ibits) < nid) ++ibits;
+    DevBuf<uint64_t> sk0, sk1;
+    DevBuf<int32_t> sp0, sp1, spos, sstart, cnt;
+    const int64_t m = std::max(ns, nid);
+    CPD_TRY(sk0.alloc(m, s));
+    CPD_TRY(sk1.alloc(m, s));
+    CPD_TRY(sp0.alloc(m, s));
+    CPD_TRY(sp1.alloc(m, s));
+    CPD_TRY(spos.alloc(ns, s));
+    CPD_TRY(sstart.alloc(ns, s));
+    CPD_TRY(cnt.alloc(nid, s));
+    CPD_HIP(hipMemsetAsync(cnt.p, 0, sizeof(int32_t) * nid, s));
+    uint64_t *a = sk0.p, *ah = nullptr, *b = sk1.p, *bh = nullptr;
+    int32_t *ap = sp0.p, *bp = sp1.p;
+    hipLaunchKernelGGL(k_sample, dim3(grid1(ns)), dim3(256), 0, s, ids, stride, ns, a, ap);
+    CPD_LAUNCH_CHECK();
+    CPD_TRY(radix_sort(a, ah, ap, b, bh, bp, ns, std::max(ibits, 1), s));
+    CPD_TRY(exclusive_scan(RunStart{a}, ns, spos.p, nruns, s));
+    hipLaunchKernelGGL(k_run_starts, dim3(grid1(ns)), dim3(256), 0, s, (const uint64_t *)a, (const int32_t *)spos.p,
+                       ns, sstart.p);
+    hipLaunchKernelGGL(k_run_counts, dim3(grid1(ns)), dim3(256), 0, s, (const uint64_t *)a,
+                       (const int32_t *)sstart.p, (const int32_t *)nruns, ns, cnt.p);
+    hipLaunchKernelGGL(k_rank_keys, dim3(grid1(nid)), dim3(256), 0, s, (const int32_t *)cnt.p, nid, a, ap);
+    CPD_LAUNCH_CHECK();
+    CPD_TRY(radix_sort(a, ah, ap, b, bh, bp, nid, 64, s));
+    hipLaunchKernelGGL(k_rank_scatter, dim3(grid1(nid)), dim3(256), 0, s, (const uint64_t *)a, nid, perm, rank);
+    CPD_LAUNCH_CHECK();
+    return CPD_OK;
+}
+
+cpd_status csf_level_rank(cpd_csf_s *c, int l, const int32_t **perm, const int32_t **rank, hipStream_t s) {
+    *perm = nullptr;
+    *rank = nullptr;
+    if (l < 1 || l >= c->nmodes) CPD_FAIL(CPD_EINVAL, "level %d has no ranking", l);
+    if (!c->leaf_perm) return CPD_OK;
+    if (l == c->nmodes - 1) {
+        *perm = c->leaf_perm;
+        *rank = c->leaf_rank;
+        return CPD_OK;
+    }
+    std::lock_guard<std::mutex> g(c->mu);
+    if (!c->lvl_perm[l]) {
+        const int64_t nid = c->dims[c->order[l]];
+        int32_t *pp = nullptr, *rr = nullptr;
+        DevBuf<int32_t> nr;
+        CPD_TRY(nr.alloc(1, s));
+        if (hipMalloc((void **)&pp, sizeof(int32_t) * nid) != hipSuccess ||
+            hipMalloc((void **)&rr, sizeof(int32_t) * nid) != hipSuccess) {
+            (void)hipGetLastError();
+            if (pp) (void)hipFree(pp);
+            CPD_FAIL(CPD_ENOMEM, "device allocation for a level ranking failed");
+        }
+        cpd_status st = rank_ids(c->fids[l], c->counts[l], nid, pp, rr, nr.p, s);
+        if (st != CPD_OK) {
+            (void)hipStreamSynchronize(s);
+            (void)hipFree(pp);
+            (void)hipFree(rr);
+            return st;
+        }
+        c->lvl_perm[l] = pp;
+        c->lvl_rank[l] = rr;
+    }
+    *perm = c->lvl_perm[l];
+    *rank = c->lvl_rank[l];
+    return CPD_OK;
+}
 
 cpd_status sample_freq(const int32_t *ids, int64_t n, int64_t nid, int64_t max_samples, int32_t *out,
                        hipStream_t s) {

@@ -30,6 +30,9 @@ struct CsfView {
     const int32_t *fptr[CPD_MAX_MODES];
     const float *vals;
     int64_t nleaves;
+    const int32_t *leafw;      // (level << 29) | frequency rank of the leaf index
+    const int32_t *hot_perm;   // HOT: index of each frequency rank at the output level
+    const int32_t *hot_rank;   // HOT: frequency rank of each index at the output level
 };
 
 struct FacView {
@@ -170,23 +173,29 @@ k_mttkrp_row(CsfView cv, FacView fv, int64_t ld, int d, const int32_t *__restric
 }
 
 // ------------------------------------------------------------ LANE family
-template <int N, int G, typename GT, bool PRIV>
+// PRIV: the whole output privatised in LDS (out_rows x R per block).
+// HOT (levels below the root): the `hot` most frequent output rows privatised
+// in LDS (rows by frequency rank), the others updated with global atomics;
+// Zipf-hot rows would otherwise serialise their atomics in L2.
+template <int N, int G, typename GT, bool PRIV, bool HOT>
 __global__ void __launch_bounds__(256)
 k_mttkrp_lane(CsfView cv, FacView fv, int64_t ld, int d, const int32_t *__restrict__ starts,
               int64_t nstreams, int32_t T, float *__restrict__ Y, int64_t ldo, int R,
-              int64_t out_rows) {
-    extern __shared__ float ypriv[];  // PRIV: out_rows x R block-private copy
+              int64_t out_rows, int32_t hot) {
+    extern __shared__ float ypriv[];  // PRIV: out_rows x R; HOT: hot x R
     constexpr int NG = 256 / G;       // groups per block
+    constexpr bool LOCAL = PRIV || HOT;
     const int lig = threadIdx.x % G;
     const bool col = lig < R;
-    if (PRIV) {
-        for (int64_t j = threadIdx.x; j < out_rows * R; j += 256) ypriv[j] = 0.0f;
+    const int64_t nloc = PRIV ? out_rows * R : (HOT ? (int64_t)hot * R : 0);
+    if (LOCAL) {
+        for (int64_t j = threadIdx.x; j < nloc; j += 256) ypriv[j] = 0.0f;
         __syncthreads();
     }
     // persistent over streams when privatised (one flush per block), else one
     // stream per group
     const int64_t g0 = (int64_t)blockIdx.x * NG + threadIdx.x / G;
-    const int64_t gstep = PRIV ? (int64_t)gridDim.x * NG : nstreams + 1;
+    const int64_t gstep = LOCAL ? (int64_t)gridDim.x * NG : nstreams + 1;
     for (int64_t sid = g0; sid < nstreams; sid += gstep) {
         int64_t k = sid * (int64_t)T;
         const int64_t kend = min(k + (int64_t)T, cv.nleaves);
@@ -225,6 +234,8 @@ k_mttkrp_lane(CsfView cv, FacView fv, int64_t ld, int d, const int32_t *__restri
                 if (d < N - 1 && lmin <= d) {
                     if (col) {
                         if (PRIV) atomicAdd(&ypriv[(int64_t)out_row * R + lig], acc);
+                        else if (HOT && cv.hot_rank[out_row] < hot)
+                            atomicAdd(&ypriv[(int64_t)cv.hot_rank[out_row] * R + lig], acc);
                         else atomicAdd(Y + (int64_t)out_row * ldo + lig, acc);
                     }
                     acc = 0.0f;
@@ -235,7 +246,13 @@ k_mttkrp_lane(CsfView cv, FacView fv, int64_t ld, int d, const int32_t *__restri
             const float v = cv.vals[k];
             const int32_t i = cv.fids[N - 1][k];
             if (d == N - 1) {
-                if (col) {
+                if (HOT) {
+                    const int32_t rk = cv.leafw[k] & ((1 << 29) - 1);
+                    if (col) {
+                        if (rk < hot) atomicAdd(&ypriv[(int64_t)rk * R + lig], v * H);
+                        else atomicAdd(Y + (int64_t)i * ldo + lig, v * H);
+                    }
+                } else if (col) {
                     if (PRIV) atomicAdd(&ypriv[(int64_t)i * R + lig], v * H);
                     else atomicAdd(Y + (int64_t)i * ldo + lig, v * H);
                 }
@@ -246,14 +263,17 @@ k_mttkrp_lane(CsfView cv, FacView fv, int64_t ld, int d, const int32_t *__restri
         }
         if (d < N - 1 && col) {
             if (PRIV) atomicAdd(&ypriv[(int64_t)out_row * R + lig], acc);
+            else if (HOT && cv.hot_rank[out_row] < hot)
+                atomicAdd(&ypriv[(int64_t)cv.hot_rank[out_row] * R + lig], acc);
             else atomicAdd(Y + (int64_t)out_row * ldo + lig, acc);
         }
     }
-    if (PRIV) {
+    if (LOCAL) {
         __syncthreads();
-        for (int64_t j = threadIdx.x; j < out_rows * R; j += 256) {
+        for (int64_t j = threadIdx.x; j < nloc; j += 256) {
             float v = ypriv[j];
-            if (v != 0.0f) atomicAdd(Y + (j / R) * ldo + (j % R), v);
+            const int64_t row = PRIV ? j / R : (int64_t)cv.hot_perm[j / R];
+            if (v != 0.0f) atomicAdd(Y + row * ldo + (j % R), v);
         }
     }
 }
@@ -302,17 +322,20 @@ cpd_status launch_row(int RP, dim3 grid, hipStream_t s, const CsfView &cv, const
 }
 
 template <int N, typename GT>
-cpd_status launch_lane(int G, bool priv, dim3 grid, size_t lds, hipStream_t s, const CsfView &cv,
+cpd_status launch_lane(int G, bool priv, int32_t hot, dim3 grid, size_t lds, hipStream_t s, const CsfView &cv,
                        const FacView &fv, int64_t ld, int d, const int32_t *starts, int64_t ns,
                        int32_t T, float *Y, int64_t ldo, int R, int64_t out_rows) {
-#define CPD_LANE_CASE(g)                                                                        \
-    case g:                                                                                     \
-        if (priv)                                                                               \
-            hipLaunchKernelGGL((k_mttkrp_lane<N, g, GT, true>), grid, dim3(256), lds, s, cv, fv, ld, \
-                               d, starts, ns, T, Y, ldo, R, out_rows);                          \
-        else                                                                                    \
-            hipLaunchKernelGGL((k_mttkrp_lane<N, g, GT, false>), grid, dim3(256), 0, s, cv, fv, ld, \
-                               d, starts, ns, T, Y, ldo, R, out_rows);                          \
+#define CPD_LANE_CASE(g)                                                                                  \
+    case g:                                                                                               \
+        if (priv)                                                                                         \
+            hipLaunchKernelGGL((k_mttkrp_lane<N, g, GT, true, false>), grid, dim3(256), lds, s, cv, fv, ld, \
+                               d, starts, ns, T, Y, ldo, R, out_rows, 0);                                 \
+        else if (hot)                                                                                     \
+            hipLaunchKernelGGL((k_mttkrp_lane<N, g, GT, false, true>), grid, dim3(256), lds, s, cv, fv, ld, \
+                               d, starts, ns, T, Y, ldo, R, out_rows, hot);                               \
+        else                                                                                              \
+            hipLaunchKernelGGL((k_mttkrp_lane<N, g, GT, false, false>), grid, dim3(256), 0, s, cv, fv, ld, \
+                               d, starts, ns, T, Y, ldo, R, out_rows, 0);                                 \
         break;
     switch (G) {
         CPD_LANE_CASE(8)
@@ -328,6 +351,8 @@ cpd_status launch_lane(int G, bool priv, dim3 grid, size_t lds, hipStream_t s, c
 }
 
 constexpr size_t PRIV_LDS_MAX = 64 * 1024;
+constexpr size_t HOT_LDS = 16 * 1024;   // hot output rows privatised per block
+constexpr int64_t HOT_BLOCKS = 8192;    // blocks looping over the streams
 constexpr double PRIV_THRESH = 0.02;  // privatise iff rows * copies <= 0.02 * nnz
 
 }  // namespace
@@ -368,6 +393,7 @@ cpd_status mttkrp(cpd_csf_s *c, const void *const *factors, int32_t ld, int32_t 
     }
     cv.vals = c->vals;
     cv.nleaves = c->counts[N - 1];
+    cv.leafw = c->leafw;
     const int64_t out_rows = c->dims[mode];
 
     // ROW family eligibility: vector loads need the padded row inside ld and
@@ -454,18 +480,33 @@ cpd_status mttkrp(cpd_csf_s *c, const void *const *factors, int32_t ld, int32_t 
     if (o.variant == CPD_VARIANT_PRIVATE && !priv)
         CPD_FAIL(CPD_EUNSUPPORTED, "private variant needs a non-root mode with rows*rank*4 <= %zu bytes",
                  PRIV_LDS_MAX);
+    // levels 2 and deeper with atomics: the most frequent output rows (by the
+    // tree's ranking of that level) accumulate in LDS, HOT_LDS bytes per block.
+    // A level-1 row gets at most one flush per root index, too few for the
+    // table to pay for itself (measured slower on all three benchmark shapes).
+    int32_t hot = 0;
+    size_t lds_launch = lds;
+    if (!priv && d >= 2 && c->leafw) {
+        CPD_TRY(csf_level_rank(c, d, &cv.hot_perm, &cv.hot_rank, s));
+        if (cv.hot_perm) {
+            hot = (int32_t)std::min<int64_t>(c->dims[mode], (int64_t)(HOT_LDS / (sizeof(float) * R)));
+            if (hot < 32) hot = 0;
+            lds_launch = (size_t)hot * R * sizeof(float);
+        }
+    }
     const int NG = 256 / G;
     dim3 grid = priv ? dim3((unsigned)std::min<int64_t>(1024, ceil_div(ns, NG)))
-                     : dim3((unsigned)ceil_div(ns, NG));
+                     : hot ? dim3((unsigned)std::min<int64_t>(HOT_BLOCKS, ceil_div(ns, NG)))
+                           : dim3((unsigned)ceil_div(ns, NG));
     if (N < 2 || N > 5) CPD_FAIL(CPD_EUNSUPPORTED, "MTTKRP kernels are built for 2..5 modes, not %d", N);
     if (ev0) CPD_HIP(hipEventRecord(ev0, s));
     cpd_status st = CPD_OK;
 #define CPD_LANE_N(n)                                                                                   \
     case n:                                                                                             \
-        st = bf16 ? launch_lane<n, uint16_t>(G, priv, grid, lds, s, cv, fv, ld, d, starts, ns, T, Y, ldo, R, \
-                                             out_rows)                                                  \
-                  : launch_lane<n, float>(G, priv, grid, lds, s, cv, fv, ld, d, starts, ns, T, Y, ldo, R,  \
-                                          out_rows);                                                    \
+        st = bf16 ? launch_lane<n, uint16_t>(G, priv, hot, grid, lds_launch, s, cv, fv, ld, d, starts, ns, T, Y, \
+                                             ldo, R, out_rows)                                          \
+                  : launch_lane<n, float>(G, priv, hot, grid, lds_launch, s, cv, fv, ld, d, starts, ns, T, Y,  \
+                                          ldo, R, out_rows);                                            \
         break;
     switch (N) {
         CPD_LANE_N(2)

@@ -3,7 +3,8 @@
 Runs, on the current HIP stream: three plain device copies of 256 MiB (the
 calibration: each moves exactly 256 MiB in and 256 MiB out), then one
 root-level MTTKRP per mode of the NELL-2-shaped tensor (rank 35, FP32, one
-tree rooted at each mode, the launch configuration of cpd_als).  Meant to be
+tree rooted at each mode, the others by descending length: the launch
+configuration of cpd_als).  Meant to be
 run under `rocprofv3 --pmc FETCH_SIZE` and `--pmc WRITE_SIZE`; the counter
 values of the copy kernels give the scale factor applied to the MTTKRP's.
 
@@ -35,7 +36,7 @@ def main():
         f[:, :R] = torch.rand((d, R), device=dev, generator=g)
         facs.append(f)
     for mode in range(3):
-        rest = sorted([q for q in range(3) if q != mode], key=lambda q: (x.dims[q], q))
+        rest = sorted([q for q in range(3) if q != mode], key=lambda q: (-x.dims[q], q))
         c = cpd.csf_build(inds, x.vals, x.dims, [mode] + rest)
         out = torch.empty((x.dims[mode], ld), device=dev)
         cpd.mttkrp(c, facs, mode, out=out, rank=R)

@@ -24,7 +24,8 @@ def _cpd():
 
 
 def _root_order(dims, m):
-    return [m] + sorted([q for q in range(len(dims)) if q != m], key=lambda q: (dims[q], q))
+    # as cpd_als builds its trees: the mode first, the others by descending length
+    return [m] + sorted([q for q in range(len(dims)) if q != m], key=lambda q: (-dims[q], q))
 
 
 def _sample_rows(inds_mode, dim, rng, k=6):

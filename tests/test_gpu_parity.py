@@ -355,17 +355,22 @@ def test_als_small3_matches_oracle(single_csf, precision):
 
 
 def test_als_planted_block_recovers():
+    """An exactly rank-8 sparse tensor is recovered (fit -> 1) from at least
+    one of a few random starts.  CP-ALS can crawl through swamps, and the root
+    kernel's few cross-range atomics make the FP32 rounding order vary from run
+    to run, so starts get up to 1500 sweeps."""
     cpd = _cpd()
     t, _ = synth.block_planted()
-    got = None
-    for s in range(3):
+    fits = []
+    for s in range(5):
         init = synth.init_factors(t.dims, 8, 100 + s)
-        got = cpd.als(_dev(t.inds), _dev(t.vals.float()), t.dims, 8, 500, 1e-9,
+        got = cpd.als(_dev(t.inds), _dev(t.vals.float()), t.dims, 8, 1500, 1e-10,
                       init=[a.float().cuda() for a in init])
+        fits.append(got["fit"])
         if got["fit"] >= 1 - 1e-4:
             break
     # FP32 factors: the fit saturates near 1 - (float rounding), not 1 - 1e-6
-    assert got["fit"] >= 1 - 1e-4
+    assert max(fits) >= 1 - 1e-4, fits
 
 
 def test_als_4mode_and_5mode_match_oracle():
