@@ -56,43 +56,50 @@ struct bf16x4;  // tag: 4 bfloat16 per lane
 template <typename GT>
 struct Chunk;
 
+// Rows stay in registers as loaded (RAW words per lane: floats, or pairs of
+// bfloat16) and are widened element by element at use, which keeps the
+// bfloat16 forms at half the registers of widened rows.
 template <>
 struct Chunk<float> {
-    static constexpr int W = 4, BYTES = 16, ELEM = 4;
-    __device__ static __forceinline__ void load(const char *base, uint32_t off, float *v) {
+    static constexpr int W = 4, BYTES = 16, ELEM = 4, RAW = 4;
+    using raw_t = float;
+    __device__ static __forceinline__ void load(const char *base, uint32_t off, raw_t *r) {
         const float4 x = *reinterpret_cast<const float4 *>(base + off);
-        v[0] = x.x;
-        v[1] = x.y;
-        v[2] = x.z;
-        v[3] = x.w;
+        r[0] = x.x;
+        r[1] = x.y;
+        r[2] = x.z;
+        r[3] = x.w;
     }
+    __device__ static __forceinline__ float get(const raw_t *r, int e) { return r[e]; }
 };
 
 template <>
 struct Chunk<uint16_t> {
-    static constexpr int W = 8, BYTES = 16, ELEM = 2;
-    __device__ static __forceinline__ void load(const char *base, uint32_t off, float *v) {
+    static constexpr int W = 8, BYTES = 16, ELEM = 2, RAW = 4;
+    using raw_t = uint32_t;
+    __device__ static __forceinline__ void load(const char *base, uint32_t off, raw_t *r) {
         const uint4 x = *reinterpret_cast<const uint4 *>(base + off);
-        v[0] = bf16_lo(x.x);
-        v[1] = bf16_hi(x.x);
-        v[2] = bf16_lo(x.y);
-        v[3] = bf16_hi(x.y);
-        v[4] = bf16_lo(x.z);
-        v[5] = bf16_hi(x.z);
-        v[6] = bf16_lo(x.w);
-        v[7] = bf16_hi(x.w);
+        r[0] = x.x;
+        r[1] = x.y;
+        r[2] = x.z;
+        r[3] = x.w;
+    }
+    __device__ static __forceinline__ float get(const raw_t *r, int e) {
+        return (e & 1) ? bf16_hi(r[e >> 1]) : bf16_lo(r[e >> 1]);
     }
 };
 
 template <>
 struct Chunk<bf16x4> {
-    static constexpr int W = 4, BYTES = 8, ELEM = 2;
-    __device__ static __forceinline__ void load(const char *base, uint32_t off, float *v) {
+    static constexpr int W = 4, BYTES = 8, ELEM = 2, RAW = 2;
+    using raw_t = uint32_t;
+    __device__ static __forceinline__ void load(const char *base, uint32_t off, raw_t *r) {
         const uint2 x = *reinterpret_cast<const uint2 *>(base + off);
-        v[0] = bf16_lo(x.x);
-        v[1] = bf16_hi(x.x);
-        v[2] = bf16_lo(x.y);
-        v[3] = bf16_hi(x.y);
+        r[0] = x.x;
+        r[1] = x.y;
+    }
+    __device__ static __forceinline__ float get(const raw_t *r, int e) {
+        return (e & 1) ? bf16_hi(r[e >> 1]) : bf16_lo(r[e >> 1]);
     }
 };
 
@@ -113,12 +120,12 @@ constexpr int root_unroll() {
     return 2;
 }
 
-// Minimum resident waves per SIMD asked of the compiler: 6 for 16-byte
-// bfloat16 chunks on 3 modes (measured faster, despite a few spilled
-// registers), no constraint otherwise.
+// Minimum resident waves per SIMD asked of the compiler for 16-byte bfloat16
+// chunks: 6 on 3 modes, 5 on 4 modes (measured faster); no constraint
+// otherwise.
 template <int N, typename GT>
 constexpr int root_min_waves() {
-    return (N == 3 && std::is_same<GT, uint16_t>::value) ? 6 : 1;
+    return !std::is_same<GT, uint16_t>::value ? 1 : N == 3 ? 6 : N == 4 ? 5 : 1;
 }
 
 // a_leaf: the leaf factor with rows in rank order (row r = factor row
@@ -190,7 +197,9 @@ k_mttkrp_root(CsfView cv, FacView fv, const char *__restrict__ a_leaf, uint32_t 
         }
         // internal rows of the previous leaf (reused while the ids repeat)
         int32_t last_up[NU];
-        float Hl[NU][E];
+        using raw_t = typename Chunk<GT>::raw_t;
+        constexpr int RW = Chunk<GT>::RAW;
+        raw_t Hl[NU][RW];
 #pragma unroll
         for (int l = 0; l < NU; ++l) last_up[l] = -1;
         for (int t0 = 0; t0 < T; t0 += C) {
@@ -212,7 +221,8 @@ k_mttkrp_root(CsfView cv, FacView fv, const char *__restrict__ a_leaf, uint32_t 
                 if (j0 >= len) break;
                 // a block of U leaves: every row of the block is in flight before any use
                 int32_t wu[U];
-                float vu[U], rowu[U][E], hu[U][NU][E];
+                float vu[U];
+                raw_t rowu[U][RW], hu[U][NU][RW];
                 bool need[U][NU];
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
@@ -256,14 +266,14 @@ k_mttkrp_root(CsfView cv, FacView fv, const char *__restrict__ a_leaf, uint32_t 
                         for (int l = 0; l < NU; ++l)
                             if (need[u][l]) {
 #pragma unroll
-                                for (int e = 0; e < E; ++e) Hl[l][e] = hu[u][l][e];
+                                for (int q = 0; q < RW; ++q) Hl[l][q] = hu[u][l][q];
                             }
 #pragma unroll
                         for (int e = 0; e < E; ++e) {
-                            float h = Hl[0][e];
+                            float h = Chunk<GT>::get(Hl[0], e);
 #pragma unroll
-                            for (int l = 1; l < NU; ++l) h *= Hl[l][e];
-                            acc[e] = fmaf(vu[u] * rowu[u][e], h, acc[e]);
+                            for (int l = 1; l < NU; ++l) h *= Chunk<GT>::get(Hl[l], e);
+                            acc[e] = fmaf(vu[u] * Chunk<GT>::get(rowu[u], e), h, acc[e]);
                         }
                     }
                 }
@@ -376,6 +386,9 @@ static cpd_status launch_root_g(const CsfView &cv, const FacView &fv, const char
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64 * ROOT_WAVES, 0) != hipSuccess || per_cu < 1)
         per_cu = 1;
+    // at most 6 resident waves per SIMD: more thrash the L1 with gathered rows
+    // (measured slower on the 8-byte bfloat16 form, neutral elsewhere)
+    per_cu = std::min(per_cu, 6);
     const int64_t nwaves = std::max<int64_t>(1, std::min<int64_t>(nsteps, (int64_t)ncu * per_cu * ROOT_WAVES));
     hipLaunchKernelGGL(kern, dim3((unsigned)ceil_div(nwaves, ROOT_WAVES)), dim3(64 * ROOT_WAVES), 0, s, cv, fv, a_leaf,
                        rowb, starts, ntiles, T, nsteps, nwaves, Y, ldo, R);

@@ -355,22 +355,29 @@ def test_als_small3_matches_oracle(single_csf, precision):
 
 
 def test_als_planted_block_recovers():
-    """An exactly rank-8 sparse tensor is recovered (fit -> 1) from at least
-    one of a few random starts.  CP-ALS can crawl through swamps, and the root
-    kernel's few cross-range atomics make the FP32 rounding order vary from run
-    to run, so starts get up to 1500 sweeps."""
+    """An exactly rank-8 sparse tensor is recovered: the FP64 oracle's fit of
+    the model cpd_als returns is 1 to within 1e-4.  The fit cpd_als reports is
+    computed from an FP32 MTTKRP; near fit 1 it is the square root of a
+    difference of nearly equal FP32-rounded terms, so it only agrees with the
+    FP64 fit to the FP32 floor (about 1e-3)."""
     cpd = _cpd()
     t, _ = synth.block_planted()
-    fits = []
-    for s in range(5):
-        init = synth.init_factors(t.dims, 8, 100 + s)
-        got = cpd.als(_dev(t.inds), _dev(t.vals.float()), t.dims, 8, 1500, 1e-10,
+    inds, vals = t.numpy()
+    R = 8
+    best = -1.0
+    for s in range(3):
+        init = synth.init_factors(t.dims, R, 100 + s)
+        got = cpd.als(_dev(t.inds), _dev(t.vals.float()), t.dims, R, 500, 1e-9,
                       init=[a.float().cuda() for a in init])
-        fits.append(got["fit"])
-        if got["fit"] >= 1 - 1e-4:
+        A = [f.cpu().double().numpy() for f in got["factors"]]
+        lam = np.asarray(got["lam"])
+        Y = ocoo.mttkrp(t.dims, inds, vals, A, 2)
+        fit64 = oals.fit_from(ocoo.sumsq(vals), lam, A[2], Y, [oals.gram(a) for a in A])
+        assert abs(got["fit"] - fit64) <= 1e-3, (got["fit"], fit64)
+        best = max(best, fit64)
+        if best >= 1 - 1e-4:
             break
-    # FP32 factors: the fit saturates near 1 - (float rounding), not 1 - 1e-6
-    assert max(fits) >= 1 - 1e-4, fits
+    assert best >= 1 - 1e-4, best
 
 
 def test_als_4mode_and_5mode_match_oracle():
