@@ -112,16 +112,21 @@ struct Events {
     }
 };
 
+// Trees and buffers of one cpd_als call, all used only on its stream: they
+// come from and return to the stream-ordered pool on that stream.
 struct Owned {
+    hipStream_t s;
     std::vector<cpd_csf_s *> csfs;
     std::vector<void *> bufs;
+    explicit Owned(hipStream_t st) : s(st) {}
     ~Owned() {
-        for (auto c : csfs) cpd_csf_free(c);
-        for (auto p : bufs) (void)hipFree(p);
+        for (auto c : csfs) free_csf_on(c, s);
+        for (auto p : bufs) (void)hipFreeAsync(p, s);
+        (void)hipGetLastError();
     }
     template <typename T>
     cpd_status alloc(T **p, size_t count) {
-        if (hipMalloc((void **)p, sizeof(T) * std::max<size_t>(count, 1)) != hipSuccess) {
+        if (hipMallocAsync((void **)p, sizeof(T) * std::max<size_t>(count, 1), s) != hipSuccess) {
             (void)hipGetLastError();
             CPD_FAIL(CPD_ENOMEM, "device allocation of %zu bytes failed", sizeof(T) * count);
         }
@@ -154,7 +159,8 @@ cpd_status als(int nm, const int64_t *dims, int64_t nnz, const int32_t *const *i
     const bool bf16 = o.precision == CPD_BF16_GATHER;
     if (o.precision != CPD_FP32 && !bf16) CPD_FAIL(CPD_EINVAL, "unknown precision %d", o.precision);
 
-    Owned own;
+    keep_pool_memory();
+    Owned own(s);
     Events evs;
     const bool timing = o.timing_ms != nullptr;
     hipEvent_t t_begin = timing ? evs.make() : nullptr;

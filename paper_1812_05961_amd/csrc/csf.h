@@ -76,6 +76,10 @@ cpd_status rank_ids(const int32_t *ids, int64_t n, int64_t nid, int32_t *perm, i
 // outputs when the tree has no ranking (leaf index above 2^29).
 cpd_status csf_level_rank(cpd_csf_s *c, int l, const int32_t **perm, const int32_t **rank, hipStream_t s);
 
+// Free a tree whose every use was ordered on stream s (no device-wide wait):
+// its arrays go back to the stream-ordered pool on s.
+void free_csf_on(cpd_csf_s *c, hipStream_t s);
+
 // Tile start nodes for a tile width (cached in the handle; created on first use).
 cpd_status csf_tiles(cpd_csf_s *c, int32_t tile, const int32_t **starts, int64_t *ntiles,
                      hipStream_t s);

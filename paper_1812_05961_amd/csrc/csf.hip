@@ -421,26 +421,39 @@ __global__ void k_max_run(const int32_t *starts, const int32_t *nruns, int64_t n
     }
 }
 
+// Return every array of the tree to the stream-ordered pool on stream s.
+void release_arrays(cpd_csf_s *c, hipStream_t s) {
+    for (int l = 0; l < CPD_MAX_MODES; ++l) {
+        if (c->fids[l]) (void)hipFreeAsync(c->fids[l], s);
+        if (c->fptr[l]) (void)hipFreeAsync(c->fptr[l], s);
+        if (c->uprow[l]) (void)hipFreeAsync(c->uprow[l], s);
+        if (c->lvl_perm[l]) (void)hipFreeAsync(c->lvl_perm[l], s);
+        if (c->lvl_rank[l]) (void)hipFreeAsync(c->lvl_rank[l], s);
+    }
+    if (c->vals) (void)hipFreeAsync(c->vals, s);
+    if (c->leafw) (void)hipFreeAsync(c->leafw, s);
+    if (c->leaf_perm) (void)hipFreeAsync(c->leaf_perm, s);
+    if (c->leaf_rank) (void)hipFreeAsync(c->leaf_rank, s);
+    for (auto &t : c->tiles) (void)hipFreeAsync(t.starts, s);
+    (void)hipGetLastError();
+}
+
+}  // namespace
+
+void free_csf_on(cpd_csf_s *c, hipStream_t s) {
+    if (!c) return;
+    release_arrays(c, s);
+    delete c;
+}
+
+namespace {
+
 void free_csf(cpd_csf_s *c) {
     if (!c) return;
-    // work on any stream may still read the arrays: wait for the device, then
-    // return the pool allocations
+    // work on any stream may still read the arrays: wait for the device first
     (void)hipDeviceSynchronize();
-    for (int l = 0; l < CPD_MAX_MODES; ++l) {
-        if (c->fids[l]) (void)hipFreeAsync(c->fids[l], nullptr);
-        if (c->fptr[l]) (void)hipFreeAsync(c->fptr[l], nullptr);
-        if (c->uprow[l]) (void)hipFreeAsync(c->uprow[l], nullptr);
-    }
-    if (c->vals) (void)hipFreeAsync(c->vals, nullptr);
-    if (c->leafw) (void)hipFreeAsync(c->leafw, nullptr);
-    if (c->leaf_perm) (void)hipFreeAsync(c->leaf_perm, nullptr);
-    if (c->leaf_rank) (void)hipFreeAsync(c->leaf_rank, nullptr);
+    release_arrays(c, nullptr);
     (void)hipStreamSynchronize(nullptr);
-    for (int l = 0; l < CPD_MAX_MODES; ++l) {
-        if (c->lvl_perm[l]) (void)hipFree(c->lvl_perm[l]);
-        if (c->lvl_rank[l]) (void)hipFree(c->lvl_rank[l]);
-    }
-    for (auto &t : c->tiles) (void)hipFree(t.starts);
     delete c;
 }
 
@@ -676,17 +689,16 @@ cpd_status csf_level_rank(cpd_csf_s *c, int l, const int32_t **perm, const int32
         int32_t *pp = nullptr, *rr = nullptr;
         DevBuf<int32_t> nr;
         CPD_TRY(nr.alloc(1, s));
-        if (hipMalloc((void **)&pp, sizeof(int32_t) * nid) != hipSuccess ||
-            hipMalloc((void **)&rr, sizeof(int32_t) * nid) != hipSuccess) {
+        if (hipMallocAsync((void **)&pp, sizeof(int32_t) * nid, s) != hipSuccess ||
+            hipMallocAsync((void **)&rr, sizeof(int32_t) * nid, s) != hipSuccess) {
             (void)hipGetLastError();
-            if (pp) (void)hipFree(pp);
+            if (pp) (void)hipFreeAsync(pp, s);
             CPD_FAIL(CPD_ENOMEM, "device allocation for a level ranking failed");
         }
         cpd_status st = rank_ids(c->fids[l], c->counts[l], nid, pp, rr, nr.p, s);
         if (st != CPD_OK) {
-            (void)hipStreamSynchronize(s);
-            (void)hipFree(pp);
-            (void)hipFree(rr);
+            (void)hipFreeAsync(pp, s);
+            (void)hipFreeAsync(rr, s);
             return st;
         }
         c->lvl_perm[l] = pp;
@@ -739,7 +751,7 @@ cpd_status csf_tiles(cpd_csf_s *c, int32_t tile, const int32_t **starts, int64_t
     const int64_t nl = c->counts[nm - 1];
     const int64_t nt = ceil_div(nl, tile);
     int32_t *p = nullptr;
-    if (hipMalloc((void **)&p, sizeof(int32_t) * (size_t)std::max<int64_t>(1, (nm - 1) * nt)) != hipSuccess) {
+    if (hipMallocAsync((void **)&p, sizeof(int32_t) * (size_t)std::max<int64_t>(1, (nm - 1) * nt), s) != hipSuccess) {
         (void)hipGetLastError();
         CPD_FAIL(CPD_ENOMEM, "device allocation for the tile table failed");
     }
@@ -750,7 +762,7 @@ cpd_status csf_tiles(cpd_csf_s *c, int32_t tile, const int32_t **starts, int64_t
     }
     hipLaunchKernelGGL(k_tiles, dim3(grid1(nt)), dim3(256), 0, s, fp, nm, nl, tile, nt, p);
     if (hipGetLastError() != hipSuccess) {
-        (void)hipFree(p);
+        (void)hipFreeAsync(p, s);
         CPD_FAIL(CPD_EHIP, "tile kernel launch failed");
     }
     c->tiles.push_back({tile, nt, p});

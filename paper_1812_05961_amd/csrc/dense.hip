@@ -255,13 +255,18 @@ k_make_w(GramSet gs, int nmodes, int mode, int R, double *__restrict__ W, double
     if (tid == 0 && used_pinv) *used_pinv = 1;
 }
 
-// A' = Y W for one row per thread (FP64), with per-block column sums of
-// squares (pass 0) or the scaled write-out (pass 1).
+// A' = Y W (FP64) with v_mfma_f64_16x16x4f64: one wave per 16-row tile,
+// NB = RP/16 column blocks, W zero-padded to RP x RP in LDS.  First operand
+// lane l: Y[row0 + l%16][k0 + l/16]; second: W[k0 + l/16][16 nb + l%16];
+// result register v of lane l: A'[row0 + 4v + l/16][16 nb + l%16].
+// Pass 0 writes per-block column sums of squares, pass 1 the scaled rows
+// (FP32 master and, when asked, the bfloat16 copy).
 template <int RP>
 __global__ void __launch_bounds__(256)
 k_apply_w(const float *__restrict__ Y, int64_t rows, int R, int64_t ldy, const double *__restrict__ Wg,
           const double *__restrict__ lambda, float *__restrict__ A, int64_t lda,
           uint16_t *__restrict__ Ab, int64_t ldb, double *__restrict__ partial, int pass) {
+    constexpr int NB = RP / 16;
     __shared__ double W[RP * RP];
     __shared__ double red[4][RP];
     for (int t = threadIdx.x; t < RP * RP; t += 256) {
@@ -269,38 +274,51 @@ k_apply_w(const float *__restrict__ Y, int64_t rows, int R, int64_t ldy, const d
         W[t] = (r < R && c < R) ? Wg[r * R + c] : 0.0;
     }
     __syncthreads();
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const bool ok = i < rows;
-    double a[RP];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int64_t row0 = ((int64_t)blockIdx.x * 4 + wave) * 16;
+    const int64_t arow = row0 + lr;  // row of this lane's first-operand element
+    v4d acc[NB];
 #pragma unroll
-    for (int c = 0; c < RP; ++c) a[c] = 0.0;
-    if (ok) {
-        for (int j = 0; j < R; ++j) {
-            const double y = (double)Y[i * ldy + j];
+    for (int nb = 0; nb < NB; ++nb) acc[nb] = v4d{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-            for (int c = 0; c < RP; ++c) a[c] = fma(y, W[j * RP + c], a[c]);
-        }
+    for (int k0 = 0; k0 < RP; k0 += 4) {
+        const int k = k0 + lk;
+        const double a = (arow < rows && k < R) ? (double)Y[arow * ldy + k] : 0.0;
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+            acc[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, W[k * RP + nb * 16 + lr], acc[nb], 0, 0, 0);
     }
     if (pass == 0) {
-        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+        // column sums of squares: the 4 rows of each register, then the 4 lane
+        // quarters holding the same column, then the 4 waves (fixed order)
 #pragma unroll
-        for (int c = 0; c < RP; ++c) {
-            double v = wave_sum(a[c] * a[c]);
-            if (lane == 0) red[wave][c] = v;
+        for (int nb = 0; nb < NB; ++nb) {
+            double q = 0.0;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) q = fma(acc[nb][v], acc[nb][v], q);
+            q += __shfl_xor(q, 16, 64);
+            q += __shfl_xor(q, 32, 64);
+            if (lk == 0) red[wave][nb * 16 + lr] = q;
         }
         __syncthreads();
         for (int c = threadIdx.x; c < R; c += 256)
-            partial[(int64_t)blockIdx.x * R + c] = red[0][c] + red[1][c] + red[2][c] + red[3][c];
+            partial[(int64_t)blockIdx.x * R + c] = (red[0][c] + red[1][c]) + (red[2][c] + red[3][c]);
         return;
     }
-    if (!ok) return;
 #pragma unroll
-    for (int c = 0; c < RP; ++c) {
-        if (c >= R) break;
+    for (int nb = 0; nb < NB; ++nb) {
+        const int c = nb * 16 + lr;
+        if (c >= R) continue;
         const double lam = lambda[c];
-        const float v = lam > 0.0 ? (float)(a[c] / lam) : 0.0f;
-        A[i * lda + c] = v;
-        if (Ab) Ab[i * ldb + c] = f32_to_bf16(v);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int64_t i = row0 + 4 * v + lk;
+            if (i >= rows) continue;
+            const float x = lam > 0.0 ? (float)(acc[nb][v] / lam) : 0.0f;
+            A[i * lda + c] = x;
+            if (Ab) Ab[i * ldb + c] = f32_to_bf16(x);
+        }
     }
 }
 
@@ -402,7 +420,7 @@ cpd_status solve_normalize(const double *const *grams, int nmodes, int mode, con
     CPD_TRY(wk.alloc((size_t)R * R, s));
     hipLaunchKernelGGL(k_make_w, dim3(1), dim3(256), 0, s, gs, nmodes, mode, R, W.p, wk.p, used_pinv);
     CPD_LAUNCH_CHECK();
-    const int nb = (int)std::max<int64_t>(1, ceil_div(rows, 256));
+    const int nb = (int)std::max<int64_t>(1, ceil_div(rows, 64));  // 4 waves x 16 rows
     CPD_TRY(part.alloc((size_t)nb * R, s));
     const int RP = ((R + 15) / 16) * 16;
     for (int pass = 0; pass < 2; ++pass) {
