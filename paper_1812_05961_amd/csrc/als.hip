@@ -113,24 +113,23 @@ struct Events {
 };
 
 // Trees and buffers of one cpd_als call, all used only on its stream: they
-// come from and return to the stream-ordered pool on that stream.
+// come from and return to the scratch cache of that stream.
 struct Owned {
     hipStream_t s;
     std::vector<cpd_csf_s *> csfs;
-    std::vector<void *> bufs;
+    std::vector<std::pair<void *, size_t>> bufs;
     explicit Owned(hipStream_t st) : s(st) {}
     ~Owned() {
         for (auto c : csfs) free_csf_on(c, s);
-        for (auto p : bufs) (void)hipFreeAsync(p, s);
-        (void)hipGetLastError();
+        for (auto &b : bufs) scratch_put(b.first, b.second, s);
     }
     template <typename T>
     cpd_status alloc(T **p, size_t count) {
-        if (hipMallocAsync((void **)p, sizeof(T) * std::max<size_t>(count, 1), s) != hipSuccess) {
-            (void)hipGetLastError();
-            CPD_FAIL(CPD_ENOMEM, "device allocation of %zu bytes failed", sizeof(T) * count);
-        }
-        bufs.push_back(*p);
+        const size_t bytes = sizeof(T) * std::max<size_t>(count, 1);
+        void *q = nullptr;
+        CPD_TRY(scratch_get(bytes, s, &q));
+        *p = static_cast<T *>(q);
+        bufs.push_back({q, bytes});
         return CPD_OK;
     }
 };

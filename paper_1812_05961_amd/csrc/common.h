@@ -45,7 +45,13 @@ void keep_pool_memory();
 
 #define CPD_LAUNCH_CHECK() CPD_HIP(hipGetLastError())
 
-// Stream-ordered device buffer that frees itself (hipFreeAsync) on scope exit.
+// Scratch blocks for stream-ordered use on stream s: reused from a cache of
+// blocks released on the same stream, else taken from the stream-ordered pool.
+cpd_status scratch_get(size_t bytes, hipStream_t s, void **p);
+void scratch_put(void *p, size_t bytes, hipStream_t s);
+
+// Stream-ordered scratch buffer that returns itself to the scratch cache on
+// scope exit.
 template <typename T>
 struct DevBuf {
     T *p = nullptr;
@@ -60,16 +66,13 @@ struct DevBuf {
         s = stream;
         n = count;
         if (count == 0) return CPD_OK;
-        hipError_t e = hipMallocAsync((void **)&p, count * sizeof(T), stream);
-        if (e != hipSuccess) {
-            p = nullptr;
-            (void)hipGetLastError();
-            CPD_FAIL(CPD_ENOMEM, "device allocation of %zu bytes failed", count * sizeof(T));
-        }
-        return CPD_OK;
+        void *q = nullptr;
+        cpd_status st = scratch_get(count * sizeof(T), stream, &q);
+        p = static_cast<T *>(q);
+        return st;
     }
     void release() {
-        if (p) (void)hipFreeAsync(p, s);
+        if (p) scratch_put(p, n * sizeof(T), s);
         p = nullptr;
         n = 0;
     }

@@ -12,6 +12,8 @@ struct cpd_csf_s {
     int64_t dims[CPD_MAX_MODES] = {};     // by mode
     int order[CPD_MAX_MODES] = {};        // level -> mode
     int64_t counts[CPD_MAX_MODES] = {};   // nodes per level (counts[N-1] = nnz)
+    char *slab = nullptr;                 // one allocation holding the arrays below
+    size_t slab_bytes = 0;
     int32_t *fids[CPD_MAX_MODES] = {};    // per level
     int32_t *fptr[CPD_MAX_MODES] = {};    // per level < N-1
     float *vals = nullptr;

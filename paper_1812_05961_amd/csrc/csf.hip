@@ -421,19 +421,14 @@ __global__ void k_max_run(const int32_t *starts, const int32_t *nruns, int64_t n
     }
 }
 
-// Return every array of the tree to the stream-ordered pool on stream s.
+// Return every array of the tree for reuse on stream s (the slab to the
+// scratch cache, lazily built tables to the stream-ordered pool).
 void release_arrays(cpd_csf_s *c, hipStream_t s) {
+    if (c->slab) scratch_put(c->slab, c->slab_bytes, s);
     for (int l = 0; l < CPD_MAX_MODES; ++l) {
-        if (c->fids[l]) (void)hipFreeAsync(c->fids[l], s);
-        if (c->fptr[l]) (void)hipFreeAsync(c->fptr[l], s);
-        if (c->uprow[l]) (void)hipFreeAsync(c->uprow[l], s);
         if (c->lvl_perm[l]) (void)hipFreeAsync(c->lvl_perm[l], s);
         if (c->lvl_rank[l]) (void)hipFreeAsync(c->lvl_rank[l], s);
     }
-    if (c->vals) (void)hipFreeAsync(c->vals, s);
-    if (c->leafw) (void)hipFreeAsync(c->leafw, s);
-    if (c->leaf_perm) (void)hipFreeAsync(c->leaf_perm, s);
-    if (c->leaf_rank) (void)hipFreeAsync(c->leaf_rank, s);
     for (auto &t : c->tiles) (void)hipFreeAsync(t.starts, s);
     (void)hipGetLastError();
 }
@@ -450,10 +445,11 @@ namespace {
 
 void free_csf(cpd_csf_s *c) {
     if (!c) return;
-    // work on any stream may still read the arrays: wait for the device first
+    // work on any stream may still read the arrays: wait for the device, after
+    // which the arrays are idle (the build stream may be gone: use the null
+    // stream)
     (void)hipDeviceSynchronize();
     release_arrays(c, nullptr);
-    (void)hipStreamSynchronize(nullptr);
     delete c;
 }
 
@@ -575,27 +571,35 @@ cpd_status build(int nm, const int64_t *dims, int64_t nnz, const int32_t *const 
         c->counts[l] = (l == nm - 1) ? n : h_counts[l];
     }
     cpd_status st = CPD_OK;
-    // the tree's arrays come from the stream-ordered pool: repeated builds
-    // reuse memory instead of mapping fresh pages
-    auto alloc_arr = [&](void **p, size_t bytes) -> bool {
-        if (hipMallocAsync(p, std::max<size_t>(bytes, 4), s) != hipSuccess) {
-            (void)hipGetLastError();
-            *p = nullptr;
-            return false;
-        }
-        return true;
-    };
-    bool ok = true;
-    for (int l = 0; l < nm && ok; ++l) {
-        ok = alloc_arr((void **)&c->fids[l], sizeof(int32_t) * c->counts[l]);
-        if (ok && l < nm - 1) ok = alloc_arr((void **)&c->fptr[l], sizeof(int32_t) * (c->counts[l] + 1));
-    }
-    if (ok) ok = alloc_arr((void **)&c->vals, sizeof(float) * n);
+    // the tree's arrays are carved from one stream-ordered pool allocation
+    // (256-byte aligned pieces): one allocation and one free per tree, and
+    // repeated builds reuse the pool's pages
     const bool want_leafw = dims[order[nm - 1]] <= (1ll << 29);
-    if (ok && want_leafw) ok = alloc_arr((void **)&c->leafw, sizeof(int32_t) * n);
-    if (ok && want_leafw) ok = alloc_arr((void **)&c->leaf_perm, sizeof(int32_t) * dims[order[nm - 1]]);
-    if (ok && want_leafw) ok = alloc_arr((void **)&c->leaf_rank, sizeof(int32_t) * dims[order[nm - 1]]);
-    for (int l = 1; l < nm - 1 && ok && want_leafw; ++l) ok = alloc_arr((void **)&c->uprow[l], sizeof(int32_t) * n);
+    std::vector<std::pair<void **, size_t>> pieces;
+    for (int l = 0; l < nm; ++l) {
+        pieces.push_back({(void **)&c->fids[l], sizeof(int32_t) * c->counts[l]});
+        if (l < nm - 1) pieces.push_back({(void **)&c->fptr[l], sizeof(int32_t) * (c->counts[l] + 1)});
+    }
+    pieces.push_back({(void **)&c->vals, sizeof(float) * n});
+    if (want_leafw) {
+        pieces.push_back({(void **)&c->leafw, sizeof(int32_t) * n});
+        pieces.push_back({(void **)&c->leaf_perm, sizeof(int32_t) * dims[order[nm - 1]]});
+        pieces.push_back({(void **)&c->leaf_rank, sizeof(int32_t) * dims[order[nm - 1]]});
+        for (int l = 1; l < nm - 1; ++l) pieces.push_back({(void **)&c->uprow[l], sizeof(int32_t) * n});
+    }
+    size_t total = 0;
+    for (auto &pc : pieces) total += (pc.second + 255) & ~(size_t)255;
+    c->slab_bytes = std::max<size_t>(total, 256);
+    void *slab = nullptr;
+    bool ok = scratch_get(c->slab_bytes, s, &slab) == CPD_OK;
+    c->slab = static_cast<char *>(slab);
+    if (ok) {
+        size_t off = 0;
+        for (auto &pc : pieces) {
+            *pc.first = c->slab + off;
+            off += (pc.second + 255) & ~(size_t)255;
+        }
+    }
     if (!ok) {
         free_csf(c);
         CPD_FAIL(CPD_ENOMEM, "device allocation for the CSF failed");
