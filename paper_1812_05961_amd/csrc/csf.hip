@@ -531,31 +531,36 @@ cpd_status build(int nm, const int64_t *dims, int64_t nnz, const int32_t *const 
     CPD_LAUNCH_CHECK();
     int32_t *d_nuniq = d_flag.p + 1;
     CPD_TRY(exclusive_scan(IsNew{dl.p, nm}, nnz, pos.p, d_nuniq, s));
-    // merged arrays reuse the other ping-pong buffers
-    DevBuf<uint8_t> udl;
-    DevBuf<float> uval;
-    CPD_TRY(udl.alloc(nnz, s));
-    CPD_TRY(uval.alloc(nnz, s));
-    hipLaunchKernelGGL(k_merge, dim3(grid1(nnz)), dim3(256), 0, s, klo, khi, kp, dl.p, pos.p, nnz, nm, olo, ohi,
-                       uval.p, udl.p);
-    CPD_LAUNCH_CHECK();
-    std::swap(klo, olo);
-    std::swap(khi, ohi);
-    dl.release();
-    p0.release();
-    p1.release();
-
     int32_t h_flag[2];
     CPD_HIP(hipMemcpyAsync(h_flag, d_flag.p, sizeof(int32_t) * 2, hipMemcpyDeviceToHost, s));
     CPD_HIP(hipStreamSynchronize(s));
     if (h_flag[0]) CPD_FAIL(CPD_EINVAL, "an index is out of range for its mode");
     const int64_t n = h_flag[1];
 
+    // merged keys, levels and values; without duplicates the sorted arrays
+    // are the merged ones (the payload carries the values' bits)
+    DevBuf<uint8_t> udl_buf;
+    DevBuf<float> uval_buf;
+    const uint8_t *udl = dl.p;
+    const float *uval = reinterpret_cast<const float *>(kp);
+    if (n != nnz) {
+        CPD_TRY(udl_buf.alloc(nnz, s));
+        CPD_TRY(uval_buf.alloc(nnz, s));
+        hipLaunchKernelGGL(k_merge, dim3(grid1(nnz)), dim3(256), 0, s, klo, khi, kp, dl.p, pos.p, nnz, nm, olo, ohi,
+                           uval_buf.p, udl_buf.p);
+        CPD_LAUNCH_CHECK();
+        std::swap(klo, olo);
+        std::swap(khi, ohi);
+        udl = udl_buf.p;
+        uval = uval_buf.p;
+    }
+    pos.release();
+
     // a5: fiber compression, levels N-2 .. 0
     std::vector<DevBuf<int32_t>> scans(nm - 1);
     for (int l = 0; l < nm - 1; ++l) {
         CPD_TRY(scans[l].alloc(n, s));
-        CPD_TRY(exclusive_scan(AtLevel{udl.p, l}, n, scans[l].p, d_flag.p + 2 + l, s));
+        CPD_TRY(exclusive_scan(AtLevel{udl, l}, n, scans[l].p, d_flag.p + 2 + l, s));
     }
     int32_t h_counts[CPD_MAX_MODES] = {};
     if (nm > 1)
@@ -606,7 +611,7 @@ cpd_status build(int nm, const int64_t *dims, int64_t nnz, const int32_t *const 
     }
     for (int l = nm - 2; l >= 0 && st == CPD_OK; --l) {
         const int32_t *next = (l == nm - 2) ? nullptr : scans[l + 1].p;
-        hipLaunchKernelGGL(k_compact, dim3(grid1(n)), dim3(256), 0, s, klo, khi, kl, udl.p, n, l,
+        hipLaunchKernelGGL(k_compact, dim3(grid1(n)), dim3(256), 0, s, klo, khi, kl, udl, n, l,
                            scans[l].p, next, c->fids[l], c->fptr[l]);
         if (hipGetLastError() != hipSuccess) st = CPD_EHIP;
         hipLaunchKernelGGL(k_set_last_const, dim3(1), dim3(1), 0, s, c->fptr[l], c->counts[l],
@@ -619,7 +624,7 @@ cpd_status build(int nm, const int64_t *dims, int64_t nnz, const int32_t *const 
         const int64_t nid = dims[order[nm - 1]];
         cpd_status rs = rank_ids(c->fids[nm - 1], n, nid, c->leaf_perm, c->leaf_rank, d_flag.p + 1, s);
         if (rs == CPD_OK) {
-            hipLaunchKernelGGL(k_leafw, dim3(grid1(n)), dim3(256), 0, s, (const uint8_t *)udl.p,
+            hipLaunchKernelGGL(k_leafw, dim3(grid1(n)), dim3(256), 0, s, udl,
                                (const int32_t *)c->fids[nm - 1], (const int32_t *)c->leaf_rank, n, c->leafw);
             if (hipGetLastError() != hipSuccess) rs = CPD_EHIP;
         }
@@ -629,7 +634,7 @@ cpd_status build(int nm, const int64_t *dims, int64_t nnz, const int32_t *const 
             if (st == CPD_OK && hipGetLastError() != hipSuccess) st = CPD_EHIP;
         }
     }
-    if (st == CPD_OK && hipMemcpyAsync(c->vals, uval.p, sizeof(float) * n, hipMemcpyDeviceToDevice, s) != hipSuccess)
+    if (st == CPD_OK && hipMemcpyAsync(c->vals, uval, sizeof(float) * n, hipMemcpyDeviceToDevice, s) != hipSuccess)
         st = CPD_EHIP;
     if (st == CPD_OK && hipStreamSynchronize(s) != hipSuccess) st = CPD_EHIP;
     if (st != CPD_OK) {
