@@ -109,43 +109,3 @@ def tile_starts(csf, tile_nnz: int):
         pos = np.searchsorted(csf["fptr"][l], pos, side="right") - 1
         out[l] = pos
     return out
-
-
-def frequency_rank(ids, nid, max_samples=1 << 22):
-    """Rank the indices 0..nid-1 by how often they occur in a strided sample
-    of `ids`: stride = max(1, n // max_samples), sample = ids[0::stride].
-    Rank 0 is the most frequent; equal counts, and indices absent from the
-    sample, are ordered by index.  Returns (perm, rank): perm[r] is the index
-    of rank r and rank is its inverse."""
-    ids = np.asarray(ids, dtype=np.int64)
-    stride = max(1, ids.size // max_samples)
-    counts = np.bincount(ids[::stride], minlength=nid)
-    perm = np.lexsort((np.arange(nid), -counts))          # by -count, then by index
-    rank = np.empty(nid, dtype=np.int64)
-    rank[perm] = np.arange(nid)
-    return perm, rank
-
-
-def build_split(dims, inds, vals, order, hot_rows):
-    """A tree split by leaf frequency: the nonzeros whose leaf index (mode
-    order[-1]) has frequency rank below hot_rows (frequency_rank of the COO's
-    leaf indices) form a first CSF, the others a second, each built as by
-    `build`; the two are stored one after the other, level by level (a root id
-    may appear once in each part; the second part's fptr values are offset by
-    the first part's child counts).  Returns the CSF dict with nhot, the number
-    of leaves of the first part."""
-    inds = np.asarray(inds, dtype=np.int64)
-    vals = np.asarray(vals, dtype=np.float32)
-    order = [int(m) for m in order]
-    leaf = order[-1]
-    _, rank = frequency_rank(inds[leaf], int(dims[leaf]))
-    hot = rank[inds[leaf]] < hot_rows
-    a = build(dims, inds[:, hot], vals[hot], order)
-    b = build(dims, inds[:, ~hot], vals[~hot], order)
-    nm = len(order)
-    out = dict(order=order, counts=[a["counts"][l] + b["counts"][l] for l in range(nm)],
-               fids=[np.concatenate([a["fids"][l], b["fids"][l]]) for l in range(nm)],
-               fptr=[np.concatenate([a["fptr"][l][:-1], b["fptr"][l] + a["counts"][l + 1]]).astype(np.int32)
-                     for l in range(nm - 1)],
-               vals=np.concatenate([a["vals"], b["vals"]]), nhot=a["counts"][nm - 1])
-    return out
