@@ -90,6 +90,17 @@ cpd_status cpd_csf_build(int32_t nmodes, const int64_t *dims, int64_t nnz,
                          const int32_t *const *inds, const float *vals, const int32_t *order,
                          void *stream, cpd_csf *out);
 
+/* One tree rooted at each mode (the layout CP-ALS reads, every MTTKRP at the
+ * root level, Section III): out[m] (host array of N handles) holds the tree
+ * with order (m, then the other modes by descending length, ties to the lower
+ * mode).  Each tree equals cpd_csf_build with that order.  The tree of the
+ * longest mode is sorted on every key field; each other tree re-sorts those
+ * sorted, merged nonzeros on its root field only (the order of the other
+ * fields is already right for keys that share a root index).  Arguments and
+ * checks as cpd_csf_build; on failure every out[m] is NULL. */
+cpd_status cpd_csf_build_rooted(int32_t nmodes, const int64_t *dims, int64_t nnz,
+                                const int32_t *const *inds, const float *vals, void *stream, cpd_csf *out);
+
 /* Mode count, mode order (host, N entries) and level counts (host, N
  * entries; count[N-1] = nonzeros after merging).  Null outputs are skipped. */
 cpd_status cpd_csf_info(cpd_csf csf, int32_t *nmodes, int32_t *order, int64_t *counts);

@@ -80,6 +80,7 @@ _SIGS = {
     "cpd_last_error": (ctypes.c_char_p, []),
     "cpd_abi_version": (_I32, []),
     "cpd_csf_build": (_I32, [_I32, _P, _I64, _P, _P, _P, _P, _P]),
+    "cpd_csf_build_rooted": (_I32, [_I32, _P, _I64, _P, _P, _P, _P]),
     "cpd_csf_info": (_I32, [_P, _P, _P, _P]),
     "cpd_csf_export": (_I32, [_P, _I32, _P, _P, _P, _P]),
     "cpd_csf_tiles": (_I32, [_P, _I32, _P, _P, _P]),
@@ -222,6 +223,21 @@ def csf_build(inds, vals, dims, order=None, stream=None) -> Csf:
     c = Csf(h.value)
     c.dims = dims
     return c
+
+
+def csf_build_rooted(inds, vals, dims, stream=None) -> list:
+    """cpd_csf_build_rooted: one tree rooted at each mode (list indexed by
+    mode), the other modes by descending length."""
+    inds, vals, dims = _coo_args(inds, vals, dims)
+    hs = (ctypes.c_void_p * len(dims))()
+    _check(lib().cpd_csf_build_rooted(len(dims), _i64s(dims), vals.numel(), _ptrs(inds), vals.data_ptr(),
+                                      _stream(stream), hs))
+    out = []
+    for m in range(len(dims)):
+        c = Csf(hs[m])
+        c.dims = dims
+        out.append(c)
+    return out
 
 
 def mttkrp(csf: Csf, factors, mode: int, out=None, rank=None, precision="fp32", variant="auto",

@@ -56,9 +56,10 @@ namespace cpd {
 template <typename F>
 cpd_status exclusive_scan(F f, int64_t n, int32_t *out, int32_t *total, hipStream_t s);
 
-// Stable LSD radix sort (see csf.hip); buffers ping-pong, k*/kp end on the result.
+// Stable LSD radix sort (see csf.hip) on key bits [lo_bit, bits); buffers
+// ping-pong, k*/kp end on the result.
 cpd_status radix_sort(uint64_t *&klo, uint64_t *&khi, int32_t *&kp, uint64_t *&olo, uint64_t *&ohi, int32_t *&op,
-                      int64_t n, int bits, hipStream_t s);
+                      int64_t n, int bits, hipStream_t s, int lo_bit = 0);
 
 // Index frequencies in a strided sample of at most max_samples of the n ids
 // (values in [0, nid)): out (device, 3 int32) = distinct ids in the sample,

@@ -125,39 +125,50 @@ k_radix_scatter(const uint64_t *klo, const uint64_t *khi, const int32_t *pay, ui
     }
 }
 
-// ---- radix sort: stable scatter of one-word keys through LDS.  The tile is
-// ranked as above, reordered by digit in LDS, and written out run by run, so
-// consecutive threads store to consecutive addresses.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// ---- radix sort: stable scatter of one-word keys through LDS.  Each wave
+// ranks a contiguous quarter of the tile against its own digit counters (no
+// block barrier per round); the per-wave counts then give every wave's start
+// for each digit.  The tile is reordered by digit in LDS and written out run
+// by run, so consecutive threads store to consecutive addresses: first the
+// keys, then the payloads through the same LDS buffer.  Equal digits keep
+// their input order (waves in tile order, rounds in wave order, lanes in
+// round order).
+constexpr int RS_WAVES = RS_THREADS / 64;
+constexpr int RS_WAVE_ITEMS = RS_TILE / RS_WAVES;
+
 __global__ void __launch_bounds__(RS_THREADS)
 k_radix_scatter1(const uint64_t *__restrict__ keys, const int32_t *__restrict__ pay, uint64_t *__restrict__ okeys,
                  int32_t *__restrict__ opay, const int32_t *__restrict__ offsets, int64_t n, int64_t ntiles,
                  int shift) {
-    __shared__ uint64_t s_key[RS_TILE];
-    __shared__ int32_t s_pay[RS_TILE];
-    __shared__ int32_t s_run[256];      // counts of earlier rounds, then the tile's digit starts
-    __shared__ int32_t s_off[256];      // global start minus tile start, per digit
-    __shared__ int32_t wcnt[2][4][256];  // per-wave digit counts, two rounds in flight
-    __shared__ int32_t s_wsum[4];
+    __shared__ uint64_t s_buf[RS_TILE];       // the tile in digit order: keys, then payloads
+    __shared__ int32_t s_cnt[RS_WAVES][256];  // per-wave digit counts, then each wave's digit starts
+    __shared__ int32_t s_off[256];            // global start minus tile start, per digit
+    __shared__ int32_t s_wsum[RS_WAVES];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    s_run[tid] = 0;
-#pragma unroll
-    for (int w = 0; w < 4; ++w) wcnt[0][w][tid] = wcnt[1][w][tid] = 0;
     const int64_t tbase = (int64_t)blockIdx.x * RS_TILE;
     const int tn = (int)min<int64_t>(RS_TILE, n - tbase);
+    int32_t *wc = s_cnt[wave];
+    for (int j = lane; j < 256; j += 64) wc[j] = 0;
     uint64_t k[RS_ITEMS];
     int32_t p[RS_ITEMS], rk[RS_ITEMS];
 #pragma unroll
     for (int r = 0; r < RS_ITEMS; ++r) {
-        const int j = r * RS_THREADS + tid;
+        const int j = wave * RS_WAVE_ITEMS + r * 64 + lane;
         k[r] = j < tn ? keys[tbase + j] : 0ull;
         p[r] = j < tn ? pay[tbase + j] : 0;
     }
-    __syncthreads();
+    wave_sync();
     const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
 #pragma unroll
     for (int r = 0; r < RS_ITEMS; ++r) {
-        const bool valid = r * RS_THREADS + tid < tn;
-        const uint32_t d = (uint32_t)((k[r] >> shift) & 255u);
+        const bool valid = wave * RS_WAVE_ITEMS + r * 64 + lane < tn;
+        const uint32_t d = (uint32_t)(k[r] >> shift) & 255u;
         uint64_t peers = __ballot(valid);
 #pragma unroll
         for (int bit = 0; bit < 8; ++bit) {
@@ -165,48 +176,72 @@ k_radix_scatter1(const uint64_t *__restrict__ keys, const int32_t *__restrict__ 
             const uint64_t m = __ballot(set);
             peers &= set ? m : ~m;
         }
-        const int rank_w = __popcll(peers & lt);
-        const int b = r & 1;
-        if (valid && rank_w == 0) wcnt[b][wave][d] = __popcll(peers);
-        __syncthreads();
-        int x = s_run[d] + rank_w;
-        for (int w = 0; w < wave; ++w) x += wcnt[b][w][d];
-        rk[r] = x;
-        __syncthreads();
-        s_run[tid] += wcnt[b][0][tid] + wcnt[b][1][tid] + wcnt[b][2][tid] + wcnt[b][3][tid];
-        wcnt[b][0][tid] = wcnt[b][1][tid] = wcnt[b][2][tid] = wcnt[b][3][tid] = 0;
+        const int below = __popcll(peers & lt);
+        const int before = valid ? wc[d] : 0;
+        rk[r] = before + below;
+        wave_sync();
+        if (valid && below == 0) wc[d] = before + __popcll(peers);
+        wave_sync();
     }
     __syncthreads();
-    // exclusive scan of the tile's digit counts
-    const int c = s_run[tid];
-    int incl = c;
+    // thread tid owns digit tid: the tile's count, its exclusive scan over
+    // digits, and each wave's start
+    int32_t c[RS_WAVES], tot = 0;
+#pragma unroll
+    for (int w = 0; w < RS_WAVES; ++w) {
+        c[w] = s_cnt[w][tid];
+        tot += c[w];
+    }
+    int32_t incl = tot;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
-        const int y = __shfl_up(incl, o, 64);
+        const int32_t y = __shfl_up(incl, o, 64);
         if (lane >= o) incl += y;
     }
     if (lane == 63) s_wsum[wave] = incl;
     __syncthreads();
-    int excl = incl - c;
+    int32_t excl = incl - tot;
     for (int w = 0; w < wave; ++w) excl += s_wsum[w];
-    s_run[tid] = excl;
+    int32_t run = excl;
+#pragma unroll
+    for (int w = 0; w < RS_WAVES; ++w) {
+        s_cnt[w][tid] = run;
+        run += c[w];
+    }
     s_off[tid] = offsets[(int64_t)tid * ntiles + blockIdx.x] - excl;
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < RS_ITEMS; ++r) {
-        if (r * RS_THREADS + tid < tn) {
-            const uint32_t d = (uint32_t)((k[r] >> shift) & 255u);
-            const int at = s_run[d] + rk[r];
-            s_key[at] = k[r];
-            s_pay[at] = p[r];
+        if (wave * RS_WAVE_ITEMS + r * 64 + lane < tn) {
+            rk[r] += wc[(uint32_t)(k[r] >> shift) & 255u];  // position in the digit-ordered tile
+            s_buf[rk[r]] = k[r];
         }
     }
     __syncthreads();
-    for (int e = tid; e < tn; e += RS_THREADS) {
-        const uint64_t key = s_key[e];
-        const int64_t g = (int64_t)s_off[(key >> shift) & 255u] + e;
-        okeys[g] = key;
-        opay[g] = s_pay[e];
+    int32_t g[RS_ITEMS];
+#pragma unroll
+    for (int i = 0; i < RS_ITEMS; ++i) {
+        const int e = i * RS_THREADS + tid;
+        g[i] = -1;
+        if (e < tn) {
+            const uint64_t key = s_buf[e];
+            const int64_t at = (int64_t)s_off[(key >> shift) & 255u] + e;
+            if ((uint64_t)at < (uint64_t)n) {  // always, when the histogram matches the tile
+                okeys[at] = key;
+                g[i] = (int32_t)at;
+            }
+        }
+    }
+    __syncthreads();
+    int32_t *s_pay = reinterpret_cast<int32_t *>(s_buf);
+#pragma unroll
+    for (int r = 0; r < RS_ITEMS; ++r)
+        if (wave * RS_WAVE_ITEMS + r * 64 + lane < tn) s_pay[rk[r]] = p[r];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < RS_ITEMS; ++i) {
+        const int e = i * RS_THREADS + tid;
+        if (e < tn && g[i] >= 0) opay[g[i]] = s_pay[e];
     }
 }
 
@@ -217,18 +252,19 @@ struct HistAt {
 
 }  // namespace
 
-// Stable LSD radix sort of n keys (one or two 64-bit words, `bits` significant
-// bits) with an int32 payload, 8 bits per pass, ping-ponging between the
-// (k*, p*) and (o*, op*) buffers; on return k*, kp point at the sorted data.
+// Stable LSD radix sort of n keys (one or two 64-bit words) on key bits
+// [lo_bit, bits) with an int32 payload, 8 bits per pass, ping-ponging between
+// the (k*, p*) and (o*, op*) buffers; on return k*, kp point at the sorted
+// data.  With lo_bit > 0 the order of equal sorted bits is the input order.
 cpd_status radix_sort(uint64_t *&klo, uint64_t *&khi, int32_t *&kp, uint64_t *&olo, uint64_t *&ohi, int32_t *&op,
-                      int64_t n, int bits, hipStream_t s) {
+                      int64_t n, int bits, hipStream_t s, int lo_bit) {
     const int64_t ntiles = ceil_div(n, RS_TILE);
     if (ntiles == 0) return CPD_OK;
     DevBuf<int32_t> hist;
     CPD_TRY(hist.alloc((size_t)256 * ntiles, s));
-    const int passes = (bits + 7) / 8;
+    const int passes = (bits - lo_bit + 7) / 8;
     for (int d = 0; d < passes; ++d) {
-        int word = (8 * d) / 64, shift = (8 * d) % 64;
+        int word = (lo_bit + 8 * d) / 64, shift = (lo_bit + 8 * d) % 64;
         const uint64_t *src = word ? khi : klo;
         hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)ntiles), dim3(RS_THREADS), 0, s, src, n, shift, hist.p, ntiles);
         CPD_LAUNCH_CHECK();
@@ -453,8 +489,9 @@ void free_csf(cpd_csf_s *c) {
     delete c;
 }
 
-cpd_status build(int nm, const int64_t *dims, int64_t nnz, const int32_t *const *inds,
-                 const float *vals, const int32_t *order_in, hipStream_t s, cpd_csf *out) {
+// Build arguments shared by every entry point.
+cpd_status check_coo(int nm, const int64_t *dims, int64_t nnz, const int32_t *const *inds, const float *vals,
+                     const void *out) {
     if (nm < 2 || nm > CPD_MAX_MODES) CPD_FAIL(CPD_EINVAL, "nmodes %d not in [2, %d]", nm, CPD_MAX_MODES);
     if (!dims || !inds || !vals || !out) CPD_FAIL(CPD_EINVAL, "null argument");
     if (nnz < 1 || nnz > INT32_MAX) CPD_FAIL(CPD_EINVAL, "nnz %lld not in [1, 2^31-1]", (long long)nnz);
@@ -462,32 +499,45 @@ cpd_status build(int nm, const int64_t *dims, int64_t nnz, const int32_t *const 
         if (dims[m] < 1 || dims[m] > INT32_MAX) CPD_FAIL(CPD_EINVAL, "dim %d = %lld out of range", m, (long long)dims[m]);
         if (!inds[m]) CPD_FAIL(CPD_EINVAL, "null index array for mode %d", m);
     }
-    keep_pool_memory();
-    int order[CPD_MAX_MODES];
-    if (order_in) {
-        bool seen[CPD_MAX_MODES] = {};
-        for (int l = 0; l < nm; ++l) {
-            int m = order_in[l];
-            if (m < 0 || m >= nm || seen[m]) CPD_FAIL(CPD_EINVAL, "order is not a permutation of the modes");
-            seen[m] = true;
-            order[l] = m;
-        }
-    } else {
-        std::iota(order, order + nm, 0);
-        std::stable_sort(order, order + nm, [&](int a, int b) { return dims[a] < dims[b]; });
-    }
+    return CPD_OK;
+}
+
+// Key layout of a tree order: level l's index at bits [shift[l], shift[l] +
+// bits[l]), the root most significant; *total: the key's bit count.
+KeyLayout key_layout(int nm, const int64_t *dims, const int32_t *order, int *total) {
     KeyLayout kl{};
     kl.nl = nm;
-    int total_bits = 0;
+    int t = 0;
     for (int l = nm - 1; l >= 0; --l) {
-        int64_t d = dims[order[l]];
+        const int64_t d = dims[order[l]];
         int b = 0;
         while ((1ll << b) < d) ++b;
         kl.bits[l] = b;
-        kl.shift[l] = total_bits;
-        total_bits += b;
+        kl.shift[l] = t;
+        t += b;
     }
-    if (total_bits > 128) CPD_FAIL(CPD_EUNSUPPORTED, "packed key needs %d bits (> 128)", total_bits);
+    *total = t;
+    return kl;
+}
+
+// The sorted, merged nonzeros of one tree order: keys, values and the level
+// at which each key first differs from the previous one.
+struct Sorted {
+    DevBuf<uint64_t> lo[2], hi[2];
+    DevBuf<int32_t> pay[2];
+    DevBuf<uint8_t> dl, mdl;
+    DevBuf<float> mval;
+    const uint64_t *klo = nullptr, *khi = nullptr;
+    const float *val = nullptr;
+    const uint8_t *udl = nullptr;
+    int64_t n = 0;
+};
+
+// Index check, key packing, sort and duplicate merge (duplicates summed in
+// input order) for one tree order.
+cpd_status sort_merge(int nm, const KeyLayout &kl, int total_bits, const int32_t *const *inds, const int32_t *order,
+                      const int64_t *dims, const float *vals, int64_t nnz, int32_t *d_flag, hipStream_t s,
+                      Sorted &S) {
     const bool two = total_bits > 64;
     LevelInds li{};
     int64_t dims_l[CPD_MAX_MODES];
@@ -495,76 +545,128 @@ cpd_status build(int nm, const int64_t *dims, int64_t nnz, const int32_t *const 
         li.p[l] = inds[order[l]];
         dims_l[l] = dims[order[l]];
     }
-
-    // a1: index check
     DevBuf<int64_t> d_dims;
-    DevBuf<int32_t> d_flag;
     CPD_TRY(d_dims.alloc(nm, s));
-    CPD_TRY(d_flag.alloc(1 + CPD_MAX_MODES, s));
     CPD_HIP(hipMemcpyAsync(d_dims.p, dims_l, sizeof(int64_t) * nm, hipMemcpyHostToDevice, s));
-    CPD_HIP(hipMemsetAsync(d_flag.p, 0, sizeof(int32_t) * (1 + CPD_MAX_MODES), s));
-
-    // a3: keys and stable LSD radix sort
-    DevBuf<uint64_t> lo0, lo1, hi0, hi1;
-    DevBuf<int32_t> p0, p1;
-    CPD_TRY(lo0.alloc(nnz, s));
-    CPD_TRY(lo1.alloc(nnz, s));
-    if (two) {
-        CPD_TRY(hi0.alloc(nnz, s));
-        CPD_TRY(hi1.alloc(nnz, s));
+    for (int b = 0; b < 2; ++b) {
+        CPD_TRY(S.lo[b].alloc(nnz, s));
+        if (two) CPD_TRY(S.hi[b].alloc(nnz, s));
+        CPD_TRY(S.pay[b].alloc(nnz, s));
     }
-    CPD_TRY(p0.alloc(nnz, s));
-    CPD_TRY(p1.alloc(nnz, s));
     hipLaunchKernelGGL(k_pack, dim3(grid1(nnz)), dim3(256), 0, s, li, kl, (const int64_t *)d_dims.p, vals, nnz,
-                       lo0.p, hi0.p, p0.p, d_flag.p);
+                       S.lo[0].p, S.hi[0].p, S.pay[0].p, d_flag);
     CPD_LAUNCH_CHECK();
-    uint64_t *klo = lo0.p, *khi = hi0.p, *olo = lo1.p, *ohi = hi1.p;
-    int32_t *kp = p0.p, *op = p1.p;
+    uint64_t *klo = S.lo[0].p, *khi = S.hi[0].p, *olo = S.lo[1].p, *ohi = S.hi[1].p;
+    int32_t *kp = S.pay[0].p, *op = S.pay[1].p;
     CPD_TRY(radix_sort(klo, khi, kp, olo, ohi, op, nnz, total_bits, s));
 
     // a4: duplicate merge
-    DevBuf<uint8_t> dl;
     DevBuf<int32_t> pos;
-    CPD_TRY(dl.alloc(nnz, s));
+    CPD_TRY(S.dl.alloc(nnz, s));
     CPD_TRY(pos.alloc(nnz, s));
-    hipLaunchKernelGGL(k_first_diff, dim3(grid1(nnz)), dim3(256), 0, s, klo, khi, kl, nnz, dl.p);
+    hipLaunchKernelGGL(k_first_diff, dim3(grid1(nnz)), dim3(256), 0, s, klo, khi, kl, nnz, S.dl.p);
     CPD_LAUNCH_CHECK();
-    int32_t *d_nuniq = d_flag.p + 1;
-    CPD_TRY(exclusive_scan(IsNew{dl.p, nm}, nnz, pos.p, d_nuniq, s));
+    CPD_TRY(exclusive_scan(IsNew{S.dl.p, nm}, nnz, pos.p, d_flag + 1, s));
     int32_t h_flag[2];
-    CPD_HIP(hipMemcpyAsync(h_flag, d_flag.p, sizeof(int32_t) * 2, hipMemcpyDeviceToHost, s));
+    CPD_HIP(hipMemcpyAsync(h_flag, d_flag, sizeof(int32_t) * 2, hipMemcpyDeviceToHost, s));
     CPD_HIP(hipStreamSynchronize(s));
     if (h_flag[0]) CPD_FAIL(CPD_EINVAL, "an index is out of range for its mode");
-    const int64_t n = h_flag[1];
-
-    // merged keys, levels and values; without duplicates the sorted arrays
-    // are the merged ones (the payload carries the values' bits)
-    DevBuf<uint8_t> udl_buf;
-    DevBuf<float> uval_buf;
-    const uint8_t *udl = dl.p;
-    const float *uval = reinterpret_cast<const float *>(kp);
-    if (n != nnz) {
-        CPD_TRY(udl_buf.alloc(nnz, s));
-        CPD_TRY(uval_buf.alloc(nnz, s));
-        hipLaunchKernelGGL(k_merge, dim3(grid1(nnz)), dim3(256), 0, s, klo, khi, kp, dl.p, pos.p, nnz, nm, olo, ohi,
-                           uval_buf.p, udl_buf.p);
+    S.n = h_flag[1];
+    // without duplicates the sorted arrays are the merged ones (the payload
+    // carries the values' bits)
+    S.klo = klo;
+    S.khi = khi;
+    S.udl = S.dl.p;
+    S.val = reinterpret_cast<const float *>(kp);
+    if (S.n != nnz) {
+        CPD_TRY(S.mdl.alloc(nnz, s));
+        CPD_TRY(S.mval.alloc(nnz, s));
+        hipLaunchKernelGGL(k_merge, dim3(grid1(nnz)), dim3(256), 0, s, klo, khi, kp, S.dl.p, pos.p, nnz, nm, olo, ohi,
+                           S.mval.p, S.mdl.p);
         CPD_LAUNCH_CHECK();
-        std::swap(klo, olo);
-        std::swap(khi, ohi);
-        udl = udl_buf.p;
-        uval = uval_buf.p;
+        S.klo = olo;
+        S.khi = ohi;
+        S.udl = S.mdl.p;
+        S.val = S.mval.p;
     }
-    pos.release();
+    return CPD_OK;
+}
 
-    // a5: fiber compression, levels N-2 .. 0
+// Keys of the same nonzeros in another tree order: level l of the new order
+// takes the field of level src[l] of the old one.
+struct LevelMap {
+    int src[CPD_MAX_MODES];
+};
+
+__global__ void k_repack(const uint64_t *__restrict__ a, const float *__restrict__ val, int64_t n, KeyLayout ka,
+                         KeyLayout kx, LevelMap map, uint64_t *__restrict__ x, int32_t *__restrict__ pay) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const uint64_t key = a[k];
+    uint64_t out = 0;
+    for (int l = 0; l < kx.nl; ++l) {
+        const int q = map.src[l];
+        if (kx.bits[l]) out |= (uint64_t)key_field(key, 0ull, ka.shift[q], ka.bits[q]) << kx.shift[l];
+    }
+    x[k] = out;
+    pay[k] = __float_as_int(val[k]);
+}
+
+// The nonzeros of tree A (one-word keys, sorted and merged) in the order of
+// a tree rooted at mode x with the other levels in A's order: A's order is
+// the order of every key sharing a root index, so a stable sort on the new
+// root field alone finishes it (Section III's sort, one field instead of all).
+cpd_status derive(int nm, const int64_t *dims, const int32_t *order_a, const KeyLayout &ka, const Sorted &A, int x,
+                  int32_t *order_x, KeyLayout *kx, hipStream_t s, Sorted &S) {
+    LevelMap map{};
+    order_x[0] = x;
+    map.src[0] = -1;
+    for (int l = 0, k = 1; l < nm; ++l) {
+        if (order_a[l] == x) map.src[0] = l;
+        else {
+            order_x[k] = order_a[l];
+            map.src[k++] = l;
+        }
+    }
+    int total = 0;
+    *kx = key_layout(nm, dims, order_x, &total);
+    const int64_t n = A.n;
+    for (int b = 0; b < 2; ++b) {
+        CPD_TRY(S.lo[b].alloc(n, s));
+        CPD_TRY(S.pay[b].alloc(n, s));
+    }
+    hipLaunchKernelGGL(k_repack, dim3(grid1(n)), dim3(256), 0, s, A.klo, A.val, n, ka, *kx, map, S.lo[0].p,
+                       S.pay[0].p);
+    CPD_LAUNCH_CHECK();
+    uint64_t *klo = S.lo[0].p, *khi = nullptr, *olo = S.lo[1].p, *ohi = nullptr;
+    int32_t *kp = S.pay[0].p, *op = S.pay[1].p;
+    CPD_TRY(radix_sort(klo, khi, kp, olo, ohi, op, n, total, s, kx->shift[0]));
+    CPD_TRY(S.dl.alloc(n, s));
+    hipLaunchKernelGGL(k_first_diff, dim3(grid1(n)), dim3(256), 0, s, klo, (const uint64_t *)nullptr, *kx, n,
+                       S.dl.p);
+    CPD_LAUNCH_CHECK();
+    S.klo = klo;
+    S.udl = S.dl.p;
+    S.val = reinterpret_cast<const float *>(kp);
+    S.n = n;
+    return CPD_OK;
+}
+
+// a5: fiber compression of sorted, merged nonzeros into a tree, with the
+// leaf words, leaf ranking and internal rows the MTTKRP kernels read.
+cpd_status compress(int nm, const int64_t *dims, const int32_t *order, const KeyLayout &kl, const Sorted &S,
+                    int32_t *d_flag, hipStream_t s, cpd_csf *out) {
+    const int64_t n = S.n;
+    const uint64_t *klo = S.klo, *khi = S.khi;
+    const uint8_t *udl = S.udl;
     std::vector<DevBuf<int32_t>> scans(nm - 1);
     for (int l = 0; l < nm - 1; ++l) {
         CPD_TRY(scans[l].alloc(n, s));
-        CPD_TRY(exclusive_scan(AtLevel{udl, l}, n, scans[l].p, d_flag.p + 2 + l, s));
+        CPD_TRY(exclusive_scan(AtLevel{udl, l}, n, scans[l].p, d_flag + 2 + l, s));
     }
     int32_t h_counts[CPD_MAX_MODES] = {};
     if (nm > 1)
-        CPD_HIP(hipMemcpyAsync(h_counts, d_flag.p + 2, sizeof(int32_t) * (nm - 1), hipMemcpyDeviceToHost, s));
+        CPD_HIP(hipMemcpyAsync(h_counts, d_flag + 2, sizeof(int32_t) * (nm - 1), hipMemcpyDeviceToHost, s));
     CPD_HIP(hipStreamSynchronize(s));
 
     cpd_csf_s *c = new (std::nothrow) cpd_csf_s();
@@ -622,7 +724,7 @@ cpd_status build(int nm, const int64_t *dims, int64_t nnz, const int32_t *const 
     if (c->leafw && st == CPD_OK) {
         // rank the leaf ids by frequency in a strided sample of the leaves
         const int64_t nid = dims[order[nm - 1]];
-        cpd_status rs = rank_ids(c->fids[nm - 1], n, nid, c->leaf_perm, c->leaf_rank, d_flag.p + 1, s);
+        cpd_status rs = rank_ids(c->fids[nm - 1], n, nid, c->leaf_perm, c->leaf_rank, d_flag + 1, s);
         if (rs == CPD_OK) {
             hipLaunchKernelGGL(k_leafw, dim3(grid1(n)), dim3(256), 0, s, udl,
                                (const int32_t *)c->fids[nm - 1], (const int32_t *)c->leaf_rank, n, c->leafw);
@@ -634,7 +736,7 @@ cpd_status build(int nm, const int64_t *dims, int64_t nnz, const int32_t *const 
             if (st == CPD_OK && hipGetLastError() != hipSuccess) st = CPD_EHIP;
         }
     }
-    if (st == CPD_OK && hipMemcpyAsync(c->vals, uval, sizeof(float) * n, hipMemcpyDeviceToDevice, s) != hipSuccess)
+    if (st == CPD_OK && hipMemcpyAsync(c->vals, S.val, sizeof(float) * n, hipMemcpyDeviceToDevice, s) != hipSuccess)
         st = CPD_EHIP;
     if (st == CPD_OK && hipStreamSynchronize(s) != hipSuccess) st = CPD_EHIP;
     if (st != CPD_OK) {
@@ -642,6 +744,86 @@ cpd_status build(int nm, const int64_t *dims, int64_t nnz, const int32_t *const 
         CPD_FAIL(st, "CSF compression kernels failed");
     }
     *out = c;
+    return CPD_OK;
+}
+
+cpd_status build(int nm, const int64_t *dims, int64_t nnz, const int32_t *const *inds,
+                 const float *vals, const int32_t *order_in, hipStream_t s, cpd_csf *out) {
+    CPD_TRY(check_coo(nm, dims, nnz, inds, vals, out));
+    keep_pool_memory();
+    int32_t order[CPD_MAX_MODES];
+    if (order_in) {
+        bool seen[CPD_MAX_MODES] = {};
+        for (int l = 0; l < nm; ++l) {
+            int m = order_in[l];
+            if (m < 0 || m >= nm || seen[m]) CPD_FAIL(CPD_EINVAL, "order is not a permutation of the modes");
+            seen[m] = true;
+            order[l] = m;
+        }
+    } else {
+        std::iota(order, order + nm, 0);
+        std::stable_sort(order, order + nm, [&](int a, int b) { return dims[a] < dims[b]; });
+    }
+    int total_bits = 0;
+    const KeyLayout kl = key_layout(nm, dims, order, &total_bits);
+    if (total_bits > 128) CPD_FAIL(CPD_EUNSUPPORTED, "packed key needs %d bits (> 128)", total_bits);
+    // d_flag: [0] bad index, [1] merged nonzeros, [2..] level counts
+    DevBuf<int32_t> d_flag;
+    CPD_TRY(d_flag.alloc(1 + CPD_MAX_MODES, s));
+    CPD_HIP(hipMemsetAsync(d_flag.p, 0, sizeof(int32_t) * (1 + CPD_MAX_MODES), s));
+    Sorted S;
+    CPD_TRY(sort_merge(nm, kl, total_bits, inds, order, dims, vals, nnz, d_flag.p, s, S));
+    return compress(nm, dims, order, kl, S, d_flag.p, s, out);
+}
+
+// One tree rooted at each mode, the other modes by descending length (ties
+// by mode index).  The tree of the longest mode is built in full; every
+// other tree is derived from its sorted nonzeros by a sort on its root field.
+cpd_status build_rooted(int nm, const int64_t *dims, int64_t nnz, const int32_t *const *inds, const float *vals,
+                        hipStream_t s, cpd_csf *out) {
+    CPD_TRY(check_coo(nm, dims, nnz, inds, vals, out));
+    for (int m = 0; m < nm; ++m) out[m] = nullptr;
+    keep_pool_memory();
+    int32_t desc[CPD_MAX_MODES];
+    std::iota(desc, desc + nm, 0);
+    std::stable_sort(desc, desc + nm, [&](int a, int b) { return dims[a] > dims[b]; });
+    int total_bits = 0;
+    const KeyLayout ka = key_layout(nm, dims, desc, &total_bits);
+    if (total_bits > 128) CPD_FAIL(CPD_EUNSUPPORTED, "packed key needs %d bits (> 128)", total_bits);
+    cpd_csf trees[CPD_MAX_MODES] = {};
+    auto fail = [&](cpd_status st) {
+        for (int m = 0; m < nm; ++m)
+            if (trees[m]) free_csf(trees[m]);
+        return st;
+    };
+    if (total_bits > 64) {
+        // two-word keys: independent builds
+        for (int m = 0; m < nm; ++m) {
+            int32_t ord[CPD_MAX_MODES];
+            ord[0] = m;
+            for (int l = 0, k = 1; l < nm; ++l)
+                if (desc[l] != m) ord[k++] = desc[l];
+            cpd_status st = build(nm, dims, nnz, inds, vals, ord, s, &trees[m]);
+            if (st != CPD_OK) return fail(st);
+        }
+    } else {
+        DevBuf<int32_t> d_flag;
+        CPD_TRY(d_flag.alloc(1 + CPD_MAX_MODES, s));
+        CPD_HIP(hipMemsetAsync(d_flag.p, 0, sizeof(int32_t) * (1 + CPD_MAX_MODES), s));
+        Sorted A;
+        CPD_TRY(sort_merge(nm, ka, total_bits, inds, desc, dims, vals, nnz, d_flag.p, s, A));
+        cpd_status st = compress(nm, dims, desc, ka, A, d_flag.p, s, &trees[desc[0]]);
+        if (st != CPD_OK) return fail(st);
+        for (int i = 1; i < nm; ++i) {
+            Sorted S;
+            int32_t ord[CPD_MAX_MODES];
+            KeyLayout kx{};
+            st = derive(nm, dims, desc, ka, A, desc[i], ord, &kx, s, S);
+            if (st == CPD_OK) st = compress(nm, dims, ord, kx, S, d_flag.p, s, &trees[desc[i]]);
+            if (st != CPD_OK) return fail(st);
+        }
+    }
+    for (int m = 0; m < nm; ++m) out[m] = trees[m];
     return CPD_OK;
 }
 
@@ -791,6 +973,14 @@ cpd_status cpd_csf_build(int32_t nmodes, const int64_t *dims, int64_t nnz, const
     clear_error();
     if (out) *out = nullptr;
     return build(nmodes, dims, nnz, inds, vals, order, (hipStream_t)stream, out);
+}
+
+cpd_status cpd_csf_build_rooted(int32_t nmodes, const int64_t *dims, int64_t nnz, const int32_t *const *inds,
+                                const float *vals, void *stream, cpd_csf *out) {
+    clear_error();
+    if (out)
+        for (int m = 0; m < std::min<int32_t>(std::max<int32_t>(nmodes, 0), CPD_MAX_MODES); ++m) out[m] = nullptr;
+    return build_rooted(nmodes, dims, nnz, inds, vals, (hipStream_t)stream, out);
 }
 
 cpd_status cpd_csf_info(cpd_csf c, int32_t *nmodes, int32_t *order, int64_t *counts) {

@@ -64,6 +64,12 @@ def test_argument_errors_return_einval_without_touching_the_gpu():
     # order not a permutation
     order = (ctypes.c_int32 * 3)(0, 0, 1)
     assert L.cpd_csf_build(3, dims, 5, ptrs, 1, order, None, ctypes.byref(h)) == cpd.CPD_EINVAL
+    # the rooted set checks the same arguments and leaves every output NULL
+    hs = (ctypes.c_void_p * 3)(7, 7, 7)
+    assert L.cpd_csf_build_rooted(3, dims, 0, ptrs, 1, None, hs) == cpd.CPD_EINVAL
+    assert list(hs) == [None, None, None]
+    assert L.cpd_csf_build_rooted(1, dims, 10, ptrs, 1, None, hs) == cpd.CPD_EINVAL
+    assert L.cpd_csf_build_rooted(3, dims, 5, ptrs, 1, None, None) == cpd.CPD_EINVAL
     # mttkrp on a null handle
     assert L.cpd_mttkrp(None, None, 8, 8, 0, None, 8, None, None) == cpd.CPD_EINVAL
     # als: rank out of range

@@ -101,6 +101,54 @@ def test_csf_bit_exact(case):
         c.free()
 
 
+def _rooted_order(nm, mode, dims):
+    rest = sorted((m for m in range(nm) if m != mode), key=lambda m: (-dims[m], m))
+    return [mode] + rest
+
+
+def _same_tree(c, ref, nm):
+    assert c.order == ref["order"]
+    assert c.counts == ref["counts"]
+    for l in range(nm):
+        fids, fptr, v = c.export(l)
+        np.testing.assert_array_equal(fids.cpu().numpy(), ref["fids"][l])
+        if l < nm - 1:
+            np.testing.assert_array_equal(fptr.cpu().numpy(), ref["fptr"][l])
+        else:
+            assert v.cpu().numpy().tobytes() == ref["vals"].tobytes()
+
+
+ROOTED_EXTRA = {
+    # equal lengths: ties go to the lower mode
+    "ties": lambda: _with_dups(_tensor((50, 40, 50, 40), 20_000, (0.8, 0.0, 0.8, 0.0), 31), 3_000, 32),
+    # 4 x 14 + 10 = 66-bit keys: every tree is built on its own
+    "wide5": lambda: _tensor((9000, 9000, 9000, 9000, 600), 30_000, (1.0, 1.0, 1.0, 1.0, 1.0), 33),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES) + list(ROOTED_EXTRA))
+def test_csf_build_rooted_bit_exact(name):
+    """One tree per mode, derived from the longest mode's sorted nonzeros:
+    each equals the oracle's tree for (mode, others by descending length)."""
+    cpd = _cpd()
+    t = (CASES.get(name) or ROOTED_EXTRA[name])()
+    inds, vals = t.numpy()
+    trees = cpd.csf_build_rooted(_dev(t.inds), _dev(t.vals), t.dims)
+    assert len(trees) == t.nmodes
+    for m, c in enumerate(trees):
+        ref = ocsf.build(t.dims, inds, t.vals.numpy(), _rooted_order(t.nmodes, m, t.dims))
+        _same_tree(c, ref, t.nmodes)
+        c.free()
+
+
+def test_csf_build_rooted_rejects_bad_indices():
+    cpd = _cpd()
+    inds = torch.tensor([[0, 1], [0, 3], [0, 1]], device="cuda")
+    with pytest.raises(cpd.CpdError) as e:
+        cpd.csf_build_rooted(inds, torch.ones(2, device="cuda"), (2, 3, 2))
+    assert e.value.status == cpd.CPD_EINVAL
+
+
 def test_csf_build_is_deterministic():
     cpd = _cpd()
     t = CASES["zipf4"]()
