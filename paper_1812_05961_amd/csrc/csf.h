@@ -74,6 +74,11 @@ cpd_status sample_freq(const int32_t *ids, int64_t n, int64_t nid, int64_t max_s
 cpd_status rank_ids(const int32_t *ids, int64_t n, int64_t nid, int32_t *perm, int32_t *rank, int32_t *nruns,
                     hipStream_t s);
 
+// The same ranking of the index field [shift, shift + bits) of n sorted
+// keys (one or two words; hi may be null).
+cpd_status rank_key_field(const uint64_t *lo, const uint64_t *hi, int shift, int bits, int64_t n, int64_t nid,
+                          int32_t *perm, int32_t *rank, int32_t *nruns, hipStream_t s);
+
 // Ranking of the indices of level l (1 <= l < N) of a tree: the leaf ranking
 // for l = N-1, else built on first use and cached in the handle.  Null
 // outputs when the tree has no ranking (leaf index above 2^29).

@@ -36,6 +36,29 @@ __device__ __forceinline__ uint32_t key_field(uint64_t lo, uint64_t hi, int s, i
     return (uint32_t)(((lo >> s) | (hi << (64 - s))) & mask);
 }
 
+// Keys of the same nonzeros in another tree order: level l of the new order
+// takes the field of level src[l] of the old one.
+struct LevelMap {
+    int src[CPD_MAX_MODES];
+};
+
+// The key of the same nonzero in the other layout (one-word keys).
+struct Repack {
+    const uint64_t *a;  // sorted keys in layout ka
+    const float *val;   // their values
+    KeyLayout ka, kx;
+    LevelMap map;
+};
+
+__device__ __forceinline__ uint64_t repack_key(const Repack &r, uint64_t key) {
+    uint64_t out = 0;
+    for (int l = 0; l < r.kx.nl; ++l) {
+        const int q = r.map.src[l];
+        if (r.kx.bits[l]) out |= (uint64_t)key_field(key, 0ull, r.ka.shift[q], r.ka.bits[q]) << r.kx.shift[l];
+    }
+    return out;
+}
+
 // Packed key of nonzero k (root index most significant) and its value as the
 // sort payload (bits of the float), with the index check of every level.
 __global__ void k_pack(LevelInds in, KeyLayout kl, const int64_t *dims_by_level, const float *vals, int64_t n,
@@ -64,8 +87,11 @@ __global__ void k_pack(LevelInds in, KeyLayout kl, const int64_t *dims_by_level,
 }
 
 // ---- radix sort: per-tile digit histogram (digit-major output)
+// RP: the keys are those of rp.a in layout rp.kx (the first pass of a
+// re-sort into another tree order).
+template <bool RP>
 __global__ void __launch_bounds__(RS_THREADS)
-k_radix_hist(const uint64_t *keys, int64_t n, int shift, int32_t *hist, int64_t ntiles) {
+k_radix_hist(const uint64_t *keys, Repack rp, int64_t n, int shift, int32_t *hist, int64_t ntiles) {
     __shared__ int32_t h[256];
     h[threadIdx.x] = 0;
     __syncthreads();
@@ -73,7 +99,7 @@ k_radix_hist(const uint64_t *keys, int64_t n, int shift, int32_t *hist, int64_t 
 #pragma unroll
     for (int j = 0; j < RS_ITEMS; ++j) {
         int64_t i = base + (int64_t)j * RS_THREADS + threadIdx.x;
-        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1);
+        if (i < n) atomicAdd(&h[((RP ? repack_key(rp, rp.a[i]) : keys[i]) >> shift) & 255u], 1);
     }
     __syncthreads();
     hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
@@ -142,10 +168,11 @@ __device__ __forceinline__ void wave_sync() {
 constexpr int RS_WAVES = RS_THREADS / 64;
 constexpr int RS_WAVE_ITEMS = RS_TILE / RS_WAVES;
 
+template <bool RP>
 __global__ void __launch_bounds__(RS_THREADS)
-k_radix_scatter1(const uint64_t *__restrict__ keys, const int32_t *__restrict__ pay, uint64_t *__restrict__ okeys,
-                 int32_t *__restrict__ opay, const int32_t *__restrict__ offsets, int64_t n, int64_t ntiles,
-                 int shift) {
+k_radix_scatter1(const uint64_t *__restrict__ keys, const int32_t *__restrict__ pay, Repack rp,
+                 uint64_t *__restrict__ okeys, int32_t *__restrict__ opay, const int32_t *__restrict__ offsets,
+                 int64_t n, int64_t ntiles, int shift) {
     __shared__ uint64_t s_buf[RS_TILE];       // the tile in digit order: keys, then payloads
     __shared__ int32_t s_cnt[RS_WAVES][256];  // per-wave digit counts, then each wave's digit starts
     __shared__ int32_t s_off[256];            // global start minus tile start, per digit
@@ -160,8 +187,13 @@ k_radix_scatter1(const uint64_t *__restrict__ keys, const int32_t *__restrict__ 
 #pragma unroll
     for (int r = 0; r < RS_ITEMS; ++r) {
         const int j = wave * RS_WAVE_ITEMS + r * 64 + lane;
-        k[r] = j < tn ? keys[tbase + j] : 0ull;
-        p[r] = j < tn ? pay[tbase + j] : 0;
+        if (RP) {
+            k[r] = j < tn ? repack_key(rp, rp.a[tbase + j]) : 0ull;
+            p[r] = j < tn ? __float_as_int(rp.val[tbase + j]) : 0;
+        } else {
+            k[r] = j < tn ? keys[tbase + j] : 0ull;
+            p[r] = j < tn ? pay[tbase + j] : 0;
+        }
     }
     wave_sync();
     const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
@@ -256,25 +288,38 @@ struct HistAt {
 // [lo_bit, bits) with an int32 payload, 8 bits per pass, ping-ponging between
 // the (k*, p*) and (o*, op*) buffers; on return k*, kp point at the sorted
 // data.  With lo_bit > 0 the order of equal sorted bits is the input order.
-cpd_status radix_sort(uint64_t *&klo, uint64_t *&khi, int32_t *&kp, uint64_t *&olo, uint64_t *&ohi, int32_t *&op,
-                      int64_t n, int bits, hipStream_t s, int lo_bit) {
+static cpd_status radix_sort_rp(uint64_t *&klo, uint64_t *&khi, int32_t *&kp, uint64_t *&olo, uint64_t *&ohi,
+                                int32_t *&op, int64_t n, int bits, hipStream_t s, int lo_bit, const Repack *rp) {
     const int64_t ntiles = ceil_div(n, RS_TILE);
     if (ntiles == 0) return CPD_OK;
     DevBuf<int32_t> hist;
     CPD_TRY(hist.alloc((size_t)256 * ntiles, s));
-    const int passes = (bits - lo_bit + 7) / 8;
+    const int passes = std::max((bits - lo_bit + 7) / 8, rp ? 1 : 0);
+    const Repack none{};
     for (int d = 0; d < passes; ++d) {
         int word = (lo_bit + 8 * d) / 64, shift = (lo_bit + 8 * d) % 64;
         const uint64_t *src = word ? khi : klo;
-        hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)ntiles), dim3(RS_THREADS), 0, s, src, n, shift, hist.p, ntiles);
+        const bool first = rp && d == 0;
+        const Repack &r = first ? *rp : none;
+        if (first)
+            hipLaunchKernelGGL(k_radix_hist<true>, dim3((unsigned)ntiles), dim3(RS_THREADS), 0, s, src, r, n, shift,
+                               hist.p, ntiles);
+        else
+            hipLaunchKernelGGL(k_radix_hist<false>, dim3((unsigned)ntiles), dim3(RS_THREADS), 0, s, src, r, n, shift,
+                               hist.p, ntiles);
         CPD_LAUNCH_CHECK();
         CPD_TRY(exclusive_scan(HistAt{hist.p}, 256 * ntiles, hist.p, (int32_t *)nullptr, s));
         if (khi)
             hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)ntiles), dim3(RS_THREADS), 0, s, klo, khi, kp, olo,
                                ohi, op, (const int32_t *)hist.p, n, ntiles, word, shift);
+        else if (first)
+            hipLaunchKernelGGL(k_radix_scatter1<true>, dim3((unsigned)ntiles), dim3(RS_THREADS), 0, s,
+                               (const uint64_t *)klo, (const int32_t *)kp, r, olo, op, (const int32_t *)hist.p, n,
+                               ntiles, shift);
         else
-            hipLaunchKernelGGL(k_radix_scatter1, dim3((unsigned)ntiles), dim3(RS_THREADS), 0, s, klo, kp, olo, op,
-                               (const int32_t *)hist.p, n, ntiles, shift);
+            hipLaunchKernelGGL(k_radix_scatter1<false>, dim3((unsigned)ntiles), dim3(RS_THREADS), 0, s,
+                               (const uint64_t *)klo, (const int32_t *)kp, r, olo, op, (const int32_t *)hist.p, n,
+                               ntiles, shift);
         CPD_LAUNCH_CHECK();
         std::swap(klo, olo);
         std::swap(khi, ohi);
@@ -283,11 +328,24 @@ cpd_status radix_sort(uint64_t *&klo, uint64_t *&khi, int32_t *&kp, uint64_t *&o
     return CPD_OK;
 }
 
+cpd_status radix_sort(uint64_t *&klo, uint64_t *&khi, int32_t *&kp, uint64_t *&olo, uint64_t *&ohi, int32_t *&op,
+                      int64_t n, int bits, hipStream_t s, int lo_bit) {
+    return radix_sort_rp(klo, khi, kp, olo, ohi, op, n, bits, s, lo_bit, nullptr);
+}
+
 namespace {
 
 // ---- leaf ranking: leaf ids ordered by how often a strided sample of the
 // leaves holds them (descending, ties by id); only the order of a private
 // copy of the leaf factor depends on it, never a result.
+__global__ void k_sample_field(const uint64_t *lo, const uint64_t *hi, int shift, int bits, int64_t stride, int64_t ns,
+                               uint64_t *key, int32_t *pay) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ns) return;
+    key[i] = key_field(lo[i * stride], hi ? hi[i * stride] : 0ull, shift, bits);
+    pay[i] = 0;
+}
+
 __global__ void k_sample(const int32_t *ids, int64_t stride, int64_t ns, uint64_t *key, int32_t *pay) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= ns) return;
@@ -315,17 +373,17 @@ __global__ void k_run_counts(const uint64_t *key, const int32_t *starts, const i
     cnt[key[b]] = e - b;
 }
 
-__global__ void k_rank_keys(const int32_t *cnt, int64_t nid, uint64_t *key, int32_t *pay) {
+__global__ void k_rank_keys(const int32_t *cnt, int64_t nid, int64_t ns, int ibits, uint64_t *key, int32_t *pay) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nid) return;
-    key[i] = ((uint64_t)(0x7fffffff - cnt[i]) << 32) | (uint64_t)i;
+    key[i] = ((uint64_t)(ns - cnt[i]) << ibits) | (uint64_t)i;
     pay[i] = 0;
 }
 
-__global__ void k_rank_scatter(const uint64_t *key, int64_t nid, int32_t *perm, int32_t *rank) {
+__global__ void k_rank_scatter(const uint64_t *key, int64_t nid, int ibits, int32_t *perm, int32_t *rank) {
     int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= nid) return;
-    const int32_t id = (int32_t)(key[r] & 0xffffffffull);
+    const int32_t id = (int32_t)(key[r] & ((1ull << ibits) - 1ull));
     perm[r] = id;
     rank[id] = (int32_t)r;
 }
@@ -354,12 +412,6 @@ struct IsNew {
     __device__ int32_t operator()(int64_t i) const { return dl[i] < nl ? 1 : 0; }
 };
 
-struct AtLevel {
-    const uint8_t *dl;
-    int l;
-    __device__ int32_t operator()(int64_t i) const { return dl[i] <= l ? 1 : 0; }
-};
-
 // One thread per run of equal keys: the float sum of the run in input order
 // (the sort is stable, so the run is in input order).
 __global__ void k_merge(const uint64_t *lo, const uint64_t *hi, const int32_t *pay, const uint8_t *dl,
@@ -374,40 +426,6 @@ __global__ void k_merge(const uint64_t *lo, const uint64_t *hi, const int32_t *p
     if (uhi) uhi[p] = hi[k];
     uval[p] = s;
     udl[p] = dl[k];
-}
-
-__global__ void k_compact(const uint64_t *lo, const uint64_t *hi, KeyLayout kl, const uint8_t *dl,
-                          int64_t n, int l, const int32_t *scan_l, const int32_t *scan_next,
-                          int32_t *fids, int32_t *fptr) {
-    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n || dl[k] > l) return;
-    int32_t j = scan_l[k];
-    fids[j] = (int32_t)key_field(lo[k], hi ? hi[k] : 0ull, kl.shift[l], kl.bits[l]);
-    fptr[j] = scan_next ? scan_next[k] : (int32_t)k;
-}
-
-__global__ void k_leaf(const uint64_t *lo, const uint64_t *hi, KeyLayout kl, int64_t n,
-                       int32_t *fids) {
-    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
-    int l = kl.nl - 1;
-    fids[k] = (int32_t)key_field(lo[k], hi ? hi[k] : 0ull, kl.shift[l], kl.bits[l]);
-}
-
-__global__ void k_leafw(const uint8_t *dl, const int32_t *fids, const int32_t *rank, int64_t n, int32_t *leafw) {
-    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
-    leafw[k] = (int32_t)(((uint32_t)dl[k] << 29) | (uint32_t)rank[fids[k]]);
-}
-
-__global__ void k_uprow(const uint64_t *lo, const uint64_t *hi, KeyLayout kl, int64_t n, int l, int32_t *out) {
-    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
-    out[k] = (int32_t)key_field(lo[k], hi ? hi[k] : 0ull, kl.shift[l], kl.bits[l]);
-}
-
-__global__ void k_set_last(int32_t *fptr, int64_t at, const int32_t *value) {
-    fptr[at] = *value;
 }
 
 __global__ void k_set_last_const(int32_t *fptr, int64_t at, int32_t value) { fptr[at] = value; }
@@ -520,6 +538,162 @@ KeyLayout key_layout(int nm, const int64_t *dims, const int32_t *order, int *tot
     return kl;
 }
 
+// ---- fiber compression in two passes over the sorted nonzeros.  Pass 1:
+// per tile of CT_TILE nonzeros, the number that open a node at each level
+// l < N-1 (first differing level <= l).
+constexpr int CT_THREADS = 256, CT_ITEMS = 16, CT_TILE = CT_THREADS * CT_ITEMS;
+
+__global__ void __launch_bounds__(CT_THREADS)
+k_level_counts(const uint8_t *__restrict__ dl, int64_t n, int nlv, int32_t *__restrict__ partial, int64_t nb) {
+    __shared__ int32_t red[CT_THREADS / 64][CPD_MAX_MODES];
+    const int64_t base = (int64_t)blockIdx.x * CT_TILE;
+    int32_t c[CPD_MAX_MODES] = {};
+#pragma unroll
+    for (int j = 0; j < CT_ITEMS; ++j) {
+        const int64_t i = base + (int64_t)j * CT_THREADS + threadIdx.x;
+        const int d = i < n ? dl[i] : 255;
+        for (int l = 0; l < nlv; ++l) c[l] += d <= l;
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int l = 0; l < nlv; ++l) {
+        int32_t v = c[l];
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        if (lane == 0) red[wave][l] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < nlv) {
+        int32_t t = 0;
+        for (int w = 0; w < CT_THREADS / 64; ++w) t += red[w][threadIdx.x];
+        partial[(int64_t)threadIdx.x * nb + blockIdx.x] = t;
+    }
+}
+
+// One block per level: exclusive scan of that level's tile counts in place,
+// the level's node count to total[level].
+__global__ void __launch_bounds__(SCAN_THREADS) k_scan_levels(int32_t *partial, int64_t nb, int32_t *total) {
+    __shared__ int32_t smem[4];
+    int32_t *p = partial + (int64_t)blockIdx.x * nb;
+    int32_t carry = 0;
+    for (int64_t b0 = 0; b0 < nb; b0 += SCAN_THREADS) {
+        const int64_t i = b0 + threadIdx.x;
+        const int32_t v = i < nb ? p[i] : 0;
+        int32_t tot;
+        const int32_t inc = block_inclusive_scan(v, smem, &tot);
+        if (i < nb) p[i] = carry + inc - v;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) total[blockIdx.x] = carry;
+}
+
+struct TreeOut {
+    int32_t *fids[CPD_MAX_MODES];
+    int32_t *fptr[CPD_MAX_MODES];
+    int32_t *uprow[CPD_MAX_MODES];  // levels 1..N-2, or null
+    int32_t *leafw;                  // or null
+    const int32_t *leaf_rank;        // with leafw
+    float *vals;
+};
+
+// Pass 2: each tile scans its nonzeros' node openings (per level, packed in
+// 16-bit fields: a tile holds at most 4096), so every node finds its slot;
+// the node's index and first child are stored there.  Each nonzero's leaf
+// index, leaf word, internal rows and value are written alongside.
+template <bool TWO>
+__global__ void __launch_bounds__(CT_THREADS)
+k_compress(const uint64_t *__restrict__ lo, const uint64_t *__restrict__ hi, KeyLayout kl,
+           const uint8_t *__restrict__ dl, const float *__restrict__ val, int64_t n,
+           const int32_t *__restrict__ partial, int64_t nb, TreeOut t) {
+    __shared__ uint8_t s_dl[CT_TILE];
+    __shared__ uint64_t s_pre[CT_TILE];  // per nonzero: openings before it in the tile, per level
+    __shared__ uint32_t s_w[2][CT_THREADS / 64];
+    const int nl = kl.nl, nlv = nl - 1;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t base = (int64_t)blockIdx.x * CT_TILE;
+#pragma unroll
+    for (int j = 0; j < CT_ITEMS; ++j) {
+        const int e = j * CT_THREADS + tid;
+        s_dl[e] = base + e < n ? dl[base + e] : (uint8_t)255;
+    }
+    __syncthreads();
+    // this thread's CT_ITEMS consecutive nonzeros
+    uint64_t own = 0;
+    for (int j = 0; j < CT_ITEMS; ++j) {
+        const int d = s_dl[tid * CT_ITEMS + j];
+        for (int l = 0; l < nlv; ++l) own += (uint64_t)(d <= l) << (16 * l);
+    }
+    // exclusive scan over the block; no field exceeds 4096, so the two
+    // 32-bit halves scan independently
+    uint32_t h[2] = {(uint32_t)own, (uint32_t)(own >> 32)};
+    uint32_t ex[2];
+    for (int q = 0; q < 2; ++q) {
+        uint32_t v = h[q];
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(v, o, 64);
+            if (lane >= o) v += y;
+        }
+        if (lane == 63) s_w[q][wave] = v;
+        ex[q] = v - h[q];
+    }
+    __syncthreads();
+    for (int q = 0; q < 2; ++q)
+        for (int w = 0; w < wave; ++w) ex[q] += s_w[q][w];
+    uint64_t run = (uint64_t)ex[0] | ((uint64_t)ex[1] << 32);
+    for (int j = 0; j < CT_ITEMS; ++j) {
+        const int e = tid * CT_ITEMS + j;
+        s_pre[e] = run;
+        const int d = s_dl[e];
+        for (int l = 0; l < nlv; ++l) run += (uint64_t)(d <= l) << (16 * l);
+    }
+    int32_t off[CPD_MAX_MODES];
+    for (int l = 0; l < nlv; ++l) off[l] = partial[(int64_t)l * nb + blockIdx.x];
+    __syncthreads();
+    // half a tile at a time: its loads first (independent), then its stores
+    constexpr int H = CT_ITEMS / 2;
+    const int32_t *__restrict__ rank = t.leaf_rank;
+    int32_t *__restrict__ fleaf = t.fids[nl - 1];
+    int32_t *__restrict__ lw = t.leafw;
+    float *__restrict__ vo = t.vals;
+    for (int j0 = 0; j0 < CT_ITEMS; j0 += H) {
+        uint64_t ka[H], kb[H];
+        float v[H];
+        int32_t leaf[H], rk[H];
+#pragma unroll
+        for (int j = 0; j < H; ++j) {
+            const int64_t k = base + (j0 + j) * CT_THREADS + tid;
+            const bool in = k < n;
+            ka[j] = in ? lo[k] : 0ull;
+            kb[j] = (TWO && in) ? hi[k] : 0ull;
+            v[j] = in ? val[k] : 0.0f;
+        }
+#pragma unroll
+        for (int j = 0; j < H; ++j) {
+            const int64_t k = base + (j0 + j) * CT_THREADS + tid;
+            leaf[j] = (int32_t)key_field(ka[j], kb[j], kl.shift[nl - 1], kl.bits[nl - 1]);
+            rk[j] = (lw && k < n) ? rank[leaf[j]] : 0;
+        }
+#pragma unroll
+        for (int j = 0; j < H; ++j) {
+            const int e = (j0 + j) * CT_THREADS + tid;
+            const int64_t k = base + e;
+            if (k < n) {
+                const int d = s_dl[e];
+                const uint64_t pre = s_pre[e];
+                for (int l = d; l < nlv; ++l) {
+                    const int32_t slot = off[l] + (int32_t)((pre >> (16 * l)) & 0xffffu);
+                    t.fids[l][slot] = (int32_t)key_field(ka[j], kb[j], kl.shift[l], kl.bits[l]);
+                    t.fptr[l][slot] =
+                        l + 1 < nlv ? off[l + 1] + (int32_t)((pre >> (16 * (l + 1))) & 0xffffu) : (int32_t)k;
+                }
+                fleaf[k] = leaf[j];
+                for (int l = 1; l < nlv; ++l)
+                    if (t.uprow[l]) t.uprow[l][k] = (int32_t)key_field(ka[j], kb[j], kl.shift[l], kl.bits[l]);
+                if (lw) lw[k] = (int32_t)(((uint32_t)d << 29) | (uint32_t)rk[j]);
+                vo[k] = v[j];
+            }
+        }
+    }
+}
+
 // The sorted, merged nonzeros of one tree order: keys, values and the level
 // at which each key first differs from the previous one.
 struct Sorted {
@@ -592,26 +766,6 @@ cpd_status sort_merge(int nm, const KeyLayout &kl, int total_bits, const int32_t
     return CPD_OK;
 }
 
-// Keys of the same nonzeros in another tree order: level l of the new order
-// takes the field of level src[l] of the old one.
-struct LevelMap {
-    int src[CPD_MAX_MODES];
-};
-
-__global__ void k_repack(const uint64_t *__restrict__ a, const float *__restrict__ val, int64_t n, KeyLayout ka,
-                         KeyLayout kx, LevelMap map, uint64_t *__restrict__ x, int32_t *__restrict__ pay) {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
-    const uint64_t key = a[k];
-    uint64_t out = 0;
-    for (int l = 0; l < kx.nl; ++l) {
-        const int q = map.src[l];
-        if (kx.bits[l]) out |= (uint64_t)key_field(key, 0ull, ka.shift[q], ka.bits[q]) << kx.shift[l];
-    }
-    x[k] = out;
-    pay[k] = __float_as_int(val[k]);
-}
-
 // The nonzeros of tree A (one-word keys, sorted and merged) in the order of
 // a tree rooted at mode x with the other levels in A's order: A's order is
 // the order of every key sharing a root index, so a stable sort on the new
@@ -635,12 +789,11 @@ cpd_status derive(int nm, const int64_t *dims, const int32_t *order_a, const Key
         CPD_TRY(S.lo[b].alloc(n, s));
         CPD_TRY(S.pay[b].alloc(n, s));
     }
-    hipLaunchKernelGGL(k_repack, dim3(grid1(n)), dim3(256), 0, s, A.klo, A.val, n, ka, *kx, map, S.lo[0].p,
-                       S.pay[0].p);
-    CPD_LAUNCH_CHECK();
+    // the first sort pass forms the new keys from A's (no separate repack)
+    const Repack rp{A.klo, A.val, ka, *kx, map};
     uint64_t *klo = S.lo[0].p, *khi = nullptr, *olo = S.lo[1].p, *ohi = nullptr;
     int32_t *kp = S.pay[0].p, *op = S.pay[1].p;
-    CPD_TRY(radix_sort(klo, khi, kp, olo, ohi, op, n, total, s, kx->shift[0]));
+    CPD_TRY(radix_sort_rp(klo, khi, kp, olo, ohi, op, n, total, s, kx->shift[0], &rp));
     CPD_TRY(S.dl.alloc(n, s));
     hipLaunchKernelGGL(k_first_diff, dim3(grid1(n)), dim3(256), 0, s, klo, (const uint64_t *)nullptr, *kx, n,
                        S.dl.p);
@@ -657,16 +810,16 @@ cpd_status derive(int nm, const int64_t *dims, const int32_t *order_a, const Key
 cpd_status compress(int nm, const int64_t *dims, const int32_t *order, const KeyLayout &kl, const Sorted &S,
                     int32_t *d_flag, hipStream_t s, cpd_csf *out) {
     const int64_t n = S.n;
-    const uint64_t *klo = S.klo, *khi = S.khi;
-    const uint8_t *udl = S.udl;
-    std::vector<DevBuf<int32_t>> scans(nm - 1);
-    for (int l = 0; l < nm - 1; ++l) {
-        CPD_TRY(scans[l].alloc(n, s));
-        CPD_TRY(exclusive_scan(AtLevel{udl, l}, n, scans[l].p, d_flag + 2 + l, s));
-    }
+    const int nlv = nm - 1;
+    const int64_t nb = ceil_div(n, CT_TILE);
+    DevBuf<int32_t> partial;
+    CPD_TRY(partial.alloc((size_t)nlv * nb, s));
+    hipLaunchKernelGGL(k_level_counts, dim3((unsigned)nb), dim3(CT_THREADS), 0, s, S.udl, n, nlv, partial.p, nb);
+    CPD_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_scan_levels, dim3(nlv), dim3(SCAN_THREADS), 0, s, partial.p, nb, d_flag + 2);
+    CPD_LAUNCH_CHECK();
     int32_t h_counts[CPD_MAX_MODES] = {};
-    if (nm > 1)
-        CPD_HIP(hipMemcpyAsync(h_counts, d_flag + 2, sizeof(int32_t) * (nm - 1), hipMemcpyDeviceToHost, s));
+    CPD_HIP(hipMemcpyAsync(h_counts, d_flag + 2, sizeof(int32_t) * nlv, hipMemcpyDeviceToHost, s));
     CPD_HIP(hipStreamSynchronize(s));
 
     cpd_csf_s *c = new (std::nothrow) cpd_csf_s();
@@ -681,7 +834,8 @@ cpd_status compress(int nm, const int64_t *dims, const int32_t *order, const Key
     // the tree's arrays are carved from one stream-ordered pool allocation
     // (256-byte aligned pieces): one allocation and one free per tree, and
     // repeated builds reuse the pool's pages
-    const bool want_leafw = dims[order[nm - 1]] <= (1ll << 29);
+    const int64_t nid = dims[order[nm - 1]];
+    const bool want_leafw = nid <= (1ll << 29);
     std::vector<std::pair<void **, size_t>> pieces;
     for (int l = 0; l < nm; ++l) {
         pieces.push_back({(void **)&c->fids[l], sizeof(int32_t) * c->counts[l]});
@@ -690,8 +844,8 @@ cpd_status compress(int nm, const int64_t *dims, const int32_t *order, const Key
     pieces.push_back({(void **)&c->vals, sizeof(float) * n});
     if (want_leafw) {
         pieces.push_back({(void **)&c->leafw, sizeof(int32_t) * n});
-        pieces.push_back({(void **)&c->leaf_perm, sizeof(int32_t) * dims[order[nm - 1]]});
-        pieces.push_back({(void **)&c->leaf_rank, sizeof(int32_t) * dims[order[nm - 1]]});
+        pieces.push_back({(void **)&c->leaf_perm, sizeof(int32_t) * nid});
+        pieces.push_back({(void **)&c->leaf_rank, sizeof(int32_t) * nid});
         for (int l = 1; l < nm - 1; ++l) pieces.push_back({(void **)&c->uprow[l], sizeof(int32_t) * n});
     }
     size_t total = 0;
@@ -711,33 +865,33 @@ cpd_status compress(int nm, const int64_t *dims, const int32_t *order, const Key
         free_csf(c);
         CPD_FAIL(CPD_ENOMEM, "device allocation for the CSF failed");
     }
-    for (int l = nm - 2; l >= 0 && st == CPD_OK; --l) {
-        const int32_t *next = (l == nm - 2) ? nullptr : scans[l + 1].p;
-        hipLaunchKernelGGL(k_compact, dim3(grid1(n)), dim3(256), 0, s, klo, khi, kl, udl, n, l,
-                           scans[l].p, next, c->fids[l], c->fptr[l]);
+    // rank the leaf ids by frequency in a strided sample of the leaves
+    if (c->leafw)
+        st = rank_key_field(S.klo, S.khi, kl.shift[nm - 1], kl.bits[nm - 1], n, nid, c->leaf_perm, c->leaf_rank,
+                            d_flag + 1, s);
+    if (st == CPD_OK) {
+        TreeOut t{};
+        for (int l = 0; l < nm; ++l) {
+            t.fids[l] = c->fids[l];
+            t.fptr[l] = c->fptr[l];
+            t.uprow[l] = c->uprow[l];
+        }
+        t.leafw = c->leafw;
+        t.leaf_rank = c->leaf_rank;
+        t.vals = c->vals;
+        if (S.khi)
+            hipLaunchKernelGGL(k_compress<true>, dim3((unsigned)nb), dim3(CT_THREADS), 0, s, S.klo, S.khi, kl, S.udl,
+                               S.val, n, (const int32_t *)partial.p, nb, t);
+        else
+            hipLaunchKernelGGL(k_compress<false>, dim3((unsigned)nb), dim3(CT_THREADS), 0, s, S.klo, S.khi, kl, S.udl,
+                               S.val, n, (const int32_t *)partial.p, nb, t);
         if (hipGetLastError() != hipSuccess) st = CPD_EHIP;
-        hipLaunchKernelGGL(k_set_last_const, dim3(1), dim3(1), 0, s, c->fptr[l], c->counts[l],
-                           (int32_t)c->counts[l + 1]);
-    }
-    hipLaunchKernelGGL(k_leaf, dim3(grid1(n)), dim3(256), 0, s, klo, khi, kl, n, c->fids[nm - 1]);
-    if (st == CPD_OK && hipGetLastError() != hipSuccess) st = CPD_EHIP;
-    if (c->leafw && st == CPD_OK) {
-        // rank the leaf ids by frequency in a strided sample of the leaves
-        const int64_t nid = dims[order[nm - 1]];
-        cpd_status rs = rank_ids(c->fids[nm - 1], n, nid, c->leaf_perm, c->leaf_rank, d_flag + 1, s);
-        if (rs == CPD_OK) {
-            hipLaunchKernelGGL(k_leafw, dim3(grid1(n)), dim3(256), 0, s, udl,
-                               (const int32_t *)c->fids[nm - 1], (const int32_t *)c->leaf_rank, n, c->leafw);
-            if (hipGetLastError() != hipSuccess) rs = CPD_EHIP;
-        }
-        if (rs != CPD_OK) st = rs;
-        for (int l = 1; l < nm - 1; ++l) {
-            hipLaunchKernelGGL(k_uprow, dim3(grid1(n)), dim3(256), 0, s, klo, khi, kl, n, l, c->uprow[l]);
-            if (st == CPD_OK && hipGetLastError() != hipSuccess) st = CPD_EHIP;
+        for (int l = 0; l < nlv && st == CPD_OK; ++l) {
+            hipLaunchKernelGGL(k_set_last_const, dim3(1), dim3(1), 0, s, c->fptr[l], c->counts[l],
+                               (int32_t)c->counts[l + 1]);
+            if (hipGetLastError() != hipSuccess) st = CPD_EHIP;
         }
     }
-    if (st == CPD_OK && hipMemcpyAsync(c->vals, S.val, sizeof(float) * n, hipMemcpyDeviceToDevice, s) != hipSuccess)
-        st = CPD_EHIP;
     if (st == CPD_OK && hipStreamSynchronize(s) != hipSuccess) st = CPD_EHIP;
     if (st != CPD_OK) {
         free_csf(c);
@@ -829,12 +983,17 @@ cpd_status build_rooted(int nm, const int64_t *dims, int64_t nnz, const int32_t 
 
 }  // namespace
 
-cpd_status rank_ids(const int32_t *ids, int64_t n, int64_t nid, int32_t *perm, int32_t *rank, int32_t *nruns,
-                    hipStream_t s) {
+// Rank ids 0..nid-1 by their count in a strided sample (stride max(1,
+// n / 2^22)) of n ids that `sample` writes as sort keys: most frequent first,
+// ties by id.
+template <typename Sampler>
+static cpd_status rank_sampled(Sampler sample, int64_t n, int64_t nid, int32_t *perm, int32_t *rank, int32_t *nruns,
+                               hipStream_t s) {
     const int64_t stride = std::max<int64_t>(1, n / (1 << 22));
     const int64_t ns = ceil_div(n, stride);
-    int ibits = 0;
+    int ibits = 0, cbits = 0;
     while ((1ll << ibits) < nid) ++ibits;
+    while ((1ll << cbits) <= ns) ++cbits;
     DevBuf<uint64_t> sk0, sk1;
     DevBuf<int32_t> sp0, sp1, spos, sstart, cnt;
     const int64_t m = std::max(ns, nid);
@@ -848,20 +1007,41 @@ cpd_status rank_ids(const int32_t *ids, int64_t n, int64_t nid, int32_t *perm, i
     CPD_HIP(hipMemsetAsync(cnt.p, 0, sizeof(int32_t) * nid, s));
     uint64_t *a = sk0.p, *ah = nullptr, *b = sk1.p, *bh = nullptr;
     int32_t *ap = sp0.p, *bp = sp1.p;
-    hipLaunchKernelGGL(k_sample, dim3(grid1(ns)), dim3(256), 0, s, ids, stride, ns, a, ap);
-    CPD_LAUNCH_CHECK();
+    CPD_TRY(sample(stride, ns, a, ap));
     CPD_TRY(radix_sort(a, ah, ap, b, bh, bp, ns, std::max(ibits, 1), s));
     CPD_TRY(exclusive_scan(RunStart{a}, ns, spos.p, nruns, s));
     hipLaunchKernelGGL(k_run_starts, dim3(grid1(ns)), dim3(256), 0, s, (const uint64_t *)a, (const int32_t *)spos.p,
                        ns, sstart.p);
     hipLaunchKernelGGL(k_run_counts, dim3(grid1(ns)), dim3(256), 0, s, (const uint64_t *)a,
                        (const int32_t *)sstart.p, (const int32_t *)nruns, ns, cnt.p);
-    hipLaunchKernelGGL(k_rank_keys, dim3(grid1(nid)), dim3(256), 0, s, (const int32_t *)cnt.p, nid, a, ap);
+    // key (ns - count, id): ascending = most frequent first, ties by id
+    hipLaunchKernelGGL(k_rank_keys, dim3(grid1(nid)), dim3(256), 0, s, (const int32_t *)cnt.p, nid, ns, ibits, a, ap);
     CPD_LAUNCH_CHECK();
-    CPD_TRY(radix_sort(a, ah, ap, b, bh, bp, nid, 64, s));
-    hipLaunchKernelGGL(k_rank_scatter, dim3(grid1(nid)), dim3(256), 0, s, (const uint64_t *)a, nid, perm, rank);
+    CPD_TRY(radix_sort(a, ah, ap, b, bh, bp, nid, ibits + cbits, s));
+    hipLaunchKernelGGL(k_rank_scatter, dim3(grid1(nid)), dim3(256), 0, s, (const uint64_t *)a, nid, ibits, perm,
+                       rank);
     CPD_LAUNCH_CHECK();
     return CPD_OK;
+}
+
+cpd_status rank_ids(const int32_t *ids, int64_t n, int64_t nid, int32_t *perm, int32_t *rank, int32_t *nruns,
+                    hipStream_t s) {
+    auto sample = [&](int64_t stride, int64_t ns, uint64_t *key, int32_t *pay) -> cpd_status {
+        hipLaunchKernelGGL(k_sample, dim3(grid1(ns)), dim3(256), 0, s, ids, stride, ns, key, pay);
+        CPD_LAUNCH_CHECK();
+        return CPD_OK;
+    };
+    return rank_sampled(sample, n, nid, perm, rank, nruns, s);
+}
+
+cpd_status rank_key_field(const uint64_t *lo, const uint64_t *hi, int shift, int bits, int64_t n, int64_t nid,
+                          int32_t *perm, int32_t *rank, int32_t *nruns, hipStream_t s) {
+    auto sample = [&](int64_t stride, int64_t ns, uint64_t *key, int32_t *pay) -> cpd_status {
+        hipLaunchKernelGGL(k_sample_field, dim3(grid1(ns)), dim3(256), 0, s, lo, hi, shift, bits, stride, ns, key, pay);
+        CPD_LAUNCH_CHECK();
+        return CPD_OK;
+    };
+    return rank_sampled(sample, n, nid, perm, rank, nruns, s);
 }
 
 cpd_status csf_level_rank(cpd_csf_s *c, int l, const int32_t **perm, const int32_t **rank, hipStream_t s) {
