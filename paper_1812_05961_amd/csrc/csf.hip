@@ -16,6 +16,15 @@ constexpr int RS_THREADS = 256;            // == radix, one digit per thread in 
 constexpr int RS_ITEMS = 16;
 constexpr int RS_TILE = RS_THREADS * RS_ITEMS;
 
+// Launch a kernel template instantiated for the level count (2..5).
+#define CPD_BY_LEVELS(nl, CALL)      \
+    switch (nl) {                    \
+        case 2: CALL(2); break;      \
+        case 3: CALL(3); break;      \
+        case 4: CALL(4); break;      \
+        default: CALL(5); break;     \
+    }
+
 // Where each level's index sits in the packed 128-bit key (root most
 // significant, leaf least).
 struct KeyLayout {
@@ -50,9 +59,11 @@ struct Repack {
     LevelMap map;
 };
 
+template <int NL>
 __device__ __forceinline__ uint64_t repack_key(const Repack &r, uint64_t key) {
     uint64_t out = 0;
-    for (int l = 0; l < r.kx.nl; ++l) {
+#pragma unroll
+    for (int l = 0; l < NL; ++l) {
         const int q = r.map.src[l];
         if (r.kx.bits[l]) out |= (uint64_t)key_field(key, 0ull, r.ka.shift[q], r.ka.bits[q]) << r.kx.shift[l];
     }
@@ -61,13 +72,15 @@ __device__ __forceinline__ uint64_t repack_key(const Repack &r, uint64_t key) {
 
 // Packed key of nonzero k (root index most significant) and its value as the
 // sort payload (bits of the float), with the index check of every level.
+template <int NL>
 __global__ void k_pack(LevelInds in, KeyLayout kl, const int64_t *dims_by_level, const float *vals, int64_t n,
                        uint64_t *lo, uint64_t *hi, int32_t *pay, int32_t *bad) {
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
     uint64_t a = 0, b = 0;
     bool ok = true;
-    for (int l = 0; l < kl.nl; ++l) {
+#pragma unroll
+    for (int l = 0; l < NL; ++l) {
         const int32_t v = in.p[l][k];
         ok = ok && v >= 0 && (int64_t)v < dims_by_level[l];
         uint64_t x = (uint64_t)(uint32_t)v;
@@ -87,9 +100,9 @@ __global__ void k_pack(LevelInds in, KeyLayout kl, const int64_t *dims_by_level,
 }
 
 // ---- radix sort: per-tile digit histogram (digit-major output)
-// RP: the keys are those of rp.a in layout rp.kx (the first pass of a
-// re-sort into another tree order).
-template <bool RP>
+// RPN > 0: the keys are those of rp.a (RPN levels) in layout rp.kx (the
+// first pass of a re-sort into another tree order).
+template <int RPN>
 __global__ void __launch_bounds__(RS_THREADS)
 k_radix_hist(const uint64_t *keys, Repack rp, int64_t n, int shift, int32_t *hist, int64_t ntiles) {
     __shared__ int32_t h[256];
@@ -99,7 +112,7 @@ k_radix_hist(const uint64_t *keys, Repack rp, int64_t n, int shift, int32_t *his
 #pragma unroll
     for (int j = 0; j < RS_ITEMS; ++j) {
         int64_t i = base + (int64_t)j * RS_THREADS + threadIdx.x;
-        if (i < n) atomicAdd(&h[((RP ? repack_key(rp, rp.a[i]) : keys[i]) >> shift) & 255u], 1);
+        if (i < n) atomicAdd(&h[((RPN ? repack_key<RPN>(rp, rp.a[i]) : keys[i]) >> shift) & 255u], 1);
     }
     __syncthreads();
     hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
@@ -168,7 +181,7 @@ __device__ __forceinline__ void wave_sync() {
 constexpr int RS_WAVES = RS_THREADS / 64;
 constexpr int RS_WAVE_ITEMS = RS_TILE / RS_WAVES;
 
-template <bool RP>
+template <int RPN>
 __global__ void __launch_bounds__(RS_THREADS)
 k_radix_scatter1(const uint64_t *__restrict__ keys, const int32_t *__restrict__ pay, Repack rp,
                  uint64_t *__restrict__ okeys, int32_t *__restrict__ opay, const int32_t *__restrict__ offsets,
@@ -187,8 +200,8 @@ k_radix_scatter1(const uint64_t *__restrict__ keys, const int32_t *__restrict__ 
 #pragma unroll
     for (int r = 0; r < RS_ITEMS; ++r) {
         const int j = wave * RS_WAVE_ITEMS + r * 64 + lane;
-        if (RP) {
-            k[r] = j < tn ? repack_key(rp, rp.a[tbase + j]) : 0ull;
+        if (RPN) {
+            k[r] = j < tn ? repack_key<RPN>(rp, rp.a[tbase + j]) : 0ull;
             p[r] = j < tn ? __float_as_int(rp.val[tbase + j]) : 0;
         } else {
             k[r] = j < tn ? keys[tbase + j] : 0ull;
@@ -301,25 +314,32 @@ static cpd_status radix_sort_rp(uint64_t *&klo, uint64_t *&khi, int32_t *&kp, ui
         const uint64_t *src = word ? khi : klo;
         const bool first = rp && d == 0;
         const Repack &r = first ? *rp : none;
-        if (first)
-            hipLaunchKernelGGL(k_radix_hist<true>, dim3((unsigned)ntiles), dim3(RS_THREADS), 0, s, src, r, n, shift,
+        if (first) {
+#define CPD_HIST_RP(L)                                                                                          \
+    hipLaunchKernelGGL(k_radix_hist<L>, dim3((unsigned)ntiles), dim3(RS_THREADS), 0, s, src, r, n, shift, hist.p, \
+                       ntiles)
+            CPD_BY_LEVELS(r.kx.nl, CPD_HIST_RP)
+#undef CPD_HIST_RP
+        } else {
+            hipLaunchKernelGGL(k_radix_hist<0>, dim3((unsigned)ntiles), dim3(RS_THREADS), 0, s, src, r, n, shift,
                                hist.p, ntiles);
-        else
-            hipLaunchKernelGGL(k_radix_hist<false>, dim3((unsigned)ntiles), dim3(RS_THREADS), 0, s, src, r, n, shift,
-                               hist.p, ntiles);
+        }
         CPD_LAUNCH_CHECK();
         CPD_TRY(exclusive_scan(HistAt{hist.p}, 256 * ntiles, hist.p, (int32_t *)nullptr, s));
         if (khi)
             hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)ntiles), dim3(RS_THREADS), 0, s, klo, khi, kp, olo,
                                ohi, op, (const int32_t *)hist.p, n, ntiles, word, shift);
-        else if (first)
-            hipLaunchKernelGGL(k_radix_scatter1<true>, dim3((unsigned)ntiles), dim3(RS_THREADS), 0, s,
+        else if (first) {
+#define CPD_SCATTER_RP(L)                                                                                       \
+    hipLaunchKernelGGL(k_radix_scatter1<L>, dim3((unsigned)ntiles), dim3(RS_THREADS), 0, s, (const uint64_t *)klo, \
+                       (const int32_t *)kp, r, olo, op, (const int32_t *)hist.p, n, ntiles, shift)
+            CPD_BY_LEVELS(r.kx.nl, CPD_SCATTER_RP)
+#undef CPD_SCATTER_RP
+        } else {
+            hipLaunchKernelGGL(k_radix_scatter1<0>, dim3((unsigned)ntiles), dim3(RS_THREADS), 0, s,
                                (const uint64_t *)klo, (const int32_t *)kp, r, olo, op, (const int32_t *)hist.p, n,
                                ntiles, shift);
-        else
-            hipLaunchKernelGGL(k_radix_scatter1<false>, dim3((unsigned)ntiles), dim3(RS_THREADS), 0, s,
-                               (const uint64_t *)klo, (const int32_t *)kp, r, olo, op, (const int32_t *)hist.p, n,
-                               ntiles, shift);
+        }
         CPD_LAUNCH_CHECK();
         std::swap(klo, olo);
         std::swap(khi, ohi);
@@ -388,22 +408,24 @@ __global__ void k_rank_scatter(const uint64_t *key, int64_t nid, int ibits, int3
     rank[id] = (int32_t)r;
 }
 
-// First level at which sorted key k differs from key k-1 (0 for k = 0, nl for
-// an exact duplicate).
-__global__ void k_first_diff(const uint64_t *lo, const uint64_t *hi, KeyLayout kl, int64_t n,
-                             uint8_t *dl) {
+// First level at which sorted key k differs from key k-1 (0 for k = 0, NL for
+// an exact duplicate, which also sets *dup).
+template <int NL>
+__global__ void k_first_diff(const uint64_t *__restrict__ lo, const uint64_t *__restrict__ hi, KeyLayout kl,
+                             int64_t n, uint8_t *__restrict__ dl, int32_t *dup) {
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
     if (k == 0) {
         dl[0] = 0;
         return;
     }
-    uint64_t a = lo[k], b = hi ? hi[k] : 0ull, pa = lo[k - 1], pb = hi ? hi[k - 1] : 0ull;
-    int l = 0;
-    for (; l < kl.nl; ++l)
-        if (key_field(a, b, kl.shift[l], kl.bits[l]) != key_field(pa, pb, kl.shift[l], kl.bits[l]))
-            break;
+    const uint64_t xa = lo[k] ^ lo[k - 1], xb = hi ? (hi[k] ^ hi[k - 1]) : 0ull;
+    int l = NL;
+#pragma unroll
+    for (int q = NL - 1; q >= 0; --q)
+        if (key_field(xa, xb, kl.shift[q], kl.bits[q]) != 0u) l = q;
     dl[k] = (uint8_t)l;
+    if (l == NL && dup) atomicOr(dup, 1);
 }
 
 struct IsNew {
@@ -507,6 +529,11 @@ void free_csf(cpd_csf_s *c) {
     delete c;
 }
 
+// Device flag words of a build: [0] an index out of range, [1] merged
+// nonzeros (and ranking scratch), [2 .. 2+N-2] node counts per level,
+// [FLAG_DUP] duplicates present.
+constexpr int FLAG_DUP = 2 + CPD_MAX_MODES, FLAG_WORDS = FLAG_DUP + 1;
+
 // Build arguments shared by every entry point.
 cpd_status check_coo(int nm, const int64_t *dims, int64_t nnz, const int32_t *const *inds, const float *vals,
                      const void *out) {
@@ -598,7 +625,7 @@ struct TreeOut {
 // 16-bit fields: a tile holds at most 4096), so every node finds its slot;
 // the node's index and first child are stored there.  Each nonzero's leaf
 // index, leaf word, internal rows and value are written alongside.
-template <bool TWO>
+template <int NL, bool TWO>
 __global__ void __launch_bounds__(CT_THREADS)
 k_compress(const uint64_t *__restrict__ lo, const uint64_t *__restrict__ hi, KeyLayout kl,
            const uint8_t *__restrict__ dl, const float *__restrict__ val, int64_t n,
@@ -606,7 +633,7 @@ k_compress(const uint64_t *__restrict__ lo, const uint64_t *__restrict__ hi, Key
     __shared__ uint8_t s_dl[CT_TILE];
     __shared__ uint64_t s_pre[CT_TILE];  // per nonzero: openings before it in the tile, per level
     __shared__ uint32_t s_w[2][CT_THREADS / 64];
-    const int nl = kl.nl, nlv = nl - 1;
+    constexpr int nl = NL, nlv = NL - 1;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t base = (int64_t)blockIdx.x * CT_TILE;
 #pragma unroll
@@ -619,6 +646,7 @@ k_compress(const uint64_t *__restrict__ lo, const uint64_t *__restrict__ hi, Key
     uint64_t own = 0;
     for (int j = 0; j < CT_ITEMS; ++j) {
         const int d = s_dl[tid * CT_ITEMS + j];
+#pragma unroll
         for (int l = 0; l < nlv; ++l) own += (uint64_t)(d <= l) << (16 * l);
     }
     // exclusive scan over the block; no field exceeds 4096, so the two
@@ -642,9 +670,11 @@ k_compress(const uint64_t *__restrict__ lo, const uint64_t *__restrict__ hi, Key
         const int e = tid * CT_ITEMS + j;
         s_pre[e] = run;
         const int d = s_dl[e];
+#pragma unroll
         for (int l = 0; l < nlv; ++l) run += (uint64_t)(d <= l) << (16 * l);
     }
     int32_t off[CPD_MAX_MODES];
+#pragma unroll
     for (int l = 0; l < nlv; ++l) off[l] = partial[(int64_t)l * nb + blockIdx.x];
     __syncthreads();
     // half a tile at a time: its loads first (independent), then its stores
@@ -678,13 +708,16 @@ k_compress(const uint64_t *__restrict__ lo, const uint64_t *__restrict__ hi, Key
             if (k < n) {
                 const int d = s_dl[e];
                 const uint64_t pre = s_pre[e];
-                for (int l = d; l < nlv; ++l) {
+#pragma unroll
+                for (int l = 0; l < nlv; ++l) {
+                    if (l < d) continue;
                     const int32_t slot = off[l] + (int32_t)((pre >> (16 * l)) & 0xffffu);
                     t.fids[l][slot] = (int32_t)key_field(ka[j], kb[j], kl.shift[l], kl.bits[l]);
                     t.fptr[l][slot] =
                         l + 1 < nlv ? off[l + 1] + (int32_t)((pre >> (16 * (l + 1))) & 0xffffu) : (int32_t)k;
                 }
                 fleaf[k] = leaf[j];
+#pragma unroll
                 for (int l = 1; l < nlv; ++l)
                     if (t.uprow[l]) t.uprow[l][k] = (int32_t)key_field(ka[j], kb[j], kl.shift[l], kl.bits[l]);
                 if (lw) lw[k] = (int32_t)(((uint32_t)d << 29) | (uint32_t)rk[j]);
@@ -727,25 +760,38 @@ cpd_status sort_merge(int nm, const KeyLayout &kl, int total_bits, const int32_t
         if (two) CPD_TRY(S.hi[b].alloc(nnz, s));
         CPD_TRY(S.pay[b].alloc(nnz, s));
     }
-    hipLaunchKernelGGL(k_pack, dim3(grid1(nnz)), dim3(256), 0, s, li, kl, (const int64_t *)d_dims.p, vals, nnz,
-                       S.lo[0].p, S.hi[0].p, S.pay[0].p, d_flag);
+#define CPD_PACK(L)                                                                                      \
+    hipLaunchKernelGGL(k_pack<L>, dim3(grid1(nnz)), dim3(256), 0, s, li, kl, (const int64_t *)d_dims.p, vals, nnz, \
+                       S.lo[0].p, S.hi[0].p, S.pay[0].p, d_flag)
+    CPD_BY_LEVELS(nm, CPD_PACK)
+#undef CPD_PACK
     CPD_LAUNCH_CHECK();
     uint64_t *klo = S.lo[0].p, *khi = S.hi[0].p, *olo = S.lo[1].p, *ohi = S.hi[1].p;
     int32_t *kp = S.pay[0].p, *op = S.pay[1].p;
     CPD_TRY(radix_sort(klo, khi, kp, olo, ohi, op, nnz, total_bits, s));
 
-    // a4: duplicate merge
+    // a4: duplicate merge (the merge positions only when there are duplicates)
     DevBuf<int32_t> pos;
     CPD_TRY(S.dl.alloc(nnz, s));
-    CPD_TRY(pos.alloc(nnz, s));
-    hipLaunchKernelGGL(k_first_diff, dim3(grid1(nnz)), dim3(256), 0, s, klo, khi, kl, nnz, S.dl.p);
+#define CPD_FIRST_DIFF(L)                                                                                    \
+    hipLaunchKernelGGL(k_first_diff<L>, dim3(grid1(nnz)), dim3(256), 0, s, klo, khi, kl, nnz, S.dl.p, \
+                       d_flag + FLAG_DUP)
+    CPD_BY_LEVELS(nm, CPD_FIRST_DIFF)
+#undef CPD_FIRST_DIFF
     CPD_LAUNCH_CHECK();
-    CPD_TRY(exclusive_scan(IsNew{S.dl.p, nm}, nnz, pos.p, d_flag + 1, s));
-    int32_t h_flag[2];
-    CPD_HIP(hipMemcpyAsync(h_flag, d_flag, sizeof(int32_t) * 2, hipMemcpyDeviceToHost, s));
+    int32_t h_flag[FLAG_WORDS];
+    CPD_HIP(hipMemcpyAsync(h_flag, d_flag, sizeof(int32_t) * FLAG_WORDS, hipMemcpyDeviceToHost, s));
     CPD_HIP(hipStreamSynchronize(s));
     if (h_flag[0]) CPD_FAIL(CPD_EINVAL, "an index is out of range for its mode");
-    S.n = h_flag[1];
+    S.n = nnz;
+    if (h_flag[FLAG_DUP]) {
+        CPD_TRY(pos.alloc(nnz, s));
+        CPD_TRY(exclusive_scan(IsNew{S.dl.p, nm}, nnz, pos.p, d_flag + 1, s));
+        int32_t h_n = 0;
+        CPD_HIP(hipMemcpyAsync(&h_n, d_flag + 1, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        CPD_HIP(hipStreamSynchronize(s));
+        S.n = h_n;
+    }
     // without duplicates the sorted arrays are the merged ones (the payload
     // carries the values' bits)
     S.klo = klo;
@@ -795,8 +841,11 @@ cpd_status derive(int nm, const int64_t *dims, const int32_t *order_a, const Key
     int32_t *kp = S.pay[0].p, *op = S.pay[1].p;
     CPD_TRY(radix_sort_rp(klo, khi, kp, olo, ohi, op, n, total, s, kx->shift[0], &rp));
     CPD_TRY(S.dl.alloc(n, s));
-    hipLaunchKernelGGL(k_first_diff, dim3(grid1(n)), dim3(256), 0, s, klo, (const uint64_t *)nullptr, *kx, n,
-                       S.dl.p);
+#define CPD_FIRST_DIFF(L)                                                                                 \
+    hipLaunchKernelGGL(k_first_diff<L>, dim3(grid1(n)), dim3(256), 0, s, klo, (const uint64_t *)nullptr, *kx, n, \
+                       S.dl.p, (int32_t *)nullptr)
+    CPD_BY_LEVELS(nm, CPD_FIRST_DIFF)
+#undef CPD_FIRST_DIFF
     CPD_LAUNCH_CHECK();
     S.klo = klo;
     S.udl = S.dl.p;
@@ -879,12 +928,15 @@ cpd_status compress(int nm, const int64_t *dims, const int32_t *order, const Key
         t.leafw = c->leafw;
         t.leaf_rank = c->leaf_rank;
         t.vals = c->vals;
-        if (S.khi)
-            hipLaunchKernelGGL(k_compress<true>, dim3((unsigned)nb), dim3(CT_THREADS), 0, s, S.klo, S.khi, kl, S.udl,
-                               S.val, n, (const int32_t *)partial.p, nb, t);
-        else
-            hipLaunchKernelGGL(k_compress<false>, dim3((unsigned)nb), dim3(CT_THREADS), 0, s, S.klo, S.khi, kl, S.udl,
-                               S.val, n, (const int32_t *)partial.p, nb, t);
+#define CPD_COMPRESS(L)                                                                                         \
+    if (S.khi)                                                                                                  \
+        hipLaunchKernelGGL((k_compress<L, true>), dim3((unsigned)nb), dim3(CT_THREADS), 0, s, S.klo, S.khi, kl,   \
+                           S.udl, S.val, n, (const int32_t *)partial.p, nb, t);                                 \
+    else                                                                                                        \
+        hipLaunchKernelGGL((k_compress<L, false>), dim3((unsigned)nb), dim3(CT_THREADS), 0, s, S.klo, S.khi, kl,  \
+                           S.udl, S.val, n, (const int32_t *)partial.p, nb, t)
+        CPD_BY_LEVELS(nm, CPD_COMPRESS)
+#undef CPD_COMPRESS
         if (hipGetLastError() != hipSuccess) st = CPD_EHIP;
         for (int l = 0; l < nlv && st == CPD_OK; ++l) {
             hipLaunchKernelGGL(k_set_last_const, dim3(1), dim3(1), 0, s, c->fptr[l], c->counts[l],
@@ -921,10 +973,9 @@ cpd_status build(int nm, const int64_t *dims, int64_t nnz, const int32_t *const 
     int total_bits = 0;
     const KeyLayout kl = key_layout(nm, dims, order, &total_bits);
     if (total_bits > 128) CPD_FAIL(CPD_EUNSUPPORTED, "packed key needs %d bits (> 128)", total_bits);
-    // d_flag: [0] bad index, [1] merged nonzeros, [2..] level counts
     DevBuf<int32_t> d_flag;
-    CPD_TRY(d_flag.alloc(1 + CPD_MAX_MODES, s));
-    CPD_HIP(hipMemsetAsync(d_flag.p, 0, sizeof(int32_t) * (1 + CPD_MAX_MODES), s));
+    CPD_TRY(d_flag.alloc(FLAG_WORDS, s));
+    CPD_HIP(hipMemsetAsync(d_flag.p, 0, sizeof(int32_t) * FLAG_WORDS, s));
     Sorted S;
     CPD_TRY(sort_merge(nm, kl, total_bits, inds, order, dims, vals, nnz, d_flag.p, s, S));
     return compress(nm, dims, order, kl, S, d_flag.p, s, out);
@@ -962,8 +1013,8 @@ cpd_status build_rooted(int nm, const int64_t *dims, int64_t nnz, const int32_t 
         }
     } else {
         DevBuf<int32_t> d_flag;
-        CPD_TRY(d_flag.alloc(1 + CPD_MAX_MODES, s));
-        CPD_HIP(hipMemsetAsync(d_flag.p, 0, sizeof(int32_t) * (1 + CPD_MAX_MODES), s));
+        CPD_TRY(d_flag.alloc(FLAG_WORDS, s));
+        CPD_HIP(hipMemsetAsync(d_flag.p, 0, sizeof(int32_t) * FLAG_WORDS, s));
         Sorted A;
         CPD_TRY(sort_merge(nm, ka, total_bits, inds, desc, dims, vals, nnz, d_flag.p, s, A));
         cpd_status st = compress(nm, dims, desc, ka, A, d_flag.p, s, &trees[desc[0]]);
