@@ -45,9 +45,10 @@ enum { CPD_FP32 = 0, CPD_BF16_GATHER = 1 };
  * privatised buffers).  On the GPU "atomic" replaces the paper's mutex pool. */
 enum { CPD_VARIANT_AUTO = 0, CPD_VARIANT_ATOMIC = 1, CPD_VARIANT_PRIVATE = 2 };
 
-/* Kernel family: AUTO picks; ROW = one factor row per lane (fused
- * accumulation, for root/internal levels); LANE = the rank spread over lanes
- * (any level). */
+/* Kernel family: AUTO picks (ROW at the root, LANE below); ROW = groups of
+ * lanes each holding 16-byte chunks of the factor rows, several leaves per
+ * wave step (root and internal levels; tile widths in multiples of 32);
+ * LANE = the rank spread over the lanes, one leaf per wave step (any level). */
 enum { CPD_KERNEL_AUTO = 0, CPD_KERNEL_ROW = 1, CPD_KERNEL_LANE = 2 };
 
 #define CPD_MAX_MODES 8

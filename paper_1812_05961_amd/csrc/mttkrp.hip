@@ -10,9 +10,10 @@
 // only when a fiber ends.
 //
 // Two kernel families:
-//   ROW  (levels d < N-1): one stream per lane, the whole factor row in the
-//        lane's registers (vector loads), accumulation in registers, one
-//        atomic flush per output node the stream touches.
+//   ROW  (levels d < N-1, in mttkrp_root.hip): groups of G lanes, each lane
+//        holding 16-byte chunks of the rows, several leaves per wave step;
+//        at the root a contention-free segmented combine, at internal levels
+//        one atomic flush per output node.
 //   LANE (any level): one stream per group of G lanes, column r on lane r of
 //        the group; coalesced row loads and coalesced atomics.  For the leaf
 //        level each nonzero adds v*H to its row, either with global atomics or
@@ -39,46 +40,6 @@ struct FacView {
     const void *a[CPD_MAX_MODES];  // by level
 };
 
-// ------------------------------------------------------------ row loaders
-template <typename GT, int RP>
-struct Row;
-
-template <int RP>
-struct Row<float, RP> {
-    static_assert(RP % 4 == 0, "fp32 rows load as float4");
-    __device__ static __forceinline__ void load(const void *base, int64_t ld, int32_t i, float (&v)[RP]) {
-        const float4 *p = reinterpret_cast<const float4 *>(static_cast<const float *>(base) + (int64_t)i * ld);
-#pragma unroll
-        for (int c = 0; c < RP / 4; ++c) {
-            float4 q = p[c];
-            v[4 * c + 0] = q.x;
-            v[4 * c + 1] = q.y;
-            v[4 * c + 2] = q.z;
-            v[4 * c + 3] = q.w;
-        }
-    }
-};
-
-template <int RP>
-struct Row<uint16_t, RP> {
-    static_assert(RP % 8 == 0, "bf16 rows load as 8-element chunks");
-    __device__ static __forceinline__ void load(const void *base, int64_t ld, int32_t i, float (&v)[RP]) {
-        const uint4 *p = reinterpret_cast<const uint4 *>(static_cast<const uint16_t *>(base) + (int64_t)i * ld);
-#pragma unroll
-        for (int c = 0; c < RP / 8; ++c) {
-            uint4 q = p[c];
-            v[8 * c + 0] = bf16_lo(q.x);
-            v[8 * c + 1] = bf16_hi(q.x);
-            v[8 * c + 2] = bf16_lo(q.y);
-            v[8 * c + 3] = bf16_hi(q.y);
-            v[8 * c + 4] = bf16_lo(q.z);
-            v[8 * c + 5] = bf16_hi(q.z);
-            v[8 * c + 6] = bf16_lo(q.w);
-            v[8 * c + 7] = bf16_hi(q.w);
-        }
-    }
-};
-
 template <typename GT>
 __device__ __forceinline__ float load1(const void *base, int64_t off);
 template <>
@@ -88,88 +49,6 @@ __device__ __forceinline__ float load1<float>(const void *base, int64_t off) {
 template <>
 __device__ __forceinline__ float load1<uint16_t>(const void *base, int64_t off) {
     return bf16_to_f32(static_cast<const uint16_t *>(base)[off]);
-}
-
-// ------------------------------------------------------------ ROW family
-template <int N, int RP, typename GT>
-__global__ void __launch_bounds__(256)
-k_mttkrp_row(CsfView cv, FacView fv, int64_t ld, int d, const int32_t *__restrict__ starts,
-             int64_t nstreams, int32_t T, float *__restrict__ Y, int64_t ldo, int R) {
-    const int64_t sid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (sid >= nstreams) return;  // no block-level synchronisation in this kernel
-    int64_t k = sid * (int64_t)T;
-    const int64_t kend = min(k + (int64_t)T, cv.nleaves);
-    int32_t c[N - 1], e[N - 1];
-#pragma unroll
-    for (int l = 0; l < N - 1; ++l) {
-        c[l] = starts[(int64_t)l * nstreams + sid];
-        e[l] = cv.fptr[l][c[l] + 1];
-    }
-    float P[RP], H[RP], acc[RP], row[RP];
-    // P: product of the rows of levels above the fiber level, except d.
-    auto make_P = [&]() {
-#pragma unroll
-        for (int r = 0; r < RP; ++r) P[r] = 1.0f;
-#pragma unroll
-        for (int l = 0; l < N - 2; ++l) {
-            if (l == d) continue;
-            Row<GT, RP>::load(fv.a[l], ld, cv.fids[l][c[l]], row);
-#pragma unroll
-            for (int r = 0; r < RP; ++r) P[r] *= row[r];
-        }
-    };
-    auto make_H = [&]() {
-        if (d == N - 2) {
-#pragma unroll
-            for (int r = 0; r < RP; ++r) H[r] = P[r];
-        } else {
-            Row<GT, RP>::load(fv.a[N - 2], ld, cv.fids[N - 2][c[N - 2]], row);
-#pragma unroll
-            for (int r = 0; r < RP; ++r) H[r] = P[r] * row[r];
-        }
-    };
-    auto flush = [&](int32_t out_row) {
-        float *y = Y + (int64_t)out_row * ldo;
-#pragma unroll
-        for (int r = 0; r < RP; ++r)
-            if (r < R) atomicAdd(y + r, acc[r]);
-    };
-    make_P();
-    make_H();
-#pragma unroll
-    for (int r = 0; r < RP; ++r) acc[r] = 0.0f;
-    int32_t out_row = cv.fids[d][c[d]];
-    const float *__restrict__ vals = cv.vals;
-    const int32_t *__restrict__ leaf = cv.fids[N - 1];
-    for (; k < kend; ++k) {
-        if (k == e[N - 2]) {  // a fiber ends: advance the cursors
-            int lmin = N - 2;
-            c[N - 2] += 1;
-            e[N - 2] = cv.fptr[N - 2][c[N - 2] + 1];
-            int32_t child = c[N - 2];
-#pragma unroll
-            for (int l = N - 3; l >= 0; --l) {
-                if (child != e[l]) break;
-                c[l] += 1;
-                e[l] = cv.fptr[l][c[l] + 1];
-                child = c[l];
-                lmin = l;
-            }
-            if (lmin <= d) {
-                flush(out_row);
-#pragma unroll
-                for (int r = 0; r < RP; ++r) acc[r] = 0.0f;
-                out_row = cv.fids[d][c[d]];
-            }
-            if (lmin < N - 2) make_P();
-            make_H();
-        }
-        const float v = vals[k];
-        Row<GT, RP>::load(fv.a[N - 1], ld, leaf[k], row);
-#pragma unroll
-        for (int r = 0; r < RP; ++r) acc[r] = fmaf(v * row[r], H[r], acc[r]);
-    }
-    flush(out_row);
 }
 
 // ------------------------------------------------------------ LANE family
@@ -296,30 +175,6 @@ inline int row_width(int R, bool bf16) {
     return 64;
 }
 
-template <int N, typename GT>
-cpd_status launch_row(int RP, dim3 grid, hipStream_t s, const CsfView &cv, const FacView &fv,
-                      int64_t ld, int d, const int32_t *starts, int64_t ns, int32_t T, float *Y,
-                      int64_t ldo, int R) {
-    constexpr bool F32 = std::is_same<GT, float>::value;
-    constexpr int MID = F32 ? 36 : 40;  // the width between 32 and 64
-#define CPD_ROW_CASE(rp)                                                                           \
-    case rp:                                                                                       \
-        hipLaunchKernelGGL((k_mttkrp_row<N, rp, GT>), grid, dim3(256), 0, s, cv, fv, ld, d, starts, \
-                           ns, T, Y, ldo, R);                                                      \
-        break;
-    switch (RP) {
-        CPD_ROW_CASE(8)
-        CPD_ROW_CASE(16)
-        CPD_ROW_CASE(32)
-        CPD_ROW_CASE(MID)
-        CPD_ROW_CASE(64)
-        default:
-            CPD_FAIL(CPD_EUNSUPPORTED, "no row kernel for padded rank %d", RP);
-    }
-#undef CPD_ROW_CASE
-    CPD_LAUNCH_CHECK();
-    return CPD_OK;
-}
 
 template <int N, typename GT>
 cpd_status launch_lane(int G, bool priv, int32_t hot, dim3 grid, size_t lds, hipStream_t s, const CsfView &cv,
@@ -357,7 +212,7 @@ constexpr double PRIV_THRESH = 0.02;  // privatise iff rows * copies <= 0.02 * n
 
 }  // namespace
 
-cpd_status launch_root(int N, bool bf16, int RP, const int32_t *const *fids, const int32_t *const *fptr,
+cpd_status launch_root(int N, bool bf16, int RP, int d, const int32_t *const *fids, const int32_t *const *fptr,
                        const float *vals, const int32_t *leafw, const int32_t *leaf_perm, const int32_t *const *uprow,
                        const int64_t *counts, const int64_t *dims_by_level, const void *const *fac_by_level,
                        int64_t ld, const int32_t *starts, int64_t ntiles, int32_t T, float *Y, int64_t ldo, int R,
@@ -399,10 +254,10 @@ cpd_status mttkrp(cpd_csf_s *c, const void *const *factors, int32_t ld, int32_t 
     // ROW family eligibility: vector loads need the padded row inside ld and
     // 16-byte aligned rows.
     const int RP = row_width(R, bf16);
-    bool row_ok = d < N - 1 && ld >= RP && (ld * (bf16 ? 2 : 4)) % 16 == 0 && (d > 0 || c->leafw);
-    // the root kernel addresses rows with 24-bit products: row ids below 2^24
-    for (int l = 1; l < N && row_ok && d == 0; ++l)
-        if (c->dims[c->order[l]] >= (1 << 24)) row_ok = false;
+    bool row_ok = d < N - 1 && ld >= RP && (ld * (bf16 ? 2 : 4)) % 16 == 0 && c->leafw;
+    // the lane-group kernels address rows with 24-bit products: row ids below 2^24
+    for (int l = 0; l < N && row_ok; ++l)
+        if (l != d && c->dims[c->order[l]] >= (1 << 24)) row_ok = false;
     for (int l = 0; l < N && row_ok; ++l)
         if (c->order[l] != mode && (reinterpret_cast<uintptr_t>(factors[c->order[l]]) & 15)) row_ok = false;
     int kernel = o.kernel;
@@ -417,7 +272,7 @@ cpd_status mttkrp(cpd_csf_s *c, const void *const *factors, int32_t ld, int32_t 
                            (int64_t)ldo, R);
         CPD_LAUNCH_CHECK();
     }
-    if (kernel == CPD_KERNEL_ROW && d == 0) {
+    if (kernel == CPD_KERNEL_ROW) {
         // default tile: 128 leaves per group run, halved (down to 32) while
         // the tile steps would not give every resident wave two of them
         int32_t T = o.tile_nnz;
@@ -435,31 +290,8 @@ cpd_status mttkrp(cpd_csf_s *c, const void *const *factors, int32_t ld, int32_t 
         if (ev0) CPD_HIP(hipEventRecord(ev0, s));
         int64_t dims_by_level[CPD_MAX_MODES];
         for (int l = 0; l < N; ++l) dims_by_level[l] = c->dims[c->order[l]];
-        cpd_status st = launch_root(N, bf16, RP, cv.fids, cv.fptr, cv.vals, c->leafw, c->leaf_perm, c->uprow,
+        cpd_status st = launch_root(N, bf16, RP, d, cv.fids, cv.fptr, cv.vals, c->leafw, c->leaf_perm, c->uprow,
                                     c->counts, dims_by_level, fac_by_level, ld, starts, ns, T, Y, ldo, R, s);
-        if (st == CPD_OK && ev1) CPD_HIP(hipEventRecord(ev1, s));
-        return st;
-    }
-    if (kernel == CPD_KERNEL_ROW) {
-        int32_t T = o.tile_nnz ? o.tile_nnz : 64;
-        const int32_t *starts;
-        int64_t ns;
-        CPD_TRY(csf_tiles(c, T, &starts, &ns, s));
-        dim3 grid((unsigned)ceil_div(ns, 256));
-        if (N < 3 || N > 5) CPD_FAIL(CPD_EUNSUPPORTED, "row kernel built for 3..5 modes, not %d", N);
-        if (ev0) CPD_HIP(hipEventRecord(ev0, s));
-        cpd_status st = CPD_OK;
-#define CPD_ROW_N(n)                                                                                   \
-    case n:                                                                                            \
-        st = bf16 ? launch_row<n, uint16_t>(RP, grid, s, cv, fv, ld, d, starts, ns, T, Y, ldo, R)      \
-                  : launch_row<n, float>(RP, grid, s, cv, fv, ld, d, starts, ns, T, Y, ldo, R);        \
-        break;
-        switch (N) {
-            CPD_ROW_N(3)
-            CPD_ROW_N(4)
-            CPD_ROW_N(5)
-        }
-#undef CPD_ROW_N
         if (st == CPD_OK && ev1) CPD_HIP(hipEventRecord(ev1, s));
         return st;
     }

@@ -357,6 +357,158 @@ k_mttkrp_root(CsfView cv, FacView fv, const char *__restrict__ a_leaf, uint32_t 
     }
 }
 
+// Internal-level MTTKRP (output mode at depth d, 1 <= d <= N-2):
+//     Y(i, :) += H_above * sum over leaves k below each level-d node with
+//                index i of x_k * A_leaf(j_k, :) * H_below(k),
+// H_above the Hadamard product of the node's ancestor rows, H_below that of
+// leaf k's rows at the levels between d and the leaf.  Same lane groups,
+// wave ranges and LDS staging as the root kernel; a level-d index recurs
+// under other ancestors, so each node's partial is added with atomics when
+// the node (or the group's run) ends.  The ancestor rows are gathered when a
+// node starts, the rows below d reused while their ids repeat.
+template <int N, int G, typename GT>
+__global__ void __launch_bounds__(64 * ROOT_WAVES)
+k_mttkrp_mid(CsfView cv, FacView fv, const char *__restrict__ a_leaf, uint32_t rowb, int d,
+             const int32_t *__restrict__ starts, int32_t T, int64_t nsteps, int64_t nwaves, float *__restrict__ Y,
+             int64_t ldo, int R) {
+    constexpr int NG = 64 / G;
+    constexpr int C = root_chunk<NG>(), U = root_unroll<N, GT>();
+    constexpr int W = Chunk<GT>::W;
+    constexpr int E = W;
+    constexpr int NU = N - 2;  // internal levels 1..N-2
+    constexpr int SS = NG * (C + 1);
+    constexpr int32_t IDMASK = (1 << 29) - 1;
+    using raw_t = typename Chunk<GT>::raw_t;
+    constexpr int RW = Chunk<GT>::RAW;
+    __shared__ int32_t s_w[ROOT_WAVES][SS];
+    __shared__ float s_v[ROOT_WAVES][SS];
+    __shared__ int32_t s_u[ROOT_WAVES][NU][SS];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int g = lane / G, lig = lane % G;  // g == NG: idle lane
+    const int64_t gw = (int64_t)blockIdx.x * ROOT_WAVES + wave;
+    if (gw >= nwaves) return;
+    const int64_t nleaves = cv.nleaves;
+    const int64_t s_begin = gw * nsteps / nwaves, s_end = (gw + 1) * nsteps / nwaves;
+    const int64_t span = NG * (int64_t)T;
+    const int32_t *__restrict__ leafw = cv.leafw;
+    const float *__restrict__ vals = cv.vals;
+    const int32_t *__restrict__ root_ids = cv.fids[0];
+    int32_t *sw = s_w[wave];
+    float *sv = s_v[wave];
+    const int gs = g < NG ? g : NG - 1;
+    auto col_of = [&](int e) { return (lig * W) + e; };
+    const uint32_t lane_off = (uint32_t)lig * Chunk<GT>::BYTES;
+
+    for (int64_t st = s_begin; st < s_end; ++st) {
+        const int64_t base = st * span;
+        const int64_t k0 = base + (int64_t)gs * T;
+        const bool active = g < NG && k0 < nleaves;
+        const int64_t kend = active ? min(k0 + (int64_t)T, nleaves) : k0;
+        int32_t c0 = active ? starts[st * NG + g] : 0;  // root node of the run's first leaf
+        float acc[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) acc[e] = 0.0f;
+        int32_t out_row = -1;   // index of the open level-d node
+        raw_t Ha[N][RW];        // its ancestor rows (levels 0..d-1)
+        int32_t last_up[NU];    // rows below d, reused while the ids repeat
+        raw_t Hl[NU][RW];
+#pragma unroll
+        for (int l = 0; l < NU; ++l) last_up[l] = -1;
+        auto flush = [&]() {
+            if (out_row < 0) return;
+            float *y = Y + (int64_t)out_row * ldo;
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                float h = acc[e];
+#pragma unroll
+                for (int l = 0; l < N - 1; ++l)
+                    if (l < d) h *= Chunk<GT>::get(Ha[l], e);
+                if (col_of(e) < R) atomicAdd(y + col_of(e), h);
+                acc[e] = 0.0f;
+            }
+        };
+        for (int t0 = 0; t0 < T; t0 += C) {
+            for (int e2 = lane; e2 < NG * C; e2 += 64) {
+                const int s = e2 / C, j = e2 % C;
+                const int64_t k = base + (int64_t)s * T + t0 + j;
+                const bool in = k < nleaves;
+                sw[s * (C + 1) + j] = in ? leafw[k] : 0;
+                sv[s * (C + 1) + j] = in ? vals[k] : 0.0f;
+#pragma unroll
+                for (int l = 0; l < NU; ++l) s_u[wave][l][s * (C + 1) + j] = in ? cv.uprow[l + 1][k] : 0;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const int len = (int)(kend - k0) - t0;
+            for (int j0 = 0; j0 < C; j0 += U) {
+                if (j0 >= len) break;
+                int32_t wu[U];
+                float vu[U];
+                raw_t rowu[U][RW], hu[U][NU][RW];
+                bool need[U][NU];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int at = gs * (C + 1) + j0 + u;
+                    wu[u] = sw[at];
+                    vu[u] = sv[at];
+                    Chunk<GT>::load(a_leaf, __umul24((uint32_t)wu[u] & IDMASK, rowb) + lane_off, rowu[u]);
+#pragma unroll
+                    for (int l = 0; l < NU; ++l) {
+                        need[u][l] = false;
+                        if (l + 1 > d) {  // levels below d
+                            const int32_t id = s_u[wave][l][at];
+                            need[u][l] = id != last_up[l];
+                            last_up[l] = id;
+                            if (need[u][l])
+                                Chunk<GT>::load(static_cast<const char *>(fv.a[l + 1]),
+                                                __umul24((uint32_t)id, rowb) + lane_off, hu[u][l]);
+                        }
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int jr = j0 + u;
+                    if (jr < len) {
+                        const int at = gs * (C + 1) + jr;
+                        const int lvl = (int)((uint32_t)wu[u] >> 29);
+                        const bool first = (t0 | jr) == 0;
+                        if (!first && lvl == 0) c0 += 1;
+                        if (first || lvl <= d) {
+                            // a level-d node opens here (or continues from an earlier run)
+                            flush();
+                            out_row = s_u[wave][d - 1][at];
+                            Chunk<GT>::load(static_cast<const char *>(fv.a[0]),
+                                            __umul24((uint32_t)root_ids[c0], rowb) + lane_off, Ha[0]);
+#pragma unroll
+                            for (int l = 1; l < N - 1; ++l)
+                                if (l < d)
+                                    Chunk<GT>::load(static_cast<const char *>(fv.a[l]),
+                                                    __umul24((uint32_t)s_u[wave][l - 1][at], rowb) + lane_off, Ha[l]);
+                        }
+#pragma unroll
+                        for (int l = 0; l < NU; ++l)
+                            if (need[u][l]) {
+#pragma unroll
+                                for (int q = 0; q < RW; ++q) Hl[l][q] = hu[u][l][q];
+                            }
+#pragma unroll
+                        for (int e = 0; e < E; ++e) {
+                            float h = vu[u] * Chunk<GT>::get(rowu[u], e);
+#pragma unroll
+                            for (int l = 0; l < NU; ++l)
+                                if (l + 1 > d) h *= Chunk<GT>::get(Hl[l], e);
+                            acc[e] += h;
+                        }
+                    }
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+        if (active) flush();
+    }
+}
+
 // Rows of the leaf factor in rank order: dst row r = src row perm[r] (16-byte chunks).
 __global__ void k_permute_rows(const uint4 *__restrict__ src, const int32_t *__restrict__ perm, int64_t rows,
                                int chunks, uint4 *__restrict__ dst) {
@@ -372,9 +524,32 @@ __global__ void k_permute_rows(const uint4 *__restrict__ src, const int32_t *__r
 // G lanes per leaf, one 16-byte chunk each, cover the padded row; one wave
 // range per resident wave.
 template <int N, int G, typename GT>
-static cpd_status launch_root_g(const CsfView &cv, const FacView &fv, const char *a_leaf, uint32_t rowb,
+static cpd_status launch_mid_g(const CsfView &cv, const FacView &fv, const char *a_leaf, uint32_t rowb, int d,
+                               const int32_t *starts, int32_t T, float *Y, int64_t ldo, int R, hipStream_t s) {
+    constexpr int NG = 64 / G;
+    auto kern = k_mttkrp_mid<N, G, GT>;
+    const int64_t nsteps = ceil_div(cv.nleaves, NG * (int64_t)T);
+    int dev = 0, ncu = 256;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) ncu = v;
+    }
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64 * ROOT_WAVES, 0) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    per_cu = std::min(per_cu, 6);
+    const int64_t nwaves = std::max<int64_t>(1, std::min<int64_t>(nsteps, (int64_t)ncu * per_cu * ROOT_WAVES));
+    hipLaunchKernelGGL(kern, dim3((unsigned)ceil_div(nwaves, ROOT_WAVES)), dim3(64 * ROOT_WAVES), 0, s, cv, fv, a_leaf,
+                       rowb, d, starts, T, nsteps, nwaves, Y, ldo, R);
+    CPD_LAUNCH_CHECK();
+    return CPD_OK;
+}
+
+template <int N, int G, typename GT>
+static cpd_status launch_root_g(const CsfView &cv, const FacView &fv, const char *a_leaf, uint32_t rowb, int d,
                                 const int32_t *starts, int64_t ntiles, int32_t T, float *Y, int64_t ldo, int R,
                                 hipStream_t s) {
+    if (d > 0) return launch_mid_g<N, G, GT>(cv, fv, a_leaf, rowb, d, starts, T, Y, ldo, R, s);
     constexpr int NG = 64 / G;
     auto kern = k_mttkrp_root<N, G, GT>;
     const int64_t nsteps = ceil_div(cv.nleaves, NG * (int64_t)T);
@@ -397,14 +572,14 @@ static cpd_status launch_root_g(const CsfView &cv, const FacView &fv, const char
 }
 
 template <int N, typename GT>
-static cpd_status launch_root_n(int RP, const CsfView &cv, const FacView &fv, const char *a_leaf, int64_t ld,
+static cpd_status launch_root_n(int RP, const CsfView &cv, const FacView &fv, const char *a_leaf, int64_t ld, int d,
                                 const int32_t *starts, int64_t ntiles, int32_t T, float *Y, int64_t ldo, int R,
                                 hipStream_t s) {
     constexpr int W = Chunk<GT>::W;
     const uint32_t rowb = (uint32_t)(ld * (int64_t)Chunk<GT>::ELEM);
     switch (RP / W) {
 #define CPD_ROOT_G(g) \
-    case g: return launch_root_g<N, g, GT>(cv, fv, a_leaf, rowb, starts, ntiles, T, Y, ldo, R, s);
+    case g: return launch_root_g<N, g, GT>(cv, fv, a_leaf, rowb, d, starts, ntiles, T, Y, ldo, R, s);
         CPD_ROOT_G(2)
         CPD_ROOT_G(4)
         CPD_ROOT_G(5)
@@ -421,11 +596,12 @@ int root_lanes_per_leaf(int RP, bool bf16) {
     return RP <= BF16_NARROW_MAX ? RP / Chunk<bf16x4>::W : RP / Chunk<uint16_t>::W;
 }
 
-cpd_status launch_root(int N, bool bf16, int RP, const int32_t *const *fids, const int32_t *const *fptr,
+cpd_status launch_root(int N, bool bf16, int RP, int d, const int32_t *const *fids, const int32_t *const *fptr,
                        const float *vals, const int32_t *leafw, const int32_t *leaf_perm, const int32_t *const *uprow,
                        const int64_t *counts, const int64_t *dims_by_level, const void *const *fac_by_level,
                        int64_t ld, const int32_t *starts, int64_t ntiles, int32_t T, float *Y, int64_t ldo, int R,
                        hipStream_t s) {
+    if (d < 0 || d > N - 2) CPD_FAIL(CPD_EINVAL, "lane-group kernel for depth %d of %d levels", d, N);
     if (!leafw || !leaf_perm) CPD_FAIL(CPD_EUNSUPPORTED, "root kernel needs leaf ids below 2^29");
     const int64_t rowb = ld * (bf16 ? 2 : 4);
     if (rowb >= (1 << 24) || rowb % 16) CPD_FAIL(CPD_EUNSUPPORTED, "root kernel needs 16-byte rows below 16 MiB");
@@ -462,9 +638,9 @@ cpd_status launch_root(int N, bool bf16, int RP, const int32_t *const *fids, con
     const bool narrow = bf16 && RP <= BF16_NARROW_MAX;
 #define CPD_ROOT_N(n)                                                                                      \
     case n:                                                                                                \
-        if (narrow) return launch_root_n<n, bf16x4>(RP, cv, fv, a_leaf, ld, starts, ntiles, T, Y, ldo, R, s); \
-        return bf16 ? launch_root_n<n, uint16_t>(RP, cv, fv, a_leaf, ld, starts, ntiles, T, Y, ldo, R, s)   \
-                    : launch_root_n<n, float>(RP, cv, fv, a_leaf, ld, starts, ntiles, T, Y, ldo, R, s);
+        if (narrow) return launch_root_n<n, bf16x4>(RP, cv, fv, a_leaf, ld, d, starts, ntiles, T, Y, ldo, R, s); \
+        return bf16 ? launch_root_n<n, uint16_t>(RP, cv, fv, a_leaf, ld, d, starts, ntiles, T, Y, ldo, R, s)   \
+                    : launch_root_n<n, float>(RP, cv, fv, a_leaf, ld, d, starts, ntiles, T, Y, ldo, R, s);
     switch (N) {
         CPD_ROOT_N(3)
         CPD_ROOT_N(4)

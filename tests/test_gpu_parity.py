@@ -246,8 +246,8 @@ def test_mttkrp_tile_widths(tile):
     for mode in range(3):
         ref = ocoo.mttkrp(t.dims, inds, vals, [f.numpy() for f in facs], mode)
         depth = c.order.index(mode)
-        # the root kernel takes tile widths in multiples of 32
-        row_ok = depth < 2 and (depth > 0 or tile % 32 == 0)
+        # the lane-group (row) kernels take tile widths in multiples of 32
+        row_ok = depth < 2 and tile % 32 == 0
         for kernel in (["lane", "row"] if row_ok else ["lane"]):
             y, _ = _run(cpd, c, facs, mode, 16, "fp32", kernel, "auto", tile)
             assert relerr(y, ref) <= 1e-5, (mode, kernel, tile)
