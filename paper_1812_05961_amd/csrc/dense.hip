@@ -75,29 +75,29 @@ k_gram(const float *__restrict__ A, int64_t rows, int R, int64_t ld, double *__r
     }
 }
 
-// sum over b < nb of p[b * stride]: eight interleaved chains (b mod 8),
-// combined in a fixed order, so loads overlap and the result is deterministic
-__device__ inline double sum_strided(const double *__restrict__ p, int nb, int64_t stride) {
-    double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    int b = 0;
-    for (; b + 7 < nb; b += 8) {
+// sum over b < nb of p[b * stride] by one wave: lane l adds the terms
+// b = l, l + 64, ... (independent loads), then a fixed butterfly combines the
+// lanes, so the result is deterministic; every lane returns the total.
+__device__ inline double wave_sum_strided(const double *__restrict__ p, int nb, int64_t stride) {
+    const int lane = threadIdx.x & 63;
+    double a = 0.0;
+    for (int b = lane; b < nb; b += 64) a += p[(int64_t)b * stride];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) a[q] += p[(int64_t)(b + q) * stride];
-    }
-    for (int q = 0; b < nb; ++b, ++q) a[q] += p[(int64_t)b * stride];
-    return ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+    for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
+    return a;
 }
 
-// Sum the per-block partials; fill both triangles.
-__global__ void k_gram_reduce(const double *__restrict__ partial, int nblocks, int P, int R,
-                              double *__restrict__ G) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+// Sum the per-block partials, one wave per entry; fill both triangles.
+__global__ void __launch_bounds__(256) k_gram_reduce(const double *__restrict__ partial, int nblocks, int P, int R,
+                                                     double *__restrict__ G) {
+    const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (t >= R * R) return;
     int r = t / R, c = t % R;
     const int rr = min(r, c), cc = max(r, c);
     // within a diagonal block both triangles were computed; outside, use the upper block
     const int src = ((rr >> 4) == (cc >> 4)) ? (r * P + c) : (rr * P + cc);
-    G[t] = sum_strided(partial + src, nblocks, (int64_t)P * P);
+    const double v = wave_sum_strided(partial + src, nblocks, (int64_t)P * P);
+    if ((threadIdx.x & 63) == 0) G[t] = v;
 }
 
 cpd_status gram(const float *A, int64_t rows, int R, int64_t ld, double *G, hipStream_t s) {
@@ -114,7 +114,7 @@ cpd_status gram(const float *A, int64_t rows, int R, int64_t ld, double *G, hipS
         default: hipLaunchKernelGGL(k_gram<4>, dim3(nb), dim3(256), 0, s, A, rows, R, ld, part.p); break;
     }
     CPD_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)ceil_div(R * R, 256)), dim3(256), 0, s,
+    hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)ceil_div(R * R, 4)), dim3(256), 0, s,
                        (const double *)part.p, nb, P, R, G);
     CPD_LAUNCH_CHECK();
     return CPD_OK;
@@ -156,30 +156,47 @@ k_make_w(GramSet gs, int nmodes, int mode, int R, double *__restrict__ W, double
     // Cholesky's L(j, j), so the same threshold decides between the inverse
     // and the fallback.  Sweeping every index leaves -V^{-1}; the update is
     // symmetric term by term, so W is exactly symmetric.
-    __shared__ double colj[CPD_MAX_RANK];
+    // Two LDS copies: step j reads one and writes the other (one barrier per
+    // step); each thread keeps the same entries for every step.
+    __shared__ double Vs[2][CPD_MAX_RANK * CPD_MAX_RANK];
+    constexpr int MAXE = CPD_MAX_RANK * CPD_MAX_RANK / 256;
+    int rr[MAXE], cc[MAXE];
+#pragma unroll
+    for (int i = 0; i < MAXE; ++i) {
+        const int t = tid + 256 * i;
+        rr[i] = t / R;
+        cc[i] = t % R;
+        if (t < R * R) Vs[0][t] = V[t];
+    }
+    __syncthreads();
     bool ok = true;
     for (int j = 0; j < R; ++j) {
-        const double d = V[j * R + j];
+        const double *Vc = Vs[j & 1];
+        double *Vn = Vs[(j + 1) & 1];
+        const double d = Vc[j * R + j];
         if (!(d > thresh)) {
             ok = false;  // every thread reads the same d
             break;
         }
-        if (tid < R) colj[tid] = V[tid * R + j];
-        __syncthreads();
         const double inv = 1.0 / d;
-        for (int t = tid; t < R * R; t += 256) {
-            const int r = t / R, c = t % R;
-            double x;
-            if (r == j && c == j) x = -inv;
-            else if (r == j) x = colj[c] * inv;
-            else if (c == j) x = colj[r] * inv;
-            else x = V[t] - colj[r] * colj[c] * inv;
-            V[t] = x;
+#pragma unroll
+        for (int i = 0; i < MAXE; ++i) {
+            const int t = tid + 256 * i;
+            if (t < R * R) {
+                const int r = rr[i], c = cc[i];
+                double x;
+                if (r == j && c == j) x = -inv;
+                else if (r == j) x = Vc[c * R + j] * inv;
+                else if (c == j) x = Vc[r * R + j] * inv;
+                else x = Vc[t] - Vc[r * R + j] * Vc[c * R + j] * inv;
+                Vn[t] = x;
+            }
         }
         __syncthreads();
     }
     if (ok) {
-        for (int t = tid; t < R * R; t += 256) W[t] = -V[t];
+        const double *Vf = Vs[R & 1];
+        for (int t = tid; t < R * R; t += 256) W[t] = -Vf[t];
         if (tid == 0 && used_pinv) *used_pinv = 0;
         return;
     }
@@ -322,10 +339,12 @@ k_apply_w(const float *__restrict__ Y, int64_t rows, int R, int64_t ldy, const d
     }
 }
 
-__global__ void k_lambda(const double *__restrict__ partial, int nblocks, int R, double *__restrict__ lambda) {
-    const int c = threadIdx.x;
+__global__ void __launch_bounds__(256) k_lambda(const double *__restrict__ partial, int nblocks, int R,
+                                                double *__restrict__ lambda) {
+    const int c = blockIdx.x * 4 + (threadIdx.x >> 6);  // one wave per column
     if (c >= R) return;
-    lambda[c] = sqrt(sum_strided(partial + c, nblocks, R));
+    const double v = wave_sum_strided(partial + c, nblocks, R);
+    if ((threadIdx.x & 63) == 0) lambda[c] = sqrt(v);
 }
 
 // ------------------------------------------------------------------ fit
@@ -350,19 +369,26 @@ __global__ void k_fit_final(const double *__restrict__ partial, int nblocks, int
                             const double *__restrict__ lambda, GramSet gs, int nmodes, double normX2,
                             double *__restrict__ fit) {
     __shared__ double inner_r[CPD_MAX_RANK], quad_r[CPD_MAX_RANK];
-    const int r = threadIdx.x;
-    if (r < R) {
-        inner_r[r] = lambda[r] * sum_strided(partial + r, nblocks, R);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int nw = blockDim.x >> 6;
+    // one wave per r: the column's partials, then sum_c lambda_r lambda_c prod_m G_m(r, c)
+    for (int r = wave; r < R; r += nw) {
+        const double in = wave_sum_strided(partial + r, nblocks, R);
         double q = 0.0;
-        for (int c = 0; c < R; ++c) {
+        if (lane < R) {
             double h = 1.0;
-            for (int m = 0; m < nmodes; ++m) h *= gs.g[m][r * R + c];
-            q += h * lambda[c];
+            for (int m = 0; m < nmodes; ++m) h *= gs.g[m][r * R + lane];
+            q = h * lambda[lane];
         }
-        quad_r[r] = lambda[r] * q;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) q += __shfl_xor(q, o, 64);
+        if (lane == 0) {
+            inner_r[r] = lambda[r] * in;
+            quad_r[r] = lambda[r] * q;
+        }
     }
     __syncthreads();
-    if (r == 0) {
+    if (threadIdx.x == 0) {
         double inner = 0.0, normK2 = 0.0;
         for (int c = 0; c < R; ++c) {
             inner += inner_r[c];
@@ -439,7 +465,8 @@ cpd_status solve_normalize(const double *const *grams, int nmodes, int mode, con
 #undef CPD_APPLY
         CPD_LAUNCH_CHECK();
         if (pass == 0) {
-            hipLaunchKernelGGL(k_lambda, dim3(1), dim3(64), 0, s, (const double *)part.p, nb, R, lambda);
+            hipLaunchKernelGGL(k_lambda, dim3((unsigned)ceil_div(R, 4)), dim3(256), 0, s, (const double *)part.p, nb,
+                               R, lambda);
             CPD_LAUNCH_CHECK();
         }
     }
@@ -464,7 +491,7 @@ cpd_status fit(double normX2, const double *lambda, const float *A, int64_t lda,
     CPD_TRY(part.alloc((size_t)nb * R, s));
     hipLaunchKernelGGL(k_fit_partial, dim3(nb), dim3(256), 0, s, A, lda, Y, ldy, rows, R, part.p);
     CPD_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_fit_final, dim3(1), dim3(64), 0, s, (const double *)part.p, nb, R, lambda, gs, nmodes,
+    hipLaunchKernelGGL(k_fit_final, dim3(1), dim3(1024), 0, s, (const double *)part.p, nb, R, lambda, gs, nmodes,
                        normX2, out);
     CPD_LAUNCH_CHECK();
     return CPD_OK;
