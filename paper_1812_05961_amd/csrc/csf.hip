@@ -99,6 +99,83 @@ __global__ void k_pack(LevelInds in, KeyLayout kl, const int64_t *dims_by_level,
     pay[k] = __float_as_int(vals[k]);
 }
 
+// The same for four consecutive nonzeros per thread with 16-byte loads and
+// stores (index arrays and values 16-byte aligned; the last partial group
+// element by element).
+template <int NL>
+__global__ void k_pack4(LevelInds in, KeyLayout kl, const int64_t *dims_by_level, const float *vals, int64_t n,
+                        uint64_t *lo, uint64_t *hi, int32_t *pay, int32_t *bad) {
+    const int64_t k0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+    if (k0 >= n) return;
+    const bool full = k0 + 4 <= n;
+    int32_t v[NL][4];
+    float x[4];
+    if (full) {
+#pragma unroll
+        for (int l = 0; l < NL; ++l) {
+            const int4 q = *reinterpret_cast<const int4 *>(in.p[l] + k0);
+            v[l][0] = q.x;
+            v[l][1] = q.y;
+            v[l][2] = q.z;
+            v[l][3] = q.w;
+        }
+        const float4 f = *reinterpret_cast<const float4 *>(vals + k0);
+        x[0] = f.x;
+        x[1] = f.y;
+        x[2] = f.z;
+        x[3] = f.w;
+    } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const bool in_r = k0 + j < n;
+#pragma unroll
+            for (int l = 0; l < NL; ++l) v[l][j] = in_r ? in.p[l][k0 + j] : 0;
+            x[j] = in_r ? vals[k0 + j] : 0.0f;
+        }
+    }
+    uint64_t a[4], b[4];
+    bool ok = true;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        a[j] = 0;
+        b[j] = 0;
+        const bool in_r = k0 + j < n;
+#pragma unroll
+        for (int l = 0; l < NL; ++l) {
+            const int32_t w = v[l][j];
+            ok = ok && (!in_r || (w >= 0 && (int64_t)w < dims_by_level[l]));
+            const uint64_t q = (uint64_t)(uint32_t)w;
+            const int sh = kl.shift[l];
+            if (kl.bits[l] == 0) continue;
+            if (sh >= 64) {
+                b[j] |= q << (sh - 64);
+            } else {
+                a[j] |= q << sh;
+                if (sh > 0 && sh + kl.bits[l] > 64) b[j] |= q >> (64 - sh);
+            }
+        }
+    }
+    if (!ok) atomicOr(bad, 1);
+    if (full) {
+        reinterpret_cast<ulonglong2 *>(lo + k0)[0] = make_ulonglong2(a[0], a[1]);
+        reinterpret_cast<ulonglong2 *>(lo + k0)[1] = make_ulonglong2(a[2], a[3]);
+        if (hi) {
+            reinterpret_cast<ulonglong2 *>(hi + k0)[0] = make_ulonglong2(b[0], b[1]);
+            reinterpret_cast<ulonglong2 *>(hi + k0)[1] = make_ulonglong2(b[2], b[3]);
+        }
+        *reinterpret_cast<int4 *>(pay + k0) =
+            make_int4(__float_as_int(x[0]), __float_as_int(x[1]), __float_as_int(x[2]), __float_as_int(x[3]));
+    } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (k0 + j < n) {
+                lo[k0 + j] = a[j];
+                if (hi) hi[k0 + j] = b[j];
+                pay[k0 + j] = __float_as_int(x[j]);
+            }
+    }
+}
+
 // ---- radix sort: per-tile digit histogram (digit-major output)
 // RPN > 0: the keys are those of rp.a (RPN levels) in layout rp.kx (the
 // first pass of a re-sort into another tree order).
@@ -109,11 +186,17 @@ k_radix_hist(const uint64_t *keys, Repack rp, int64_t n, int shift, int32_t *his
     h[threadIdx.x] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * RS_TILE;
+    // every load of the tile in flight before the first count
+    uint32_t dg[RS_ITEMS];
 #pragma unroll
     for (int j = 0; j < RS_ITEMS; ++j) {
-        int64_t i = base + (int64_t)j * RS_THREADS + threadIdx.x;
-        if (i < n) atomicAdd(&h[((RPN ? repack_key<RPN>(rp, rp.a[i]) : keys[i]) >> shift) & 255u], 1);
+        const int64_t i = base + (int64_t)j * RS_THREADS + threadIdx.x;
+        const uint64_t key = i < n ? (RPN ? repack_key<RPN>(rp, rp.a[i]) : keys[i]) : 0ull;
+        dg[j] = i < n ? (uint32_t)(key >> shift) & 255u : 256u;
     }
+#pragma unroll
+    for (int j = 0; j < RS_ITEMS; ++j)
+        if (dg[j] < 256u) atomicAdd(&h[dg[j]], 1);
     __syncthreads();
     hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
 }
@@ -409,23 +492,48 @@ __global__ void k_rank_scatter(const uint64_t *key, int64_t nid, int ibits, int3
 }
 
 // First level at which sorted key k differs from key k-1 (0 for k = 0, NL for
-// an exact duplicate, which also sets *dup).
+// an exact duplicate, which also sets *dup).  Four consecutive keys per
+// thread, their four levels stored as one word (dl 4-byte aligned).
 template <int NL>
-__global__ void k_first_diff(const uint64_t *__restrict__ lo, const uint64_t *__restrict__ hi, KeyLayout kl,
-                             int64_t n, uint8_t *__restrict__ dl, int32_t *dup) {
-    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
-    if (k == 0) {
-        dl[0] = 0;
-        return;
-    }
-    const uint64_t xa = lo[k] ^ lo[k - 1], xb = hi ? (hi[k] ^ hi[k - 1]) : 0ull;
+__device__ __forceinline__ int first_diff_level(const KeyLayout &kl, uint64_t xa, uint64_t xb) {
     int l = NL;
 #pragma unroll
     for (int q = NL - 1; q >= 0; --q)
         if (key_field(xa, xb, kl.shift[q], kl.bits[q]) != 0u) l = q;
-    dl[k] = (uint8_t)l;
-    if (l == NL && dup) atomicOr(dup, 1);
+    return l;
+}
+
+template <int NL>
+__global__ void k_first_diff(const uint64_t *__restrict__ lo, const uint64_t *__restrict__ hi, KeyLayout kl,
+                             int64_t n, uint8_t *__restrict__ dl, int32_t *dup) {
+    const int64_t k0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+    if (k0 >= n) return;
+    uint64_t a[5], b[5];  // keys k0-1 .. k0+3
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+        const int64_t k = k0 - 1 + j;
+        const bool in = k >= 0 && k < n;
+        a[j] = in ? lo[k] : 0ull;
+        b[j] = (in && hi) ? hi[k] : 0ull;
+    }
+    uint32_t w = 0;
+    bool seen_dup = false;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int64_t k = k0 + j;
+        int l = 0;
+        if (k > 0 && k < n) l = first_diff_level<NL>(kl, a[j + 1] ^ a[j], b[j + 1] ^ b[j]);
+        seen_dup = seen_dup || (k < n && l == NL);
+        w |= (uint32_t)l << (8 * j);
+    }
+    if (k0 + 4 <= n) {
+        *reinterpret_cast<uint32_t *>(dl + k0) = w;
+    } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (k0 + j < n) dl[k0 + j] = (uint8_t)(w >> (8 * j));
+    }
+    if (seen_dup && dup) atomicOr(dup, 1);
 }
 
 struct IsNew {
@@ -570,17 +678,32 @@ KeyLayout key_layout(int nm, const int64_t *dims, const int32_t *order, int *tot
 // l < N-1 (first differing level <= l).
 constexpr int CT_THREADS = 256, CT_ITEMS = 16, CT_TILE = CT_THREADS * CT_ITEMS;
 
+// CT_ITEMS consecutive first-difference levels from position i (255 past n):
+// one 16-byte load when the run is whole (the array is 16-byte aligned).
+__device__ __forceinline__ void load_levels(const uint8_t *__restrict__ dl, int64_t n, int64_t i,
+                                            uint8_t (&d)[CT_ITEMS]) {
+    static_assert(CT_ITEMS == 16, "one 16-byte load per thread");
+    if (i + CT_ITEMS <= n) {
+        const uint4 q = *reinterpret_cast<const uint4 *>(dl + i);
+        const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+        for (int j = 0; j < CT_ITEMS; ++j) d[j] = (uint8_t)(w[j >> 2] >> (8 * (j & 3)));
+    } else {
+#pragma unroll
+        for (int j = 0; j < CT_ITEMS; ++j) d[j] = i + j < n ? dl[i + j] : (uint8_t)255;
+    }
+}
+
 __global__ void __launch_bounds__(CT_THREADS)
 k_level_counts(const uint8_t *__restrict__ dl, int64_t n, int nlv, int32_t *__restrict__ partial, int64_t nb) {
     __shared__ int32_t red[CT_THREADS / 64][CPD_MAX_MODES];
     const int64_t base = (int64_t)blockIdx.x * CT_TILE;
     int32_t c[CPD_MAX_MODES] = {};
+    uint8_t d[CT_ITEMS];
+    load_levels(dl, n, base + (int64_t)threadIdx.x * CT_ITEMS, d);
 #pragma unroll
-    for (int j = 0; j < CT_ITEMS; ++j) {
-        const int64_t i = base + (int64_t)j * CT_THREADS + threadIdx.x;
-        const int d = i < n ? dl[i] : 255;
-        for (int l = 0; l < nlv; ++l) c[l] += d <= l;
-    }
+    for (int j = 0; j < CT_ITEMS; ++j)
+        for (int l = 0; l < nlv; ++l) c[l] += d[j] <= l;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int l = 0; l < nlv; ++l) {
         int32_t v = c[l];
@@ -630,16 +753,19 @@ __global__ void __launch_bounds__(CT_THREADS)
 k_compress(const uint64_t *__restrict__ lo, const uint64_t *__restrict__ hi, KeyLayout kl,
            const uint8_t *__restrict__ dl, const float *__restrict__ val, int64_t n,
            const int32_t *__restrict__ partial, int64_t nb, TreeOut t) {
-    __shared__ uint8_t s_dl[CT_TILE];
+    __shared__ __align__(16) uint8_t s_dl[CT_TILE];
     __shared__ uint64_t s_pre[CT_TILE];  // per nonzero: openings before it in the tile, per level
     __shared__ uint32_t s_w[2][CT_THREADS / 64];
     constexpr int nl = NL, nlv = NL - 1;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t base = (int64_t)blockIdx.x * CT_TILE;
+    {
+        uint8_t d[CT_ITEMS];
+        load_levels(dl, n, base + (int64_t)tid * CT_ITEMS, d);
+        uint32_t w[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
-    for (int j = 0; j < CT_ITEMS; ++j) {
-        const int e = j * CT_THREADS + tid;
-        s_dl[e] = base + e < n ? dl[base + e] : (uint8_t)255;
+        for (int j = 0; j < CT_ITEMS; ++j) w[j >> 2] |= (uint32_t)d[j] << (8 * (j & 3));
+        *reinterpret_cast<uint4 *>(s_dl + tid * CT_ITEMS) = make_uint4(w[0], w[1], w[2], w[3]);
     }
     __syncthreads();
     // this thread's CT_ITEMS consecutive nonzeros
@@ -760,9 +886,15 @@ cpd_status sort_merge(int nm, const KeyLayout &kl, int total_bits, const int32_t
         if (two) CPD_TRY(S.hi[b].alloc(nnz, s));
         CPD_TRY(S.pay[b].alloc(nnz, s));
     }
-#define CPD_PACK(L)                                                                                      \
-    hipLaunchKernelGGL(k_pack<L>, dim3(grid1(nnz)), dim3(256), 0, s, li, kl, (const int64_t *)d_dims.p, vals, nnz, \
-                       S.lo[0].p, S.hi[0].p, S.pay[0].p, d_flag)
+    bool aligned = (reinterpret_cast<uintptr_t>(vals) & 15) == 0;
+    for (int l = 0; l < nm; ++l) aligned = aligned && (reinterpret_cast<uintptr_t>(li.p[l]) & 15) == 0;
+#define CPD_PACK(L)                                                                                          \
+    if (aligned)                                                                                             \
+        hipLaunchKernelGGL(k_pack4<L>, dim3(grid1(ceil_div(nnz, 4))), dim3(256), 0, s, li, kl,              \
+                           (const int64_t *)d_dims.p, vals, nnz, S.lo[0].p, S.hi[0].p, S.pay[0].p, d_flag); \
+    else                                                                                                     \
+        hipLaunchKernelGGL(k_pack<L>, dim3(grid1(nnz)), dim3(256), 0, s, li, kl, (const int64_t *)d_dims.p,  \
+                           vals, nnz, S.lo[0].p, S.hi[0].p, S.pay[0].p, d_flag)
     CPD_BY_LEVELS(nm, CPD_PACK)
 #undef CPD_PACK
     CPD_LAUNCH_CHECK();
@@ -774,7 +906,7 @@ cpd_status sort_merge(int nm, const KeyLayout &kl, int total_bits, const int32_t
     DevBuf<int32_t> pos;
     CPD_TRY(S.dl.alloc(nnz, s));
 #define CPD_FIRST_DIFF(L)                                                                                    \
-    hipLaunchKernelGGL(k_first_diff<L>, dim3(grid1(nnz)), dim3(256), 0, s, klo, khi, kl, nnz, S.dl.p, \
+    hipLaunchKernelGGL(k_first_diff<L>, dim3(grid1(ceil_div(nnz, 4))), dim3(256), 0, s, klo, khi, kl, nnz, S.dl.p, \
                        d_flag + FLAG_DUP)
     CPD_BY_LEVELS(nm, CPD_FIRST_DIFF)
 #undef CPD_FIRST_DIFF
@@ -842,8 +974,8 @@ cpd_status derive(int nm, const int64_t *dims, const int32_t *order_a, const Key
     CPD_TRY(radix_sort_rp(klo, khi, kp, olo, ohi, op, n, total, s, kx->shift[0], &rp));
     CPD_TRY(S.dl.alloc(n, s));
 #define CPD_FIRST_DIFF(L)                                                                                 \
-    hipLaunchKernelGGL(k_first_diff<L>, dim3(grid1(n)), dim3(256), 0, s, klo, (const uint64_t *)nullptr, *kx, n, \
-                       S.dl.p, (int32_t *)nullptr)
+    hipLaunchKernelGGL(k_first_diff<L>, dim3(grid1(ceil_div(n, 4))), dim3(256), 0, s, klo, (const uint64_t *)nullptr, \
+                       *kx, n, S.dl.p, (int32_t *)nullptr)
     CPD_BY_LEVELS(nm, CPD_FIRST_DIFF)
 #undef CPD_FIRST_DIFF
     CPD_LAUNCH_CHECK();

@@ -141,6 +141,25 @@ def test_csf_build_rooted_bit_exact(name):
         c.free()
 
 
+def test_csf_build_from_unaligned_views():
+    """Index and value arrays that start 4 bytes into their allocations (the
+    element-by-element key packing) give the same tree."""
+    cpd = _cpd()
+    t = CASES["dups3"]()
+    inds = _dev(t.inds)
+    vals = _dev(t.vals)
+    pad_i = torch.zeros((t.nmodes, 1), dtype=inds.dtype, device="cuda")
+    big_i = torch.cat([pad_i, inds], 1).to(torch.int32)
+    big_v = torch.cat([torch.zeros(1, device="cuda"), vals])
+    views = [big_i[m, 1:] for m in range(t.nmodes)]
+    assert all(v.data_ptr() % 16 != 0 for v in views) and big_v[1:].data_ptr() % 16 != 0
+    c = cpd.csf_build(views, big_v[1:], t.dims)
+    i_np, v_np = t.numpy()
+    ref = ocsf.build(t.dims, i_np, t.vals.numpy(), ocsf.heuristic_order(t.dims))
+    _same_tree(c, ref, t.nmodes)
+    c.free()
+
+
 def test_csf_build_rooted_rejects_bad_indices():
     cpd = _cpd()
     inds = torch.tensor([[0, 1], [0, 3], [0, 1]], device="cuda")
