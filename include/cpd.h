@@ -236,6 +236,49 @@ cpd_status cpd_als(int32_t nmodes, const int64_t *dims, int64_t nnz, const int32
                    double *fit_out, int32_t *iters_out, void *stream);
 
 /* ---------------------------------------------------------------------------
+ * CP with missing values (tensor completion; the paper lists it next to
+ * least-squares CP among the CPD library's decompositions, Section III):
+ * the nonzeros are the observed entries, every other entry is unknown.  Mode
+ * by mode, row i of A_n solves (G_i + reg I) a = y_i with
+ * G_i = sum over observed entries of row i of h h^T and y_i = sum of x h
+ * (h: the Hadamard product of the other modes' rows of the entry; y is the
+ * MTTKRP of the observed entries), and after each sweep the RMSE over the
+ * observed entries is sqrt((sum x^2 - 2 sum_i a_i.y_i + sum_i a_i^T G_i a_i)
+ * / n_obs) from the last mode.  No column weights; rows without observations
+ * become zero.  reg must be > 0 (every row system is then positive definite).
+ * ------------------------------------------------------------------------- */
+
+/* Row Grams of `mode`, which must be the root of the tree (e.g. a tree of
+ * cpd_csf_build_rooted): G (device, dims[mode] x rank x rank doubles,
+ * row-major per row) is zeroed, then G[i][r][c] for r <= c receives
+ * sum over row i's entries of h_r h_c, products formed in FP64 from the FP32
+ * factors (host array of N device pointers, row stride ld >= rank; the
+ * root's entry is not read).  Entries below the diagonal are left zero.
+ * FP64 atomics: the summation order varies between calls.  3..5 modes, leaf
+ * indices below 2^29. */
+cpd_status cpd_row_gram(cpd_csf csf, const float *const *factors, int64_t ld, int32_t rank, int32_t mode,
+                        double *G, void *stream);
+
+/* For each of `rows` rows: solve (G_i + reg I) a = y_i (G as cpd_row_gram
+ * writes it, only r <= c read; Y device rows x ldy floats) by Gauss-Jordan in
+ * FP64 and write a to A (device rows x lda floats, columns < rank).  terms:
+ * device, 2 doubles receiving sum_i a_i.y_i and sum_i a_i^T G_i a_i, or NULL.
+ * CPD_EINVAL unless reg > 0. */
+cpd_status cpd_row_solve(const double *G, const float *Y, int64_t ldy, int64_t rows, int32_t rank, double reg,
+                         float *A, int64_t lda, double *terms, void *stream);
+
+/* Completion ALS from COO (arguments of cpd_csf_build; duplicates are merged
+ * by summing), `rank` components, at most max_iters sweeps (stop from the
+ * second on once the RMSE changes by less than tol > 0).  factors: host array
+ * of N device pointers to I_m x rank floats (stride rank): the initial values
+ * (factor 0 is not read: mode 0 is solved first), overwritten with the
+ * result.  rmse: host, max_iters doubles (the RMSE after each sweep), or NULL.
+ * iters: host, sweeps run.  3..5 modes.  Waits for `stream`. */
+cpd_status cpd_complete(int32_t nmodes, const int64_t *dims, int64_t nnz, const int32_t *const *inds,
+                        const float *vals, int32_t rank, int32_t max_iters, double tol, double reg,
+                        float *const *factors, double *rmse, int32_t *iters, void *stream);
+
+/* ---------------------------------------------------------------------------
  * Variant selector.  Section V-D2 of the paper settles the lock-or-privatise
  * question by a rule on the output length, the thread count and the nonzero
  * count, and observes that the better choice depends on the tensor.  Here a

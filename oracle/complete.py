@@ -63,10 +63,16 @@ def row_grams(dims, inds, vals, factors, mode, rows=None):
     R = factors[0].shape[1]
     pos = np.full(int(dims[mode]), -1, dtype=np.int64)
     pos[rows] = np.arange(rows.size)
-    take = pos[inds[mode]] >= 0
+    take = np.flatnonzero(pos[inds[mode]] >= 0)
+    # group the observations by output row; G_i = H_i^T H_i over row i's h's
+    take = take[np.argsort(pos[inds[mode][take]], kind="stable")]
     H = _hadamard_rows(inds[:, take], factors, mode)
+    owner = pos[inds[mode][take]]
     G = np.zeros((rows.size, R, R))
-    np.add.at(G, pos[inds[mode][take]], H[:, :, None] * H[:, None, :])
+    bounds = np.flatnonzero(np.diff(owner)) + 1
+    for a, b in zip(np.r_[0, bounds], np.r_[bounds, owner.size]):
+        if b > a:
+            G[owner[a]] = H[a:b].T @ H[a:b]
     return G
 
 

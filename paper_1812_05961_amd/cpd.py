@@ -92,6 +92,9 @@ _SIGS = {
     "cpd_fit": (_I32, [_F64, _P, _P, _I32, _P, _I32, _I64, _I32, _P, _I32, _P, _P]),
     "cpd_sumsq": (_I32, [_P, _I64, _P, _P]),
     "cpd_als": (_I32, [_I32, _P, _I64, _P, _P, _I32, _I32, _F64, _P, _P, _P, _P, _P, _P]),
+    "cpd_row_gram": (_I32, [_P, _P, _I64, _I32, _I32, _P, _P]),
+    "cpd_row_solve": (_I32, [_P, _P, _I64, _I64, _I32, _F64, _P, _I64, _P, _P]),
+    "cpd_complete": (_I32, [_I32, _P, _I64, _P, _P, _I32, _I32, _F64, _F64, _P, _P, _P, _P]),
     "cpd_tensor_stats": (_I32, [_I32, _P, _I64, _P, _P, _P]),
     "cpd_zipf_alpha": (_F64, [_F64, _I64]),
     "cpd_select_candidates": (_I32, [_P, _I32, _I32, _P, _P]),
@@ -309,6 +312,48 @@ def sumsq(vals, stream=None):
     out = torch.empty(1, dtype=torch.float64, device="cuda")
     _check(lib().cpd_sumsq(vals.data_ptr(), vals.numel(), out.data_ptr(), _stream(stream)))
     return out
+
+
+def row_gram(csf: Csf, factors, mode: int, rank=None, stream=None):
+    """cpd_row_gram: (dims[mode], rank, rank) float64 row Grams (upper triangle)."""
+    facs = [None if f is None else _need_cuda(f, "factor") for f in factors]
+    f0 = next(f for f in facs if f is not None)
+    ld = f0.stride(0)
+    rank = rank or f0.shape[1]
+    G = torch.empty((csf.dims[mode], rank, rank), dtype=torch.float64, device=f0.device)
+    _check(lib().cpd_row_gram(csf.handle, _ptrs([None if m == mode else f for m, f in enumerate(facs)]), ld, rank,
+                              mode, G.data_ptr(), _stream(stream)))
+    return G
+
+
+def row_solve(G, Y, reg, rank=None, out=None, stream=None):
+    """cpd_row_solve: rows of (G_i + reg I)^{-1} y_i; returns (A, (cross, quad))."""
+    G = _need_cuda(G, "G")
+    Y = _need_cuda(Y, "Y")
+    rows = Y.shape[0]
+    rank = rank or G.shape[1]
+    A = out if out is not None else torch.zeros((rows, rank), dtype=torch.float32, device=Y.device)
+    terms = torch.zeros(2, dtype=torch.float64, device=Y.device)
+    _check(lib().cpd_row_solve(G.data_ptr(), Y.data_ptr(), Y.stride(0), rows, rank, float(reg), A.data_ptr(),
+                               A.stride(0), terms.data_ptr(), _stream(stream)))
+    t = terms.cpu().tolist()
+    return A, (t[0], t[1])
+
+
+def complete(inds, vals, dims, rank, iters, reg, init, tol=0.0, stream=None):
+    """cpd_complete: completion ALS; init is a list of N (I_m x rank) device
+    tensors (copied, not modified).  Returns dict(factors, rmses, rmse, iters)."""
+    inds, vals, dims = _coo_args(inds, vals, dims)
+    facs = [_need_cuda(a, "init").to(torch.float32).contiguous().clone() for a in init]
+    for m, f in enumerate(facs):
+        if tuple(f.shape) != (dims[m], rank):
+            raise ValueError("init factor %d has shape %s" % (m, tuple(f.shape)))
+    rm = (_F64 * iters)()
+    it = _I32()
+    _check(lib().cpd_complete(len(dims), _i64s(dims), vals.numel(), _ptrs(inds), vals.data_ptr(), rank, iters,
+                              float(tol), float(reg), _ptrs(facs), rm, ctypes.byref(it), _stream(stream)))
+    rmses = [rm[i] for i in range(it.value)]
+    return dict(factors=facs, rmses=rmses, rmse=rmses[-1] if rmses else 0.0, iters=it.value)
 
 
 def als(inds, vals, dims, rank, iters, tol=0.0, init=None, precision="fp32", variant="auto",

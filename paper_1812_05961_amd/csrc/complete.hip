@@ -1,0 +1,421 @@
+// CP with missing values (tensor completion) by row-wise alternating least
+// squares over the observed entries, the decomposition the paper lists next
+// to least-squares CP among the CPD library's routines (Section III).  For
+// mode n, row i of A_n solves
+//     (G_i + reg I) a = y_i,   G_i = sum_{k in O_i} h_k h_k^T,   y_i = sum_{k in O_i} x_k h_k,
+// with O_i the observed entries in row i and h_k the Hadamard product of the
+// other modes' rows.  y is the MTTKRP of the observed entries (the root-level
+// kernel on the tree rooted at mode n); G is new work: a Gram per row,
+// accumulated here on the same tree.
+//
+// Row Gram kernel: one wave per run of T leaves.  Chunks of C leaves are
+// staged in LDS as FP64 rows h (their gathers all in flight together); the
+// wave then walks the chunk's leaves in order, each lane accumulating 4x4
+// blocks of the upper triangle of h h^T in registers, and adds them to G_i
+// with FP64 atomics when the leaf's root node (row i) ends or the run ends.
+// Row solve kernel: one wave per row, Gauss-Jordan on [G_i + reg I | y_i] in
+// LDS (the matrix is symmetric positive definite for reg > 0, so no pivoting),
+// with the row's loss terms a.y and a^T G a for the RMSE.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "csf.h"
+
+namespace cpd {
+
+cpd_status mttkrp(cpd_csf_s *c, const void *const *factors, int32_t ld, int32_t R, int32_t mode, float *Y,
+                  int32_t ldo, const cpd_mttkrp_opts *opts, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
+cpd_status sumsq(const float *v, int64_t n, double *out, hipStream_t s);
+
+namespace {
+
+constexpr int RG_WAVES = 4;   // waves per block
+constexpr int RG_C = 16;      // leaves staged per chunk
+constexpr int RG_T = 512;     // leaves per wave run
+
+struct TreeRefs {
+    const int32_t *ids[CPD_MAX_MODES];  // per-leaf index at level l (uprow for 1..N-2, fids at the leaf)
+    const float *fac[CPD_MAX_MODES];    // factor of level l
+    const int32_t *root_ids;
+    const int32_t *leafw;               // (level << 29) | rank
+    int64_t nleaves;
+};
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// QB: 4x4 blocks of the upper triangle owned per lane (ceil(blocks / 64)).
+template <int N, int QB>
+__global__ void __launch_bounds__(64 * RG_WAVES)
+k_row_gram(TreeRefs tr, int64_t ld, int R, const int32_t *__restrict__ starts, int64_t nruns, double *__restrict__ G) {
+    constexpr int RPMAX = CPD_MAX_RANK;
+    __shared__ double s_h[RG_WAVES][RG_C][RPMAX];
+    __shared__ int32_t s_id[RG_WAVES][N][RG_C];
+    __shared__ int32_t s_lv[RG_WAVES][RG_C];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t run = (int64_t)blockIdx.x * RG_WAVES + wave;
+    if (run >= nruns) return;  // waves are independent: no block barriers
+    const int NB = (R + 3) / 4, RP = NB * 4;
+    const int nblk = NB * (NB + 1) / 2;
+    // this lane's blocks (bi <= bj), enumerated row by row
+    int bi[QB], bj[QB];
+    bool own[QB];
+#pragma unroll
+    for (int q = 0; q < QB; ++q) {
+        int p = lane + 64 * q;
+        own[q] = p < nblk;
+        int i = 0;
+        while (own[q] && p >= NB - i) {
+            p -= NB - i;
+            ++i;
+        }
+        bi[q] = i;
+        bj[q] = i + p;
+    }
+    double acc[QB][16];
+#pragma unroll
+    for (int q = 0; q < QB; ++q)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) acc[q][e] = 0.0;
+    const int64_t k0 = run * RG_T, k1 = min(k0 + (int64_t)RG_T, tr.nleaves);
+    int32_t c0 = starts[run];
+    int32_t row = tr.root_ids[c0];
+    auto flush = [&]() {
+        double *g = G + (int64_t)row * R * R;
+#pragma unroll
+        for (int q = 0; q < QB; ++q) {
+            if (!own[q]) continue;
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int r = bi[q] * 4 + u, c = bj[q] * 4 + v;
+                    if (r < R && c < R && r <= c) atomicAdd(g + r * R + c, acc[q][u * 4 + v]);
+                    acc[q][u * 4 + v] = 0.0;
+                }
+        }
+    };
+    for (int64_t t0 = k0; t0 < k1; t0 += RG_C) {
+        const int len = (int)min((int64_t)RG_C, k1 - t0);
+        // leaf ids of every level and the leaf words, then the rows h in FP64
+        for (int e = lane; e < N * RG_C; e += 64) {
+            const int l = e / RG_C, b = e % RG_C;
+            if (l >= 1) s_id[wave][l][b] = b < len ? tr.ids[l][t0 + b] : 0;
+            else s_lv[wave][b] = b < len ? (int32_t)((uint32_t)tr.leafw[t0 + b] >> 29) : 0;
+        }
+        wave_sync();
+        for (int e = lane; e < RG_C * RP; e += 64) {
+            const int b = e / RP, r = e % RP;
+            double h = 0.0;
+            if (b < len && r < R) {
+                h = 1.0;
+#pragma unroll
+                for (int l = 1; l < N; ++l) h *= (double)tr.fac[l][(int64_t)s_id[wave][l][b] * ld + r];
+            }
+            s_h[wave][b][r] = h;
+        }
+        wave_sync();
+        for (int b = 0; b < len; ++b) {
+            if (s_lv[wave][b] == 0 && t0 + b > k0) {  // a new root node (row) starts at this leaf
+                flush();
+                c0 += 1;
+                row = tr.root_ids[c0];
+            }
+            const double *h = s_h[wave][b];
+#pragma unroll
+            for (int q = 0; q < QB; ++q) {
+                if (!own[q]) continue;
+                double hr[4], hc[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    hr[u] = h[bi[q] * 4 + u];
+                    hc[u] = h[bj[q] * 4 + u];
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) acc[q][u * 4 + v] = fma(hr[u], hc[v], acc[q][u * 4 + v]);
+            }
+        }
+        wave_sync();
+    }
+    flush();
+}
+
+// Row i: solve (G_i + reg I) a = y_i (G_i upper triangle, row-major R x R),
+// write a as FP32, and the loss terms a.y and a^T G_i a.
+__global__ void __launch_bounds__(64)
+k_row_solve(const double *__restrict__ G, const float *__restrict__ Y, int64_t ldy, int64_t rows, int R,
+            double reg, float *__restrict__ A, int64_t lda, double *__restrict__ terms) {
+    __shared__ double M[CPD_MAX_RANK][CPD_MAX_RANK + 2];
+    __shared__ double colj[CPD_MAX_RANK], rowj[CPD_MAX_RANK + 1];
+    const int64_t i = blockIdx.x;
+    const int lane = threadIdx.x;
+    if (i >= rows) return;
+    const double *g = G + i * R * R;
+    const int W = R + 1;  // augmented width
+    for (int t = lane; t < R * W; t += 64) {
+        const int r = t / W, c = t % W;
+        double x;
+        if (c == R) x = (double)Y[i * ldy + r];
+        else x = g[min(r, c) * R + max(r, c)] + (r == c ? reg : 0.0);
+        M[r][c] = x;
+    }
+    __syncthreads();
+    for (int j = 0; j < R; ++j) {
+        // pivot column and pivot row as they stand before step j
+        for (int t = lane; t < R; t += 64) colj[t] = M[t][j];
+        for (int t = j + lane; t < W; t += 64) rowj[t] = M[j][t];
+        __syncthreads();
+        const double inv = 1.0 / colj[j];
+        for (int t = lane; t < R * (W - j); t += 64) {
+            const int r = t / (W - j), c = j + t % (W - j);
+            if (r == j) M[r][c] = rowj[c] * inv;
+            else M[r][c] = M[r][c] - colj[r] * inv * rowj[c];
+        }
+        __syncthreads();
+    }
+    // a = last column; the loss terms with the unregularised Gram
+    double cross = 0.0, quad = 0.0;
+    for (int r = lane; r < R; r += 64) {
+        const double a = M[r][R];
+        A[i * lda + r] = (float)a;
+        cross += a * (double)Y[i * ldy + r];
+        double s = 0.0;
+        for (int c = 0; c < R; ++c) s += g[min(r, c) * R + max(r, c)] * M[c][R];
+        quad += a * s;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        cross += __shfl_xor(cross, o, 64);
+        quad += __shfl_xor(quad, o, 64);
+    }
+    if (lane == 0) {
+        terms[2 * i] = cross;
+        terms[2 * i + 1] = quad;
+    }
+}
+
+// Sum the per-row loss terms (one block, fixed order).
+__global__ void __launch_bounds__(256) k_sum_terms(const double *__restrict__ terms, int64_t rows,
+                                                   double *__restrict__ out) {
+    __shared__ double sc[4], sq[4];
+    double c = 0.0, q = 0.0;
+    for (int64_t i = threadIdx.x; i < rows; i += 256) {
+        c += terms[2 * i];
+        q += terms[2 * i + 1];
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        c += __shfl_xor(c, o, 64);
+        q += __shfl_xor(q, o, 64);
+    }
+    if (lane == 0) {
+        sc[wave] = c;
+        sq[wave] = q;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        out[0] = (sc[0] + sc[1]) + (sc[2] + sc[3]);
+        out[1] = (sq[0] + sq[1]) + (sq[2] + sq[3]);
+    }
+}
+
+__global__ void k_zero_f64(double *p, int64_t n) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) p[t] = 0.0;
+}
+
+__global__ void k_copy_rows(const float *__restrict__ src, int64_t lds, float *__restrict__ dst, int64_t ldd,
+                            int64_t rows, int R) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= rows * R) return;
+    dst[(t / R) * ldd + t % R] = src[(t / R) * lds + t % R];
+}
+
+inline int pad_rank(int R) { return R <= 8 ? 8 : R <= 16 ? 16 : R <= 32 ? 32 : R <= 36 ? 36 : 64; }
+
+}  // namespace
+
+// Row Grams of the mode at the root of tree c into G (rows x R x R FP64,
+// upper triangle, accumulated: the caller zeroes it).
+cpd_status row_gram(cpd_csf_s *c, const float *const *factors, int64_t ld, int R, int mode, double *G,
+                    hipStream_t s) {
+    if (!c || !factors || !G) CPD_FAIL(CPD_EINVAL, "null argument");
+    const int N = c->nmodes;
+    if (R < 1 || R > CPD_MAX_RANK || ld < R) CPD_FAIL(CPD_EINVAL, "rank %d / ld %lld out of range", R, (long long)ld);
+    if (c->order[0] != mode) CPD_FAIL(CPD_EINVAL, "row Grams need the mode at the root of the tree");
+    if (!c->leafw) CPD_FAIL(CPD_EUNSUPPORTED, "row Grams need leaf ids below 2^29");
+    if (N < 3 || N > 5) CPD_FAIL(CPD_EUNSUPPORTED, "row Grams built for 3..5 modes, not %d", N);
+    TreeRefs tr{};
+    for (int l = 1; l < N; ++l) {
+        tr.ids[l] = (l == N - 1) ? c->fids[N - 1] : c->uprow[l];
+        tr.fac[l] = factors[c->order[l]];
+        if (!tr.fac[l]) CPD_FAIL(CPD_EINVAL, "null factor for mode %d", c->order[l]);
+    }
+    tr.root_ids = c->fids[0];
+    tr.leafw = c->leafw;
+    tr.nleaves = c->counts[N - 1];
+    const int32_t *starts;
+    int64_t nruns;
+    CPD_TRY(csf_tiles(c, RG_T, &starts, &nruns, s));
+    const int NB = (R + 3) / 4, nblk = NB * (NB + 1) / 2, QB = (nblk + 63) / 64;
+    const dim3 grid((unsigned)ceil_div(nruns, RG_WAVES)), block(64 * RG_WAVES);
+#define CPD_RG(n, q) hipLaunchKernelGGL((k_row_gram<n, q>), grid, block, 0, s, tr, ld, R, starts, nruns, G)
+#define CPD_RG_N(n)                  \
+    if (QB == 1) CPD_RG(n, 1);       \
+    else if (QB == 2) CPD_RG(n, 2);  \
+    else CPD_RG(n, 3);
+    switch (N) {
+        case 3: CPD_RG_N(3) break;
+        case 4: CPD_RG_N(4) break;
+        default: CPD_RG_N(5) break;
+    }
+#undef CPD_RG_N
+#undef CPD_RG
+    CPD_LAUNCH_CHECK();
+    return CPD_OK;
+}
+
+cpd_status row_solve(const double *G, const float *Y, int64_t ldy, int64_t rows, int R, double reg, float *A,
+                     int64_t lda, double *terms2, hipStream_t s) {
+    if (!G || !Y || !A) CPD_FAIL(CPD_EINVAL, "null argument");
+    if (R < 1 || R > CPD_MAX_RANK || ldy < R || lda < R || rows < 0) CPD_FAIL(CPD_EINVAL, "bad row solve sizes");
+    if (!(reg > 0.0)) CPD_FAIL(CPD_EINVAL, "row solve needs reg > 0 (got %g)", reg);
+    if (rows == 0) return CPD_OK;
+    DevBuf<double> terms;
+    CPD_TRY(terms.alloc((size_t)rows * 2, s));
+    hipLaunchKernelGGL(k_row_solve, dim3((unsigned)rows), dim3(64), 0, s, G, Y, ldy, rows, R, reg, A, lda, terms.p);
+    CPD_LAUNCH_CHECK();
+    if (terms2) {
+        hipLaunchKernelGGL(k_sum_terms, dim3(1), dim3(256), 0, s, (const double *)terms.p, rows, terms2);
+        CPD_LAUNCH_CHECK();
+    }
+    return CPD_OK;
+}
+
+}  // namespace cpd
+
+using namespace cpd;
+
+extern "C" {
+
+cpd_status cpd_row_gram(cpd_csf csf, const float *const *factors, int64_t ld, int32_t rank, int32_t mode,
+                        double *G, void *stream) {
+    clear_error();
+    if (!csf) CPD_FAIL(CPD_EINVAL, "null CSF handle");
+    if (mode < 0 || mode >= csf->nmodes) CPD_FAIL(CPD_EINVAL, "mode %d out of range", mode);
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t n = csf->dims[mode] * (int64_t)rank * rank;
+    if (G) {
+        hipLaunchKernelGGL(k_zero_f64, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, G, n);
+        CPD_LAUNCH_CHECK();
+    }
+    return row_gram(csf, factors, ld, rank, mode, G, s);
+}
+
+cpd_status cpd_row_solve(const double *G, const float *Y, int64_t ldy, int64_t rows, int32_t rank, double reg,
+                         float *A, int64_t lda, double *terms, void *stream) {
+    clear_error();
+    return row_solve(G, Y, ldy, rows, rank, reg, A, lda, terms, (hipStream_t)stream);
+}
+
+cpd_status cpd_complete(int32_t nmodes, const int64_t *dims, int64_t nnz, const int32_t *const *inds,
+                        const float *vals, int32_t rank, int32_t max_iters, double tol, double reg,
+                        float *const *factors, double *rmse, int32_t *iters, void *stream) {
+    clear_error();
+    hipStream_t s = (hipStream_t)stream;
+    if (iters) *iters = 0;
+    if (nmodes < 3 || nmodes > 5) CPD_FAIL(CPD_EUNSUPPORTED, "completion built for 3..5 modes, not %d", nmodes);
+    if (!dims || !inds || !vals || !factors) CPD_FAIL(CPD_EINVAL, "null argument");
+    if (rank < 1 || rank > CPD_MAX_RANK) CPD_FAIL(CPD_EINVAL, "rank %d not in [1, %d]", rank, CPD_MAX_RANK);
+    if (max_iters < 1) CPD_FAIL(CPD_EINVAL, "max_iters %d < 1", max_iters);
+    if (!(reg > 0.0)) CPD_FAIL(CPD_EINVAL, "completion needs reg > 0 (got %g)", reg);
+    for (int m = 0; m < nmodes; ++m)
+        if (!factors[m]) CPD_FAIL(CPD_EINVAL, "null factor %d", m);
+    keep_pool_memory();
+    cpd_csf trees[CPD_MAX_MODES] = {};
+    CPD_TRY(cpd_csf_build_rooted(nmodes, dims, nnz, inds, vals, stream, trees));
+    std::vector<DevBuf<float>> A(nmodes);
+    DevBuf<float> Y;
+    DevBuf<double> G, d_terms, d_norm;
+    const int ld = pad_rank(rank);
+    int64_t maxrows = 0;
+    cpd_status st = CPD_OK;
+    auto done = [&](cpd_status r) {
+        for (int m = 0; m < nmodes; ++m)
+            if (trees[m]) free_csf_on(trees[m], s);
+        return r;
+    };
+    for (int m = 0; m < nmodes && st == CPD_OK; ++m) {
+        maxrows = std::max<int64_t>(maxrows, dims[m]);
+        st = A[m].alloc((size_t)dims[m] * ld, s);
+        if (st == CPD_OK && hipMemsetAsync(A[m].p, 0, sizeof(float) * dims[m] * ld, s) != hipSuccess) st = CPD_EHIP;
+        if (st == CPD_OK) {
+            hipLaunchKernelGGL(k_copy_rows, dim3((unsigned)ceil_div(dims[m] * rank, 256)), dim3(256), 0, s,
+                               (const float *)factors[m], (int64_t)rank, A[m].p, (int64_t)ld, (int64_t)dims[m], rank);
+            if (hipGetLastError() != hipSuccess) st = CPD_EHIP;
+        }
+    }
+    if (st == CPD_OK) st = Y.alloc((size_t)maxrows * ld, s);
+    if (st == CPD_OK) st = G.alloc((size_t)maxrows * rank * rank, s);
+    if (st == CPD_OK) st = d_terms.alloc(2, s);
+    if (st == CPD_OK) st = d_norm.alloc(1, s);
+    // the observed entries are the merged nonzeros of the trees
+    const int64_t nobs = trees[0]->counts[nmodes - 1];
+    if (st == CPD_OK) st = sumsq(trees[0]->vals, nobs, d_norm.p, s);
+    if (st != CPD_OK) return done(st);
+    double normX2 = 0.0;
+    if (hipMemcpyAsync(&normX2, d_norm.p, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return done(CPD_EHIP);
+    const void *fac[CPD_MAX_MODES];
+    const float *facf[CPD_MAX_MODES];
+    for (int m = 0; m < nmodes; ++m) {
+        fac[m] = A[m].p;
+        facf[m] = A[m].p;
+    }
+    cpd_mttkrp_opts mo{CPD_FP32, CPD_VARIANT_AUTO, CPD_KERNEL_AUTO, 0};
+    double prev = -1.0;
+    int it = 0;
+    for (it = 1; it <= max_iters; ++it) {
+        for (int n = 0; n < nmodes && st == CPD_OK; ++n) {
+            const int64_t rows = dims[n];
+            const void *fk[CPD_MAX_MODES];
+            for (int m = 0; m < nmodes; ++m) fk[m] = (m == n) ? nullptr : fac[m];
+            st = mttkrp(trees[n], fk, ld, rank, n, Y.p, ld, &mo, s, nullptr, nullptr);
+            if (st == CPD_OK) {
+                const int64_t ng = rows * (int64_t)rank * rank;
+                hipLaunchKernelGGL(k_zero_f64, dim3((unsigned)ceil_div(ng, 256)), dim3(256), 0, s, G.p, ng);
+                if (hipGetLastError() != hipSuccess) st = CPD_EHIP;
+            }
+            if (st == CPD_OK) st = row_gram(trees[n], facf, ld, rank, n, G.p, s);
+            if (st == CPD_OK)
+                st = row_solve(G.p, Y.p, ld, rows, rank, reg, A[n].p, ld, n == nmodes - 1 ? d_terms.p : nullptr, s);
+        }
+        if (st != CPD_OK) return done(st);
+        double t2[2];
+        if (hipMemcpyAsync(t2, d_terms.p, sizeof(t2), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return done(CPD_EHIP);
+        const double r = std::sqrt(std::max(0.0, normX2 - 2.0 * t2[0] + t2[1]) / (double)std::max<int64_t>(nobs, 1));
+        if (rmse) rmse[it - 1] = r;
+        if (iters) *iters = it;
+        if (tol > 0.0 && prev >= 0.0 && std::fabs(r - prev) < tol) break;
+        prev = r;
+    }
+    for (int m = 0; m < nmodes && st == CPD_OK; ++m) {
+        hipLaunchKernelGGL(k_copy_rows, dim3((unsigned)ceil_div(dims[m] * rank, 256)), dim3(256), 0, s,
+                           (const float *)A[m].p, (int64_t)ld, factors[m], (int64_t)rank, (int64_t)dims[m], rank);
+        if (hipGetLastError() != hipSuccess) st = CPD_EHIP;
+    }
+    if (st == CPD_OK && hipStreamSynchronize(s) != hipSuccess) st = CPD_EHIP;
+    return done(st);
+}
+
+}  // extern "C"
