@@ -147,6 +147,63 @@ def single_tree(cpd, x, R):
     return res
 
 
+FP64_PEAK_TFLOPS = 78.6
+
+
+def completion(cpd, x, R, reg=0.1, sweeps=3):
+    """CP with missing values on the same tensor (its nonzeros observed):
+    per mode the root MTTKRP, the row Grams and the row solves, each timed
+    alone (median of 3), then cpd_complete end to end (trees included)."""
+    import statistics as st
+    import time as _t
+
+    import torch
+
+    def timed(fn):
+        ts = []
+        for _ in range(3):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return st.median(ts)
+
+    trees = cpd.csf_build_rooted(x.inds, x.vals, x.dims)
+    ld = next(w for w in (8, 16, 32, 36, 64) if w >= R)
+    g = torch.Generator(device="cuda").manual_seed(5)
+    facs = []
+    for d in x.dims:
+        f = torch.zeros((d, ld), dtype=torch.float32, device="cuda")
+        f[:, :R] = torch.rand((d, R), device="cuda", generator=g)
+        facs.append(f)
+    nnz = trees[0].counts[-1]
+    modes = []
+    for m, c in enumerate(trees):
+        Y = torch.empty((x.dims[m], R), dtype=torch.float32, device="cuda")
+        t_m = timed(lambda: cpd.mttkrp(c, facs, m, out=Y, rank=R))
+        G = cpd.row_gram(c, facs, m, rank=R)
+        t_g = timed(lambda: cpd.row_gram(c, facs, m, rank=R))
+        A = torch.zeros((x.dims[m], R), dtype=torch.float32, device="cuda")
+        t_s = timed(lambda: cpd.row_solve(G, Y, reg, rank=R, out=A))
+        flops = 2.0 * nnz * R * (R + 1) / 2
+        modes.append(dict(mode=m, mttkrp_ms=round(t_m, 4), row_gram_ms=round(t_g, 4), row_solve_ms=round(t_s, 4),
+                          row_gram_gflop=round(flops / 1e9, 2),
+                          row_gram_fp64_frac=round(flops / (t_g * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4)))
+        del G, Y, A
+        c.free()
+    init = [f[:, :R].contiguous() for f in facs]
+    torch.cuda.synchronize()
+    t0 = _t.perf_counter()
+    got = cpd.complete(x.inds, x.vals, x.dims, R, sweeps, reg, init)
+    torch.cuda.synchronize()
+    wall = _t.perf_counter() - t0
+    return dict(workload="observed entries = the tensor's nonzeros, rank %d, reg %g, %d sweeps" % (R, reg, sweeps),
+                modes=modes, s_per_sweep_with_trees=round(wall / sweeps, 5), rmses=[round(r, 6) for r in got["rmses"]])
+
+
 def summarize(runs, nm):
     import statistics as st
     csf = st.mean(r["timing_ms"]["csf_build"] for r in runs)
@@ -214,6 +271,7 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16"])
     ap.add_argument("--cpu-sample-nnz", type=int, default=16_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-completion", action="store_true", help="skip the CP-with-missing-values timings")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the BF16-vs-FP32 comparison on the NETFLIX-shaped tensor")
     args = ap.parse_args()
@@ -309,6 +367,10 @@ def main():
         out["precision_compare"] = cmp
         del y
         log("precision comparison done")
+
+    if not args.no_completion:
+        out["completion"] = completion(cpd, x, R)
+        log("completion timings done")
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(x, R, args.cpu_sample_nnz)
