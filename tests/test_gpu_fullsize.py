@@ -88,3 +88,45 @@ def test_full_size_als_fit_matches_oracle_fit_of_returned_model():
     for a in A:
         assert np.isfinite(a).all()
         np.testing.assert_allclose(np.linalg.norm(a, axis=0), 1.0, atol=1e-4)
+
+
+def test_full_size_completion_kernels_sampled_rows():
+    """CP with missing values at the benchmark size (NELL-2 shape, rank 35):
+    the row Grams of sampled rows (the fullest three among them) against the
+    oracle's, and the row solves of those rows against the oracle's solve of
+    the same Gram and right side."""
+    from oracle import complete as oc
+    cpd = _cpd()
+    x = synth.make_config("nell2", device="cuda")
+    R = synth.CONFIGS["nell2"]["rank"]
+    inds_h = x.inds.cpu().numpy()
+    vals_h = x.vals.cpu().double().numpy()
+    rng = np.random.default_rng(9)
+    g = torch.Generator().manual_seed(4)
+    facs, facs_used = [], []
+    for d in x.dims:
+        buf = torch.zeros((d, 36), dtype=torch.float32)
+        buf[:, :R] = torch.rand((d, R), generator=g)
+        facs.append(buf.cuda())
+        facs_used.append(buf[:, :R].double().numpy())
+    trees = cpd.csf_build_rooted(x.inds.to(torch.int32), x.vals, x.dims)
+    reg = 0.1
+    for m, c in enumerate(trees):
+        rows = _sample_rows(inds_h[m], x.dims[m], rng, k=4)
+        G = cpd.row_gram(c, facs, m, rank=R)
+        y = cpd.mttkrp(c, facs, m, rank=R)
+        A, _ = cpd.row_solve(G, y, reg, rank=R)
+        torch.cuda.synchronize()
+        got = G.cpu().numpy()[rows]
+        ref = oc.row_grams(x.dims, inds_h, vals_h, facs_used, m, rows=rows)
+        iu = np.triu_indices(R)
+        scale = float(np.abs(ref).max())
+        np.testing.assert_allclose(got[:, iu[0], iu[1]], ref[:, iu[0], iu[1]], rtol=0, atol=1e-12 * scale)
+        # the solve of those rows from the same G and y, in the oracle
+        ysel = y.cpu().numpy()[rows].astype(np.float64)
+        full = np.stack([np.triu(gg) + np.triu(gg, 1).T for gg in got])
+        want, _ = oc.solve_rows(full, ysel, reg, np.ones(rows.size, dtype=np.int64))
+        err = np.linalg.norm(A.cpu().numpy()[rows] - want) / np.linalg.norm(want)
+        assert err <= 1e-6, (m, err)
+        del G, y, A
+        c.free()
