@@ -52,21 +52,36 @@ struct LevelMap {
 };
 
 // The key of the same nonzero in the other layout (one-word keys).
+// Level l of the new key: the field at bit src_shift[l] (mask[l] wide, already
+// shifted down) of the old key, moved to bit dst_shift[l] -- resolved on the
+// host, so the device reads each level's three numbers at fixed offsets.
 struct Repack {
-    const uint64_t *a;  // sorted keys in layout ka
+    const uint64_t *a;  // sorted keys in the old layout
     const float *val;   // their values
-    KeyLayout ka, kx;
-    LevelMap map;
+    int src_shift[CPD_MAX_MODES], dst_shift[CPD_MAX_MODES];
+    uint64_t mask[CPD_MAX_MODES];
 };
+
+Repack make_repack(const uint64_t *a, const float *val, const KeyLayout &ka, const KeyLayout &kx,
+                   const LevelMap &map) {
+    Repack r{};
+    r.a = a;
+    r.val = val;
+    for (int l = 0; l < kx.nl; ++l) {
+        const int q = map.src[l];
+        const bool used = kx.bits[l] > 0;  // a length-1 mode has no field (and may sit at bit 64)
+        r.src_shift[l] = used ? ka.shift[q] : 0;
+        r.dst_shift[l] = used ? kx.shift[l] : 0;
+        r.mask[l] = used ? ((1ull << ka.bits[q]) - 1ull) : 0ull;
+    }
+    return r;
+}
 
 template <int NL>
 __device__ __forceinline__ uint64_t repack_key(const Repack &r, uint64_t key) {
     uint64_t out = 0;
 #pragma unroll
-    for (int l = 0; l < NL; ++l) {
-        const int q = r.map.src[l];
-        if (r.kx.bits[l]) out |= (uint64_t)key_field(key, 0ull, r.ka.shift[q], r.ka.bits[q]) << r.kx.shift[l];
-    }
+    for (int l = 0; l < NL; ++l) out |= ((key >> r.src_shift[l]) & r.mask[l]) << r.dst_shift[l];
     return out;
 }
 
@@ -385,7 +400,8 @@ struct HistAt {
 // the (k*, p*) and (o*, op*) buffers; on return k*, kp point at the sorted
 // data.  With lo_bit > 0 the order of equal sorted bits is the input order.
 static cpd_status radix_sort_rp(uint64_t *&klo, uint64_t *&khi, int32_t *&kp, uint64_t *&olo, uint64_t *&ohi,
-                                int32_t *&op, int64_t n, int bits, hipStream_t s, int lo_bit, const Repack *rp) {
+                                int32_t *&op, int64_t n, int bits, hipStream_t s, int lo_bit, const Repack *rp,
+                                int rp_levels = 0) {
     const int64_t ntiles = ceil_div(n, RS_TILE);
     if (ntiles == 0) return CPD_OK;
     DevBuf<int32_t> hist;
@@ -401,7 +417,7 @@ static cpd_status radix_sort_rp(uint64_t *&klo, uint64_t *&khi, int32_t *&kp, ui
 #define CPD_HIST_RP(L)                                                                                          \
     hipLaunchKernelGGL(k_radix_hist<L>, dim3((unsigned)ntiles), dim3(RS_THREADS), 0, s, src, r, n, shift, hist.p, \
                        ntiles)
-            CPD_BY_LEVELS(r.kx.nl, CPD_HIST_RP)
+            CPD_BY_LEVELS(rp_levels, CPD_HIST_RP)
 #undef CPD_HIST_RP
         } else {
             hipLaunchKernelGGL(k_radix_hist<0>, dim3((unsigned)ntiles), dim3(RS_THREADS), 0, s, src, r, n, shift,
@@ -416,7 +432,7 @@ static cpd_status radix_sort_rp(uint64_t *&klo, uint64_t *&khi, int32_t *&kp, ui
 #define CPD_SCATTER_RP(L)                                                                                       \
     hipLaunchKernelGGL(k_radix_scatter1<L>, dim3((unsigned)ntiles), dim3(RS_THREADS), 0, s, (const uint64_t *)klo, \
                        (const int32_t *)kp, r, olo, op, (const int32_t *)hist.p, n, ntiles, shift)
-            CPD_BY_LEVELS(r.kx.nl, CPD_SCATTER_RP)
+            CPD_BY_LEVELS(rp_levels, CPD_SCATTER_RP)
 #undef CPD_SCATTER_RP
         } else {
             hipLaunchKernelGGL(k_radix_scatter1<0>, dim3((unsigned)ntiles), dim3(RS_THREADS), 0, s,
@@ -968,10 +984,10 @@ cpd_status derive(int nm, const int64_t *dims, const int32_t *order_a, const Key
         CPD_TRY(S.pay[b].alloc(n, s));
     }
     // the first sort pass forms the new keys from A's (no separate repack)
-    const Repack rp{A.klo, A.val, ka, *kx, map};
+    const Repack rp = make_repack(A.klo, A.val, ka, *kx, map);
     uint64_t *klo = S.lo[0].p, *khi = nullptr, *olo = S.lo[1].p, *ohi = nullptr;
     int32_t *kp = S.pay[0].p, *op = S.pay[1].p;
-    CPD_TRY(radix_sort_rp(klo, khi, kp, olo, ohi, op, n, total, s, kx->shift[0], &rp));
+    CPD_TRY(radix_sort_rp(klo, khi, kp, olo, ohi, op, n, total, s, kx->shift[0], &rp, nm));
     CPD_TRY(S.dl.alloc(n, s));
 #define CPD_FIRST_DIFF(L)                                                                                 \
     hipLaunchKernelGGL(k_first_diff<L>, dim3(grid1(ceil_div(n, 4))), dim3(256), 0, s, klo, (const uint64_t *)nullptr, \
