@@ -123,7 +123,7 @@ cpd_status cpd_csf_tiles(cpd_csf csf, int32_t tile_nnz, int32_t *starts, int64_t
 void cpd_csf_free(cpd_csf csf);
 
 /* ---------------------------------------------------------------------------
- * MTTKRP (Algorithm 1, lines 5, 8, 11: Y = X_(n) times the Khatri-Rao product
+ * MTTKRP (the MTTKRP step of Algorithm 1: Y = X_(n) times the Khatri-Rao product
  * of the other factors), computed on the CSF tree, element-wise:
  *     Y(i, r) = sum over nonzeros with i_mode = i of x * prod_{m != mode} A_m(i_m, r).
  * `mode` may sit at any level of the tree (root, internal or leaf). */
@@ -149,12 +149,12 @@ cpd_status cpd_mttkrp(cpd_csf csf, const void *const *factors, int32_t ld, int32
 /* ---------------------------------------------------------------------------
  * Dense steps of Algorithm 1 (FP64 on the GPU). */
 
-/* G = A^T A (the A^T A terms of Algorithm 1, lines 4, 7, 10).
+/* G = A^T A (the A^T A terms of Algorithm 1).
  * A: device, rows x rank floats, stride ld.  G: device, rank x rank doubles. */
 cpd_status cpd_gram(const float *A, int64_t rows, int32_t rank, int32_t ld, double *G,
                     void *stream);
 
-/* One mode update after its MTTKRP (Algorithm 1, lines 4-6 and 7-9, ...):
+/* One mode update after its MTTKRP (the per-mode steps of Algorithm 1: V, solve, normalise):
  *   V = Hadamard product of grams[m] over m != mode;
  *   A = Y V^+, with V^+ = V^{-1} by symmetric Gauss-Jordan elimination when
  *       every pivot (the square of Cholesky's diagonal) exceeds
@@ -175,7 +175,7 @@ cpd_status cpd_solve_normalize(const double *const *grams, int32_t nmodes, int32
                                double *lambda, double *G_new, int32_t *used_pinv,
                                void *stream);
 
-/* Fit of K = [[lambda; A_0..A_{N-1}]] (Algorithm 1, line 13):
+/* Fit of K = [[lambda; A_0..A_{N-1}]] (the fit step of Algorithm 1):
  *   fit = 1 - sqrt(max(0, normX2 - 2 <X,K> + ||K||^2)) / sqrt(normX2), with
  *   <X,K> = sum_r lambda_r sum_i A_last(i, r) Y_last(i, r) (Y_last = MTTKRP of
  *   the last mode with the other final factors) and

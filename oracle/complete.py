@@ -15,7 +15,7 @@ entries.  Readings (each listed in the design notes):
                                   y_i = sum_{k in O_i} x_k h_k,
       O_i the observations with i_n = i and h_k the Hadamard product of the
       other modes' rows of observation k: y_i is row i of the MTTKRP of the
-      observed entries (Algorithm 1's line 5/8/11 kernel), G_i a Gram
+      observed entries (Algorithm 1's MTTKRP step), G_i a Gram
       restricted to the row's observations.
   C4  a row with no observation becomes zero; a system whose Cholesky pivot
       falls below R*eps*max diag (reg = 0, rank-deficient rows) uses the

@@ -1,7 +1,7 @@
 """MTTKRP on COO by a direct FP64 loop (oracle; test infrastructure only).
 
 Y_n(i, r) = sum over nonzeros with i_n = i of x * prod_{m != n} A_m(i_m, r):
-the element-wise form of Algorithm 1's MTTKRP lines (Section III).  The loop
+the element-wise form of Algorithm 1's MTTKRP step (Section III).  The loop
 itself is plain C (``oracle.c``), compiled here with gcc on first use.
 
 Pinned by: a dense unfolding times an explicit Khatri-Rao product on tiny

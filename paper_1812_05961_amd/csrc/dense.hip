@@ -1,11 +1,12 @@
 // Dense FP64 steps of CP-ALS (Algorithm 1, Section III):
-//   Gram  G = A^T A                       (lines 4, 7, 10)  -- FP64 MFMA
-//   V     Hadamard of the other Grams      (lines 4, 7, 10)
-//   solve A = Y V^+                         (lines 5, 8, 11)  -- Cholesky, or the
-//         Moore-Penrose inverse from a Jacobi eigendecomposition when a pivot
-//         is <= R*eps*max(diag V) (the paper's code uses potrf/potrs, Section V-A)
-//   norms lambda_r = ||A(:, r)||_2, unit columns     (lines 6, 9, 12)
-//   fit   1 - ||X - K|| / ||X||                      (line 13)
+//   Gram  G = A^T A                       (the A^T A products)  -- FP64 MFMA
+//   V     Hadamard of the other Grams
+//   solve A = Y V^+   -- V^{-1} by symmetric Gauss-Jordan elimination (its
+//         pivots are Cholesky's squared diagonal; the paper's code uses
+//         potrf/potrs, Section V-A), or the Moore-Penrose inverse from a Jacobi
+//         eigendecomposition when a pivot is <= R*eps*max(diag V)
+//   norms lambda_r = ||A(:, r)||_2, unit columns
+//   fit   1 - ||X - K|| / ||X||
 #include "common.h"
 
 namespace cpd {
@@ -142,11 +143,14 @@ k_make_w(GramSet gs, int nmodes, int mode, int R, double *__restrict__ W, double
         __syncthreads();
     };
     load_v();
-    if (tid == 0) {
+    if (tid < 64) {  // wave 0: largest diagonal entry
         double mx = 0.0;
-        for (int r = 0; r < R; ++r) mx = fmax(mx, V[r * R + r]);
-        sh[0] = (double)R * EPS64 * mx;
-        fail = 0;
+        for (int r = tid; r < R; r += 64) mx = fmax(mx, V[r * R + r]);
+        for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+        if (tid == 0) {
+            sh[0] = (double)R * EPS64 * mx;
+            fail = 0;
+        }
     }
     __syncthreads();
     const double thresh = sh[0];
@@ -157,16 +161,22 @@ k_make_w(GramSet gs, int nmodes, int mode, int R, double *__restrict__ W, double
     // and the fallback.  Sweeping every index leaves -V^{-1}; the update is
     // symmetric term by term, so W is exactly symmetric.
     // Two LDS copies: step j reads one and writes the other (one barrier per
-    // step); each thread keeps the same entries for every step.
+    // step); each thread keeps the same entries for every step.  A step first
+    // issues all of the thread's LDS reads (its entry and the two pivot-column
+    // entries of each), then selects the result without branches: the reads
+    // of a step overlap instead of each waiting out the LDS latency.
     __shared__ double Vs[2][CPD_MAX_RANK * CPD_MAX_RANK];
     constexpr int MAXE = CPD_MAX_RANK * CPD_MAX_RANK / 256;
+    const int RR = R * R;
+    const int ne = (RR + 255) / 256;  // entry slots in use (block-uniform)
     int rr[MAXE], cc[MAXE];
 #pragma unroll
     for (int i = 0; i < MAXE; ++i) {
         const int t = tid + 256 * i;
-        rr[i] = t / R;
-        cc[i] = t % R;
-        if (t < R * R) Vs[0][t] = V[t];
+        const bool in = t < RR;
+        rr[i] = in ? t / R : 0;
+        cc[i] = in ? t % R : 0;
+        if (in) Vs[0][t] = V[t];
     }
     __syncthreads();
     bool ok = true;
@@ -178,17 +188,26 @@ k_make_w(GramSet gs, int nmodes, int mode, int R, double *__restrict__ W, double
             ok = false;  // every thread reads the same d
             break;
         }
+        double cur[MAXE], pr[MAXE], pc[MAXE];
+#pragma unroll
+        for (int i = 0; i < MAXE; ++i) {
+            if (i < ne) {
+                const int t = tid + 256 * i;
+                cur[i] = Vc[t < RR ? t : 0];
+                pr[i] = Vc[rr[i] * R + j];
+                pc[i] = Vc[cc[i] * R + j];
+            }
+        }
         const double inv = 1.0 / d;
 #pragma unroll
         for (int i = 0; i < MAXE; ++i) {
             const int t = tid + 256 * i;
-            if (t < R * R) {
+            if (i < ne && t < RR) {
                 const int r = rr[i], c = cc[i];
-                double x;
-                if (r == j && c == j) x = -inv;
-                else if (r == j) x = Vc[c * R + j] * inv;
-                else if (c == j) x = Vc[r * R + j] * inv;
-                else x = Vc[t] - Vc[r * R + j] * Vc[c * R + j] * inv;
+                double x = cur[i] - pr[i] * pc[i] * inv;
+                x = (c == j) ? pr[i] * inv : x;
+                x = (r == j) ? pc[i] * inv : x;
+                x = (r == j && c == j) ? -inv : x;
                 Vn[t] = x;
             }
         }
@@ -404,9 +423,21 @@ __global__ void __launch_bounds__(256)
 k_sumsq_partial(const float *__restrict__ v, int64_t n, double *__restrict__ partial) {
     __shared__ double red[4];
     double s = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
-        double x = (double)v[i];
-        s += x * x;
+    const int64_t tid = (int64_t)blockIdx.x * 256 + threadIdx.x, nt = (int64_t)gridDim.x * 256;
+    if ((reinterpret_cast<uintptr_t>(v) & 15) == 0) {
+        // 16-byte loads: four values per thread and step, the tail one by one
+        const int64_t n4 = n >> 2;
+        const float4 *v4 = reinterpret_cast<const float4 *>(v);
+        for (int64_t i = tid; i < n4; i += nt) {
+            const float4 q = v4[i];
+            s += (double)q.x * q.x;
+            s += (double)q.y * q.y;
+            s += (double)q.z * q.z;
+            s += (double)q.w * q.w;
+        }
+        for (int64_t i = (n4 << 2) + tid; i < n; i += nt) s += (double)v[i] * v[i];
+    } else {
+        for (int64_t i = tid; i < n; i += nt) s += (double)v[i] * v[i];
     }
     s = wave_sum(s);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
@@ -414,12 +445,11 @@ k_sumsq_partial(const float *__restrict__ v, int64_t n, double *__restrict__ par
     if (threadIdx.x == 0) partial[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
 }
 
-__global__ void k_sum_partials(const double *__restrict__ partial, int n, double *__restrict__ out) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        double s = 0.0;
-        for (int i = 0; i < n; ++i) s += partial[i];
-        *out = s;
-    }
+// One wave: the sum of n partials in a fixed order.
+__global__ void __launch_bounds__(64) k_sum_partials(const double *__restrict__ partial, int n,
+                                                     double *__restrict__ out) {
+    const double s = wave_sum_strided(partial, n, 1);
+    if (threadIdx.x == 0) *out = s;
 }
 
 }  // namespace
@@ -499,7 +529,7 @@ cpd_status fit(double normX2, const double *lambda, const float *A, int64_t lda,
 
 cpd_status sumsq(const float *v, int64_t n, double *out, hipStream_t s) {
     if (!v || !out || n < 0) CPD_FAIL(CPD_EINVAL, "bad sumsq arguments");
-    const int nb = (int)std::min<int64_t>(1024, std::max<int64_t>(1, ceil_div(n, 256)));
+    const int nb = (int)std::min<int64_t>(2048, std::max<int64_t>(1, ceil_div(n, 1024)));
     DevBuf<double> part;
     CPD_TRY(part.alloc(nb, s));
     hipLaunchKernelGGL(k_sumsq_partial, dim3(nb), dim3(256), 0, s, v, n, part.p);

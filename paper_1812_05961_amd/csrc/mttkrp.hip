@@ -1,4 +1,4 @@
-// MTTKRP on a CSF tree (Algorithm 1, lines 5, 8, 11; Section III):
+// MTTKRP on a CSF tree (the MTTKRP step of Algorithm 1; Section III):
 //     Y(i, r) = sum over nonzeros with i_mode = i of x * prod_{m != mode} A_m(i_m, r)
 // for an output mode at any level d of the tree.
 //
