@@ -122,11 +122,17 @@ cpd_status gram(const float *A, int64_t rows, int R, int64_t ld, double *G, hipS
 }
 
 // ------------------------------------------------------------------ W = V^+
-// One block of 256 threads.  V (R x R, FP64) lives in LDS; the fallback's
+// One block of NT threads: 256 when R^2 <= 256, else 1024.  The elimination
+// runs R dependent steps of a few instructions per matrix entry, so above
+// R = 16 sixteen waves (four per SIMD) hide each other's instruction and LDS
+// latency (one wave per SIMD left every step latency-bound, about 2,900
+// cycles at R = 35).  V (R x R, FP64) lives in LDS, built from the upper
+// triangles of the Grams so that it is exactly symmetric; the fallback's
 // eigenvectors in global scratch `wk` (R^2 doubles).  Writes W = V^{-1}
 // (symmetric Gauss-Jordan) or V^+ (Jacobi eigendecomposition) to W, and the
 // fallback flag.
-__global__ void __launch_bounds__(256)
+template <int NT>
+__global__ void __launch_bounds__(NT)
 k_make_w(GramSet gs, int nmodes, int mode, int R, double *__restrict__ W, double *__restrict__ wk,
          int32_t *__restrict__ used_pinv) {
     __shared__ double V[CPD_MAX_RANK * CPD_MAX_RANK];
@@ -134,10 +140,12 @@ k_make_w(GramSet gs, int nmodes, int mode, int R, double *__restrict__ W, double
     __shared__ int fail;
     const int tid = threadIdx.x;
     auto load_v = [&]() {
-        for (int t = tid; t < R * R; t += 256) {
+        for (int t = tid; t < R * R; t += NT) {
+            const int r = t / R, c = t % R;
+            const int u = min(r, c) * R + max(r, c);
             double v = 1.0;
             for (int m = 0; m < nmodes; ++m)
-                if (m != mode) v *= gs.g[m][t];
+                if (m != mode) v *= gs.g[m][u];
             V[t] = v;
         }
         __syncthreads();
@@ -162,17 +170,20 @@ k_make_w(GramSet gs, int nmodes, int mode, int R, double *__restrict__ W, double
     // symmetric term by term, so W is exactly symmetric.
     // Two LDS copies: step j reads one and writes the other (one barrier per
     // step); each thread keeps the same entries for every step.  A step first
-    // issues all of the thread's LDS reads (its entry and the two pivot-column
+    // issues all of the thread's LDS reads (its entry and the two pivot-row
     // entries of each), then selects the result without branches: the reads
-    // of a step overlap instead of each waiting out the LDS latency.
+    // of a step overlap instead of each waiting out the LDS latency.  V stays
+    // exactly symmetric, so the pivot column is read as the pivot row:
+    // consecutive lanes then read consecutive words (a column read at R = 64
+    // puts every lane of a wave in one LDS bank).
     __shared__ double Vs[2][CPD_MAX_RANK * CPD_MAX_RANK];
-    constexpr int MAXE = CPD_MAX_RANK * CPD_MAX_RANK / 256;
+    constexpr int MAXE = CPD_MAX_RANK * CPD_MAX_RANK / NT;
     const int RR = R * R;
-    const int ne = (RR + 255) / 256;  // entry slots in use (block-uniform)
+    const int ne = (RR + NT - 1) / NT;  // entry slots in use (block-uniform)
     int rr[MAXE], cc[MAXE];
 #pragma unroll
     for (int i = 0; i < MAXE; ++i) {
-        const int t = tid + 256 * i;
+        const int t = tid + NT * i;
         const bool in = t < RR;
         rr[i] = in ? t / R : 0;
         cc[i] = in ? t % R : 0;
@@ -192,16 +203,16 @@ k_make_w(GramSet gs, int nmodes, int mode, int R, double *__restrict__ W, double
 #pragma unroll
         for (int i = 0; i < MAXE; ++i) {
             if (i < ne) {
-                const int t = tid + 256 * i;
+                const int t = tid + NT * i;
                 cur[i] = Vc[t < RR ? t : 0];
-                pr[i] = Vc[rr[i] * R + j];
-                pc[i] = Vc[cc[i] * R + j];
+                pr[i] = Vc[j * R + rr[i]];
+                pc[i] = Vc[j * R + cc[i]];
             }
         }
         const double inv = 1.0 / d;
 #pragma unroll
         for (int i = 0; i < MAXE; ++i) {
-            const int t = tid + 256 * i;
+            const int t = tid + NT * i;
             if (i < ne && t < RR) {
                 const int r = rr[i], c = cc[i];
                 double x = cur[i] - pr[i] * pc[i] * inv;
@@ -215,7 +226,7 @@ k_make_w(GramSet gs, int nmodes, int mode, int R, double *__restrict__ W, double
     }
     if (ok) {
         const double *Vf = Vs[R & 1];
-        for (int t = tid; t < R * R; t += 256) W[t] = -Vf[t];
+        for (int t = tid; t < R * R; t += NT) W[t] = -Vf[t];
         if (tid == 0 && used_pinv) *used_pinv = 0;
         return;
     }
@@ -223,7 +234,7 @@ k_make_w(GramSet gs, int nmodes, int mode, int R, double *__restrict__ W, double
     __syncthreads();
     load_v();
     double *Q = wk;
-    for (int t = tid; t < R * R; t += 256) Q[t] = (t / R == t % R) ? 1.0 : 0.0;
+    for (int t = tid; t < R * R; t += NT) Q[t] = (t / R == t % R) ? 1.0 : 0.0;
     __syncthreads();
     for (int sweep = 0; sweep < 60; ++sweep) {
         if (tid == 0) {
@@ -253,7 +264,7 @@ k_make_w(GramSet gs, int nmodes, int mode, int R, double *__restrict__ W, double
                 __syncthreads();
                 const double c = sh[1], s = sh[2];
                 if (s != 0.0) {
-                    for (int k = tid; k < R; k += 256) {  // columns p, q
+                    for (int k = tid; k < R; k += NT) {  // columns p, q
                         double akp = V[k * R + p], akq = V[k * R + q];
                         V[k * R + p] = c * akp - s * akq;
                         V[k * R + q] = s * akp + c * akq;
@@ -262,7 +273,7 @@ k_make_w(GramSet gs, int nmodes, int mode, int R, double *__restrict__ W, double
                         Q[k * R + q] = s * qkp + c * qkq;
                     }
                     __syncthreads();
-                    for (int k = tid; k < R; k += 256) {  // rows p, q
+                    for (int k = tid; k < R; k += NT) {  // rows p, q
                         double apk = V[p * R + k], aqk = V[q * R + k];
                         V[p * R + k] = c * apk - s * aqk;
                         V[q * R + k] = s * apk + c * aqk;
@@ -279,7 +290,7 @@ k_make_w(GramSet gs, int nmodes, int mode, int R, double *__restrict__ W, double
     }
     __syncthreads();
     const double cut = sh[3];
-    for (int t = tid; t < R * R; t += 256) {
+    for (int t = tid; t < R * R; t += NT) {
         const int r = t / R, c = t % R;
         double x = 0.0;
         for (int k = 0; k < R; ++k) {
@@ -474,7 +485,10 @@ cpd_status solve_normalize(const double *const *grams, int nmodes, int mode, con
     DevBuf<double> W, wk, part;
     CPD_TRY(W.alloc((size_t)R * R, s));
     CPD_TRY(wk.alloc((size_t)R * R, s));
-    hipLaunchKernelGGL(k_make_w, dim3(1), dim3(256), 0, s, gs, nmodes, mode, R, W.p, wk.p, used_pinv);
+    if (R * R <= 256)
+        hipLaunchKernelGGL(k_make_w<256>, dim3(1), dim3(256), 0, s, gs, nmodes, mode, R, W.p, wk.p, used_pinv);
+    else
+        hipLaunchKernelGGL(k_make_w<1024>, dim3(1), dim3(1024), 0, s, gs, nmodes, mode, R, W.p, wk.p, used_pinv);
     CPD_LAUNCH_CHECK();
     const int nb = (int)std::max<int64_t>(1, ceil_div(rows, 64));  // 4 waves x 16 rows
     CPD_TRY(part.alloc((size_t)nb * R, s));
