@@ -135,14 +135,17 @@ def single_tree(cpd, x, R):
     for depth, mode in enumerate(c.order):
         level = "root" if depth == 0 else ("leaf" if depth == x.nmodes - 1 else "internal")
         b = alg_bytes(c.counts, x.dims, mode, R)
-        variants = ["auto"] if depth == 0 else ["atomic"]
-        if depth > 0 and x.dims[mode] * R * 4 <= 64 * 1024:
-            variants.append("private")
+        # private: a copy of the output in LDS per block when it fits 64 KiB,
+        # else one HBM copy per XCD, summed after the kernel
+        variants = ["auto"] if depth == 0 else ["atomic", "private"]
         for v in variants:
             ms = time_mttkrp(cpd, c, facs, mode, R, v)
-            res["modes"].append(dict(mode=mode, level=level, variant=v, ms=round(ms, 4),
-                                     ns_per_nnz=round(ms * 1e6 / nnz, 4), alg_bytes=b,
-                                     roofline_frac=round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)))
+            row = dict(mode=mode, level=level, variant=v, ms=round(ms, 4),
+                       ns_per_nnz=round(ms * 1e6 / nnz, 4), alg_bytes=b,
+                       roofline_frac=round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4))
+            if v == "private":
+                row["copies"] = "lds" if x.dims[mode] * R * 4 <= 64 * 1024 else "hbm_per_xcd"
+            res["modes"].append(row)
     c.free()
     return res
 

@@ -42,7 +42,13 @@ typedef enum {
 enum { CPD_FP32 = 0, CPD_BF16_GATHER = 1 };
 
 /* Conflict handling where output rows collide (Section V-D2: locks versus
- * privatised buffers).  On the GPU "atomic" replaces the paper's mutex pool. */
+ * privatised buffers).  On the GPU "atomic" replaces the paper's mutex pool.
+ * PRIVATE (non-root modes only): every block keeps a copy of the output in LDS
+ * when it fits 64 KiB, else each of the chip's eight XCDs adds into its own
+ * HBM copy and the copies are summed into the output afterwards.  AUTO: no
+ * copies at the root; below it the LDS copy iff
+ * rows * 1024 <= 0.02 * nnz and it fits, else atomics (with the most frequent
+ * output rows accumulated in LDS at levels >= 2). */
 enum { CPD_VARIANT_AUTO = 0, CPD_VARIANT_ATOMIC = 1, CPD_VARIANT_PRIVATE = 2 };
 
 /* Kernel family: AUTO picks (ROW at the root, LANE below); ROW = groups of

@@ -18,13 +18,18 @@
 //        the group; coalesced row loads and coalesced atomics.  For the leaf
 //        level each nonzero adds v*H to its row, either with global atomics or
 //        into a block-private copy of Y in LDS (the paper's privatisation,
-//        Section IV-B / V-D2) that is flushed once per block.
+//        Section IV-B / V-D2) that is flushed once per block.  When Y is too
+//        large for LDS, the privatised form gives each of the chip's eight
+//        XCDs its own copy of Y in HBM (blocks are dispatched to the XCDs in
+//        turn, so block b adds into copy b mod 8), summed into Y afterwards.
 #include <type_traits>
 
 #include "csf.h"
 
 namespace cpd {
 namespace {
+
+constexpr int XCD_COPIES = 8;  // private HBM copies of Y: one per XCD of the chip
 
 struct CsfView {
     const int32_t *fids[CPD_MAX_MODES];
@@ -58,15 +63,19 @@ __device__ __forceinline__ float load1<uint16_t>(const void *base, int64_t off) 
 // Zipf-hot rows would otherwise serialise their atomics in L2.
 // CPL: columns per lane (lane j of a group holds columns j, j + G, ...), so
 // that ranks above 32 run two groups of 32 lanes per wave rather than one of 64.
+// copy_stride: 0, or the element distance between the per-XCD copies of Y
+// (block b then adds into copy b mod XCD_COPIES; any mapping is correct, the
+// device-scope atomics only contend less when a copy stays on one XCD).
 template <int N, int G, typename GT, bool PRIV, bool HOT, int CPL>
 __global__ void __launch_bounds__(256)
 k_mttkrp_lane(CsfView cv, FacView fv, int64_t ld, int d, const int32_t *__restrict__ starts,
               int64_t nstreams, int32_t T, float *__restrict__ Y, int64_t ldo, int R,
-              int64_t out_rows, int32_t hot) {
+              int64_t out_rows, int32_t hot, int64_t copy_stride) {
     extern __shared__ float ypriv[];  // PRIV: out_rows x R; HOT: hot x R
     constexpr int NG = 256 / G;       // groups per block
     constexpr bool LOCAL = PRIV || HOT;
     const int lig = threadIdx.x % G;
+    Y += (int64_t)(blockIdx.x % XCD_COPIES) * copy_stride;
     bool col[CPL];
 #pragma unroll
     for (int q = 0; q < CPL; ++q) col[q] = lig + G * q < R;
@@ -183,6 +192,16 @@ k_mttkrp_lane(CsfView cv, FacView fv, int64_t ld, int d, const int32_t *__restri
     }
 }
 
+// Y(i, r) = sum of the per-XCD copies in copy order (copies: P x rows x R).
+__global__ void __launch_bounds__(256)
+k_sum_copies(const float *__restrict__ cp, int P, int64_t rows, int R, float *__restrict__ Y, int64_t ldo) {
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j >= rows * R) return;
+    float v = 0.0f;
+    for (int q = 0; q < P; ++q) v += cp[(int64_t)q * rows * R + j];
+    Y[(j / R) * ldo + (j % R)] = v;
+}
+
 __global__ void k_zero_rows(float *Y, int64_t rows, int64_t ldo, int R) {
     int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= rows * R) return;
@@ -205,18 +224,18 @@ inline int row_width(int R, bool bf16) {
 template <int N, typename GT>
 cpd_status launch_lane(int G, bool priv, int32_t hot, dim3 grid, size_t lds, hipStream_t s, const CsfView &cv,
                        const FacView &fv, int64_t ld, int d, const int32_t *starts, int64_t ns,
-                       int32_t T, float *Y, int64_t ldo, int R, int64_t out_rows) {
+                       int32_t T, float *Y, int64_t ldo, int R, int64_t out_rows, int64_t copy_stride) {
 #define CPD_LANE_CASE2(gcase, g, cpl)                                                                          \
     case gcase:                                                                                               \
         if (priv)                                                                                             \
             hipLaunchKernelGGL((k_mttkrp_lane<N, g, GT, true, false, cpl>), grid, dim3(256), lds, s, cv, fv, ld, \
-                               d, starts, ns, T, Y, ldo, R, out_rows, 0);                                     \
+                               d, starts, ns, T, Y, ldo, R, out_rows, 0, 0);                                  \
         else if (hot)                                                                                         \
             hipLaunchKernelGGL((k_mttkrp_lane<N, g, GT, false, true, cpl>), grid, dim3(256), lds, s, cv, fv, ld, \
-                               d, starts, ns, T, Y, ldo, R, out_rows, hot);                                   \
+                               d, starts, ns, T, Y, ldo, R, out_rows, hot, copy_stride);                      \
         else                                                                                                  \
             hipLaunchKernelGGL((k_mttkrp_lane<N, g, GT, false, false, cpl>), grid, dim3(256), 0, s, cv, fv, ld, \
-                               d, starts, ns, T, Y, ldo, R, out_rows, 0);                                     \
+                               d, starts, ns, T, Y, ldo, R, out_rows, 0, copy_stride);                        \
         break;
 #define CPD_LANE_CASE(g) CPD_LANE_CASE2(g, g, 1)
     switch (G) {
@@ -338,9 +357,10 @@ cpd_status mttkrp(cpd_csf_s *c, const void *const *factors, int32_t ld, int32_t 
         else if (o.variant == CPD_VARIANT_AUTO)
             priv = (double)out_rows * copies <= PRIV_THRESH * (double)cv.nleaves;
     }
-    if (o.variant == CPD_VARIANT_PRIVATE && !priv)
-        CPD_FAIL(CPD_EUNSUPPORTED, "private variant needs a non-root mode with rows*rank*4 <= %zu bytes",
-                 PRIV_LDS_MAX);
+    // privatised but too large for LDS: one HBM copy of Y per XCD (asked for
+    // explicitly; AUTO keeps global atomics there)
+    const bool xcd_copies = o.variant == CPD_VARIANT_PRIVATE && !priv;
+    if (xcd_copies && d < 1) CPD_FAIL(CPD_EUNSUPPORTED, "private variant needs a non-root mode");
     // levels 2 and deeper with atomics: the most frequent output rows (by the
     // tree's ranking of that level) accumulate in LDS, HOT_LDS bytes per block.
     // A level-1 row gets at most one flush per root index, too few for the
@@ -365,14 +385,27 @@ cpd_status mttkrp(cpd_csf_s *c, const void *const *factors, int32_t ld, int32_t 
                      : hot ? dim3((unsigned)std::min<int64_t>(HOT_BLOCKS, ceil_div(ns, NG)))
                            : dim3((unsigned)ceil_div(ns, NG));
     if (N < 2 || N > 5) CPD_FAIL(CPD_EUNSUPPORTED, "MTTKRP kernels are built for 2..5 modes, not %d", N);
+    DevBuf<float> copies;
+    float *Yk = Y;
+    int64_t ldk = ldo, copy_stride = 0;
+    if (xcd_copies) {
+        copy_stride = out_rows * R;
+        CPD_TRY(copies.alloc((size_t)XCD_COPIES * copy_stride, s));
+        const int64_t tot = XCD_COPIES * copy_stride;
+        hipLaunchKernelGGL(k_zero_rows, dim3((unsigned)ceil_div(tot, 256)), dim3(256), 0, s, copies.p,
+                           (int64_t)XCD_COPIES * out_rows, (int64_t)R, R);
+        CPD_LAUNCH_CHECK();
+        Yk = copies.p;
+        ldk = R;
+    }
     if (ev0) CPD_HIP(hipEventRecord(ev0, s));
     cpd_status st = CPD_OK;
 #define CPD_LANE_N(n)                                                                                   \
     case n:                                                                                             \
-        st = bf16 ? launch_lane<n, uint16_t>(G, priv, hot, grid, lds_launch, s, cv, fv, ld, d, starts, ns, T, Y, \
-                                             ldo, R, out_rows)                                          \
-                  : launch_lane<n, float>(G, priv, hot, grid, lds_launch, s, cv, fv, ld, d, starts, ns, T, Y,  \
-                                          ldo, R, out_rows);                                            \
+        st = bf16 ? launch_lane<n, uint16_t>(G, priv, hot, grid, lds_launch, s, cv, fv, ld, d, starts, ns, T, Yk, \
+                                             ldk, R, out_rows, copy_stride)                             \
+                  : launch_lane<n, float>(G, priv, hot, grid, lds_launch, s, cv, fv, ld, d, starts, ns, T, Yk, \
+                                          ldk, R, out_rows, copy_stride);                               \
         break;
     switch (N) {
         CPD_LANE_N(2)
@@ -381,6 +414,11 @@ cpd_status mttkrp(cpd_csf_s *c, const void *const *factors, int32_t ld, int32_t 
         CPD_LANE_N(5)
     }
 #undef CPD_LANE_N
+    if (st == CPD_OK && xcd_copies) {
+        hipLaunchKernelGGL(k_sum_copies, dim3((unsigned)ceil_div(copy_stride, 256)), dim3(256), 0, s,
+                           (const float *)copies.p, XCD_COPIES, out_rows, R, Y, (int64_t)ldo);
+        CPD_LAUNCH_CHECK();
+    }
     if (st == CPD_OK && ev1) CPD_HIP(hipEventRecord(ev1, s));
     return st;
 }

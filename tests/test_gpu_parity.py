@@ -238,7 +238,9 @@ def test_mttkrp_every_level(case, R, ld):
     for mode in range(t.nmodes):
         depth = c.order.index(mode)
         kernels = ["lane"] + (["row"] if depth < t.nmodes - 1 and (ld or R) >= 8 and R in (8, 16, 32, 35, 64) and t.nmodes <= 5 else [])
-        variants = ["atomic"] + (["private"] if depth >= 1 and t.dims[mode] * R * 4 <= 65536 else [])
+        # private: a copy of Y in LDS per block when it fits 64 KiB, else one
+        # HBM copy per XCD summed afterwards
+        variants = ["atomic"] + (["private"] if depth >= 1 else [])
         for kernel in kernels:
             for variant in (variants if kernel == "lane" else ["auto"]):
                 for prec in ("fp32", "bf16"):
@@ -311,6 +313,10 @@ def test_mttkrp_rejects_bad_arguments():
     leaf = c.order[-1]
     with pytest.raises(cpd.CpdError) as e:
         cpd.mttkrp(c, facs, leaf, kernel="row")
+    assert e.value.status == cpd.CPD_EUNSUPPORTED
+    # nor privatisation at the root (its rows never collide)
+    with pytest.raises(cpd.CpdError) as e:
+        cpd.mttkrp(c, facs, c.order[0], kernel="lane", variant="private")
     assert e.value.status == cpd.CPD_EUNSUPPORTED
 
 
