@@ -49,13 +49,17 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 // QB: 4x4 blocks of the upper triangle owned per lane (ceil(blocks / 64)).
+// The chunks are software-pipelined: while the wave accumulates chunk c from
+// LDS, the gathers of chunk c + 1 (their ids staged a chunk earlier) and the
+// leaf ids of chunk c + 2 are in flight in registers.
 template <int N, int QB>
 __global__ void __launch_bounds__(64 * RG_WAVES)
 k_row_gram(TreeRefs tr, int64_t ld, int R, const int32_t *__restrict__ starts, int64_t nruns, double *__restrict__ G) {
     constexpr int RPMAX = CPD_MAX_RANK;
+    constexpr int NI = (N * RG_C + 63) / 64;    // staged ids per lane and chunk
     __shared__ double s_h[RG_WAVES][RG_C][RPMAX];
     __shared__ int32_t s_id[RG_WAVES][N][RG_C];
-    __shared__ int32_t s_lv[RG_WAVES][RG_C];
+    __shared__ int32_t s_lv[RG_WAVES][2][RG_C];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t run = (int64_t)blockIdx.x * RG_WAVES + wave;
     if (run >= nruns) return;  // waves are independent: no block barriers
@@ -99,28 +103,80 @@ k_row_gram(TreeRefs tr, int64_t ld, int R, const int32_t *__restrict__ starts, i
                 }
         }
     };
-    for (int64_t t0 = k0; t0 < k1; t0 += RG_C) {
-        const int len = (int)min((int64_t)RG_C, k1 - t0);
-        // leaf ids of every level and the leaf words, then the rows h in FP64
-        for (int e = lane; e < N * RG_C; e += 64) {
-            const int l = e / RG_C, b = e % RG_C;
-            if (l >= 1) s_id[wave][l][b] = b < len ? tr.ids[l][t0 + b] : 0;
-            else s_lv[wave][b] = b < len ? (int32_t)((uint32_t)tr.leafw[t0 + b] >> 29) : 0;
+    auto chunk_len = [&](int64_t t) { return (int)max((int64_t)0, min((int64_t)RG_C, k1 - t)); };
+    // leaf ids of every level below the root and the leaf words of chunk t:
+    // issued into registers, stored to LDS later
+    int32_t idr[NI];
+    auto load_ids = [&](int64_t t) {
+        const int len = chunk_len(t);
+#pragma unroll
+        for (int j = 0; j < NI; ++j) {
+            const int e = lane + 64 * j, l = e / RG_C, b = e % RG_C;
+            idr[j] = 0;
+            if (e < N * RG_C && b < len)
+                idr[j] = l >= 1 ? tr.ids[l][t + b] : (int32_t)((uint32_t)tr.leafw[t + b] >> 29);
         }
-        wave_sync();
-        for (int e = lane; e < RG_C * RP; e += 64) {
-            const int b = e / RP, r = e % RP;
+    };
+    auto store_ids = [&](int buf) {
+#pragma unroll
+        for (int j = 0; j < NI; ++j) {
+            const int e = lane + 64 * j, l = e / RG_C, b = e % RG_C;
+            if (e < N * RG_C) {
+                if (l >= 1) s_id[wave][l][b] = idr[j];
+                else s_lv[wave][buf][b] = idr[j];
+            }
+        }
+    };
+    // the factor entries of chunk t's rows h (ids in s_id), issued into
+    // registers: lane r gathers column r of every leaf's rows (one contiguous
+    // row per load instruction)
+    float fr[N - 1][RG_C];
+    auto load_rows = [&](int64_t t) {
+        const int len = chunk_len(t);
+#pragma unroll
+        for (int b = 0; b < RG_C; ++b) {
+            const bool in = b < len && lane < R;
+#pragma unroll
+            for (int l = 1; l < N; ++l) {
+                // the row id is wave-uniform: a scalar base, the lane as offset
+                const int32_t id = __builtin_amdgcn_readfirstlane(s_id[wave][l][b]);
+                const float *rowp = tr.fac[l] + (int64_t)id * ld;
+                fr[l - 1][b] = in ? rowp[lane] : 0.0f;
+            }
+        }
+    };
+    // h = product of the gathered entries in FP64 (zero past the rank)
+    auto store_rows = [&](int64_t t) {
+        const int len = chunk_len(t);
+        if (lane >= RP) return;
+#pragma unroll
+        for (int b = 0; b < RG_C; ++b) {
             double h = 0.0;
-            if (b < len && r < R) {
+            if (b < len && lane < R) {
                 h = 1.0;
 #pragma unroll
-                for (int l = 1; l < N; ++l) h *= (double)tr.fac[l][(int64_t)s_id[wave][l][b] * ld + r];
+                for (int l = 1; l < N; ++l) h *= (double)fr[l - 1][b];
             }
-            s_h[wave][b][r] = h;
+            s_h[wave][b][lane] = h;
         }
+    };
+    load_ids(k0);
+    store_ids(0);
+    wave_sync();
+    load_rows(k0);
+    load_ids(k0 + RG_C);
+    int cb = 0;  // s_lv buffer of the current chunk
+    for (int64_t t0 = k0; t0 < k1; t0 += RG_C, cb ^= 1) {
+        const int len = chunk_len(t0);
+        store_rows(t0);
+        store_ids(cb ^ 1);  // the next chunk's ids and leaf words
         wave_sync();
+        if (t0 + RG_C < k1) {
+            load_rows(t0 + RG_C);
+            load_ids(t0 + 2 * RG_C);
+        }
         for (int b = 0; b < len; ++b) {
-            if (s_lv[wave][b] == 0 && t0 + b > k0) {  // a new root node (row) starts at this leaf
+            if (s_lv[wave][cb][b] == 0 && t0 + b > k0) {  // a new root node (row) starts at this leaf
                 flush();
                 c0 += 1;
                 row = tr.root_ids[c0];
