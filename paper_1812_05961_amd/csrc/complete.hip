@@ -210,9 +210,14 @@ k_row_gram(TreeRefs tr, int64_t ld, int R, const int32_t *__restrict__ starts, i
 __global__ void __launch_bounds__(64)
 k_row_solve(const double *__restrict__ G, const float *__restrict__ Y, int64_t ldy, int64_t rows, int R,
             double reg, float *__restrict__ A, int64_t lda, double *__restrict__ terms) {
-    constexpr int LDM = CPD_MAX_RANK + 1;  // odd stride: a lane's row starts two banks after its neighbour's
-    __shared__ double M[CPD_MAX_RANK * LDM];
-    __shared__ double rowj[CPD_MAX_RANK + 1];
+    // M (R rows of stride LDM) and the pivot-row copy in dynamic LDS sized
+    // for this rank: at rank 35 a block takes 10.6 KB instead of 33 KB, so
+    // about four waves share each SIMD instead of one.
+    // LDM: the odd stride >= R + 1, so lane rows start on distinct bank pairs
+    extern __shared__ double s_dyn[];
+    const int LDM = (R + 1) | 1;
+    double *M = s_dyn;
+    double *rowj = s_dyn + R * LDM;
     const int64_t i = blockIdx.x;
     const int lane = threadIdx.x;
     if (i >= rows) return;
@@ -352,7 +357,9 @@ cpd_status row_solve(const double *G, const float *Y, int64_t ldy, int64_t rows,
     if (rows == 0) return CPD_OK;
     DevBuf<double> terms;
     CPD_TRY(terms.alloc((size_t)rows * 2, s));
-    hipLaunchKernelGGL(k_row_solve, dim3((unsigned)rows), dim3(64), 0, s, G, Y, ldy, rows, R, reg, A, lda, terms.p);
+    const size_t lds = (size_t)(R * ((R + 1) | 1) + R + 1) * sizeof(double);
+    hipLaunchKernelGGL(k_row_solve, dim3((unsigned)rows), dim3(64), lds, s, G, Y, ldy, rows, R, reg, A, lda,
+                       terms.p);
     CPD_LAUNCH_CHECK();
     if (terms2) {
         hipLaunchKernelGGL(k_sum_terms, dim3(1), dim3(256), 0, s, (const double *)terms.p, rows, terms2);
