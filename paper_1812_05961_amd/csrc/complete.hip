@@ -59,7 +59,6 @@ k_row_gram(TreeRefs tr, int64_t ld, int R, const int32_t *__restrict__ starts, i
     constexpr int NI = (N * RG_C + 63) / 64;    // staged ids per lane and chunk
     __shared__ double s_h[RG_WAVES][RG_C][RPMAX];
     __shared__ int32_t s_id[RG_WAVES][N][RG_C];
-    __shared__ int32_t s_lv[RG_WAVES][2][RG_C];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t run = (int64_t)blockIdx.x * RG_WAVES + wave;
     if (run >= nruns) return;  // waves are independent: no block barriers
@@ -117,15 +116,15 @@ k_row_gram(TreeRefs tr, int64_t ld, int R, const int32_t *__restrict__ starts, i
                 idr[j] = l >= 1 ? tr.ids[l][t + b] : (int32_t)((uint32_t)tr.leafw[t + b] >> 29);
         }
     };
-    auto store_ids = [&](int buf) {
+    // stores the ids to LDS; returns the chunk's leaves that open a root node
+    // (bit b: leaf word level 0), a wave-uniform mask
+    auto store_ids = [&]() {
 #pragma unroll
         for (int j = 0; j < NI; ++j) {
             const int e = lane + 64 * j, l = e / RG_C, b = e % RG_C;
-            if (e < N * RG_C) {
-                if (l >= 1) s_id[wave][l][b] = idr[j];
-                else s_lv[wave][buf][b] = idr[j];
-            }
+            if (e < N * RG_C && l >= 1) s_id[wave][l][b] = idr[j];
         }
+        return (uint64_t)__ballot(lane < RG_C && idr[0] == 0);
     };
     // the factor entries of chunk t's rows h (ids in s_id), issued into
     // registers: lane r gathers column r of every leaf's rows (one contiguous
@@ -161,42 +160,52 @@ k_row_gram(TreeRefs tr, int64_t ld, int R, const int32_t *__restrict__ starts, i
         }
     };
     load_ids(k0);
-    store_ids(0);
+    uint64_t opens = store_ids();
     wave_sync();
     load_rows(k0);
     load_ids(k0 + RG_C);
-    int cb = 0;  // s_lv buffer of the current chunk
-    for (int64_t t0 = k0; t0 < k1; t0 += RG_C, cb ^= 1) {
+    for (int64_t t0 = k0; t0 < k1; t0 += RG_C) {
         const int len = chunk_len(t0);
         store_rows(t0);
-        store_ids(cb ^ 1);  // the next chunk's ids and leaf words
+        const uint64_t opens_next = store_ids();  // the next chunk's ids
         wave_sync();
         if (t0 + RG_C < k1) {
             load_rows(t0 + RG_C);
             load_ids(t0 + 2 * RG_C);
         }
-        for (int b = 0; b < len; ++b) {
-            if (s_lv[wave][cb][b] == 0 && t0 + b > k0) {  // a new root node (row) starts at this leaf
+        // segments of leaves in one root node (from the wave-uniform mask of
+        // opening leaves, no per-leaf LDS read): a flush between segments, the
+        // products of a segment in a loop unrolled by 8, so that the LDS reads
+        // of later leaves issue before the products of earlier ones
+        for (int b = 0; b < len;) {
+            if (((opens >> b) & 1ull) && t0 + b > k0) {  // a new root node (row) starts at this leaf
                 flush();
                 c0 += 1;
                 row = tr.root_ids[c0];
             }
-            const double *h = s_h[wave][b];
+            const uint64_t later = (opens >> b) >> 1;  // opens after leaf b
+            const int e = later ? min(len, b + 1 + (int)__builtin_ctzll(later)) : len;
+#pragma unroll 8
+            for (int bb = b; bb < e; ++bb) {
+                const double *h = s_h[wave][bb];
 #pragma unroll
-            for (int q = 0; q < QB; ++q) {
-                if (!own[q]) continue;
-                double hr[4], hc[4];
+                for (int q = 0; q < QB; ++q) {
+                    if (!own[q]) continue;
+                    double hr[4], hc[4];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    hr[u] = h[bi[q] * 4 + u];
-                    hc[u] = h[bj[q] * 4 + u];
+                    for (int u = 0; u < 4; ++u) {
+                        hr[u] = h[bi[q] * 4 + u];
+                        hc[u] = h[bj[q] * 4 + u];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) acc[q][u * 4 + v] = fma(hr[u], hc[v], acc[q][u * 4 + v]);
                 }
-#pragma unroll
-                for (int u = 0; u < 4; ++u)
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) acc[q][u * 4 + v] = fma(hr[u], hc[v], acc[q][u * 4 + v]);
             }
+            b = e;
         }
+        opens = opens_next;
         wave_sync();
     }
     flush();
