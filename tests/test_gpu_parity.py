@@ -354,12 +354,12 @@ def test_solve_normalize(R):
     np.testing.assert_allclose(out["G"].cpu().numpy(), Gn, rtol=1e-10, atol=1e-12)
 
 
-def test_solve_normalize_singular_uses_pinv():
+@pytest.mark.parametrize("R", [6, 20])  # the 256- and the 1024-thread inverse block
+def test_solve_normalize_singular_uses_pinv(R):
     cpd = _cpd()
     rng = np.random.default_rng(3)
-    R = 6
-    M = rng.standard_normal((40, R))
-    M[:, 4] = M[:, 2]
+    M = rng.standard_normal((3 * R + 20, R))
+    M[:, R - 2] = M[:, 2]
     G1 = M.T @ M
     grams = [np.ones((R, R)), G1, np.ones((R, R))]
     Y = rng.standard_normal((25, R)).astype(np.float32)
