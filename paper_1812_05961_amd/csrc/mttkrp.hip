@@ -125,7 +125,26 @@ k_mttkrp_lane(CsfView cv, FacView fv, int64_t ld, int d, const int32_t *__restri
 #pragma unroll
         for (int q = 0; q < CPL; ++q) acc[q] = 0.0f;
         int32_t out_row = d < N - 1 ? cv.fids[d][c[d]] : 0;
+        // without the hot-row table the next leaf's value and index are loaded
+        // a leaf ahead (6-14% faster at level 1 on the three benchmark shapes;
+        // with the table the extra registers cost more than the latency saved)
+        float v_n = 0.0f;
+        int32_t i_n = 0;
+        if (!HOT && k < kend) {
+            v_n = cv.vals[k];
+            i_n = cv.fids[N - 1][k];
+        }
         for (; k < kend; ++k) {
+            float v;
+            int32_t i;
+            if (!HOT) {
+                v = v_n;
+                i = i_n;
+                if (k + 1 < kend) {
+                    v_n = cv.vals[k + 1];
+                    i_n = cv.fids[N - 1][k + 1];
+                }
+            }
             if (k == e[N - 2]) {
                 int lmin = N - 2;
                 c[N - 2] += 1;
@@ -147,8 +166,10 @@ k_mttkrp_lane(CsfView cv, FacView fv, int64_t ld, int d, const int32_t *__restri
                 }
                 make_H();
             }
-            const float v = cv.vals[k];
-            const int32_t i = cv.fids[N - 1][k];
+            if (HOT) {
+                v = cv.vals[k];
+                i = cv.fids[N - 1][k];
+            }
             if (d == N - 1) {
                 float t[CPL];
 #pragma unroll
