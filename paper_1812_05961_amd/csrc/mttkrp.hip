@@ -127,7 +127,8 @@ k_mttkrp_lane(CsfView cv, FacView fv, int64_t ld, int d, const int32_t *__restri
         int32_t out_row = d < N - 1 ? cv.fids[d][c[d]] : 0;
         // without the hot-row table the next leaf's value and index are loaded
         // a leaf ahead (6-14% faster at level 1 on the three benchmark shapes;
-        // with the table the extra registers cost more than the latency saved)
+        // with the table it measured 0-15% slower, also with the leaf's rank
+        // loaded ahead, so those forms load in place)
         float v_n = 0.0f;
         int32_t i_n = 0;
         if (!HOT && k < kend) {
