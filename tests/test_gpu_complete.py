@@ -46,7 +46,7 @@ def _padded(dims, R, ld, seed):
 
 
 @pytest.mark.parametrize("name", ["small3", "zipf3", "zipf4", "zipf5", "dups3", "one_nnz"])
-@pytest.mark.parametrize("R,ld", [(5, 8), (16, 16), (35, 36)])
+@pytest.mark.parametrize("R,ld", [(5, 8), (16, 16), (35, 36), (48, 48), (64, 64)])  # 1, 2 and 3 blocks a lane
 def test_row_gram_matches_oracle(name, R, ld):
     cpd = _cpd()
     t = CASES[name]()
