@@ -9,10 +9,10 @@
 // accumulated here on the same tree.
 //
 // Row Gram kernel: one wave per run of T leaves.  Chunks of C leaves are
-// staged in LDS as FP64 rows h (their gathers all in flight together); the
-// wave then walks the chunk's leaves in order, each lane accumulating 4x4
-// blocks of the upper triangle of h h^T in registers, and adds them to G_i
-// with FP64 atomics when the leaf's root node (row i) ends or the run ends.
+// staged in LDS as FP64 rows h, the next chunk's gathers in flight while the
+// wave walks the current chunk's leaves in order, each lane accumulating 4x4
+// blocks of the upper triangle of h h^T in registers; the blocks are added to
+// G_i with FP64 atomics when the leaf's root node (row i) ends or the run ends.
 // Row solve kernel: one wave per row, Gauss-Jordan on [G_i + reg I | y_i] in
 // LDS, one matrix row per lane (the matrix is symmetric positive definite for
 // reg > 0, so no pivoting), with the row's loss terms a.y and a^T G a.
