@@ -31,7 +31,7 @@ Pinned by (tests/test_oracle_complete.py): the row Grams against a plain
 loop over observations; a fully observed tensor with reg = 0 against the
 unnormalised dense ALS update A_n = X_(n) KR (KR^T KR)^{-1} built from an
 explicit unfolding and Khatri-Rao product; the closed form of a row with one
-observation; the RMSE identity against residuals of the explicit model; exact
+observation, with reg > 0 and (the pseudo-inverse path, C4) at reg = 0; the RMSE identity against residuals of the explicit model; exact
 recovery of a planted low-rank tensor from a subset of its entries.
 """
 from __future__ import annotations

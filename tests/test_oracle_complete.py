@@ -146,3 +146,25 @@ def test_solved_rows_satisfy_their_regularised_normal_equations():
             np.testing.assert_allclose(X[i], ref, rtol=1e-9, atol=1e-12)
         norms.append(np.linalg.norm(X))
     assert norms[1] < norms[0]
+
+
+def test_rank_deficient_row_at_zero_reg_takes_the_minimum_norm_solution():
+    """Reading C4: one observation and reg = 0 give G_i = h h^T (rank one), so
+    the pseudo-inverse path must return the minimum-norm solution of
+    h h^T a = x h, which is a = x h / (h.h)."""
+    from oracle import coo
+    dims, R = (3, 4, 5), 3
+    inds = np.array([[0, 1, 1, 2], [1, 2, 3, 0], [4, 0, 2, 3]])
+    vals = np.array([1.5, -2.0, 0.75, 3.0])
+    A = _factors(dims, R, 7)
+    counts = oc.row_counts(dims, inds, 0)
+    Y = coo.mttkrp(dims, inds, vals, A, 0)
+    G = oc.row_grams(dims, inds, vals, A, 0)
+    A0, pinv = oc.solve_rows(G, Y, 0.0, counts)
+    h = A[1][1] * A[2][4]
+    np.testing.assert_allclose(A0[0], 1.5 * h / (h @ h), rtol=1e-10)
+    # row 2 (one observation too) and row 1 (two: rank two, still below R = 3)
+    assert pinv == 3
+    h2 = A[1][0] * A[2][3]
+    np.testing.assert_allclose(A0[2], 3.0 * h2 / (h2 @ h2), rtol=1e-10)
+    np.testing.assert_allclose(A0[1], np.linalg.pinv(G[1]) @ Y[1], rtol=1e-8, atol=1e-12)
