@@ -168,3 +168,22 @@ def test_rank_deficient_row_at_zero_reg_takes_the_minimum_norm_solution():
     h2 = A[1][0] * A[2][3]
     np.testing.assert_allclose(A0[2], 3.0 * h2 / (h2 @ h2), rtol=1e-10)
     np.testing.assert_allclose(A0[1], np.linalg.pinv(G[1]) @ Y[1], rtol=1e-8, atol=1e-12)
+
+
+def test_stopping_rule():
+    """Reading C6: with tol > 0 the sweeps stop once the RMSE changes by less
+    than tol, checked from the second sweep; tol = 0 runs every sweep."""
+    dims, R = (6, 5, 4), 2
+    inds = _observed(dims, 0.6, 50)
+    vals = np.random.default_rng(51).random(inds.shape[1])
+    init = _factors(dims, R, 52)
+    full = oc.cp_complete(dims, inds, vals, R, 6, 0.0, 0.1, init)
+    assert full["iters"] == 6 and len(full["rmses"]) == 6
+    early = oc.cp_complete(dims, inds, vals, R, 6, 1e9, 0.1, init)
+    assert early["iters"] == 2 and early["rmses"] == full["rmses"][:2]
+    # a tolerance between two consecutive changes stops right after the first change below it
+    d = np.abs(np.diff(full["rmses"]))
+    k = int(np.argmax(d < d[0])) if (d < d[0]).any() else None
+    if k is not None:
+        mid = oc.cp_complete(dims, inds, vals, R, 6, float(d[0]), 0.1, init)
+        assert mid["iters"] == k + 2
