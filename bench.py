@@ -267,6 +267,56 @@ def cpu_baseline(x, R, sample_nnz, seed=11):
                 sample="%s of the FP64 oracle (C MTTKRP loop, numpy solve), %.2f s measured" % (what, t))
 
 
+def profile_workload(workload, precision, what):
+    """A short fixed workload to run under rocprofv3 (kernel traces and
+    counters): three plain 256 MiB device copies (the calibration of the
+    FETCH_SIZE / WRITE_SIZE counters: each reads and writes exactly 256 MiB),
+    then, on the per-mode trees cpd_als builds, one root-level MTTKRP per mode
+    (what = "root"), or on the ascending-length tree every mode's MTTKRP at its
+    level, atomic variant (what = "single")."""
+    import torch
+
+    from paper_1812_05961_amd import cpd, synth
+    cpd.lib()
+    dev = torch.device("cuda:0")
+    n = 64 << 20  # floats: 256 MiB
+    a = torch.ones(n, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+    log("calibration copies done")
+    x = synth.make_config(workload, device=dev)
+    x.inds = x.inds.to(torch.int32)
+    R = synth.CONFIGS[workload]["rank"]
+    ld = next(w for w in (8, 16, 32, 36, 64) if w >= R)
+    g = torch.Generator(device="cuda").manual_seed(1)
+    facs = []
+    for d in x.dims:
+        f = torch.zeros((d, ld), dtype=torch.float32, device=dev)
+        f[:, :R] = torch.rand((d, R), device=dev, generator=g)
+        facs.append(f if precision == "fp32" else f.to(torch.bfloat16))
+    if what == "root":
+        for mode, order in enumerate(root_orders(x.dims)):
+            c = cpd.csf_build(x.inds, x.vals, x.dims, order)
+            out = torch.empty((x.dims[mode], ld), device=dev)
+            cpd.mttkrp(c, facs, mode, out=out, rank=R, precision=precision)
+            torch.cuda.synchronize()
+            c.free()
+            log("root MTTKRP of mode %d done" % mode)
+    else:
+        c = cpd.csf_build(x.inds, x.vals, x.dims, None)
+        for mode in c.order:
+            out = torch.empty((x.dims[mode], ld), device=dev)
+            cpd.mttkrp(c, facs, mode, out=out, rank=R, precision=precision,
+                       variant="auto" if mode == c.order[0] else "atomic")
+            torch.cuda.synchronize()
+            log("single-tree MTTKRP of mode %d (level %d) done" % (mode, c.order.index(mode)))
+        c.free()
+    log("profile workload done")
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -280,7 +330,12 @@ def main():
     ap.add_argument("--no-completion", action="store_true", help="skip the CP-with-missing-values timings")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the BF16-vs-FP32 comparison on the NETFLIX-shaped tensor")
+    ap.add_argument("--profile-workload", choices=["root", "single"],
+                    help="run only a short MTTKRP workload for rocprofv3 (no JSON line)")
     args = ap.parse_args()
+    if args.profile_workload:
+        profile_workload(args.workload, args.precision, args.profile_workload)
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the hot path is built and measured on a single "
               "MI355X (--gpus %d was requested)" % args.gpus, file=sys.stderr)

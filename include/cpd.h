@@ -17,8 +17,10 @@
  *     cpd_last_error() gives a message for the calling thread.
  *   - The caller owns every buffer it passes; the library never frees them.
  *     Objects the library creates (cpd_csf) are freed by their *_free call.
- *   - Tensors have 2..8 modes, each of length 1..2^31-1, and 1..2^31-1
- *     nonzeros; ranks are 1..64.  Indices are 0-based int32.
+ *   - Tensors have 2..5 modes (CSF trees, MTTKRP, CP-ALS; the dense steps
+ *     take up to CPD_MAX_MODES = 8 Gram matrices), each of length
+ *     1..2^31-1, and 1..2^31-1 nonzeros; ranks are 1..64.  Indices are
+ *     0-based int32.
  *   - Factor matrices are row-major: element (i, r) at ptr[i * ld + r].
  */
 #ifndef CPD_H
@@ -83,7 +85,8 @@ int32_t cpd_abi_version(void);
 typedef struct cpd_csf_s *cpd_csf;
 
 /* Build a CSF from COO.
- *   nmodes  N in [2, 8];  dims: host, N lengths;  nnz in [1, 2^31-1].
+ *   nmodes  N in [2, 5] (CPD_EUNSUPPORTED for 6..8, CPD_EINVAL otherwise);
+ *           dims: host, N lengths;  nnz in [1, 2^31-1].
  *   inds    host array of N device pointers, each nnz int32 indices.
  *   vals    device, nnz floats.
  *   order   host, a permutation of 0..N-1 (root first), or NULL for modes by
@@ -152,6 +155,26 @@ cpd_status cpd_mttkrp(cpd_csf csf, const void *const *factors, int32_t ld, int32
                       int32_t mode, float *out, int32_t ldo, const cpd_mttkrp_opts *opts,
                       void *stream);
 
+/* The kernel family cpd_mttkrp runs for a request, by the rule it applies,
+ * decided on the host without touching the device.
+ *   nmodes         N (MTTKRP kernels exist for 2..5);
+ *   dims_by_level  host, N lengths in tree order (dims[order[l]]);
+ *   depth          level of the output mode (0 = root);
+ *   ld, rank, precision, kernel: as for cpd_mttkrp (kernel = the request);
+ *   rows_aligned   nonzero when every non-output factor starts 16-byte aligned;
+ *   leaf_words     nonzero when the tree has leaf words (every leaf length
+ *                  below 2^29, always so for trees cpd_csf_build makes).
+ * ROW is eligible for 3..5 modes at non-leaf levels, when the padded rank
+ * fits in ld and rows are 16-byte multiples below 16 MiB, and every gathered
+ * level (all but `depth`) has fewer than 2^24 rows with rows * row bytes
+ * <= 2^32 (its rows are addressed by 32-bit byte offsets).  AUTO picks ROW at
+ * the root when eligible, LANE otherwise.
+ * *kernel_out (host) = CPD_KERNEL_ROW or CPD_KERNEL_LANE; CPD_EUNSUPPORTED
+ * when ROW is requested and not eligible, or N is outside 2..5. */
+cpd_status cpd_mttkrp_plan(int32_t nmodes, const int64_t *dims_by_level, int32_t depth, int32_t ld,
+                           int32_t rank, int32_t precision, int32_t kernel, int32_t rows_aligned,
+                           int32_t leaf_words, int32_t *kernel_out);
+
 /* ---------------------------------------------------------------------------
  * Dense steps of Algorithm 1 (FP64 on the GPU). */
 
@@ -199,8 +222,7 @@ cpd_status cpd_sumsq(const float *vals, int64_t n, double *out, void *stream);
  * CP-ALS (Algorithm 1) from COO. */
 typedef struct {
     int32_t precision;       /* CPD_FP32 or CPD_BF16_GATHER (MTTKRP gathers only;
-                                the solve, norms and fit stay FP64; with BF16 the
-                                final fit is recomputed with FP32 gathers) */
+                                the solve, norms and fit stay FP64) */
     int32_t variant;         /* CPD_VARIANT_* for every MTTKRP */
     int32_t kernel;          /* CPD_KERNEL_* */
     int32_t tile_nnz;        /* 0 = automatic */
@@ -208,7 +230,16 @@ typedef struct {
                                 other modes by descending length (the default:
                                 every MTTKRP is a root-level one);
                                 1: one CSF in `order` (or ascending lengths) */
-    int32_t reserved;
+    int32_t fast_fit;        /* 0 (default): after the last sweep the reported
+                                fit is evaluated from one more MTTKRP of the last
+                                mode with the final FP32 factors, FP64 products
+                                and FP64 sums, so it is the fit of the returned
+                                model to ~1e-8 also as the fit nears 1;
+                                1: no extra pass with FP32 gathers (the last
+                                sweep's fit, from its FP32 MTTKRP; near fit 1 it
+                                is good to about sqrt(rel. error of that MTTKRP),
+                                ~1e-3); with BF16 gathers the extra pass then uses
+                                FP32 rows and FP32 sums */
     const int32_t *order;    /* host, N entries, or NULL (used with single_csf) */
     const float *const *init;/* host array of N device pointers to I_m x rank
                                 floats (stride rank), or NULL: seeded U(0,1) */
@@ -231,7 +262,9 @@ typedef struct {
 } cpd_als_opts;
 
 /* Run CP-ALS with `rank` components for at most max_iters sweeps; when tol > 0
- * stop from the second sweep on once |fit - previous fit| < tol.
+ * stop from the second sweep on once |fit - previous fit| < tol (the per-sweep
+ * fit, from that sweep's MTTKRP of the last mode; fit_trace holds these).
+ * fit_out: the fit of the returned model (see fast_fit).
  * factors_out: host array of N device pointers, I_m x rank floats (stride
  *              rank), written with unit-norm columns.
  * lambda_out:  host, rank doubles.  fit_out, iters_out: host.
@@ -278,7 +311,10 @@ cpd_status cpd_row_solve(const double *G, const float *Y, int64_t ldy, int64_t r
  * second on once the RMSE changes by less than tol > 0).  factors: host array
  * of N device pointers to I_m x rank floats (stride rank): the initial values
  * (factor 0 is not read: mode 0 is solved first), overwritten with the
- * result.  rmse: host, max_iters doubles (the RMSE after each sweep), or NULL.
+ * result.  rmse: host, max_iters doubles (the RMSE after each sweep; the last
+ * one evaluated once more for the returned factors from an MTTKRP of the last
+ * mode with FP64 products and sums, accurate to ~1e-8 of the data's scale also
+ * as the RMSE nears 0), or NULL.
  * iters: host, sweeps run.  3..5 modes.  Waits for `stream`. */
 cpd_status cpd_complete(int32_t nmodes, const int64_t *dims, int64_t nnz, const int32_t *const *inds,
                         const float *vals, int32_t rank, int32_t max_iters, double tol, double reg,

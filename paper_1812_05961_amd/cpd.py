@@ -38,7 +38,7 @@ class MttkrpOpts(ctypes.Structure):
 
 class AlsOpts(ctypes.Structure):
     _fields_ = [("precision", _I32), ("variant", _I32), ("kernel", _I32), ("tile_nnz", _I32),
-                ("single_csf", _I32), ("reserved", _I32), ("order", _P), ("init", _P),
+                ("single_csf", _I32), ("fast_fit", _I32), ("order", _P), ("init", _P),
                 ("seed", ctypes.c_uint64), ("fit_trace", _P), ("timing_ms", _P),
                 ("select", _I32), ("selector_hidden", _I32), ("selector_params", _P)]
 
@@ -86,6 +86,7 @@ _SIGS = {
     "cpd_csf_tiles": (_I32, [_P, _I32, _P, _P, _P]),
     "cpd_csf_free": (None, [_P]),
     "cpd_mttkrp": (_I32, [_P, _P, _I32, _I32, _I32, _P, _I32, _P, _P]),
+    "cpd_mttkrp_plan": (_I32, [_I32, _P, _I32, _I32, _I32, _I32, _I32, _I32, _I32, _P]),
     "cpd_gram": (_I32, [_P, _I64, _I32, _I32, _P, _P]),
     "cpd_solve_normalize": (_I32, [_P, _I32, _I32, _P, _I64, _I32, _I32, _P, _I32, _P, _I32, _P,
                                    _P, _P, _P]),
@@ -243,6 +244,17 @@ def csf_build_rooted(inds, vals, dims, stream=None) -> list:
     return out
 
 
+
+def mttkrp_plan(dims_by_level, depth, rank, ld=None, precision="fp32", kernel="auto",
+                rows_aligned=True, leaf_words=True):
+    """Kernel family ("row" or "lane") cpd_mttkrp runs for this request (host only)."""
+    out = _I32()
+    nm = len(dims_by_level)
+    _check(lib().cpd_mttkrp_plan(nm, _i64s(dims_by_level), int(depth), int(ld or rank), int(rank),
+                                 PRECISION[precision], KERNEL[kernel], int(bool(rows_aligned)),
+                                 int(bool(leaf_words)), ctypes.byref(out)))
+    return _KERNEL_NAME[out.value]
+
 def mttkrp(csf: Csf, factors, mode: int, out=None, rank=None, precision="fp32", variant="auto",
            kernel="auto", tile_nnz=0, stream=None):
     """cpd_mttkrp: Y (dims[mode] x rank, float32) for the given factors.
@@ -358,11 +370,11 @@ def complete(inds, vals, dims, rank, iters, reg, init, tol=0.0, stream=None):
 
 def als(inds, vals, dims, rank, iters, tol=0.0, init=None, precision="fp32", variant="auto",
         kernel="auto", tile_nnz=0, single_csf=False, order=None, seed=0, timing=False,
-        select="none", selector=None, stream=None):
+        select="none", selector=None, fast_fit=False, stream=None):
     """cpd_als -> dict(factors, lam, fit, iters, fits, timing_ms).
 
     select: "none", "network" (selector = (params CUDA tensor, hidden)) or
-    "heuristic"."""
+    "heuristic".  fast_fit: skip the FP64 evaluation of the returned model's fit."""
     inds, vals, dims = _coo_args(inds, vals, dims)
     nm = len(dims)
     outs = [torch.empty((d, rank), dtype=torch.float32, device="cuda") for d in dims]
@@ -376,7 +388,7 @@ def als(inds, vals, dims, rank, iters, tol=0.0, init=None, precision="fp32", var
     ordarr = None if order is None else (_I32 * nm)(*[int(m) for m in order])
     initarr = None if init is None else _ptrs(init)
     opts = AlsOpts(PRECISION[precision], VARIANT[variant], KERNEL[kernel], int(tile_nnz),
-                   int(bool(single_csf)), 0,
+                   int(bool(single_csf)), int(bool(fast_fit)),
                    ctypes.cast(ordarr, ctypes.c_void_p) if ordarr is not None else None,
                    ctypes.cast(initarr, ctypes.c_void_p) if initarr is not None else None,
                    int(seed), ctypes.cast(trace, ctypes.c_void_p),

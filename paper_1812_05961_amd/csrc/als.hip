@@ -53,6 +53,11 @@ cpd_status fit(double normX2, const double *lambda, const float *A, int64_t lda,
                int64_t ldy, int64_t rows, int R, const double *const *grams, int nmodes, double *out,
                hipStream_t s);
 cpd_status sumsq(const float *v, int64_t n, double *out, hipStream_t s);
+cpd_status mttkrp64(cpd_csf_s *c, const float *const *factors, int32_t ld, int32_t R, int32_t mode, double *Y,
+                    int32_t ldo, hipStream_t s);
+cpd_status fit64(double normX2, const double *lambda, const float *A, int64_t lda, const double *Y,
+                 int64_t ldy, int64_t rows, int R, const double *const *grams, int nmodes, double *out,
+                 hipStream_t s);
 
 namespace {
 
@@ -157,6 +162,8 @@ cpd_status als(int nm, const int64_t *dims, int64_t nnz, const int32_t *const *i
     if (opts_in) o = *opts_in;
     const bool bf16 = o.precision == CPD_BF16_GATHER;
     if (o.precision != CPD_FP32 && !bf16) CPD_FAIL(CPD_EINVAL, "unknown precision %d", o.precision);
+    if (o.fast_fit != 0 && o.fast_fit != 1) CPD_FAIL(CPD_EINVAL, "fast_fit must be 0 or 1, not %d", o.fast_fit);
+    const bool exact_fit = o.fast_fit == 0;
 
     keep_pool_memory();
     Owned own(s);
@@ -221,6 +228,7 @@ cpd_status als(int nm, const int64_t *dims, int64_t nnz, const int32_t *const *i
     uint16_t *Ab[CPD_MAX_MODES] = {};
     double *G[CPD_MAX_MODES] = {};
     float *Y = nullptr;
+    double *Y64 = nullptr;
     double *lambda = nullptr, *d_fit = nullptr, *normX2 = nullptr;
     int32_t *d_pinv = nullptr;
     for (int m = 0; m < nm; ++m) {
@@ -229,6 +237,7 @@ cpd_status als(int nm, const int64_t *dims, int64_t nnz, const int32_t *const *i
         if (bf16) CPD_TRY(own.alloc(&Ab[m], (size_t)dims[m] * ldb));
     }
     CPD_TRY(own.alloc(&Y, (size_t)maxrows * ldf));
+    if (exact_fit) CPD_TRY(own.alloc(&Y64, (size_t)dims[nm - 1] * ldf));
     CPD_TRY(own.alloc(&lambda, R));
     CPD_TRY(own.alloc(&d_fit, (size_t)max_iters + 1));
     CPD_TRY(own.alloc(&normX2, 1));
@@ -299,9 +308,19 @@ cpd_status als(int nm, const int64_t *dims, int64_t nnz, const int32_t *const *i
     const int iters = std::min(it, max_iters);
     hipEvent_t t_loop1 = timing ? evs.make() : nullptr;
     if (timing) CPD_HIP(hipEventRecord(t_loop1, s));
-    // With BF16 gathers the reported fit is that of the returned model: redo the
-    // last mode's MTTKRP with FP32 rows and evaluate the fit from it.
-    if (bf16) {
+    // The reported fit is that of the returned model, evaluated once more from
+    // an MTTKRP of the last mode with the final FP32 factors: by default with
+    // FP64 products and sums, so that the residual ||X||^2 - 2<X,K> + ||K||^2
+    // keeps its accuracy as the fit nears 1 (the FP32 MTTKRP's relative error,
+    // ~1e-6 on rows of millions of terms, would otherwise bound the fit near 1
+    // to about sqrt(2e-6) ~ 1e-3); with fast_fit and BF16 gathers, with FP32
+    // rows and sums.
+    if (exact_fit) {
+        const float *f32_ptrs[CPD_MAX_MODES];
+        for (int m = 0; m < nm; ++m) f32_ptrs[m] = A[m];
+        CPD_TRY(mttkrp64(csf_of[nm - 1], f32_ptrs, ldf, R, nm - 1, Y64, ldf, s));
+        CPD_TRY(fit64(h_normX2, lambda, A[nm - 1], ldf, Y64, ldf, dims[nm - 1], R, gptr, nm, d_fit + max_iters, s));
+    } else if (bf16) {
         const void *f32_ptrs[CPD_MAX_MODES];
         for (int m = 0; m < nm; ++m) f32_ptrs[m] = A[m];
         cpd_mttkrp_opts mf = mo_of[nm - 1];
@@ -320,7 +339,7 @@ cpd_status als(int nm, const int64_t *dims, int64_t nnz, const int32_t *const *i
     CPD_HIP(hipMemcpyAsync(fits.data(), d_fit, sizeof(double) * (max_iters + 1), hipMemcpyDeviceToHost, s));
     CPD_HIP(hipStreamSynchronize(s));
     *iters_out = iters;
-    *fit_out = bf16 ? fits[max_iters] : fits[iters - 1];
+    *fit_out = (exact_fit || bf16) ? fits[max_iters] : fits[iters - 1];
     if (o.fit_trace)
         for (int i = 0; i < iters; ++i) o.fit_trace[i] = fits[i];
     if (timing) {

@@ -27,6 +27,8 @@ namespace cpd {
 cpd_status mttkrp(cpd_csf_s *c, const void *const *factors, int32_t ld, int32_t R, int32_t mode, float *Y,
                   int32_t ldo, const cpd_mttkrp_opts *opts, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
 cpd_status sumsq(const float *v, int64_t n, double *out, hipStream_t s);
+cpd_status mttkrp64(cpd_csf_s *c, const float *const *factors, int32_t ld, int32_t R, int32_t mode, double *Y,
+                    int32_t ldo, hipStream_t s);
 
 namespace {
 
@@ -277,6 +279,35 @@ k_row_solve(const double *__restrict__ G, const float *__restrict__ Y, int64_t l
 }
 
 // Sum the per-row loss terms (one block, fixed order).
+// Loss terms of the stored (FP32) rows a_i of A against an FP64 MTTKRP y
+// (rows x ldy doubles) and the row Grams G (upper triangles): terms[2i] =
+// a_i . y_i, terms[2i+1] = a_i^T G_i a_i, in FP64.  One wave per row, lane r
+// holding a_r.
+__global__ void __launch_bounds__(256) k_row_terms(const double *__restrict__ G, const double *__restrict__ Y,
+                                                   int64_t ldy, int64_t rows, int R, const float *__restrict__ A,
+                                                   int64_t lda, double *__restrict__ terms) {
+    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int r = threadIdx.x & 63;
+    if (i >= rows) return;
+    const double a = r < R ? (double)A[i * lda + r] : 0.0;
+    const double *g = G + i * (int64_t)R * R;
+    double t = 0.0;
+    for (int c = 0; c < R; ++c) {
+        const double ac = __shfl(a, c, 64);
+        if (r < R) t += (r <= c ? g[r * R + c] : g[c * R + r]) * ac;
+    }
+    double cross = r < R ? a * Y[i * ldy + r] : 0.0, quad = a * t;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        cross += __shfl_xor(cross, o, 64);
+        quad += __shfl_xor(quad, o, 64);
+    }
+    if (r == 0) {
+        terms[2 * i] = cross;
+        terms[2 * i + 1] = quad;
+    }
+}
+
 __global__ void __launch_bounds__(256) k_sum_terms(const double *__restrict__ terms, int64_t rows,
                                                    double *__restrict__ out) {
     __shared__ double sc[4], sq[4];
@@ -486,6 +517,32 @@ cpd_status cpd_complete(int32_t nmodes, const int64_t *dims, int64_t nnz, const 
         if (iters) *iters = it;
         if (tol > 0.0 && prev >= 0.0 && std::fabs(r - prev) < tol) break;
         prev = r;
+    }
+    // The last RMSE is evaluated once more for the returned (FP32) factors from
+    // an MTTKRP of the last mode with FP64 products and sums: the sweep's
+    // value takes a.y from its FP32 MTTKRP, whose relative error (~1e-6 on
+    // long rows) bounds an RMSE near 0 to about 1e-3 of the data's scale.
+    if (rmse && st == CPD_OK) {
+        const int nl = nmodes - 1;
+        const int64_t rows = dims[nl];
+        DevBuf<double> Y64, terms;
+        st = Y64.alloc((size_t)rows * ld, s);
+        if (st == CPD_OK) st = terms.alloc((size_t)rows * 2, s);
+        if (st == CPD_OK) st = mttkrp64(trees[nl], facf, ld, rank, nl, Y64.p, ld, s);
+        if (st == CPD_OK && rows > 0) {
+            hipLaunchKernelGGL(k_row_terms, dim3((unsigned)ceil_div(rows, 4)), dim3(256), 0, s, (const double *)G.p,
+                               (const double *)Y64.p, (int64_t)ld, rows, rank, (const float *)A[nl].p, (int64_t)ld,
+                               terms.p);
+            hipLaunchKernelGGL(k_sum_terms, dim3(1), dim3(256), 0, s, (const double *)terms.p, rows, d_terms.p);
+            if (hipGetLastError() != hipSuccess) st = CPD_EHIP;
+        }
+        double t2[2] = {0.0, 0.0};
+        if (st == CPD_OK && (hipMemcpyAsync(t2, d_terms.p, sizeof(t2), hipMemcpyDeviceToHost, s) != hipSuccess ||
+                             hipStreamSynchronize(s) != hipSuccess))
+            st = CPD_EHIP;
+        if (st != CPD_OK) return done(st);
+        rmse[std::min(it, max_iters) - 1] =
+            std::sqrt(std::max(0.0, normX2 - 2.0 * t2[0] + t2[1]) / (double)std::max<int64_t>(nobs, 1));
     }
     for (int m = 0; m < nmodes && st == CPD_OK; ++m) {
         hipLaunchKernelGGL(k_copy_rows, dim3((unsigned)ceil_div(dims[m] * rank, 256)), dim3(256), 0, s,

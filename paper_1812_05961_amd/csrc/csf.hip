@@ -16,13 +16,16 @@ constexpr int RS_THREADS = 256;            // == radix, one digit per thread in 
 constexpr int RS_ITEMS = 16;
 constexpr int RS_TILE = RS_THREADS * RS_ITEMS;
 
-// Launch a kernel template instantiated for the level count (2..5).
+// Launch a kernel template instantiated for the level count (2..5; check_coo
+// rejects other counts before any launch, and the rest are never launched).
+constexpr int CSF_MAX_LEVELS = 5;
 #define CPD_BY_LEVELS(nl, CALL)      \
     switch (nl) {                    \
         case 2: CALL(2); break;      \
         case 3: CALL(3); break;      \
         case 4: CALL(4); break;      \
-        default: CALL(5); break;     \
+        case 5: CALL(5); break;      \
+        default: break;              \
     }
 
 // Where each level's index sits in the packed 128-bit key (root most
@@ -662,6 +665,10 @@ constexpr int FLAG_DUP = 2 + CPD_MAX_MODES, FLAG_WORDS = FLAG_DUP + 1;
 cpd_status check_coo(int nm, const int64_t *dims, int64_t nnz, const int32_t *const *inds, const float *vals,
                      const void *out) {
     if (nm < 2 || nm > CPD_MAX_MODES) CPD_FAIL(CPD_EINVAL, "nmodes %d not in [2, %d]", nm, CPD_MAX_MODES);
+    // the build kernels are instantiated for 2..5 levels (key packing, first
+    // differing level, per-level node counts in 16-bit fields of one word)
+    if (nm > CSF_MAX_LEVELS)
+        CPD_FAIL(CPD_EUNSUPPORTED, "CSF trees are built for 2..%d modes, not %d", CSF_MAX_LEVELS, nm);
     if (!dims || !inds || !vals || !out) CPD_FAIL(CPD_EINVAL, "null argument");
     if (nnz < 1 || nnz > INT32_MAX) CPD_FAIL(CPD_EINVAL, "nnz %lld not in [1, 2^31-1]", (long long)nnz);
     for (int m = 0; m < nm; ++m) {

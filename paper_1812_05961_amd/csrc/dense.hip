@@ -378,9 +378,11 @@ __global__ void __launch_bounds__(256) k_lambda(const double *__restrict__ parti
 }
 
 // ------------------------------------------------------------------ fit
-// partial[b][r] = sum over this block's rows of A(i, r) * Y(i, r)
+// partial[b][r] = sum over this block's rows of A(i, r) * Y(i, r) (Y float,
+// or double for the exact fit pass)
+template <typename YT>
 __global__ void __launch_bounds__(256)
-k_fit_partial(const float *__restrict__ A, int64_t lda, const float *__restrict__ Y, int64_t ldy,
+k_fit_partial(const float *__restrict__ A, int64_t lda, const YT *__restrict__ Y, int64_t ldy,
               int64_t rows, int R, double *__restrict__ partial) {
     __shared__ double red[4][64];
     const int r = threadIdx.x & 63, grp = threadIdx.x >> 6;
@@ -518,9 +520,9 @@ cpd_status solve_normalize(const double *const *grams, int nmodes, int mode, con
     return CPD_OK;
 }
 
-cpd_status fit(double normX2, const double *lambda, const float *A, int64_t lda, const float *Y,
-               int64_t ldy, int64_t rows, int R, const double *const *grams, int nmodes, double *out,
-               hipStream_t s) {
+template <typename YT>
+static cpd_status fit_t(double normX2, const double *lambda, const float *A, int64_t lda, const YT *Y, int64_t ldy,
+                        int64_t rows, int R, const double *const *grams, int nmodes, double *out, hipStream_t s) {
     if (!lambda || !A || !Y || !grams || !out) CPD_FAIL(CPD_EINVAL, "null argument");
     if (R < 1 || R > CPD_MAX_RANK || nmodes < 2 || nmodes > CPD_MAX_MODES || lda < R || ldy < R)
         CPD_FAIL(CPD_EINVAL, "bad fit sizes");
@@ -533,12 +535,26 @@ cpd_status fit(double normX2, const double *lambda, const float *A, int64_t lda,
     const int nb = (int)std::min<int64_t>(256, std::max<int64_t>(1, ceil_div(rows, 64)));
     DevBuf<double> part;
     CPD_TRY(part.alloc((size_t)nb * R, s));
-    hipLaunchKernelGGL(k_fit_partial, dim3(nb), dim3(256), 0, s, A, lda, Y, ldy, rows, R, part.p);
+    hipLaunchKernelGGL(k_fit_partial<YT>, dim3(nb), dim3(256), 0, s, A, lda, Y, ldy, rows, R, part.p);
     CPD_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_fit_final, dim3(1), dim3(1024), 0, s, (const double *)part.p, nb, R, lambda, gs, nmodes,
                        normX2, out);
     CPD_LAUNCH_CHECK();
     return CPD_OK;
+}
+
+cpd_status fit(double normX2, const double *lambda, const float *A, int64_t lda, const float *Y,
+               int64_t ldy, int64_t rows, int R, const double *const *grams, int nmodes, double *out,
+               hipStream_t s) {
+    return fit_t<float>(normX2, lambda, A, lda, Y, ldy, rows, R, grams, nmodes, out, s);
+}
+
+// The fit from an FP64 MTTKRP of the last mode: <X, K> then carries FP64
+// rounding only, so the residual keeps its accuracy as the fit nears 1.
+cpd_status fit64(double normX2, const double *lambda, const float *A, int64_t lda, const double *Y,
+                 int64_t ldy, int64_t rows, int R, const double *const *grams, int nmodes, double *out,
+                 hipStream_t s) {
+    return fit_t<double>(normX2, lambda, A, lda, Y, ldy, rows, R, grams, nmodes, out, s);
 }
 
 cpd_status sumsq(const float *v, int64_t n, double *out, hipStream_t s) {

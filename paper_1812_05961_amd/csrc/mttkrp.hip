@@ -66,14 +66,17 @@ __device__ __forceinline__ float load1<uint16_t>(const void *base, int64_t off) 
 // copy_stride: 0, or the element distance between the per-XCD copies of Y
 // (block b then adds into copy b mod XCD_COPIES; any mapping is correct, the
 // device-scope atomics only contend less when a copy stays on one XCD).
-template <int N, int G, typename GT, bool PRIV, bool HOT, int CPL>
+// AT: accumulator and output type (double: FP64 products and sums for the
+// exact fit pass, without LDS copies).
+template <int N, int G, typename GT, bool PRIV, bool HOT, int CPL, typename AT = float>
 __global__ void __launch_bounds__(256)
 k_mttkrp_lane(CsfView cv, FacView fv, int64_t ld, int d, const int32_t *__restrict__ starts,
-              int64_t nstreams, int32_t T, float *__restrict__ Y, int64_t ldo, int R,
+              int64_t nstreams, int32_t T, AT *__restrict__ Y, int64_t ldo, int R,
               int64_t out_rows, int32_t hot, int64_t copy_stride) {
     extern __shared__ float ypriv[];  // PRIV: out_rows x R; HOT: hot x R
     constexpr int NG = 256 / G;       // groups per block
     constexpr bool LOCAL = PRIV || HOT;
+    static_assert(std::is_same<AT, float>::value || !LOCAL, "LDS copies accumulate in float");
     const int lig = threadIdx.x % G;
     Y += (int64_t)(blockIdx.x % XCD_COPIES) * copy_stride;
     bool col[CPL];
@@ -89,14 +92,19 @@ k_mttkrp_lane(CsfView cv, FacView fv, int64_t ld, int d, const int32_t *__restri
     const int64_t g0 = (int64_t)blockIdx.x * NG + threadIdx.x / G;
     const int64_t gstep = LOCAL ? (int64_t)gridDim.x * NG : nstreams + 1;
     // add acc to output row `row` (column lig + G*q)
-    auto add_row = [&](int32_t row, const float (&acc)[CPL]) {
+    auto add_row = [&](int32_t row, const AT (&acc)[CPL]) {
 #pragma unroll
         for (int q = 0; q < CPL; ++q) {
             if (!col[q]) continue;
             const int cq = lig + G * q;
-            if (PRIV) atomicAdd(&ypriv[(int64_t)row * R + cq], acc[q]);
-            else if (HOT && cv.hot_rank[row] < hot) atomicAdd(&ypriv[(int64_t)cv.hot_rank[row] * R + cq], acc[q]);
-            else atomicAdd(Y + (int64_t)row * ldo + cq, acc[q]);
+            if constexpr (LOCAL) {
+                if (PRIV) atomicAdd(&ypriv[(int64_t)row * R + cq], acc[q]);
+                else if (HOT && cv.hot_rank[row] < hot)
+                    atomicAdd(&ypriv[(int64_t)cv.hot_rank[row] * R + cq], acc[q]);
+                else atomicAdd(Y + (int64_t)row * ldo + cq, acc[q]);
+            } else {
+                atomicAdd(Y + (int64_t)row * ldo + cq, acc[q]);
+            }
         }
     };
     for (int64_t sid = g0; sid < nstreams; sid += gstep) {
@@ -108,22 +116,22 @@ k_mttkrp_lane(CsfView cv, FacView fv, int64_t ld, int d, const int32_t *__restri
             c[l] = starts[(int64_t)l * nstreams + sid];
             e[l] = cv.fptr[l][c[l] + 1];
         }
-        float H[CPL];
+        AT H[CPL];
         auto make_H = [&]() {
 #pragma unroll
-            for (int q = 0; q < CPL; ++q) H[q] = 1.0f;
+            for (int q = 0; q < CPL; ++q) H[q] = 1;
 #pragma unroll
             for (int l = 0; l < N - 1; ++l) {
                 if (l == d) continue;
                 const int64_t base = (int64_t)cv.fids[l][c[l]] * ld + lig;
 #pragma unroll
-                for (int q = 0; q < CPL; ++q) H[q] *= col[q] ? load1<GT>(fv.a[l], base + G * q) : 0.0f;
+                for (int q = 0; q < CPL; ++q) H[q] *= col[q] ? (AT)load1<GT>(fv.a[l], base + G * q) : (AT)0;
             }
         };
         make_H();
-        float acc[CPL];
+        AT acc[CPL];
 #pragma unroll
-        for (int q = 0; q < CPL; ++q) acc[q] = 0.0f;
+        for (int q = 0; q < CPL; ++q) acc[q] = 0;
         int32_t out_row = d < N - 1 ? cv.fids[d][c[d]] : 0;
         // without the hot-row table the next leaf's value and index are loaded
         // a leaf ahead (6-14% faster at level 1 on the three benchmark shapes;
@@ -162,7 +170,7 @@ k_mttkrp_lane(CsfView cv, FacView fv, int64_t ld, int d, const int32_t *__restri
                 if (d < N - 1 && lmin <= d) {
                     add_row(out_row, acc);
 #pragma unroll
-                    for (int q = 0; q < CPL; ++q) acc[q] = 0.0f;
+                    for (int q = 0; q < CPL; ++q) acc[q] = 0;
                     out_row = cv.fids[d][c[d]];
                 }
                 make_H();
@@ -172,10 +180,10 @@ k_mttkrp_lane(CsfView cv, FacView fv, int64_t ld, int d, const int32_t *__restri
                 i = cv.fids[N - 1][k];
             }
             if (d == N - 1) {
-                float t[CPL];
+                AT t[CPL];
 #pragma unroll
-                for (int q = 0; q < CPL; ++q) t[q] = v * H[q];
-                if (HOT) {
+                for (int q = 0; q < CPL; ++q) t[q] = (AT)v * H[q];
+                if constexpr (HOT) {
                     const int32_t rk = cv.leafw[k] & ((1 << 29) - 1);
 #pragma unroll
                     for (int q = 0; q < CPL; ++q) {
@@ -189,7 +197,7 @@ k_mttkrp_lane(CsfView cv, FacView fv, int64_t ld, int d, const int32_t *__restri
                     for (int q = 0; q < CPL; ++q) {
                         if (!col[q]) continue;
                         const int cq = lig + G * q;
-                        if (PRIV) atomicAdd(&ypriv[(int64_t)i * R + cq], t[q]);
+                        if constexpr (PRIV) atomicAdd(&ypriv[(int64_t)i * R + cq], t[q]);
                         else atomicAdd(Y + (int64_t)i * ldo + cq, t[q]);
                     }
                 }
@@ -198,13 +206,14 @@ k_mttkrp_lane(CsfView cv, FacView fv, int64_t ld, int d, const int32_t *__restri
 #pragma unroll
                 for (int q = 0; q < CPL; ++q) {
                     const float a = col[q] ? load1<GT>(fv.a[N - 1], base + G * q) : 0.0f;
-                    acc[q] = fmaf(v * a, H[q], acc[q]);
+                    if constexpr (std::is_same<AT, float>::value) acc[q] = fmaf(v * a, H[q], acc[q]);
+                    else acc[q] = fma((double)v * (double)a, H[q], acc[q]);
                 }
             }
         }
         if (d < N - 1) add_row(out_row, acc);
     }
-    if (LOCAL) {
+    if constexpr (LOCAL) {
         __syncthreads();
         for (int64_t j = threadIdx.x; j < nloc; j += 256) {
             float v = ypriv[j];
@@ -224,10 +233,11 @@ k_sum_copies(const float *__restrict__ cp, int P, int64_t rows, int R, float *__
     Y[(j / R) * ldo + (j % R)] = v;
 }
 
-__global__ void k_zero_rows(float *Y, int64_t rows, int64_t ldo, int R) {
+template <typename AT>
+__global__ void k_zero_rows(AT *Y, int64_t rows, int64_t ldo, int R) {
     int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= rows * R) return;
-    Y[(j / R) * ldo + (j % R)] = 0.0f;
+    Y[(j / R) * ldo + (j % R)] = 0;
 }
 
 // ------------------------------------------------------------ dispatch
@@ -286,10 +296,48 @@ cpd_status launch_root(int N, bool bf16, int RP, int d, const int32_t *const *fi
                        const float *vals, const int32_t *leafw, const int32_t *leaf_perm, const int32_t *const *uprow,
                        const int64_t *counts, const int64_t *dims_by_level, const void *const *fac_by_level,
                        int64_t ld, const int32_t *starts, int64_t ntiles, int32_t T, float *Y, int64_t ldo, int R,
-                       hipStream_t s);
+                       void *perm_buf, hipStream_t s);
+cpd_status launch_root64(int N, int RP, const int32_t *const *fids, const int32_t *const *fptr, const float *vals,
+                         const int32_t *leafw, const int32_t *leaf_perm, const int32_t *const *uprow,
+                         const int64_t *counts, const int64_t *dims_by_level, const void *const *fac_by_level,
+                         int64_t ld, const int32_t *starts, int64_t ntiles, int32_t T, double *Y, int64_t ldo, int R,
+                         hipStream_t s);
 
 // Lanes the root kernel gives one leaf for a padded rank RP.
 int root_lanes_per_leaf(int RP, bool bf16);
+
+// Kernel family for a request (host-only rule, also exported as
+// cpd_mttkrp_plan).  The ROW kernels are instantiated for 3..5 modes and
+// non-leaf output levels; they load 16-byte row chunks, so the padded row must
+// fit in ld and rows must be 16-byte multiples; they address a gathered row
+// as a 32-bit byte offset formed by a 24-bit multiply (row id times row
+// bytes), so every gathered level needs row ids below 2^24 and
+// rows * row bytes <= 2^32; they read the tree's leaf words.
+cpd_status mttkrp_plan(int N, const int64_t *dims_by_level, int d, int64_t ld, int R, bool bf16, int request,
+                       bool rows_aligned, bool leaf_words, int *kernel) {
+    if (N < 2 || N > 5) CPD_FAIL(CPD_EUNSUPPORTED, "MTTKRP kernels are built for 2..5 modes, not %d", N);
+    if (d < 0 || d >= N) CPD_FAIL(CPD_EINVAL, "depth %d not in [0, %d)", d, N);
+    if (R < 1 || R > CPD_MAX_RANK) CPD_FAIL(CPD_EINVAL, "rank %d not in [1, %d]", R, CPD_MAX_RANK);
+    if (ld < R) CPD_FAIL(CPD_EINVAL, "ld %lld below rank %d", (long long)ld, R);
+    if (request != CPD_KERNEL_AUTO && request != CPD_KERNEL_ROW && request != CPD_KERNEL_LANE)
+        CPD_FAIL(CPD_EINVAL, "unknown kernel %d", request);
+    const int RP = row_width(R, bf16);
+    const int64_t rowb = ld * (bf16 ? 2 : 4);
+    bool row_ok = N >= 3 && d < N - 1 && ld >= RP && rowb % 16 == 0 && rowb < (1 << 24) && rows_aligned &&
+                  leaf_words;
+    for (int l = 0; l < N && row_ok; ++l) {
+        if (l == d) continue;
+        const int64_t rows = dims_by_level[l];
+        if (rows >= (1 << 24) || rows * rowb > (int64_t(1) << 32)) row_ok = false;
+    }
+    if (request == CPD_KERNEL_ROW && !row_ok)
+        CPD_FAIL(CPD_EUNSUPPORTED,
+                 "row kernel needs 3..5 modes, a non-leaf mode, ld >= %d, 16-byte rows, row ids below 2^24 and "
+                 "rows * row bytes <= 2^32 at every gathered level",
+                 RP);
+    *kernel = request == CPD_KERNEL_AUTO ? ((row_ok && d == 0) ? CPD_KERNEL_ROW : CPD_KERNEL_LANE) : request;
+    return CPD_OK;
+}
 
 // Internal entry (also used by the ALS driver).
 cpd_status mttkrp(cpd_csf_s *c, const void *const *factors, int32_t ld, int32_t R, int32_t mode,
@@ -321,24 +369,19 @@ cpd_status mttkrp(cpd_csf_s *c, const void *const *factors, int32_t ld, int32_t 
     cv.leafw = c->leafw;
     const int64_t out_rows = c->dims[mode];
 
-    // ROW family eligibility: vector loads need the padded row inside ld and
-    // 16-byte aligned rows.
     const int RP = row_width(R, bf16);
-    bool row_ok = d < N - 1 && ld >= RP && (ld * (bf16 ? 2 : 4)) % 16 == 0 && c->leafw;
-    // the lane-group kernels address rows with 24-bit products: row ids below 2^24
-    for (int l = 0; l < N && row_ok; ++l)
-        if (l != d && c->dims[c->order[l]] >= (1 << 24)) row_ok = false;
-    for (int l = 0; l < N && row_ok; ++l)
-        if (c->order[l] != mode && (reinterpret_cast<uintptr_t>(factors[c->order[l]]) & 15)) row_ok = false;
-    int kernel = o.kernel;
-    if (kernel == CPD_KERNEL_AUTO) kernel = (row_ok && d == 0) ? CPD_KERNEL_ROW : CPD_KERNEL_LANE;
-    if (kernel == CPD_KERNEL_ROW && !row_ok)
-        CPD_FAIL(CPD_EUNSUPPORTED, "row kernel needs a non-leaf mode, ld >= %d, 16-byte rows", RP);
+    int64_t dims_by_level[CPD_MAX_MODES];
+    for (int l = 0; l < N; ++l) dims_by_level[l] = c->dims[c->order[l]];
+    bool aligned = true;
+    for (int l = 0; l < N; ++l)
+        if (c->order[l] != mode && (reinterpret_cast<uintptr_t>(factors[c->order[l]]) & 15)) aligned = false;
+    int kernel = CPD_KERNEL_LANE;
+    CPD_TRY(mttkrp_plan(N, dims_by_level, d, ld, R, bf16, o.kernel, aligned, c->leafw != nullptr, &kernel));
 
     // zero the output (columns < R)
     {
         int64_t tot = out_rows * R;
-        hipLaunchKernelGGL(k_zero_rows, dim3((unsigned)ceil_div(tot, 256)), dim3(256), 0, s, Y, out_rows,
+        hipLaunchKernelGGL(k_zero_rows<float>, dim3((unsigned)ceil_div(tot, 256)), dim3(256), 0, s, Y, out_rows,
                            (int64_t)ldo, R);
         CPD_LAUNCH_CHECK();
     }
@@ -358,10 +401,8 @@ cpd_status mttkrp(cpd_csf_s *c, const void *const *factors, int32_t ld, int32_t 
         const void *fac_by_level[CPD_MAX_MODES];
         for (int l = 0; l < N; ++l) fac_by_level[l] = fv.a[l];
         if (ev0) CPD_HIP(hipEventRecord(ev0, s));
-        int64_t dims_by_level[CPD_MAX_MODES];
-        for (int l = 0; l < N; ++l) dims_by_level[l] = c->dims[c->order[l]];
         cpd_status st = launch_root(N, bf16, RP, d, cv.fids, cv.fptr, cv.vals, c->leafw, c->leaf_perm, c->uprow,
-                                    c->counts, dims_by_level, fac_by_level, ld, starts, ns, T, Y, ldo, R, s);
+                                    c->counts, dims_by_level, fac_by_level, ld, starts, ns, T, Y, ldo, R, nullptr, s);
         if (st == CPD_OK && ev1) CPD_HIP(hipEventRecord(ev1, s));
         return st;
     }
@@ -414,7 +455,7 @@ cpd_status mttkrp(cpd_csf_s *c, const void *const *factors, int32_t ld, int32_t 
         copy_stride = out_rows * R;
         CPD_TRY(copies.alloc((size_t)XCD_COPIES * copy_stride, s));
         const int64_t tot = XCD_COPIES * copy_stride;
-        hipLaunchKernelGGL(k_zero_rows, dim3((unsigned)ceil_div(tot, 256)), dim3(256), 0, s, copies.p,
+        hipLaunchKernelGGL(k_zero_rows<float>, dim3((unsigned)ceil_div(tot, 256)), dim3(256), 0, s, copies.p,
                            (int64_t)XCD_COPIES * out_rows, (int64_t)R, R);
         CPD_LAUNCH_CHECK();
         Yk = copies.p;
@@ -445,7 +486,101 @@ cpd_status mttkrp(cpd_csf_s *c, const void *const *factors, int32_t ld, int32_t 
     return st;
 }
 
+// MTTKRP with float rows and FP64 products and sums into a double output (the
+// exact fit pass of the ALS driver): the root kernel when the mode is the
+// tree's root and the ROW rule allows it, else the LANE kernel with FP64
+// atomics.  Y: dims[mode] x ldo doubles, columns < R overwritten.
+cpd_status mttkrp64(cpd_csf_s *c, const float *const *factors, int32_t ld, int32_t R, int32_t mode, double *Y,
+                    int32_t ldo, hipStream_t s) {
+    if (!c || !factors || !Y) CPD_FAIL(CPD_EINVAL, "null argument");
+    const int N = c->nmodes;
+    if (R < 1 || R > CPD_MAX_RANK || mode < 0 || mode >= N || ld < R || ldo < R)
+        CPD_FAIL(CPD_EINVAL, "bad FP64 MTTKRP arguments");
+    const int d = c->depth_of(mode);
+    CsfView cv{};
+    FacView fv{};
+    int64_t dims_by_level[CPD_MAX_MODES];
+    bool aligned = true;
+    for (int l = 0; l < N; ++l) {
+        cv.fids[l] = c->fids[l];
+        cv.fptr[l] = c->fptr[l];
+        const int m = c->order[l];
+        fv.a[l] = factors[m];
+        dims_by_level[l] = c->dims[m];
+        if (m != mode && !factors[m]) CPD_FAIL(CPD_EINVAL, "null factor for mode %d", m);
+        if (m != mode && (reinterpret_cast<uintptr_t>(factors[m]) & 15)) aligned = false;
+    }
+    cv.vals = c->vals;
+    cv.nleaves = c->counts[N - 1];
+    cv.leafw = c->leafw;
+    const int64_t out_rows = c->dims[mode];
+    int kernel = CPD_KERNEL_LANE;
+    CPD_TRY(mttkrp_plan(N, dims_by_level, d, ld, R, false, CPD_KERNEL_AUTO, aligned, c->leafw != nullptr, &kernel));
+    {
+        const int64_t tot = out_rows * R;
+        hipLaunchKernelGGL(k_zero_rows<double>, dim3((unsigned)ceil_div(tot, 256)), dim3(256), 0, s, Y, out_rows,
+                           (int64_t)ldo, R);
+        CPD_LAUNCH_CHECK();
+    }
+    if (kernel == CPD_KERNEL_ROW) {
+        const int RP = row_width(R, false);
+        const int64_t groups = 64 / root_lanes_per_leaf(RP, false), waves = 256 * 16;
+        int32_t T = 128;
+        while (T > 32 && cv.nleaves < groups * T * 2 * waves) T /= 2;
+        const int32_t *starts;
+        int64_t ns;
+        CPD_TRY(csf_tiles(c, T, &starts, &ns, s));
+        const void *fac_by_level[CPD_MAX_MODES];
+        for (int l = 0; l < N; ++l) fac_by_level[l] = fv.a[l];
+        return launch_root64(N, RP, cv.fids, cv.fptr, cv.vals, c->leafw, c->leaf_perm, c->uprow, c->counts,
+                             dims_by_level, fac_by_level, ld, starts, ns, T, Y, ldo, R, s);
+    }
+    int G = R <= 8 ? 8 : R <= 16 ? 16 : R <= 32 ? 32 : 64;
+    const int32_t T = 256;
+    const int32_t *starts;
+    int64_t ns;
+    CPD_TRY(csf_tiles(c, T, &starts, &ns, s));
+    if (G == 64 && d < N - 1) G = -64;
+    const int NG = 256 / (G == -64 ? 32 : G);
+    const dim3 grid((unsigned)ceil_div(ns, NG));
+#define CPD_LANE64(n, g, cpl)                                                                                  \
+    hipLaunchKernelGGL((k_mttkrp_lane<n, g, float, false, false, cpl, double>), grid, dim3(256), 0, s, cv, fv, \
+                       (int64_t)ld, d, starts, ns, T, Y, (int64_t)ldo, R, out_rows, 0, (int64_t)0)
+#define CPD_LANE64_G(n)                          \
+    switch (G) {                                 \
+        case 8: CPD_LANE64(n, 8, 1); break;      \
+        case 16: CPD_LANE64(n, 16, 1); break;    \
+        case 32: CPD_LANE64(n, 32, 1); break;    \
+        case 64: CPD_LANE64(n, 64, 1); break;    \
+        default: CPD_LANE64(n, 32, 2); break;    \
+    }
+    switch (N) {
+        case 2: CPD_LANE64_G(2) break;
+        case 3: CPD_LANE64_G(3) break;
+        case 4: CPD_LANE64_G(4) break;
+        case 5: CPD_LANE64_G(5) break;
+        default: CPD_FAIL(CPD_EUNSUPPORTED, "MTTKRP kernels are built for 2..5 modes, not %d", N);
+    }
+#undef CPD_LANE64_G
+#undef CPD_LANE64
+    CPD_LAUNCH_CHECK();
+    return CPD_OK;
+}
+
 }  // namespace cpd
+
+extern "C" cpd_status cpd_mttkrp_plan(int32_t nmodes, const int64_t *dims_by_level, int32_t depth, int32_t ld,
+                                      int32_t rank, int32_t precision, int32_t kernel, int32_t rows_aligned,
+                                      int32_t leaf_words, int32_t *kernel_out) {
+    cpd::clear_error();
+    if (!dims_by_level || !kernel_out) CPD_FAIL(CPD_EINVAL, "null argument");
+    if (precision != CPD_FP32 && precision != CPD_BF16_GATHER) CPD_FAIL(CPD_EINVAL, "unknown precision %d", precision);
+    if (nmodes >= 2 && nmodes <= CPD_MAX_MODES)
+        for (int l = 0; l < nmodes; ++l)
+            if (dims_by_level[l] < 1) CPD_FAIL(CPD_EINVAL, "length %lld at level %d", (long long)dims_by_level[l], l);
+    return cpd::mttkrp_plan(nmodes, dims_by_level, depth, ld, rank, precision == CPD_BF16_GATHER, kernel,
+                            rows_aligned != 0, leaf_words != 0, kernel_out);
+}
 
 extern "C" cpd_status cpd_mttkrp(cpd_csf csf, const void *const *factors, int32_t ld, int32_t rank,
                                  int32_t mode, float *out, int32_t ldo, const cpd_mttkrp_opts *opts,

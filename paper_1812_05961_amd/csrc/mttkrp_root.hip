@@ -132,13 +132,33 @@ constexpr int root_min_waves() {
     return !std::is_same<GT, uint16_t>::value ? 1 : N == 3 ? 6 : N == 4 ? 5 : 1;
 }
 
+// One leaf's contribution x * A_leaf(j, c) * H(c) for element e of a lane's
+// chunk, added to the accumulator: FP32 products and sums, or (AT = double,
+// float rows only) FP64 products and sums.
+template <typename GT, int NU, typename AT, typename raw_t>
+__device__ __forceinline__ void leaf_fma(AT &acc, float v, const raw_t *row, const raw_t (*H)[Chunk<GT>::RAW],
+                                         int e) {
+    if constexpr (std::is_same<AT, float>::value) {
+        float h = Chunk<GT>::get(H[0], e);
+#pragma unroll
+        for (int l = 1; l < NU; ++l) h *= Chunk<GT>::get(H[l], e);
+        acc = fmaf(v * Chunk<GT>::get(row, e), h, acc);
+    } else {
+        double h = (double)Chunk<GT>::get(H[0], e);
+#pragma unroll
+        for (int l = 1; l < NU; ++l) h *= (double)Chunk<GT>::get(H[l], e);
+        acc = fma((double)v * (double)Chunk<GT>::get(row, e), h, acc);
+    }
+}
+
 // a_leaf: the leaf factor with rows in rank order (row r = factor row
 // leaf_perm[r]), so the most used rows share cache lines and pages.
-template <int N, int G, typename GT>
+// AT: the accumulator and output type (float; double for the exact fit pass).
+template <int N, int G, typename GT, typename AT>
 __global__ void __launch_bounds__(64 * ROOT_WAVES, (root_min_waves<N, GT>()))
 k_mttkrp_root(CsfView cv, FacView fv, const char *__restrict__ a_leaf, uint32_t rowb,
               const int32_t *__restrict__ starts, int64_t ntiles, int32_t T, int64_t nsteps, int64_t nwaves,
-              float *__restrict__ Y, int64_t ldo, int R) {
+              AT *__restrict__ Y, int64_t ldo, int R) {
     constexpr int NG = 64 / G;  // groups per wave
     constexpr int C = root_chunk<NG>(), U = root_unroll<N, GT>();
     static_assert(C % U == 0 && ROOT_C % C == 0, "staging chunk must hold whole blocks");
@@ -170,9 +190,9 @@ k_mttkrp_root(CsfView cv, FacView fv, const char *__restrict__ a_leaf, uint32_t 
 #pragma unroll
     for (int l = 0; l < NU; ++l) a_up[l] = static_cast<const char *>(fv.a[l + 1]);
 
-    float acc[E];
+    AT acc[E];
 #pragma unroll
-    for (int e = 0; e < E; ++e) acc[e] = 0.0f;
+    for (int e = 0; e < E; ++e) acc[e] = 0;
     int32_t carry_row = -1;  // row carried into group 0 of the next tile step
 
     for (int64_t st = s_begin; st < s_end; ++st) {
@@ -197,7 +217,7 @@ k_mttkrp_root(CsfView cv, FacView fv, const char *__restrict__ a_leaf, uint32_t 
         bool is_first = true;
         if (g != 0 || carry_row < 0) {
 #pragma unroll
-            for (int e = 0; e < E; ++e) acc[e] = 0.0f;
+            for (int e = 0; e < E; ++e) acc[e] = 0;
         }
         // internal rows of the previous leaf (reused while the ids repeat)
         int32_t last_up[NU];
@@ -247,7 +267,7 @@ k_mttkrp_root(CsfView cv, FacView fv, const char *__restrict__ a_leaf, uint32_t 
                     const int jr = j0 + u;  // position in the chunk
                     if (jr < len) {
                         if (((uint32_t)wu[u] >> 29) == 0 && (t0 | jr) != 0) {  // a new root row starts here
-                            float *y = Y + (int64_t)cur_row * ldo;
+                            AT *y = Y + (int64_t)cur_row * ldo;
                             if (is_first && !first_here) {
                                 // began in an earlier run: add this part now, the
                                 // earlier groups' part after the scan
@@ -261,7 +281,7 @@ k_mttkrp_root(CsfView cv, FacView fv, const char *__restrict__ a_leaf, uint32_t 
                                     if (col_of(e) < R) y[col_of(e)] = acc[e];
                             }
 #pragma unroll
-                            for (int e = 0; e < E; ++e) acc[e] = 0.0f;
+                            for (int e = 0; e < E; ++e) acc[e] = 0;
                             is_first = false;
                             c0 += 1;
                             cur_row = root_ids[c0];
@@ -273,12 +293,7 @@ k_mttkrp_root(CsfView cv, FacView fv, const char *__restrict__ a_leaf, uint32_t 
                                 for (int q = 0; q < RW; ++q) Hl[l][q] = hu[u][l][q];
                             }
 #pragma unroll
-                        for (int e = 0; e < E; ++e) {
-                            float h = Chunk<GT>::get(Hl[0], e);
-#pragma unroll
-                            for (int l = 1; l < NU; ++l) h *= Chunk<GT>::get(Hl[l], e);
-                            acc[e] = fmaf(vu[u] * Chunk<GT>::get(rowu[u], e), h, acc[e]);
-                        }
+                        for (int e = 0; e < E; ++e) leaf_fma<GT, NU>(acc[e], vu[u], rowu[u], Hl, e);
                     }
                 }
             }
@@ -290,12 +305,12 @@ k_mttkrp_root(CsfView cv, FacView fv, const char *__restrict__ a_leaf, uint32_t 
         const bool open_in_range = is_first ? first_in_range : true;
         const int32_t key = active ? cur_row : INT32_MAX;
         if (active && closes_at_end && open_here) {
-            float *y = Y + (int64_t)cur_row * ldo;
+            AT *y = Y + (int64_t)cur_row * ldo;
 #pragma unroll
             for (int e = 0; e < E; ++e)
                 if (col_of(e) < R) y[col_of(e)] = acc[e];
 #pragma unroll
-            for (int e = 0; e < E; ++e) acc[e] = 0.0f;
+            for (int e = 0; e < E; ++e) acc[e] = 0;
         }
         // segment heads: first group of each run of equal keys (rows are sorted)
         const int32_t key_prev = __shfl_up(key, G, 64);
@@ -315,7 +330,7 @@ k_mttkrp_root(CsfView cv, FacView fv, const char *__restrict__ a_leaf, uint32_t 
             const bool take = g >= o && ko == key;
 #pragma unroll
             for (int e = 0; e < E; ++e) {
-                const float x = __shfl_up(acc[e], o * G, 64);
+                const AT x = __shfl_up(acc[e], o * G, 64);
                 if (take) acc[e] += x;
             }
         }
@@ -324,12 +339,12 @@ k_mttkrp_root(CsfView cv, FacView fv, const char *__restrict__ a_leaf, uint32_t 
         const bool add_prev = active && head_closed && g > 0;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-            const float x = __shfl_up(acc[e], G, 64);
+            const AT x = __shfl_up(acc[e], G, 64);
             if (add_prev && col_of(e) < R) atomicAdd(Y + (int64_t)key_prev * ldo + col_of(e), x);
         }
         // open row closing exactly at the end of this run (not exclusive)
         if (active && closes_at_end && !open_here) {
-            float *y = Y + (int64_t)cur_row * ldo;
+            AT *y = Y + (int64_t)cur_row * ldo;
             if (seg_in_range) {
 #pragma unroll
                 for (int e = 0; e < E; ++e)
@@ -349,12 +364,12 @@ k_mttkrp_root(CsfView cv, FacView fv, const char *__restrict__ a_leaf, uint32_t 
         carry_row = last_open ? last_key : -1;
         if (g != 0 || !last_open) {
 #pragma unroll
-            for (int e = 0; e < E; ++e) acc[e] = 0.0f;
+            for (int e = 0; e < E; ++e) acc[e] = 0;
         }
     }
     // the row still open at the end of the range continues in the next wave
     if (g == 0 && carry_row >= 0) {
-        float *y = Y + (int64_t)carry_row * ldo;
+        AT *y = Y + (int64_t)carry_row * ldo;
 #pragma unroll
         for (int e = 0; e < E; ++e)
             if (col_of(e) < R) atomicAdd(y + col_of(e), acc[e]);
@@ -549,13 +564,17 @@ static cpd_status launch_mid_g(const CsfView &cv, const FacView &fv, const char 
     return CPD_OK;
 }
 
-template <int N, int G, typename GT>
+template <int N, int G, typename GT, typename AT>
 static cpd_status launch_root_g(const CsfView &cv, const FacView &fv, const char *a_leaf, uint32_t rowb, int d,
-                                const int32_t *starts, int64_t ntiles, int32_t T, float *Y, int64_t ldo, int R,
+                                const int32_t *starts, int64_t ntiles, int32_t T, AT *Y, int64_t ldo, int R,
                                 hipStream_t s) {
-    if (d > 0) return launch_mid_g<N, G, GT>(cv, fv, a_leaf, rowb, d, starts, T, Y, ldo, R, s);
+    if constexpr (std::is_same<AT, float>::value) {
+        if (d > 0) return launch_mid_g<N, G, GT>(cv, fv, a_leaf, rowb, d, starts, T, Y, ldo, R, s);
+    } else {
+        if (d > 0) CPD_FAIL(CPD_EUNSUPPORTED, "FP64 accumulation at the root level only");
+    }
     constexpr int NG = 64 / G;
-    auto kern = k_mttkrp_root<N, G, GT>;
+    auto kern = k_mttkrp_root<N, G, GT, AT>;
     const int64_t nsteps = ceil_div(cv.nleaves, NG * (int64_t)T);
     int dev = 0, ncu = 256;
     if (hipGetDevice(&dev) == hipSuccess) {
@@ -575,15 +594,15 @@ static cpd_status launch_root_g(const CsfView &cv, const FacView &fv, const char
     return CPD_OK;
 }
 
-template <int N, typename GT>
+template <int N, typename GT, typename AT>
 static cpd_status launch_root_n(int RP, const CsfView &cv, const FacView &fv, const char *a_leaf, int64_t ld, int d,
-                                const int32_t *starts, int64_t ntiles, int32_t T, float *Y, int64_t ldo, int R,
+                                const int32_t *starts, int64_t ntiles, int32_t T, AT *Y, int64_t ldo, int R,
                                 hipStream_t s) {
     constexpr int W = Chunk<GT>::W;
     const uint32_t rowb = (uint32_t)(ld * (int64_t)Chunk<GT>::ELEM);
     switch (RP / W) {
 #define CPD_ROOT_G(g) \
-    case g: return launch_root_g<N, g, GT>(cv, fv, a_leaf, rowb, d, starts, ntiles, T, Y, ldo, R, s);
+    case g: return launch_root_g<N, g, GT, AT>(cv, fv, a_leaf, rowb, d, starts, ntiles, T, Y, ldo, R, s);
         CPD_ROOT_G(2)
         CPD_ROOT_G(4)
         CPD_ROOT_G(5)
@@ -600,15 +619,25 @@ int root_lanes_per_leaf(int RP, bool bf16) {
     return RP <= BF16_NARROW_MAX ? RP / Chunk<bf16x4>::W : RP / Chunk<uint16_t>::W;
 }
 
-cpd_status launch_root(int N, bool bf16, int RP, int d, const int32_t *const *fids, const int32_t *const *fptr,
-                       const float *vals, const int32_t *leafw, const int32_t *leaf_perm, const int32_t *const *uprow,
-                       const int64_t *counts, const int64_t *dims_by_level, const void *const *fac_by_level,
-                       int64_t ld, const int32_t *starts, int64_t ntiles, int32_t T, float *Y, int64_t ldo, int R,
-                       hipStream_t s) {
+// Shared body of the float and double launches.  perm_buf: device scratch of
+// at least leaf rows * row bytes for the leaf factor in rank order, or null
+// to take it from the stream's scratch cache.
+template <typename AT>
+static cpd_status launch_root_t(int N, bool bf16, int RP, int d, const int32_t *const *fids,
+                                const int32_t *const *fptr, const float *vals, const int32_t *leafw,
+                                const int32_t *leaf_perm, const int32_t *const *uprow, const int64_t *counts,
+                                const int64_t *dims_by_level, const void *const *fac_by_level, int64_t ld,
+                                const int32_t *starts, int64_t ntiles, int32_t T, AT *Y, int64_t ldo, int R,
+                                void *perm_buf, hipStream_t s) {
     if (d < 0 || d > N - 2) CPD_FAIL(CPD_EINVAL, "lane-group kernel for depth %d of %d levels", d, N);
     if (!leafw || !leaf_perm) CPD_FAIL(CPD_EUNSUPPORTED, "root kernel needs leaf ids below 2^29");
     const int64_t rowb = ld * (bf16 ? 2 : 4);
     if (rowb >= (1 << 24) || rowb % 16) CPD_FAIL(CPD_EUNSUPPORTED, "root kernel needs 16-byte rows below 16 MiB");
+    // gathered rows are addressed as 32-bit byte offsets (24-bit row id times row bytes)
+    for (int l = 0; l < N; ++l)
+        if (l != d && (dims_by_level[l] >= (1 << 24) || dims_by_level[l] * rowb > (int64_t(1) << 32)))
+            CPD_FAIL(CPD_EUNSUPPORTED, "level %d: %lld rows of %lld bytes exceed 32-bit row offsets", l,
+                     (long long)dims_by_level[l], (long long)rowb);
     if (T < ROOT_C || T % ROOT_C)
         CPD_FAIL(CPD_EINVAL, "root kernel tile width %d must be a multiple of %d", T, ROOT_C);
     CsfView cv{};
@@ -628,30 +657,63 @@ cpd_status launch_root(int N, bool bf16, int RP, int d, const int32_t *const *fi
     // the leaf factor in rank order (hot rows first)
     const int64_t leaf_rows = dims_by_level[N - 1];
     DevBuf<uint4> perm;
-    CPD_TRY(perm.alloc((size_t)leaf_rows * (rowb / 16), s));
+    uint4 *pb = static_cast<uint4 *>(perm_buf);
+    if (!pb) {
+        CPD_TRY(perm.alloc((size_t)leaf_rows * (rowb / 16), s));
+        pb = perm.p;
+    }
     {
         const int chunks = (int)(rowb / 16);
         const int64_t tot = leaf_rows * chunks;
         hipLaunchKernelGGL(k_permute_rows, dim3((unsigned)ceil_div(tot, 256)), dim3(256), 0, s,
-                           static_cast<const uint4 *>(fac_by_level[N - 1]), leaf_perm, leaf_rows, chunks, perm.p);
+                           static_cast<const uint4 *>(fac_by_level[N - 1]), leaf_perm, leaf_rows, chunks, pb);
         CPD_LAUNCH_CHECK();
     }
-    const char *a_leaf = reinterpret_cast<const char *>(perm.p);
-    // bfloat16 rows: 8-byte chunks (the float layout at half the bytes) up to
-    // a padded rank of BF16_NARROW_MAX, 16-byte chunks above
-    const bool narrow = bf16 && RP <= BF16_NARROW_MAX;
-#define CPD_ROOT_N(n)                                                                                      \
-    case n:                                                                                                \
+    const char *a_leaf = reinterpret_cast<const char *>(pb);
+    if constexpr (std::is_same<AT, double>::value) {
+        if (bf16) CPD_FAIL(CPD_EUNSUPPORTED, "FP64 accumulation takes float rows");
+        switch (N) {
+            case 3: return launch_root_n<3, float>(RP, cv, fv, a_leaf, ld, d, starts, ntiles, T, Y, ldo, R, s);
+            case 4: return launch_root_n<4, float>(RP, cv, fv, a_leaf, ld, d, starts, ntiles, T, Y, ldo, R, s);
+            case 5: return launch_root_n<5, float>(RP, cv, fv, a_leaf, ld, d, starts, ntiles, T, Y, ldo, R, s);
+            default: CPD_FAIL(CPD_EUNSUPPORTED, "root kernel built for 3..5 modes, not %d", N);
+        }
+    } else {
+        // bfloat16 rows: 8-byte chunks (the float layout at half the bytes) up to
+        // a padded rank of BF16_NARROW_MAX, 16-byte chunks above
+        const bool narrow = bf16 && RP <= BF16_NARROW_MAX;
+#define CPD_ROOT_N(n)                                                                                           \
+    case n:                                                                                                     \
         if (narrow) return launch_root_n<n, bf16x4>(RP, cv, fv, a_leaf, ld, d, starts, ntiles, T, Y, ldo, R, s); \
-        return bf16 ? launch_root_n<n, uint16_t>(RP, cv, fv, a_leaf, ld, d, starts, ntiles, T, Y, ldo, R, s)   \
+        return bf16 ? launch_root_n<n, uint16_t>(RP, cv, fv, a_leaf, ld, d, starts, ntiles, T, Y, ldo, R, s)    \
                     : launch_root_n<n, float>(RP, cv, fv, a_leaf, ld, d, starts, ntiles, T, Y, ldo, R, s);
-    switch (N) {
-        CPD_ROOT_N(3)
-        CPD_ROOT_N(4)
-        CPD_ROOT_N(5)
-        default: CPD_FAIL(CPD_EUNSUPPORTED, "root kernel built for 3..5 modes, not %d", N);
-    }
+        switch (N) {
+            CPD_ROOT_N(3)
+            CPD_ROOT_N(4)
+            CPD_ROOT_N(5)
+            default: CPD_FAIL(CPD_EUNSUPPORTED, "root kernel built for 3..5 modes, not %d", N);
+        }
 #undef CPD_ROOT_N
+    }
+}
+
+cpd_status launch_root(int N, bool bf16, int RP, int d, const int32_t *const *fids, const int32_t *const *fptr,
+                       const float *vals, const int32_t *leafw, const int32_t *leaf_perm, const int32_t *const *uprow,
+                       const int64_t *counts, const int64_t *dims_by_level, const void *const *fac_by_level,
+                       int64_t ld, const int32_t *starts, int64_t ntiles, int32_t T, float *Y, int64_t ldo, int R,
+                       void *perm_buf, hipStream_t s) {
+    return launch_root_t<float>(N, bf16, RP, d, fids, fptr, vals, leafw, leaf_perm, uprow, counts, dims_by_level,
+                                fac_by_level, ld, starts, ntiles, T, Y, ldo, R, perm_buf, s);
+}
+
+// Root-level MTTKRP with float rows and FP64 products and sums (the exact fit pass).
+cpd_status launch_root64(int N, int RP, const int32_t *const *fids, const int32_t *const *fptr, const float *vals,
+                         const int32_t *leafw, const int32_t *leaf_perm, const int32_t *const *uprow,
+                         const int64_t *counts, const int64_t *dims_by_level, const void *const *fac_by_level,
+                         int64_t ld, const int32_t *starts, int64_t ntiles, int32_t T, double *Y, int64_t ldo, int R,
+                         hipStream_t s) {
+    return launch_root_t<double>(N, false, RP, 0, fids, fptr, vals, leafw, leaf_perm, uprow, counts, dims_by_level,
+                                 fac_by_level, ld, starts, ntiles, T, Y, ldo, R, nullptr, s);
 }
 
 }  // namespace cpd

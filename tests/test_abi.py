@@ -81,3 +81,67 @@ def test_argument_errors_return_einval_without_touching_the_gpu():
                      ctypes.byref(it), None) == cpd.CPD_EINVAL
     assert L.cpd_als(3, dims, 5, ptrs, 1, 65, 5, 0.0, None, f, lam, ctypes.byref(fit),
                      ctypes.byref(it), None) == cpd.CPD_EINVAL
+
+
+def test_csf_build_rejects_six_to_eight_modes_without_touching_the_gpu():
+    """Trees are built for 2..5 modes: 6..8 are refused before any device work
+    (the build kernels are instantiated for at most 5 levels)."""
+    from paper_1812_05961_amd import cpd
+    L = cpd.lib()
+    h = ctypes.c_void_p()
+    for nm in (6, 7, 8):
+        dims = (ctypes.c_int64 * nm)(*([4] * nm))
+        ptrs = (ctypes.c_void_p * nm)(*([1] * nm))
+        assert L.cpd_csf_build(nm, dims, 10, ptrs, 1, None, None, ctypes.byref(h)) == cpd.CPD_EUNSUPPORTED
+        assert b"2..5 modes" in L.cpd_last_error()
+        hs = (ctypes.c_void_p * nm)()
+        assert L.cpd_csf_build_rooted(nm, dims, 10, ptrs, 1, None, hs) == cpd.CPD_EUNSUPPORTED
+    dims = (ctypes.c_int64 * 9)(*([4] * 9))
+    ptrs = (ctypes.c_void_p * 9)(*([1] * 9))
+    assert L.cpd_csf_build(9, dims, 10, ptrs, 1, None, None, ctypes.byref(h)) == cpd.CPD_EINVAL
+
+
+def test_mttkrp_plan_rule():
+    """The host-side kernel choice: ROW only for 3..5 modes at non-leaf levels,
+    with 16-byte rows inside ld and 32-bit row offsets at every gathered level."""
+    from paper_1812_05961_amd import cpd
+    plan = cpd.mttkrp_plan
+    nell = (9000, 12000, 29000)
+    assert plan(nell, 0, 35, ld=36) == "row"
+    assert plan(nell, 1, 35, ld=36) == "lane"      # AUTO keeps LANE below the root
+    assert plan(nell, 1, 35, ld=36, kernel="row") == "row"
+    assert plan(nell, 2, 35, ld=36) == "lane"      # the leaf level
+    with pytest.raises(cpd.CpdError) as e:
+        plan(nell, 2, 35, ld=36, kernel="row")
+    assert e.value.status == cpd.CPD_EUNSUPPORTED
+    # two modes: no ROW kernel is built, AUTO takes LANE at the root
+    assert plan((300, 500), 0, 16) == "lane"
+    with pytest.raises(cpd.CpdError):
+        plan((300, 500), 0, 16, kernel="row")
+    # padded rank beyond ld, rows not 16-byte multiples, misaligned factors,
+    # trees without leaf words
+    assert plan(nell, 0, 35, ld=35) == "lane"
+    assert plan(nell, 0, 16, ld=18) == "lane"
+    assert plan(nell, 0, 16, rows_aligned=False) == "lane"
+    assert plan(nell, 0, 16, leaf_words=False) == "lane"
+    assert plan(nell, 0, 16, ld=24, precision="bf16") == "row"
+    # 32-bit row offsets: rows * ld * 4 <= 2^32 at every gathered level
+    big = 2 ** 32 // (128 * 4)                       # 8,388,608 rows of 512 bytes fit exactly
+    assert plan((10, big, 100), 0, 32, ld=128) == "row"
+    assert plan((10, big + 1, 100), 0, 32, ld=128) == "lane"
+    assert plan((10, 100, big + 1), 0, 32, ld=128) == "lane"
+    assert plan((big + 1, 100, 100), 0, 32, ld=128) == "row"   # the output level is not gathered
+    assert plan((100, big + 1, 100), 1, 32, ld=128, kernel="row") == "row"
+    with pytest.raises(cpd.CpdError):
+        plan((big + 1, 100, 100), 1, 32, ld=128, kernel="row")  # root rows gathered below the root
+    # row ids below 2^24 even when the offsets fit
+    assert plan((10, 2 ** 24, 100), 0, 8, ld=8) == "lane"
+    assert plan((10, 2 ** 24 - 1, 100), 0, 8, ld=8) == "row"
+    # bad requests
+    for args in (((4, 4), 2, 8), ((4, 4, 4), 0, 0), ((4, 4, 4), 0, 65)):
+        with pytest.raises(cpd.CpdError) as e:
+            plan(*args)
+        assert e.value.status == cpd.CPD_EINVAL
+    with pytest.raises(cpd.CpdError) as e:
+        plan((4,) * 6, 0, 8)
+    assert e.value.status == cpd.CPD_EUNSUPPORTED
