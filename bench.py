@@ -67,25 +67,44 @@ def alg_bytes(counts, dims, mode, R):
     return b
 
 
-def run_steps(cpd, x, R, iters, steps, warmup, precision, seed=7):
+def run_steps(cpd, x, R, iters, steps, warmup, precision, init):
     """Time `steps` whole cpd_als jobs (after `warmup` untimed ones) as a
-    caller runs them, without the library's per-kernel event timing; then one
-    more job with event timing on, outside the timed region, for the
-    breakdown.  Returns (wall seconds of the timed steps, [the timed job's
-    result dict], [the fits of the timed steps])."""
+    caller runs them, from the given initial factors, without the library's
+    per-kernel event timing; then one more job with event timing on, outside
+    the timed region, for the breakdown.  Returns (wall seconds of the timed
+    steps, [the timed job's result dict], [the fits of the timed steps])."""
     import torch
     inds, vals = x.inds, x.vals
     for _ in range(warmup):
-        cpd.als(inds, vals, x.dims, R, iters, 0.0, precision=precision, seed=seed)
+        cpd.als(inds, vals, x.dims, R, iters, 0.0, precision=precision, init=init)
     torch.cuda.synchronize()
     fits = []
     t0 = time.perf_counter()
     for _ in range(steps):
-        fits.append(cpd.als(inds, vals, x.dims, R, iters, 0.0, precision=precision, seed=seed)["fit"])
+        fits.append(cpd.als(inds, vals, x.dims, R, iters, 0.0, precision=precision, init=init)["fit"])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    timed = cpd.als(inds, vals, x.dims, R, iters, 0.0, precision=precision, seed=seed, timing=True)
+    timed = cpd.als(inds, vals, x.dims, R, iters, 0.0, precision=precision, init=init, timing=True)
     return wall, [timed], fits
+
+
+def device_init(x, R, seed):
+    """U(0,1) initial factors (the seeded generator of the inputs), on the device."""
+    from paper_1812_05961_amd import synth
+    return [a.float().cuda() for a in synth.init_factors(x.dims, R, seed)]
+
+
+def heuristic_alg_bytes(cpd, x, R):
+    """B_alg of one MTTKRP: the heuristic-order CSF once (int32 ids and
+    pointers, float values), every factor once as input or output (float rows
+    of R entries); the same for every mode.  Returns (bytes, level counts)."""
+    c = cpd.csf_build(x.inds, x.vals, x.dims, None)
+    counts = c.counts
+    c.free()
+    nm = len(x.dims)
+    b = sum(4 * counts[l] + 4 * (counts[l] + 1) for l in range(nm - 1)) + 8 * counts[nm - 1]
+    b += sum(4 * d * R for d in x.dims)
+    return b, counts
 
 
 def gather_bytes(counts, R, precision):
@@ -238,33 +257,104 @@ def measured_traffic(kernel):
     return int(t["hbm_bytes_per_launch"])
 
 
-def cpu_baseline(x, R, sample_nnz, seed=11):
-    """The oracle (single-threaded C MTTKRP + numpy ALS steps, BLAS limited to
-    one thread) on the first sample_nnz nonzeros, one sweep; scaled to the
-    full tensor by the nonzero ratio."""
+def cpu_model():
+    """The host CPU's model name (as lscpu reports it), from /proc/cpuinfo."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(x, R, init, gpu_fits, sample_nnz=8_000_000):
+    """The oracle on the host: per mode the COO MTTKRP loop (median of 3 after
+    a warm-up) at 1 thread on the first sample_nnz nonzeros (a uniform random
+    subset: the generator emits coordinates in seeded random order) and at all
+    the process's cores on every nonzero; then one CP-ALS sweep at all cores
+    over every nonzero from the GPU job's initial factors, whose fit is
+    compared with the GPU's first-sweep fit."""
+    import statistics as st
+
     import numpy as np
     from threadpoolctl import threadpool_limits
 
     from oracle import als as oals
     from oracle import coo as ocoo
-    from paper_1812_05961_amd import synth
 
-    S = min(sample_nnz, x.nnz)
-    inds = x.inds[:, :S].cpu().numpy().astype(np.int64)
-    vals = x.vals[:S].cpu().double().numpy()
-    init = [a.numpy() for a in synth.init_factors(x.dims, R, seed)]
+    threads = int(os.environ.get("OMP_NUM_THREADS") or 0) or len(os.sched_getaffinity(0))
+    inds = x.inds.cpu().numpy().astype(np.int64)
+    vals = x.vals.cpu().double().numpy()
+    nnz = vals.size
+    S = min(sample_nnz, nnz)
+    inds_s = np.ascontiguousarray(inds[:, :S])
+    vals_s = np.ascontiguousarray(vals[:S])
+    A = [a.cpu().double().numpy() for a in init]
     ocoo.build()
-    with threadpool_limits(limits=1):
+
+    def med3(fn):
+        fn()
+        ts = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            fn()
+            ts.append(time.perf_counter() - t0)
+        return st.median(ts)
+
+    per_mode = []
+    for m in range(x.nmodes):
+        t1 = med3(lambda: ocoo.mttkrp(x.dims, inds_s, vals_s, A, m))
+        ta = med3(lambda: ocoo.mttkrp(x.dims, inds, vals, A, m, threads=threads))
+        per_mode.append(dict(mode=m, ns_per_nnz_1thread=round(t1 / S * 1e9, 3),
+                             ns_per_nnz_all_cores=round(ta / nnz * 1e9, 3)))
+    with threadpool_limits(limits=threads):
         t0 = time.perf_counter()
-        oals.cp_als(x.dims, inds, vals, R, 1, 0.0, init)
-        t = time.perf_counter() - t0
-    if S == x.nnz:
-        what = "all %d nonzeros, one CP-ALS sweep (of the 10 the job runs)" % x.nnz
-    else:
-        what = ("first %d of %d nonzeros (a uniform random subset: the generator emits coordinates in "
-                "seeded random order), one CP-ALS sweep, scaled by the nonzero ratio" % (S, x.nnz))
-    return dict(value=t * x.nnz / S, unit="s/iter", cores=1, kind="oracle",
-                sample="%s of the FP64 oracle (C MTTKRP loop, numpy solve), %.2f s measured" % (what, t))
+        ref = oals.cp_als(x.dims, inds, vals, R, 1, 0.0, A, threads=threads)
+        t_sweep = time.perf_counter() - t0
+    return dict(value=round(t_sweep, 4), unit="s/iter", cores=threads, kind="oracle",
+                sample=("one CP-ALS sweep (of the job's %d) of the FP64 oracle over all %d nonzeros at %d "
+                        "threads (C MTTKRP loop with private copies, numpy solve), from the GPU job's initial "
+                        "factors; per-mode MTTKRP loop times at 1 thread on the first %d nonzeros and at %d "
+                        "threads on all, median of 3" % (x.meta.get("iters", 0), nnz, threads, S, threads)),
+                nproc=os.cpu_count(), affinity=len(os.sched_getaffinity(0)), cpu_model=cpu_model(),
+                per_mode=per_mode, oracle_fit_sweep1=ref["fit"], gpu_fit_sweep1=gpu_fits[0],
+                fit_diff_sweep1=abs(ref["fit"] - gpu_fits[0]))
+
+
+def config_report(cpd, name, dev, x=None):
+    """One benchmark configuration: cpd_als from the same initial factors with
+    FP32 and with BF16 gathers (one untimed job, then one with the library's
+    event timing); per mode the root MTTKRP time (mean over sweeps 2..K),
+    ns/nnz and the HBM-roofline fraction on the heuristic tree's B_alg; the
+    fits of the returned models and their difference."""
+    import torch
+
+    from paper_1812_05961_amd import synth
+    cfg = synth.CONFIGS[name]
+    R, iters = cfg["rank"], cfg["iters"]
+    if x is None:
+        x = synth.make_config(name, device=dev)
+        x.inds = x.inds.to(torch.int32)
+    init = device_init(x, R, cfg["init_seed"])
+    b_alg, hcounts = heuristic_alg_bytes(cpd, x, R)
+    nnz = hcounts[-1]
+    out = dict(workload="%s: %s, %d nonzeros, Zipf alphas %s, %s values, rank %d, %d sweeps" % (
+        name, "x".join(map(str, x.dims)), nnz, cfg["alphas"], cfg["values"], R, iters),
+        alg_bytes=b_alg, heuristic_counts=hcounts)
+    for prec in ("fp32", "bf16"):
+        _, runs, _ = run_steps(cpd, x, R, iters, 0, 1, prec, init)
+        sm = summarize(runs, x.nmodes)
+        ms = sm["mttkrp_ms"]
+        out[prec] = dict(s_per_iter=round(sm["iter_ms"] / 1e3, 6), mttkrp_ms=[round(v, 4) for v in ms],
+                         ns_per_nnz=[round(v * 1e6 / nnz, 4) for v in ms],
+                         roofline_frac=[round(b_alg / (v * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) for v in ms],
+                         fit=runs[-1]["fit"])
+    out["fit_diff"] = abs(out["fp32"]["fit"] - out["bf16"]["fit"])
+    out["bf16_speedup_per_mode"] = [round(a / b, 3) for a, b in zip(out["fp32"]["mttkrp_ms"],
+                                                                    out["bf16"]["mttkrp_ms"])]
+    return out
 
 
 def profile_workload(workload, precision, what):
@@ -324,12 +414,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="nell2")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16"])
-    # the whole tensor for one sweep: about 10 s of host work at the default workload
-    ap.add_argument("--cpu-sample-nnz", type=int, default=76_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-completion", action="store_true", help="skip the CP-with-missing-values timings")
     ap.add_argument("--no-compare", action="store_true",
-                    help="skip the BF16-vs-FP32 comparison on the NETFLIX-shaped tensor")
+                    help="skip the FP32 / BF16 per-mode reports of the three benchmark tensors")
     ap.add_argument("--profile-workload", choices=["root", "single"],
                     help="run only a short MTTKRP workload for rocprofv3 (no JSON line)")
     args = ap.parse_args()
@@ -355,27 +443,30 @@ def main():
     x.inds = x.inds.to(torch.int32)
     torch.cuda.synchronize()
     log("generated %s: %d nnz in %.1f s" % (args.workload, x.nnz, time.perf_counter() - t0))
+    init = device_init(x, R, cfg["init_seed"])
 
-    wall, runs, step_fits = run_steps(cpd, x, R, iters, args.steps, args.warmup, args.precision)
+    wall, runs, step_fits = run_steps(cpd, x, R, iters, args.steps, args.warmup, args.precision, init)
     s = summarize(runs, x.nmodes)
     log("steps done: %.3f s wall for %d steps" % (wall, args.steps))
 
-    # level counts of the per-mode trees, for the algorithmic bytes
+    # level counts of the per-mode trees (gathered bytes) and of the
+    # heuristic-order tree (the algorithmic bytes B_alg)
     counts = []
     for m, order in enumerate(root_orders(x.dims)):
         c = cpd.csf_build(x.inds, x.vals, x.dims, order)
         counts.append(c.counts)
         c.free()
     nnz_csf = counts[0][-1]
-    bytes_mode = [alg_bytes(counts[m], x.dims, m, R) for m in range(x.nmodes)]
-    avg_bytes = sum(bytes_mode) / len(bytes_mode)
+    b_alg, hcounts = heuristic_alg_bytes(cpd, x, R)
     avg_ms = sum(s["mttkrp_ms"]) / len(s["mttkrp_ms"])
-    achieved = avg_bytes / (avg_ms * 1e-3) / 1e9
+    achieved = b_alg / (avg_ms * 1e-3) / 1e9
     kernel = root_kernel_name(x.nmodes, R, args.precision)
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4),
                     traffic=measured_traffic(kernel) if args.precision == "fp32" else None, kernel=kernel,
-                    bytes_per_launch=int(avg_bytes), avg_launch_us=round(avg_ms * 1e3, 2))
+                    bytes_per_launch=int(b_alg), avg_launch_us=round(avg_ms * 1e3, 2),
+                    alg_bytes_tree="heuristic order %s, level counts %s" % (
+                        sorted(range(x.nmodes), key=lambda m: (x.dims[m], m)), hcounts))
 
     gathered = [gather_bytes(counts[m], R, args.precision) for m in range(x.nmodes)]
     one_tree = single_tree(cpd, x, R)
@@ -397,44 +488,35 @@ def main():
         breakdown=dict(csf_build_ms=round(s["csf_build_ms"], 3), als_iter_ms=round(s["iter_ms"], 4),
                        mttkrp_ms=[round(v, 4) for v in s["mttkrp_ms"]],
                        mttkrp_ns_per_nnz=[round(v * 1e6 / nnz_csf, 4) for v in s["mttkrp_ms"]],
-                       mttkrp_alg_bytes=bytes_mode,
-                       mttkrp_roofline_frac=[round(b / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
-                                             for b, t in zip(bytes_mode, s["mttkrp_ms"])],
+                       mttkrp_alg_bytes=b_alg,
+                       mttkrp_roofline_frac=[round(b_alg / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+                                             for t in s["mttkrp_ms"]],
                        mttkrp_gather_bytes=gathered,
-                       mttkrp_gather_inclusive_gbs=[round((b + gb) / (t * 1e-3) / 1e9, 1)
-                                                    for b, gb, t in zip(bytes_mode, gathered, s["mttkrp_ms"])],
+                       mttkrp_gather_inclusive_gbs=[round((b_alg + gb) / (t * 1e-3) / 1e9, 1)
+                                                    for gb, t in zip(gathered, s["mttkrp_ms"])],
                        als_events_total_ms=round(runs[-1]["timing_ms"]["total"], 3),
+                       final_fit_ms=round(runs[-1]["timing_ms"]["final_fit"], 3),
                        fit=step_fits[-1], single_tree=one_tree),
         roofline=roofline,
     )
     log("main line ready; value %.5f s/iter" % out["value"])
 
     if not args.no_compare and args.workload == "nell2":
-        cmp = {}
-        y = synth.make_config("netflix", device=dev)
-        y.inds = y.inds.to(torch.int32)
-        torch.cuda.synchronize()
-        ycfg = synth.CONFIGS["netflix"]
-        for prec in ("fp32", "bf16"):
-            w, rr, _ = run_steps(cpd, y, ycfg["rank"], ycfg["iters"], 1, 1, prec)
-            ss = summarize(rr, y.nmodes)
-            cmp[prec] = dict(s_per_iter=round(ss["iter_ms"] / 1e3, 6),
-                             mttkrp_ms=[round(v, 4) for v in ss["mttkrp_ms"]],
-                             fit=rr[-1]["fit"])
-        cmp["fit_diff"] = abs(cmp["fp32"]["fit"] - cmp["bf16"]["fit"])
-        cmp["bf16_speedup_mttkrp"] = round(sum(cmp["fp32"]["mttkrp_ms"]) / sum(cmp["bf16"]["mttkrp_ms"]), 3)
-        cmp["workload"] = "netflix: %s, %d nnz, rank %d, %d sweeps" % (
-            "x".join(map(str, y.dims)), y.nnz, ycfg["rank"], ycfg["iters"])
-        out["precision_compare"] = cmp
-        del y
-        log("precision comparison done")
+        rep = {"nell2": config_report(cpd, "nell2", dev, x)}
+        log("nell2 fp32/bf16 done")
+        for name in ("netflix", "fourmode"):
+            rep[name] = config_report(cpd, name, dev)
+            torch.cuda.empty_cache()
+            log("%s fp32/bf16 done" % name)
+        out["configs"] = rep
 
     if not args.no_completion:
         out["completion"] = completion(cpd, x, R)
         log("completion timings done")
 
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(x, R, args.cpu_sample_nnz)
+        x.meta["iters"] = iters
+        out["cpu_baseline"] = cpu_baseline(x, R, init, runs[-1]["fits"])
         log("cpu baseline done")
     print(json.dumps(out), flush=True)
 

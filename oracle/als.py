@@ -129,8 +129,9 @@ def fit_from(normX2, lam, A_last, Y_last, grams):
     return 1.0 - np.sqrt(resid2) / np.sqrt(normX2)
 
 
-def cp_als(dims, inds, vals, rank, iters, tol, init, norm="2"):
-    """Run CP-ALS; init is a list of N (I_m x R) arrays (A_0 is not read).
+def cp_als(dims, inds, vals, rank, iters, tol, init, norm="2", threads=1):
+    """Run CP-ALS; init is a list of N (I_m x R) arrays (A_0 is not read);
+    threads: host threads of the MTTKRP loop (1: the sequential loop).
 
     Returns dict(lam, factors, fit, iters, fits, pinv_used)."""
     nm = len(dims)
@@ -147,7 +148,7 @@ def cp_als(dims, inds, vals, rank, iters, tol, init, norm="2"):
     for it in range(1, iters + 1):
         for n in range(nm):
             V = hadamard_v(grams, n)
-            Y = coo.mttkrp(dims, inds, vals, A, n)
+            Y = coo.mttkrp(dims, inds, vals, A, n, threads=threads)
             An, used = normal_solve(V, Y)
             pinv_used += int(used)
             A[n], lam = normalize_columns(An, norm)

@@ -23,10 +23,11 @@ _lib = None
 
 
 def build(force: bool = False) -> str:
-    """Compile oracle.c into liboracle.so with gcc (plain -O2, one thread)."""
+    """Compile oracle.c into liboracle.so with gcc (plain -O2; OpenMP only for
+    the multi-threaded timing loop)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-std=c99", "-o", tmp, _SRC])
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99", "-o", tmp, _SRC])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -39,6 +40,9 @@ def _load():
         lib.oracle_mttkrp_coo.argtypes = [ctypes.c_int, P, ctypes.c_int64, P, P, P,
                                           ctypes.c_int, ctypes.c_int, P]
         lib.oracle_mttkrp_coo.restype = ctypes.c_int
+        lib.oracle_mttkrp_coo_par.argtypes = [ctypes.c_int, P, ctypes.c_int64, P, P, P,
+                                              ctypes.c_int, ctypes.c_int, ctypes.c_int, P]
+        lib.oracle_mttkrp_coo_par.restype = ctypes.c_int
         lib.oracle_mttkrp_coo_rows.argtypes = [ctypes.c_int, P, ctypes.c_int64, P, P, P,
                                                ctypes.c_int, ctypes.c_int, ctypes.c_int64, P, P]
         lib.oracle_mttkrp_coo_rows.restype = ctypes.c_int
@@ -72,12 +76,18 @@ def _prep(dims, inds, vals, factors, mode):
     return dims, inds, vals, facs, ptrs, rank
 
 
-def mttkrp(dims, inds, vals, factors, mode):
-    """Y_mode (I_mode x R, float64) by the direct COO loop."""
+def mttkrp(dims, inds, vals, factors, mode, threads=1):
+    """Y_mode (I_mode x R, float64) by the direct COO loop; threads > 1 splits
+    the nonzeros over that many threads with private copies of Y (the same
+    sums in another FP64 addition order)."""
     dims, inds, vals, facs, ptrs, rank = _prep(dims, inds, vals, factors, mode)
     Y = np.empty((int(dims[mode]), rank), dtype=np.float64)
-    rc = _load().oracle_mttkrp_coo(dims.size, dims.ctypes.data, vals.size, inds.ctypes.data,
-                                   vals.ctypes.data, ptrs, rank, mode, Y.ctypes.data)
+    if threads > 1:
+        rc = _load().oracle_mttkrp_coo_par(dims.size, dims.ctypes.data, vals.size, inds.ctypes.data,
+                                           vals.ctypes.data, ptrs, rank, mode, int(threads), Y.ctypes.data)
+    else:
+        rc = _load().oracle_mttkrp_coo(dims.size, dims.ctypes.data, vals.size, inds.ctypes.data,
+                                       vals.ctypes.data, ptrs, rank, mode, Y.ctypes.data)
     if rc:
         raise MemoryError("oracle_mttkrp_coo")
     return Y

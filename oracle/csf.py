@@ -14,7 +14,9 @@ Duplicates (R8): equal coordinates become one nonzero whose value is the
 float32 sum of the duplicates in input order, added one after another.
 
 Steps: (1) stable lexicographic sort of the index tuples in pi order
-(numpy.lexsort); (2) duplicate merge; (3) one run scan per level.
+(numpy.lexsort; or, when the tuple fits 62 bits, a stable library sort of
+the tuple written as one integer, i_pi0 most significant, which is the same
+order); (2) duplicate merge; (3) one run scan per level.
 
 Pinned by: brute-force tree construction from Python tuples on tiny inputs;
 expanding the CSF reproduces the sorted, merged COO exactly; fptr strictly
@@ -30,8 +32,34 @@ def heuristic_order(dims) -> list:
     return sorted(range(len(dims)), key=lambda m: (int(dims[m]), m))
 
 
-def build(dims, inds, vals, order):
-    """Return dict(order, counts, fids, fptr, vals) for the mode order `order`."""
+def sort_perm(dims, inds, order, method="auto"):
+    """Stable permutation sorting the nonzeros lexicographically by
+    (i_pi0, i_pi1, ...).  "lexsort": numpy.lexsort on the index rows;
+    "packed": the tuple as one integer sum_l i_pil * prod_{l' > l} dims[pi_l']
+    (mixed radix, i_pi0 most significant, exact below 2^62), stably sorted by
+    torch's CPU sort; "auto": packed when it fits."""
+    nm = len(dims)
+    span = 1
+    for m in order:
+        span *= int(dims[m])
+    if method == "auto":
+        method = "packed" if span < (1 << 62) else "lexsort"
+    if method == "lexsort":
+        keys = [inds[m] for m in order]                   # primary key first
+        return np.lexsort(keys[::-1])                     # lexsort: last key is primary
+    if span >= (1 << 62):
+        raise ValueError("index tuples do not fit 62 bits")
+    import torch
+    key = np.zeros(inds.shape[1], dtype=np.int64)
+    for m in order:
+        key = key * int(dims[m]) + inds[m]
+    _, perm = torch.sort(torch.from_numpy(key), stable=True)
+    return perm.numpy()
+
+
+def build(dims, inds, vals, order, method="auto"):
+    """Return dict(order, counts, fids, fptr, vals) for the mode order `order`
+    (method: the sort of step 1, see sort_perm)."""
     dims = [int(d) for d in dims]
     inds = np.asarray(inds, dtype=np.int64)
     vals = np.asarray(vals, dtype=np.float32)
@@ -39,8 +67,7 @@ def build(dims, inds, vals, order):
     order = [int(m) for m in order]
     if sorted(order) != list(range(nm)):
         raise ValueError("order must be a permutation of the modes")
-    keys = [inds[m] for m in order]                       # primary key first
-    perm = np.lexsort(keys[::-1])                         # lexsort: last key is primary
+    perm = sort_perm(dims, inds, order, method)
     srt = inds[order][:, perm]                            # rows in pi order
     v = vals[perm]
     nnz = srt.shape[1]

@@ -16,6 +16,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 /* MTTKRP by a direct loop over the COO nonzeros in storage order.
  * inds: N x nnz int64 (mode-major), vals: nnz doubles, factors: N pointers
@@ -39,6 +42,63 @@ int oracle_mttkrp_coo(int nmodes, const int64_t *dims, int64_t nnz, const int64_
         for (int r = 0; r < rank; ++r) y[r] += row[r];
     }
     free(row);
+    return 0;
+}
+
+/* The same MTTKRP with the nonzeros split into `nthreads` contiguous ranges,
+ * thread t summing range t into a private copy of Y; the copies are then
+ * added into Y in range order (the privatised parallel MTTKRP the paper
+ * times, Section IV-B, with OpenMP threads in place of Chapel tasks).  It
+ * differs from the sequential loop only in the order of the FP64 additions;
+ * it serves to time the oracle on all host cores.  Returns 0, or -1 when the
+ * copies cannot be allocated. */
+int oracle_mttkrp_coo_par(int nmodes, const int64_t *dims, int64_t nnz, const int64_t *inds,
+                          const double *vals, const double *const *factors, int rank, int mode,
+                          int nthreads, double *Y)
+{
+    if (nthreads < 1) nthreads = 1;
+    const size_t ylen = (size_t)dims[mode] * (size_t)rank;
+    double *copies = (double *)calloc((size_t)nthreads * ylen, sizeof(double));
+    if (!copies) return -1;
+    int failed = 0;
+#pragma omp parallel num_threads(nthreads) reduction(|| : failed)
+    {
+#ifdef _OPENMP
+        const int t = omp_get_thread_num(), nt = omp_get_num_threads();
+#else
+        const int t = 0, nt = 1;
+#endif
+        const int64_t k0 = nnz * t / nt, k1 = nnz * (t + 1) / nt;
+        double *Yt = copies + (size_t)t * ylen;
+        double *row = (double *)malloc(sizeof(double) * (size_t)rank);
+        if (!row) {
+            failed = 1;
+        } else {
+            for (int64_t k = k0; k < k1; ++k) {
+                for (int r = 0; r < rank; ++r) row[r] = vals[k];
+                for (int m = 0; m < nmodes; ++m) {
+                    if (m == mode) continue;
+                    const double *a = factors[m] + inds[(int64_t)m * nnz + k] * rank;
+                    for (int r = 0; r < rank; ++r) row[r] *= a[r];
+                }
+                double *y = Yt + inds[(int64_t)mode * nnz + k] * rank;
+                for (int r = 0; r < rank; ++r) y[r] += row[r];
+            }
+            free(row);
+        }
+    }
+    if (failed) {
+        free(copies);
+        return -1;
+    }
+    memset(Y, 0, sizeof(double) * ylen);
+#pragma omp parallel for num_threads(nthreads) schedule(static)
+    for (int64_t j = 0; j < (int64_t)ylen; ++j) {
+        double s = 0.0;
+        for (int t = 0; t < nthreads; ++t) s += copies[(size_t)t * ylen + (size_t)j];
+        Y[j] = s;
+    }
+    free(copies);
     return 0;
 }
 

@@ -84,9 +84,36 @@ cpd_status rank_key_field(const uint64_t *lo, const uint64_t *hi, int shift, int
 // outputs when the tree has no ranking (leaf index above 2^29).
 cpd_status csf_level_rank(cpd_csf_s *c, int l, const int32_t **perm, const int32_t **rank, hipStream_t s);
 
+// Device memory that temporaries are carved from (the allocation-free
+// MTTKRP entry point): 256-byte aligned bump allocation, null when full.
+struct Workspace {
+    char *base = nullptr;
+    size_t bytes = 0, used = 0;
+    void *take(size_t n) {
+        const size_t at = (used + 255) & ~size_t(255);
+        if (!base || at > bytes || n > bytes - at) return nullptr;
+        used = at + n;
+        return base + at;
+    }
+};
+
+// MTTKRP (cpd_mttkrp) with every temporary taken from ws (null: the scratch
+// cache of stream s, tables cached in the handle).
+cpd_status mttkrp_ws(cpd_csf_s *c, const void *const *factors, int32_t ld, int32_t R, int32_t mode, float *Y,
+                     int32_t ldo, const cpd_mttkrp_opts *opts, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1,
+                     Workspace *ws);
+
 // Free a tree whose every use was ordered on stream s (no device-wide wait):
 // its arrays go back to the stream-ordered pool on s.
 void free_csf_on(cpd_csf_s *c, hipStream_t s);
+
+// The ranking of level l if it exists already (no allocation; null otherwise).
+void csf_level_rank_cached(cpd_csf_s *c, int l, const int32_t **perm, const int32_t **rank);
+
+// Tile table without allocating: the cached one, else computed into dst
+// (dst_bytes of device memory; CPD_EUNSUPPORTED when it does not fit).
+cpd_status csf_tiles_into(cpd_csf_s *c, int32_t tile, int32_t *dst, size_t dst_bytes, const int32_t **starts,
+                          int64_t *ntiles, hipStream_t s);
 
 // Tile start nodes for a tile width (cached in the handle; created on first use).
 cpd_status csf_tiles(cpd_csf_s *c, int32_t tile, const int32_t **starts, int64_t *ntiles,

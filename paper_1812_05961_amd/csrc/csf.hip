@@ -1314,6 +1314,54 @@ cpd_status sample_freq(const int32_t *ids, int64_t n, int64_t nid, int64_t max_s
     return CPD_OK;
 }
 
+// The ranking of level l when it already exists (the leaf ranking is made
+// with the tree; internal levels once csf_level_rank has run): no allocation.
+void csf_level_rank_cached(cpd_csf_s *c, int l, const int32_t **perm, const int32_t **rank) {
+    *perm = nullptr;
+    *rank = nullptr;
+    if (l < 1 || l >= c->nmodes || !c->leaf_perm) return;
+    if (l == c->nmodes - 1) {
+        *perm = c->leaf_perm;
+        *rank = c->leaf_rank;
+        return;
+    }
+    std::lock_guard<std::mutex> g(c->mu);
+    *perm = c->lvl_perm[l];
+    *rank = c->lvl_rank[l];
+}
+
+// Tile table for a width without allocating: the cached table when it
+// exists, else computed into dst (dst_bytes of device memory), not cached.
+cpd_status csf_tiles_into(cpd_csf_s *c, int32_t tile, int32_t *dst, size_t dst_bytes, const int32_t **starts,
+                          int64_t *ntiles, hipStream_t s) {
+    if (tile < 1) CPD_FAIL(CPD_EINVAL, "tile width %d < 1", tile);
+    const int nm = c->nmodes;
+    const int64_t nl = c->counts[nm - 1];
+    const int64_t nt = ceil_div(nl, tile);
+    {
+        std::lock_guard<std::mutex> g(c->mu);
+        for (auto &t : c->tiles)
+            if (t.tile == tile) {
+                *starts = t.starts;
+                *ntiles = t.ntiles;
+                return CPD_OK;
+            }
+    }
+    const size_t need = sizeof(int32_t) * (size_t)std::max<int64_t>(1, (nm - 1) * nt);
+    if (!dst || need > dst_bytes)
+        CPD_FAIL(CPD_EUNSUPPORTED, "tile table of %zu bytes does not fit the %zu-byte workspace", need, dst_bytes);
+    FptrSet fp{};
+    for (int l = 0; l < nm - 1; ++l) {
+        fp.p[l] = c->fptr[l];
+        fp.len[l] = c->counts[l];
+    }
+    hipLaunchKernelGGL(k_tiles, dim3(grid1(nt)), dim3(256), 0, s, fp, nm, nl, tile, nt, dst);
+    CPD_LAUNCH_CHECK();
+    *starts = dst;
+    *ntiles = nt;
+    return CPD_OK;
+}
+
 cpd_status csf_tiles(cpd_csf_s *c, int32_t tile, const int32_t **starts, int64_t *ntiles,
                      hipStream_t s) {
     if (tile < 1) CPD_FAIL(CPD_EINVAL, "tile width %d < 1", tile);

@@ -339,10 +339,31 @@ cpd_status mttkrp_plan(int N, const int64_t *dims_by_level, int d, int64_t ld, i
     return CPD_OK;
 }
 
+// Tile table for width T: cached in the handle (created on first use), or
+// with a workspace the cached one or one computed into the workspace.
+static cpd_status tiles_for(cpd_csf_s *c, int32_t T, Workspace *ws, const int32_t **starts, int64_t *ns,
+                            hipStream_t s) {
+    if (!ws) return csf_tiles(c, T, starts, ns, s);
+    const int64_t nt = ceil_div(c->counts[c->nmodes - 1], T);
+    const size_t need = sizeof(int32_t) * (size_t)std::max<int64_t>(1, (c->nmodes - 1) * nt);
+    void *dst = ws->take(need);
+    return csf_tiles_into(c, T, static_cast<int32_t *>(dst), dst ? need : 0, starts, ns, s);
+}
+
 // Internal entry (also used by the ALS driver).
 cpd_status mttkrp(cpd_csf_s *c, const void *const *factors, int32_t ld, int32_t R, int32_t mode,
                   float *Y, int32_t ldo, const cpd_mttkrp_opts *opts, hipStream_t s, hipEvent_t ev0,
                   hipEvent_t ev1) {
+    return mttkrp_ws(c, factors, ld, R, mode, Y, ldo, opts, s, ev0, ev1, nullptr);
+}
+
+// ws: null (temporaries from the stream's scratch cache, tables cached in
+// the handle on first use), or device memory every temporary is carved from
+// (no allocation; missing tables are computed into it, a level without a
+// ranking runs without the hot-row table).
+cpd_status mttkrp_ws(cpd_csf_s *c, const void *const *factors, int32_t ld, int32_t R, int32_t mode, float *Y,
+                     int32_t ldo, const cpd_mttkrp_opts *opts, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1,
+                     Workspace *ws) {
     if (!c) CPD_FAIL(CPD_EINVAL, "null CSF handle");
     const int N = c->nmodes;
     if (R < 1 || R > CPD_MAX_RANK) CPD_FAIL(CPD_EINVAL, "rank %d not in [1, %d]", R, CPD_MAX_RANK);
@@ -397,12 +418,21 @@ cpd_status mttkrp(cpd_csf_s *c, const void *const *factors, int32_t ld, int32_t 
 
         const int32_t *starts;
         int64_t ns;
-        CPD_TRY(csf_tiles(c, T, &starts, &ns, s));
+        CPD_TRY(tiles_for(c, T, ws, &starts, &ns, s));
         const void *fac_by_level[CPD_MAX_MODES];
         for (int l = 0; l < N; ++l) fac_by_level[l] = fv.a[l];
+        void *perm_buf = nullptr;  // the leaf factor in rank order
+        if (ws) {
+            const size_t need = (size_t)dims_by_level[N - 1] * ld * (bf16 ? 2 : 4);
+            perm_buf = ws->take(need);
+            if (!perm_buf)
+                CPD_FAIL(CPD_EUNSUPPORTED, "the leaf factor copy (%zu bytes) does not fit the %zu-byte workspace",
+                         need, ws->bytes);
+        }
         if (ev0) CPD_HIP(hipEventRecord(ev0, s));
         cpd_status st = launch_root(N, bf16, RP, d, cv.fids, cv.fptr, cv.vals, c->leafw, c->leaf_perm, c->uprow,
-                                    c->counts, dims_by_level, fac_by_level, ld, starts, ns, T, Y, ldo, R, nullptr, s);
+                                    c->counts, dims_by_level, fac_by_level, ld, starts, ns, T, Y, ldo, R, perm_buf,
+                                    s);
         if (st == CPD_OK && ev1) CPD_HIP(hipEventRecord(ev1, s));
         return st;
     }
@@ -411,7 +441,7 @@ cpd_status mttkrp(cpd_csf_s *c, const void *const *factors, int32_t ld, int32_t 
     int32_t T = o.tile_nnz ? o.tile_nnz : 256;
     const int32_t *starts;
     int64_t ns;
-    CPD_TRY(csf_tiles(c, T, &starts, &ns, s));
+    CPD_TRY(tiles_for(c, T, ws, &starts, &ns, s));
     const size_t lds = (size_t)out_rows * R * sizeof(float);
     bool priv = false;
     if (d >= 1 && lds <= PRIV_LDS_MAX) {
@@ -431,7 +461,8 @@ cpd_status mttkrp(cpd_csf_s *c, const void *const *factors, int32_t ld, int32_t 
     int32_t hot = 0;
     size_t lds_launch = lds;
     if (!priv && d >= 2 && c->leafw) {
-        CPD_TRY(csf_level_rank(c, d, &cv.hot_perm, &cv.hot_rank, s));
+        if (ws) csf_level_rank_cached(c, d, &cv.hot_perm, &cv.hot_rank);
+        else CPD_TRY(csf_level_rank(c, d, &cv.hot_perm, &cv.hot_rank, s));
         if (cv.hot_perm) {
             hot = (int32_t)std::min<int64_t>(c->dims[mode], (int64_t)(HOT_LDS / (sizeof(float) * R)));
             if (hot < 32) hot = 0;
@@ -453,12 +484,22 @@ cpd_status mttkrp(cpd_csf_s *c, const void *const *factors, int32_t ld, int32_t 
     int64_t ldk = ldo, copy_stride = 0;
     if (xcd_copies) {
         copy_stride = out_rows * R;
-        CPD_TRY(copies.alloc((size_t)XCD_COPIES * copy_stride, s));
+        float *cp = nullptr;
+        if (ws) {
+            const size_t need = sizeof(float) * (size_t)XCD_COPIES * copy_stride;
+            cp = static_cast<float *>(ws->take(need));
+            if (!cp)
+                CPD_FAIL(CPD_EUNSUPPORTED, "the per-XCD copies (%zu bytes) do not fit the %zu-byte workspace", need,
+                         ws->bytes);
+        } else {
+            CPD_TRY(copies.alloc((size_t)XCD_COPIES * copy_stride, s));
+            cp = copies.p;
+        }
         const int64_t tot = XCD_COPIES * copy_stride;
-        hipLaunchKernelGGL(k_zero_rows<float>, dim3((unsigned)ceil_div(tot, 256)), dim3(256), 0, s, copies.p,
+        hipLaunchKernelGGL(k_zero_rows<float>, dim3((unsigned)ceil_div(tot, 256)), dim3(256), 0, s, cp,
                            (int64_t)XCD_COPIES * out_rows, (int64_t)R, R);
         CPD_LAUNCH_CHECK();
-        Yk = copies.p;
+        Yk = cp;
         ldk = R;
     }
     if (ev0) CPD_HIP(hipEventRecord(ev0, s));

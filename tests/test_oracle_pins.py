@@ -368,3 +368,53 @@ def test_splitmix64_published_first_output():
     assert synth.splitmix64_int(0) == 0xE220A8397B1DCDAF
     import torch
     assert synth.splitmix64(torch.tensor([0]))[0].item() == synth._s64(0xE220A8397B1DCDAF)
+
+
+def test_threaded_mttkrp_equals_the_sequential_loop():
+    """The multi-threaded oracle loop (private copies summed in range order)
+    gives the sequential loop's sums up to FP64 addition order, for thread
+    counts that do and do not divide the nonzeros, and more threads than
+    nonzeros."""
+    import numpy as np
+
+    from oracle import coo
+    rng = np.random.default_rng(41)
+    dims = (30, 20, 10, 7)
+    nnz = 5003
+    inds = np.stack([rng.integers(0, d, nnz) for d in dims])
+    vals = rng.standard_normal(nnz)
+    F = [rng.standard_normal((d, 5)) for d in dims]
+    for mode in range(4):
+        ref = coo.mttkrp(dims, inds, vals, F, mode)
+        for th in (2, 3, 16):
+            got = coo.mttkrp(dims, inds, vals, F, mode, threads=th)
+            np.testing.assert_allclose(got, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+    few = coo.mttkrp(dims, inds[:, :3], vals[:3], F, 1, threads=8)
+    np.testing.assert_allclose(few, coo.mttkrp(dims, inds[:, :3], vals[:3], F, 1), rtol=0, atol=1e-15)
+
+
+def test_csf_packed_sort_equals_lexsort():
+    """The packed-integer sort of the CSF oracle orders the nonzeros exactly as
+    numpy.lexsort on the index rows (stable, duplicates in input order), for
+    every mode order of 3- and 4-mode tensors with repeated coordinates."""
+    import itertools
+
+    import numpy as np
+
+    from oracle import csf
+    rng = np.random.default_rng(5)
+    for dims in ((7, 5, 9), (4, 6, 3, 5)):
+        n = 400
+        inds = np.stack([rng.integers(0, d, n) for d in dims])
+        inds[:, 300:] = inds[:, :100]                    # duplicates
+        vals = rng.standard_normal(n).astype(np.float32)
+        for order in itertools.permutations(range(len(dims))):
+            a = csf.sort_perm(dims, inds, list(order), "lexsort")
+            b = csf.sort_perm(dims, inds, list(order), "packed")
+            np.testing.assert_array_equal(a, b)
+            ta = csf.build(dims, inds, vals, list(order), "lexsort")
+            tb = csf.build(dims, inds, vals, list(order), "packed")
+            assert ta["counts"] == tb["counts"]
+            for l in range(len(dims)):
+                np.testing.assert_array_equal(ta["fids"][l], tb["fids"][l])
+            assert ta["vals"].tobytes() == tb["vals"].tobytes()
