@@ -26,6 +26,7 @@
 #ifndef CPD_H
 #define CPD_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -154,6 +155,28 @@ typedef struct {
 cpd_status cpd_mttkrp(cpd_csf csf, const void *const *factors, int32_t ld, int32_t rank,
                       int32_t mode, float *out, int32_t ldo, const cpd_mttkrp_opts *opts,
                       void *stream);
+
+/* The allocation-free form of cpd_mttkrp, for callers that cannot allocate
+ * device memory: code under stream capture, tight serving loops, hosts that
+ * forbid hipMalloc.  Same arguments, result and kernels as cpd_mttkrp; every
+ * temporary of the call (a tile table the tree has not cached for the width,
+ * the leaf factor in frequency-rank order, the per-XCD output copies of
+ * CPD_VARIANT_PRIVATE) is carved from one fixed device array of the library
+ * (cpd_mttkrp_noalloc_workspace_bytes() bytes, 64 MiB), one copy per device,
+ * held until the process ends; its device address is looked up once per
+ * device, on the first call with that device current.  Internal-level hot-row
+ * tables are used only when the tree already holds the level's ranking (a
+ * cpd_mttkrp call has built it); otherwise that level runs with atomics alone.
+ * Errors: as cpd_mttkrp, plus CPD_EUNSUPPORTED ("... workspace") when the
+ * call's temporaries exceed the array; nothing is allocated either way.
+ * Every call on a device shares that device's array and it keeps the last
+ * call's contents (what must start at zero is cleared by a kernel in the
+ * call): calls that overlap in time on one device, from several streams or
+ * host threads, race and give wrong results; serialise them. */
+size_t cpd_mttkrp_noalloc_workspace_bytes(void);
+cpd_status cpd_mttkrp_noalloc(cpd_csf csf, const void *const *factors, int32_t ld, int32_t rank,
+                              int32_t mode, float *out, int32_t ldo, const cpd_mttkrp_opts *opts,
+                              void *stream);
 
 /* The kernel family cpd_mttkrp runs for a request, by the rule it applies,
  * decided on the host without touching the device.

@@ -86,6 +86,8 @@ _SIGS = {
     "cpd_csf_tiles": (_I32, [_P, _I32, _P, _P, _P]),
     "cpd_csf_free": (None, [_P]),
     "cpd_mttkrp": (_I32, [_P, _P, _I32, _I32, _I32, _P, _I32, _P, _P]),
+    "cpd_mttkrp_noalloc": (_I32, [_P, _P, _I32, _I32, _I32, _P, _I32, _P, _P]),
+    "cpd_mttkrp_noalloc_workspace_bytes": (ctypes.c_size_t, []),
     "cpd_mttkrp_plan": (_I32, [_I32, _P, _I32, _I32, _I32, _I32, _I32, _I32, _I32, _P]),
     "cpd_gram": (_I32, [_P, _I64, _I32, _I32, _P, _P]),
     "cpd_solve_normalize": (_I32, [_P, _I32, _I32, _P, _I64, _I32, _I32, _P, _I32, _P, _I32, _P,
@@ -255,12 +257,7 @@ def mttkrp_plan(dims_by_level, depth, rank, ld=None, precision="fp32", kernel="a
                                  int(bool(leaf_words)), ctypes.byref(out)))
     return _KERNEL_NAME[out.value]
 
-def mttkrp(csf: Csf, factors, mode: int, out=None, rank=None, precision="fp32", variant="auto",
-           kernel="auto", tile_nnz=0, stream=None):
-    """cpd_mttkrp: Y (dims[mode] x rank, float32) for the given factors.
-
-    factors: list of N CUDA tensors (row-major, unit column stride; entry
-    `mode` may be None): float32 for "fp32", bfloat16 for "bf16"."""
+def _mttkrp_call(entry, csf, factors, mode, out, rank, precision, variant, kernel, tile_nnz, stream):
     fdt = torch.float32 if precision == "fp32" else torch.bfloat16
     if out is None and not 0 <= mode < len(csf.dims):
         raise ValueError("mode %d out of range" % mode)
@@ -277,10 +274,34 @@ def mttkrp(csf: Csf, factors, mode: int, out=None, rank=None, precision="fp32", 
         out = torch.empty((csf.dims[mode], R), dtype=torch.float32, device="cuda")
     _need_cuda(out, "out", torch.float32)
     opts = MttkrpOpts(PRECISION[precision], VARIANT[variant], KERNEL[kernel], int(tile_nnz))
-    _check(lib().cpd_mttkrp(csf.handle, _ptrs([None if m == mode else f for m, f in enumerate(factors)]),
-                            ld, R, int(mode), out.data_ptr(), int(out.stride(0)), ctypes.byref(opts),
-                            _stream(stream)))
+    _check(entry(csf.handle, _ptrs([None if m == mode else f for m, f in enumerate(factors)]),
+                 ld, R, int(mode), out.data_ptr(), int(out.stride(0)), ctypes.byref(opts), _stream(stream)))
     return out
+
+
+def mttkrp(csf: Csf, factors, mode: int, out=None, rank=None, precision="fp32", variant="auto",
+           kernel="auto", tile_nnz=0, stream=None):
+    """cpd_mttkrp: Y (dims[mode] x rank, float32) for the given factors.
+
+    factors: list of N CUDA tensors (row-major, unit column stride; entry
+    `mode` may be None): float32 for "fp32", bfloat16 for "bf16"."""
+    return _mttkrp_call(lib().cpd_mttkrp, csf, factors, mode, out, rank, precision, variant, kernel,
+                        tile_nnz, stream)
+
+
+def mttkrp_noalloc(csf: Csf, factors, mode: int, out, rank=None, precision="fp32", variant="auto",
+                   kernel="auto", tile_nnz=0, stream=None):
+    """cpd_mttkrp_noalloc: cpd_mttkrp with every temporary in the library's
+    fixed per-device workspace (no device allocation by the library; `out`
+    is the caller's).  Calls overlapping on one device race."""
+    if out is None:
+        raise ValueError("mttkrp_noalloc writes into a caller-allocated out")
+    return _mttkrp_call(lib().cpd_mttkrp_noalloc, csf, factors, mode, out, rank, precision, variant, kernel,
+                        tile_nnz, stream)
+
+
+def noalloc_workspace_bytes():
+    return int(lib().cpd_mttkrp_noalloc_workspace_bytes())
 
 
 def gram(A, stream=None):

@@ -519,8 +519,9 @@ cpd_status mttkrp_ws(cpd_csf_s *c, const void *const *factors, int32_t ld, int32
     }
 #undef CPD_LANE_N
     if (st == CPD_OK && xcd_copies) {
+        // the copies live in the workspace or in `copies`: Yk points at them either way
         hipLaunchKernelGGL(k_sum_copies, dim3((unsigned)ceil_div(copy_stride, 256)), dim3(256), 0, s,
-                           (const float *)copies.p, XCD_COPIES, out_rows, R, Y, (int64_t)ldo);
+                           (const float *)Yk, XCD_COPIES, out_rows, R, Y, (int64_t)ldo);
         CPD_LAUNCH_CHECK();
     }
     if (st == CPD_OK && ev1) CPD_HIP(hipEventRecord(ev1, s));

@@ -15,20 +15,19 @@ pytestmark = pytest.mark.gpu
 
 def _cpd():
     from paper_1812_05961_amd import cpd
-    L = cpd.lib()
-    f = L.cpd_mttkrp_noalloc
-    f.restype = ctypes.c_int32
-    f.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
-                  ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]
-    L.cpd_mttkrp_noalloc_workspace_bytes.restype = ctypes.c_size_t
-    return cpd, L
+    return cpd, cpd.lib()
 
 
 def _noalloc(cpd, L, c, facs, mode, R, ld, kernel="auto", variant="auto", precision="fp32"):
+    """cpd_mttkrp_noalloc into an output with two spare columns (set to 5.0,
+    which must stay untouched); returns (status, output)."""
     out = torch.full((c.dims[mode], R + 2), 5.0, device="cuda")
-    opts = cpd.MttkrpOpts(cpd.PRECISION[precision], cpd.VARIANT[variant], cpd.KERNEL[kernel], 0)
-    st = L.cpd_mttkrp_noalloc(c.handle, cpd._ptrs(facs), ld, R, mode, out.data_ptr(), R + 2,
-                              ctypes.byref(opts), cpd._stream())
+    try:
+        cpd.mttkrp_noalloc(c, facs, mode, out[:, :R], rank=R, precision=precision, variant=variant,
+                           kernel=kernel)
+        st = cpd.CPD_OK
+    except cpd.CpdError as e:
+        st = e.status
     return st, out
 
 
@@ -58,9 +57,11 @@ def _check_tree(cpd, L, t, R, ld, seed):
             for variant in (variants if kernel != "row" else ["auto"]):
                 for prec in ("fp32", "bf16"):
                     fk = facs if prec == "fp32" else [f.to(torch.bfloat16) for f in facs]
+                    # the allocation-free call first: on a fresh tree its tile tables and
+                    # leaf-factor copy come from the workspace, not from the handle's cache
+                    st, out = _noalloc(cpd, L, c, fk, mode, R, ld, kernel, variant, prec)
                     ref = torch.empty((t.dims[mode], R), device="cuda")
                     cpd.mttkrp(c, fk, mode, out=ref, rank=R, precision=prec, kernel=kernel, variant=variant)
-                    st, out = _noalloc(cpd, L, c, fk, mode, R, ld, kernel, variant, prec)
                     torch.cuda.synchronize()
                     assert st == cpd.CPD_OK, (mode, kernel, variant, prec, L.cpd_last_error())
                     assert (out[:, R:] == 5.0).all()
@@ -71,7 +72,7 @@ def _check_tree(cpd, L, t, R, ld, seed):
 
 def test_noalloc_matches_mttkrp_twice_second_smaller():
     cpd, L = _cpd()
-    assert L.cpd_mttkrp_noalloc_workspace_bytes() == 64 << 20
+    assert cpd.noalloc_workspace_bytes() == 64 << 20
     big = synth.gen_sparse((900, 700, 1300), 300_000, (1.1, 1.1, 1.1), "lognormal:1.0", 5, topup=True)
     small = synth.gen_sparse((60, 50, 40, 30), 20_000, (0.5, 0.8, 0.0, 1.2), "lognormal:1.0", 7, topup=True)
     _check_tree(cpd, L, big, 35, 40, 1)
