@@ -42,6 +42,11 @@ THREADS = min(16, len(os.sched_getaffinity(0)))
 EPS32 = 2.0 ** -24
 
 
+def _say(*what):
+    """One progress line per finished step (these tests run minutes each)."""
+    print("  [full-size]", *what, flush=True)
+
+
 def _cpd():
     from paper_1812_05961_amd import cpd
     cpd.lib()
@@ -67,6 +72,7 @@ class Full:
         self.inds_h = x.inds.cpu().numpy().astype(np.int64)
         self.vals_h = x.vals.cpu().double().numpy()
         self.row_nnz = [np.bincount(self.inds_h[m], minlength=self.dims[m]) for m in range(self.nm)]
+        _say("generated", name, self.vals_h.size, "nonzeros")
 
 
 _CACHE = {}
@@ -130,6 +136,7 @@ def test_full_size_csf_bit_exact():
             else:
                 assert v.cpu().numpy().tobytes() == ref["vals"].tobytes()
             del fids, fptr, v
+        _say("tree", order, "bit-exact")
         if k == 0:
             for T in (32, 128, 256):
                 np.testing.assert_array_equal(c.tiles(T).cpu().numpy(), ocsf.tile_starts(ref, T))
@@ -153,6 +160,7 @@ def test_full_size_mttkrp_all_rows_als_layout(name, precision):
         c.free()
         ref = ocoo.mttkrp(t.dims, t.inds_h, t.vals_h, used, m, threads=THREADS)
         _check_all_rows(t, m, y, ref, (name, precision, "mode", m))
+        _say(name, precision, "mode", m, "all rows checked")
 
 
 @pytest.mark.parametrize("precision", ["fp32", "bf16"])
@@ -172,6 +180,7 @@ def test_full_size_single_tree_every_level(precision):
         for kernel, variant in runs:
             y = cpd.mttkrp(c, facs, m, rank=t.R, precision=precision, kernel=kernel, variant=variant)
             _check_all_rows(t, m, y.cpu().numpy(), ref, ("single", precision, depth, kernel, variant))
+            _say("single tree", precision, "depth", depth, kernel, variant, "all rows checked")
             del y
     c.free()
 
@@ -187,8 +196,10 @@ def test_full_size_als_trajectory_nell2():
     iters = synth.CONFIGS["nell2"]["iters"]
     init = synth.init_factors(t.dims, t.R, synth.CONFIGS["nell2"]["init_seed"])
     got = cpd.als(t.inds, t.vals, t.dims, t.R, iters, 0.0, init=[a.float().cuda() for a in init])
+    _say("GPU CP-ALS done")
     init32 = [a.float().double().numpy() for a in init]
     ref = oals.cp_als(t.dims, t.inds_h, t.vals_h, t.R, iters, 0.0, init32, threads=THREADS)
+    _say("oracle CP-ALS done")
     np.testing.assert_allclose(got["fits"], ref["fits"], rtol=0, atol=1e-5)
     assert abs(got["fit"] - ref["fit"]) <= 1e-4, (got["fit"], ref["fit"])
     A = [f.cpu().double().numpy() for f in got["factors"]]
@@ -215,6 +226,7 @@ def test_full_size_als_final_fit_netflix(precision):
         init32 = [a.float().double().numpy() for a in init]
         _NETFLIX_REF.update(oals.cp_als(t.dims, t.inds_h, t.vals_h, t.R, cfg["iters"], 0.0, init32,
                                         threads=THREADS))
+        _say("oracle CP-ALS done")
     got = cpd.als(t.inds, t.vals, t.dims, t.R, cfg["iters"], 0.0, init=[a.float().cuda() for a in init],
                   precision=precision)
     assert abs(got["fit"] - _NETFLIX_REF["fit"]) <= 1e-4, (precision, got["fit"], _NETFLIX_REF["fit"])
@@ -261,5 +273,6 @@ def test_full_size_completion_kernels_sampled_rows():
         want, _ = oc.solve_rows(full, ysel, reg, np.ones(rows.size, dtype=np.int64))
         err = np.linalg.norm(A.cpu().numpy()[rows] - want) / np.linalg.norm(want)
         assert err <= 1e-6, (m, err)
+        _say("completion mode", m, "checked")
         del G, y, A
         c.free()
