@@ -118,18 +118,18 @@ def gather_bytes(counts, R, precision):
     return (counts[nm - 1] + sum(counts[l] for l in range(1, nm - 1))) * width * esz
 
 
-def time_mttkrp(cpd, csf, facs, mode, R, variant, reps=10):
+def time_mttkrp(cpd, csf, facs, mode, R, variant, reps=10, kernel="auto"):
     import statistics as st
 
     import torch
     out = torch.empty((csf.dims[mode], R), dtype=torch.float32, device="cuda")
-    cpd.mttkrp(csf, facs, mode, out=out, rank=R, variant=variant)
+    cpd.mttkrp(csf, facs, mode, out=out, rank=R, variant=variant, kernel=kernel)
     ts = []
     for _ in range(reps):
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record()
-        cpd.mttkrp(csf, facs, mode, out=out, rank=R, variant=variant)
+        cpd.mttkrp(csf, facs, mode, out=out, rank=R, variant=variant, kernel=kernel)
         e1.record()
         e1.synchronize()
         ts.append(e0.elapsed_time(e1))
@@ -138,8 +138,9 @@ def time_mttkrp(cpd, csf, facs, mode, R, variant, reps=10):
 
 def single_tree(cpd, x, R):
     """Every mode's MTTKRP on one tree in ascending-length order: the root,
-    internal and leaf kernels, each conflict-handling variant that applies,
-    timed around the whole call (median of 10)."""
+    internal and leaf kernels (every kernel family and conflict-handling
+    variant that applies; "auto" is what the library picks), timed around
+    the whole call (median of 10)."""
     import torch
     c = cpd.csf_build(x.inds, x.vals, x.dims, None)
     ld = next(w for w in (8, 16, 32, 36, 64) if w >= R)
@@ -156,10 +157,18 @@ def single_tree(cpd, x, R):
         b = alg_bytes(c.counts, x.dims, mode, R)
         # private: a copy of the output in LDS per block when it fits 64 KiB,
         # else one HBM copy per XCD, summed after the kernel
-        variants = ["auto"] if depth == 0 else ["atomic", "private"]
-        for v in variants:
-            ms = time_mttkrp(cpd, c, facs, mode, R, v)
-            row = dict(mode=mode, level=level, variant=v, ms=round(ms, 4),
+        if depth == 0:
+            runs = [("auto", "auto")]
+        elif depth < x.nmodes - 1:
+            runs = [("auto", "auto"), ("lane", "atomic"), ("lane", "private"), ("row", "auto")]
+        else:
+            runs = [("auto", "auto"), ("lane", "atomic"), ("lane", "private")]
+        dims_by_level = [x.dims[m] for m in c.order]
+        for kern, v in runs:
+            ms = time_mttkrp(cpd, c, facs, mode, R, v, kernel=kern)
+            family = kern if kern != "auto" else cpd.mttkrp_plan(dims_by_level, depth, R, ld=ld,
+                                                                    counts_by_level=c.counts)
+            row = dict(mode=mode, level=level, kernel=family, variant=v, ms=round(ms, 4),
                        ns_per_nnz=round(ms * 1e6 / nnz, 4), alg_bytes=b,
                        roofline_frac=round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4))
             if v == "private":

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libcpd.so")
 CPD_OK, CPD_EINVAL, CPD_ENOMEM, CPD_EHIP, CPD_EUNSUPPORTED = range(5)
 FP32, BF16_GATHER = 0, 1
 VARIANT = {"auto": 0, "atomic": 1, "private": 2}
-KERNEL = {"auto": 0, "row": 1, "lane": 2}
+KERNEL = {"auto": 0, "row": 1, "lane": 2, "round": 3}
 PRECISION = {"fp32": FP32, "bf16": BF16_GATHER}
 MAX_MODES = 8
 
@@ -88,7 +88,7 @@ _SIGS = {
     "cpd_mttkrp": (_I32, [_P, _P, _I32, _I32, _I32, _P, _I32, _P, _P]),
     "cpd_mttkrp_noalloc": (_I32, [_P, _P, _I32, _I32, _I32, _P, _I32, _P, _P]),
     "cpd_mttkrp_noalloc_workspace_bytes": (ctypes.c_size_t, []),
-    "cpd_mttkrp_plan": (_I32, [_I32, _P, _I32, _I32, _I32, _I32, _I32, _I32, _I32, _P]),
+    "cpd_mttkrp_plan": (_I32, [_I32, _P, _P, _I32, _I32, _I32, _I32, _I32, _I32, _I32, _P]),
     "cpd_gram": (_I32, [_P, _I64, _I32, _I32, _P, _P]),
     "cpd_solve_normalize": (_I32, [_P, _I32, _I32, _P, _I64, _I32, _I32, _P, _I32, _P, _I32, _P,
                                    _P, _P, _P]),
@@ -248,14 +248,17 @@ def csf_build_rooted(inds, vals, dims, stream=None) -> list:
 
 
 def mttkrp_plan(dims_by_level, depth, rank, ld=None, precision="fp32", kernel="auto",
-                rows_aligned=True, leaf_words=True):
-    """Kernel family ("row" or "lane") cpd_mttkrp runs for this request (host only)."""
+                rows_aligned=True, leaf_words=True, counts_by_level=None):
+    """Kernel family ("row", "lane" or "round") cpd_mttkrp runs for this
+    request (host only); counts_by_level: the tree's node counts, if known."""
     out = _I32()
     nm = len(dims_by_level)
-    _check(lib().cpd_mttkrp_plan(nm, _i64s(dims_by_level), int(depth), int(ld or rank), int(rank),
+    counts = None if counts_by_level is None else _i64s(counts_by_level)
+    _check(lib().cpd_mttkrp_plan(nm, _i64s(dims_by_level), counts, int(depth), int(ld or rank), int(rank),
                                  PRECISION[precision], KERNEL[kernel], int(bool(rows_aligned)),
                                  int(bool(leaf_words)), ctypes.byref(out)))
     return _KERNEL_NAME[out.value]
+
 
 def _mttkrp_call(entry, csf, factors, mode, out, rank, precision, variant, kernel, tile_nnz, stream):
     fdt = torch.float32 if precision == "fp32" else torch.bfloat16

@@ -1,0 +1,262 @@
+// Leaf-level MTTKRP on a CSF tree (the output mode sits at the tree's leaf
+// level; the MTTKRP step of Algorithm 1, Section III):
+//     Y(j_k, :) += x_k * H_f,
+// H_f = Hadamard product of the rows of the levels above leaf k, one row per
+// fiber f (the leaves that share every index but the last).
+//
+// Work split: each wave owns a contiguous range of tiles (T leaves each, T a
+// multiple of 64) and takes it in rounds of 64 leaves.
+//   - Lane j loads leaf j's value, leaf index, leaf word and per-leaf internal
+//     ids with coalesced loads.  The leaves that open a root node and those
+//     that open a fiber (leaf-word level 0, resp. <= N-2, plus the round's first
+//     leaf) form wave-uniform bit masks; popcounts give every leaf its root
+//     node and its fiber.
+//   - The H rows of the round's fibers are gathered a batch at a time into a
+//     per-wave LDS table (G lanes per row, four elements each, so a load
+//     instruction fetches 64/G rows).
+//   - The wave then walks the batch's leaves one per step, the rank spread over
+//     the lanes: value, index and frequency rank read from the leaf's lane, the
+//     row of H from LDS, one FP32 atomic add per leaf -- into a block-private
+//     LDS copy of the most frequent output rows (Zipf-hot rows would otherwise
+//     serialise their atomics in L2), else into Y.
+// The walk issues no loads, so its atomics go out back to back; a wave waits
+// on memory once per batch of fibers (the gathers), not once per leaf.
+#include <type_traits>
+
+#include "csf.h"
+
+namespace cpd {
+namespace {
+
+constexpr int LEAF_WAVES = 4;  // waves per block
+constexpr int32_t LEAF_IDMASK = (1 << 29) - 1;
+
+struct LeafView {
+    const int32_t *root_ids;              // fids[0]
+    const int32_t *leaf_ids;              // fids[N-1]
+    const float *vals;
+    const int32_t *leafw;                 // (level << 29) | frequency rank of the leaf index
+    const int32_t *uprow[CPD_MAX_MODES];  // per-leaf ids of levels 1..N-2
+    const int32_t *hot_perm;              // output row of each frequency rank
+    int64_t nleaves;
+};
+
+struct LeafFac {
+    const void *a[CPD_MAX_MODES];  // factor of each level (levels 0..N-2 are read)
+};
+
+// Four consecutive row elements (float, or bfloat16 widened to float) at
+// element offset off (a multiple of 4; rows 16-byte resp. 8-byte aligned).
+template <typename GT>
+struct Quad;
+template <>
+struct Quad<float> {
+    __device__ static __forceinline__ float4 load(const void *base, int64_t off) {
+        return *reinterpret_cast<const float4 *>(static_cast<const float *>(base) + off);
+    }
+};
+template <>
+struct Quad<uint16_t> {
+    __device__ static __forceinline__ float4 load(const void *base, int64_t off) {
+        const uint2 w = *reinterpret_cast<const uint2 *>(static_cast<const uint16_t *>(base) + off);
+        return make_float4(bf16_lo(w.x), bf16_hi(w.x), bf16_lo(w.y), bf16_hi(w.y));
+    }
+};
+
+__device__ __forceinline__ void wave_sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// UF: gather instructions per level and batch (a batch holds UF * 64/G fibers).
+// Dynamic LDS: LEAF_WAVES x PF x RQ floats (each wave's table of H rows; RQ =
+// R rounded up to a multiple of 4, so rows are 16-byte aligned), then hot x R
+// floats (the hot output rows).
+template <int N, typename GT, int UF>
+__global__ void __launch_bounds__(64 * LEAF_WAVES)
+k_mttkrp_leaf(LeafView cv, LeafFac fv, int64_t ld, const int32_t *__restrict__ starts, int64_t ntiles, int32_t T,
+              int64_t nwaves, float *__restrict__ Y, int64_t ldo, int R, int32_t hot) {
+    extern __shared__ float4 lds4[];
+    __shared__ int32_t s_fpos[LEAF_WAVES][65];
+    float *lds = reinterpret_cast<float *>(lds4);
+    const int RQ = (R + 3) & ~3;
+    const int G = RQ >> 2;      // lanes per row in the gather
+    const int NG = 64 / G;      // rows per gather instruction
+    const int PF = NG * UF;     // fibers per batch
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int g = lane / G, lig = lane - (lane / G) * G;
+    float *Hs = lds + (int64_t)wave * PF * RQ;
+    float *ypriv = lds + (int64_t)LEAF_WAVES * PF * RQ;
+    int32_t *fpos = s_fpos[wave];
+    const int64_t nloc = (int64_t)hot * R;
+    for (int64_t j = threadIdx.x; j < nloc; j += 64 * LEAF_WAVES) ypriv[j] = 0.0f;
+    __syncthreads();
+
+    const int64_t gw = (int64_t)blockIdx.x * LEAF_WAVES + wave;
+    if (gw < nwaves) {  // no early return: the block flushes its hot rows below
+        const int64_t t_begin = gw * ntiles / nwaves, t_end = (gw + 1) * ntiles / nwaves;
+        const int64_t kb = t_begin * (int64_t)T;
+        const int64_t ke = min(t_end * (int64_t)T, cv.nleaves);
+        int32_t c_base = starts[t_begin];  // root node holding leaf kb
+        bool first = true;
+        for (int64_t k0 = kb; k0 < ke; k0 += 64) {
+            const int64_t k = k0 + lane;
+            const bool in = k < ke;
+            // lanes past the range load the range's last leaf (straight-line loads) and drop it
+            const int64_t kk = in ? k : ke - 1;
+            const int32_t w = cv.leafw[kk];
+            const float x = cv.vals[kk];
+            const int32_t oi = cv.leaf_ids[kk];
+            int32_t up[N > 2 ? N - 2 : 1];
+#pragma unroll
+            for (int l = 0; l < N - 2; ++l) up[l] = cv.uprow[l + 1][kk];
+            const int lvl = (int)((uint32_t)w >> 29);
+            const uint64_t nrmask = __ballot(in && lvl == 0);
+            const uint64_t fmask = __ballot(in && (lvl <= N - 2 || lane == 0));
+            const int nin = (int)min<int64_t>(64, ke - k0);
+            // c_base: root node of the leaf before the round (the tile table
+            // gives the node holding leaf kb itself)
+            if (first && (nrmask & 1ull)) c_base -= 1;
+            first = false;
+            const uint64_t upto = ~0ull >> (63 - lane);  // bits 0..lane
+            // root node of each leaf (lanes past the range: that of the last leaf)
+            const int32_t rid = cv.root_ids[c_base + __popcll(nrmask & upto)];
+            c_base += __popcll(nrmask);
+            const int F = __popcll(fmask);
+            if ((fmask >> lane) & 1ull) fpos[__popcll(fmask & upto) - 1] = lane;
+            if (lane == 0) fpos[F] = nin;
+            wave_sync_lds();
+            for (int f0 = 0; f0 < F; f0 += PF) {
+                const int f1 = min(F, f0 + PF);
+                // gather the H rows of fibers f0..f1-1: every load is issued before any
+                // use (lanes without a fiber of the batch load fiber f0's rows again
+                // and store nothing)
+                int32_t ids[UF][N - 1];
+                bool ok[UF];
+#pragma unroll
+                for (int u = 0; u < UF; ++u) {
+                    const int f = f0 + u * NG + g;
+                    ok[u] = g < NG && f < f1;
+                    const int p = fpos[ok[u] ? f : f0];
+                    ids[u][0] = __shfl(rid, p, 64);
+#pragma unroll
+                    for (int l = 1; l < N - 1; ++l) ids[u][l] = __shfl(up[l - 1], p, 64);
+                }
+                float4 rows[UF][N - 1];
+#pragma unroll
+                for (int u = 0; u < UF; ++u)
+#pragma unroll
+                    for (int l = 0; l < N - 1; ++l)
+                        rows[u][l] = Quad<GT>::load(fv.a[l], (int64_t)ids[u][l] * ld + 4 * lig);
+#pragma unroll
+                for (int u = 0; u < UF; ++u) {
+                    float4 h = rows[u][0];
+#pragma unroll
+                    for (int l = 1; l < N - 1; ++l) {
+                        h.x *= rows[u][l].x;
+                        h.y *= rows[u][l].y;
+                        h.z *= rows[u][l].z;
+                        h.w *= rows[u][l].w;
+                    }
+                    if (ok[u]) *reinterpret_cast<float4 *>(Hs + (int64_t)(u * NG + g) * RQ + 4 * lig) = h;
+                }
+                wave_sync_lds();
+                // the batch's leaves, one per step
+                const int jb = __builtin_amdgcn_readfirstlane(fpos[f0]);
+                const int je = __builtin_amdgcn_readfirstlane(fpos[f1]);
+                for (int j = jb; j < je; ++j) {
+                    const int f = __popcll(fmask & (~0ull >> (63 - j))) - 1 - f0;
+                    const float xj = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), j));
+                    const int32_t oj = __builtin_amdgcn_readlane(oi, j);
+                    const int32_t rk = __builtin_amdgcn_readlane(w, j) & LEAF_IDMASK;
+                    if (lane < R) {
+                        const float t = xj * Hs[f * RQ + lane];
+                        if (rk < hot) atomicAdd(&ypriv[(int64_t)rk * R + lane], t);
+                        else atomicAdd(Y + (int64_t)oj * ldo + lane, t);
+                    }
+                }
+                wave_sync_lds();
+            }
+        }
+    }
+    __syncthreads();
+    for (int64_t j = threadIdx.x; j < nloc; j += 64 * LEAF_WAVES) {
+        const float v = ypriv[j];
+        if (v != 0.0f) atomicAdd(Y + (int64_t)cv.hot_perm[j / R] * ldo + (j % R), v);
+    }
+}
+
+template <int N, typename GT>
+cpd_status launch_leaf_n(const LeafView &cv, const LeafFac &fv, int64_t ld, const int32_t *starts, int64_t ntiles,
+                         int32_t T, float *Y, int64_t ldo, int R, int32_t hot, hipStream_t s) {
+    const int RQ = (R + 3) & ~3;
+    const int NG = 64 / (RQ / 4);
+    const int UF = NG >= 7 ? 2 : 4;
+    const int PF = NG * UF;
+    const size_t lds = sizeof(float) * ((size_t)hot * R + (size_t)LEAF_WAVES * PF * RQ);
+    auto kern = UF == 2 ? k_mttkrp_leaf<N, GT, 2> : k_mttkrp_leaf<N, GT, 4>;
+    int dev = 0, ncu = 256;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) ncu = v;
+    }
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64 * LEAF_WAVES, lds) != hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    const int64_t nwaves = std::max<int64_t>(1, std::min<int64_t>(ntiles, (int64_t)ncu * per_cu * LEAF_WAVES));
+    hipLaunchKernelGGL(kern, dim3((unsigned)ceil_div(nwaves, LEAF_WAVES)), dim3(64 * LEAF_WAVES), lds, s, cv, fv,
+                       ld, starts, ntiles, T, nwaves, Y, ldo, R, hot);
+    CPD_LAUNCH_CHECK();
+    return CPD_OK;
+}
+
+}  // namespace
+
+// Leaf-level MTTKRP with the round kernel: Y (out_rows x R floats, stride
+// ldo) must be zeroed.  fac_by_level: factors in tree order (levels 0..N-2
+// read), row stride ld elements with ld % 4 == 0 and ld >= R rounded up to a
+// multiple of 4, bases 16-byte (float) or 8-byte (bfloat16) aligned.
+// starts: the level-0 rows of the tile table for width T (a multiple of 64).
+// hot_perm / hot: the leaf level's frequency ranking and the number of hot
+// rows held in LDS (0: none).
+cpd_status launch_leaf(int N, bool bf16, const int32_t *const *fids, const float *vals, const int32_t *leafw,
+                       const int32_t *const *uprow, const int32_t *hot_perm, int32_t hot, int64_t nleaves,
+                       const void *const *fac_by_level, int64_t ld, const int32_t *starts, int64_t ntiles, int32_t T,
+                       float *Y, int64_t ldo, int R, hipStream_t s) {
+    if (N < 2 || N > 5) CPD_FAIL(CPD_EUNSUPPORTED, "leaf round kernel built for 2..5 modes, not %d", N);
+    if (T < 64 || T % 64) CPD_FAIL(CPD_EINVAL, "leaf round kernel tile width %d must be a multiple of 64", T);
+    if (R < 1 || R > 64 || ld % 4 || ld < ((R + 3) & ~3))
+        CPD_FAIL(CPD_EUNSUPPORTED, "leaf round kernel needs rank <= 64 and ld a multiple of 4 covering the rank");
+    if (!leafw) CPD_FAIL(CPD_EUNSUPPORTED, "leaf round kernel needs the tree's leaf words");
+    if (hot > 0 && !hot_perm) CPD_FAIL(CPD_EINVAL, "hot rows without a ranking");
+    LeafView cv{};
+    LeafFac fv{};
+    cv.root_ids = fids[0];
+    cv.leaf_ids = fids[N - 1];
+    cv.vals = vals;
+    cv.leafw = leafw;
+    cv.hot_perm = hot_perm;
+    cv.nleaves = nleaves;
+    for (int l = 1; l < N - 1; ++l) {
+        if (!uprow[l]) CPD_FAIL(CPD_EUNSUPPORTED, "leaf round kernel needs the per-leaf internal ids");
+        cv.uprow[l] = uprow[l];
+    }
+    for (int l = 0; l < N - 1; ++l) fv.a[l] = fac_by_level[l];
+    if (nleaves == 0) return CPD_OK;
+    switch (N) {
+#define CPD_LEAF_N(n)                                                                                        \
+    case n:                                                                                                  \
+        return bf16 ? launch_leaf_n<n, uint16_t>(cv, fv, ld, starts, ntiles, T, Y, ldo, R, hot, s)           \
+                    : launch_leaf_n<n, float>(cv, fv, ld, starts, ntiles, T, Y, ldo, R, hot, s);
+        CPD_LEAF_N(2)
+        CPD_LEAF_N(3)
+        CPD_LEAF_N(4)
+        CPD_LEAF_N(5)
+#undef CPD_LEAF_N
+    }
+    return CPD_OK;
+}
+
+}  // namespace cpd

@@ -132,6 +132,12 @@ constexpr int root_min_waves() {
     return !std::is_same<GT, uint16_t>::value ? 1 : N == 3 ? 6 : N == 4 ? 5 : 1;
 }
 
+__device__ __forceinline__ void wave_sync_lds_root() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // One leaf's contribution x * A_leaf(j, c) * H(c) for element e of a lane's
 // chunk, added to the accumulator: FP32 products and sums, or (AT = double,
 // float rows only) FP64 products and sums.
@@ -381,10 +387,16 @@ k_mttkrp_root(CsfView cv, FacView fv, const char *__restrict__ a_leaf, uint32_t 
 //                index i of x_k * A_leaf(j_k, :) * H_below(k),
 // H_above the Hadamard product of the node's ancestor rows, H_below that of
 // leaf k's rows at the levels between d and the leaf.  Same lane groups,
-// wave ranges and LDS staging as the root kernel; a level-d index recurs
-// under other ancestors, so each node's partial is added with atomics when
-// the node (or the group's run) ends.  The ancestor rows are gathered when a
-// node starts, the rows below d reused while their ids repeat.
+// wave ranges and LDS staging of the leaf stream as the root kernel; the
+// ancestor rows are gathered when a node starts, the rows below d reused
+// while their ids repeat.  A level-d index recurs under other ancestors, so
+// each node's partial (times H_above) is added to its output row -- batched:
+// when a node (or the group's run) ends, the group writes its partial into a
+// per-wave LDS list of finished nodes, and when the list is nearly full the
+// wave adds the listed rows to Y one row per instruction, the rank spread
+// over the lanes (consecutive addresses, no loads in between).  A direct add
+// from the lane groups would take E atomic instructions per node with
+// addresses a chunk apart.
 template <int N, int G, typename GT>
 __global__ void __launch_bounds__(64 * ROOT_WAVES)
 k_mttkrp_mid(CsfView cv, FacView fv, const char *__restrict__ a_leaf, uint32_t rowb, int d,
@@ -397,15 +409,19 @@ k_mttkrp_mid(CsfView cv, FacView fv, const char *__restrict__ a_leaf, uint32_t r
     constexpr int NU = N - 2;  // internal levels 1..N-2
     constexpr int SS = NG * (C + 1);
     constexpr int32_t IDMASK = (1 << 29) - 1;
+    constexpr int SR = G * W;            // row stride of the list of finished nodes
+    constexpr int CAP = NG * U + NG;  // its length: drained once more than NG entries wait
     using raw_t = typename Chunk<GT>::raw_t;
     constexpr int RW = Chunk<GT>::RAW;
     __shared__ int32_t s_w[ROOT_WAVES][SS];
     __shared__ float s_v[ROOT_WAVES][SS];
     __shared__ int32_t s_u[ROOT_WAVES][NU][SS];
+    __shared__ float4 s_y4[ROOT_WAVES][CAP * SR / 4];
+    __shared__ int32_t s_yr[ROOT_WAVES][CAP];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int g = lane / G, lig = lane % G;  // g == NG: idle lane
     const int64_t gw = (int64_t)blockIdx.x * ROOT_WAVES + wave;
-    if (gw >= nwaves) return;
+    if (gw >= nwaves) return;  // waves are independent: no block barriers below
     const int64_t nleaves = cv.nleaves;
     const int64_t s_begin = gw * nsteps / nwaves, s_end = (gw + 1) * nsteps / nwaves;
     const int64_t span = NG * (int64_t)T;
@@ -414,9 +430,47 @@ k_mttkrp_mid(CsfView cv, FacView fv, const char *__restrict__ a_leaf, uint32_t r
     const int32_t *__restrict__ root_ids = cv.fids[0];
     int32_t *sw = s_w[wave];
     float *sv = s_v[wave];
+    float *sy = reinterpret_cast<float *>(s_y4[wave]);
+    int32_t *syr = s_yr[wave];
     const int gs = g < NG ? g : NG - 1;
+    const uint64_t below = (1ull << (gs * G)) - 1;  // lanes of the groups before this one
     auto col_of = [&](int e) { return (lig * W) + e; };
     const uint32_t lane_off = (uint32_t)lig * Chunk<GT>::BYTES;
+    int nst = 0;  // finished nodes in the list (wave-uniform)
+
+    float acc[E];
+    int32_t out_row = -1;   // index of the open level-d node
+    raw_t Ha[N][RW];        // its ancestor rows (levels 0..d-1)
+    // list the open node of every group with `fin` set (the same call on every lane)
+    auto finish = [&](bool fin) {
+        const uint64_t m = __ballot(fin && lig == 0);
+        if (fin) {
+            const int slot = nst + __popcll(m & below);
+            float *y = sy + slot * SR + lig * W;
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                float h = acc[e];
+#pragma unroll
+                for (int l = 0; l < N - 1; ++l)
+                    if (l < d) h *= Chunk<GT>::get(Ha[l], e);
+                y[e] = h;
+                acc[e] = 0.0f;
+            }
+            if (lig == 0) syr[slot] = out_row;
+        }
+        nst += __popcll(m);
+    };
+    // add the listed rows to Y when fewer than `room` entries are left
+    auto drain = [&](int room) {
+        if (nst <= CAP - room) return;
+        wave_sync_lds_root();
+        for (int q = 0; q < nst; ++q) {
+            const int32_t row = __builtin_amdgcn_readfirstlane(syr[q]);
+            if (lane < R) atomicAdd(Y + (int64_t)row * ldo + lane, sy[q * SR + lane]);
+        }
+        wave_sync_lds_root();
+        nst = 0;
+    };
 
     for (int64_t st = s_begin; st < s_end; ++st) {
         const int64_t base = st * span;
@@ -424,28 +478,13 @@ k_mttkrp_mid(CsfView cv, FacView fv, const char *__restrict__ a_leaf, uint32_t r
         const bool active = g < NG && k0 < nleaves;
         const int64_t kend = active ? min(k0 + (int64_t)T, nleaves) : k0;
         int32_t c0 = active ? starts[st * NG + g] : 0;  // root node of the run's first leaf
-        float acc[E];
 #pragma unroll
         for (int e = 0; e < E; ++e) acc[e] = 0.0f;
-        int32_t out_row = -1;   // index of the open level-d node
-        raw_t Ha[N][RW];        // its ancestor rows (levels 0..d-1)
+        out_row = -1;
         int32_t last_up[NU];    // rows below d, reused while the ids repeat
         raw_t Hl[NU][RW];
 #pragma unroll
         for (int l = 0; l < NU; ++l) last_up[l] = -1;
-        auto flush = [&]() {
-            if (out_row < 0) return;
-            float *y = Y + (int64_t)out_row * ldo;
-#pragma unroll
-            for (int e = 0; e < E; ++e) {
-                float h = acc[e];
-#pragma unroll
-                for (int l = 0; l < N - 1; ++l)
-                    if (l < d) h *= Chunk<GT>::get(Ha[l], e);
-                if (col_of(e) < R) atomicAdd(y + col_of(e), h);
-                acc[e] = 0.0f;
-            }
-        };
         for (int t0 = 0; t0 < T; t0 += C) {
             for (int e2 = lane; e2 < NG * C; e2 += 64) {
                 const int s = e2 / C, j = e2 % C;
@@ -456,12 +495,11 @@ k_mttkrp_mid(CsfView cv, FacView fv, const char *__restrict__ a_leaf, uint32_t r
 #pragma unroll
                 for (int l = 0; l < NU; ++l) s_u[wave][l][s * (C + 1) + j] = in ? cv.uprow[l + 1][k] : 0;
             }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            const int len = (int)(kend - k0) - t0;
+            wave_sync_lds_root();
+            const int len = (int)(kend - k0) - t0;  // this group's leaves left in the chunk
+            // every group steps through the whole chunk (the list is filled and
+            // drained by the whole wave); positions past a group's run do nothing
             for (int j0 = 0; j0 < C; j0 += U) {
-                if (j0 >= len) break;
                 int32_t wu[U];
                 float vu[U];
                 raw_t rowu[U][RW], hu[U][NU][RW];
@@ -488,14 +526,15 @@ k_mttkrp_mid(CsfView cv, FacView fv, const char *__restrict__ a_leaf, uint32_t r
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     const int jr = j0 + u;
-                    if (jr < len) {
-                        const int at = gs * (C + 1) + jr;
-                        const int lvl = (int)((uint32_t)wu[u] >> 29);
-                        const bool first = (t0 | jr) == 0;
+                    const bool live = active && jr < len;
+                    const int at = gs * (C + 1) + jr;
+                    const int lvl = (int)((uint32_t)wu[u] >> 29);
+                    const bool first = (t0 | jr) == 0;
+                    const bool opens = live && (first || lvl <= d);  // a level-d node opens here
+                    finish(opens && out_row >= 0);
+                    if (live) {
                         if (!first && lvl == 0) c0 += 1;
-                        if (first || lvl <= d) {
-                            // a level-d node opens here (or continues from an earlier run)
-                            flush();
+                        if (opens) {
                             out_row = s_u[wave][d - 1][at];
                             Chunk<GT>::load(static_cast<const char *>(fv.a[0]),
                                             __umul24((uint32_t)root_ids[c0], rowb) + lane_off, Ha[0]);
@@ -521,11 +560,15 @@ k_mttkrp_mid(CsfView cv, FacView fv, const char *__restrict__ a_leaf, uint32_t r
                         }
                     }
                 }
+                drain(NG * U);
             }
             __builtin_amdgcn_wave_barrier();
         }
-        if (active) flush();
+        // the node open at the end of the run
+        finish(active && out_row >= 0);
+        drain(NG * U);
     }
+    drain(CAP);
 }
 
 // Rows of the leaf factor in rank order: dst row r = src row perm[r] (16-byte chunks).

@@ -216,6 +216,12 @@ def _row_ok(R, ld, prec):
     return ld >= w and (ld * esize) % 16 == 0
 
 
+def _round_ok(R, ld):
+    """Whether the leaf-level round kernel takes this rank and row stride: ld a
+    multiple of 4 covering the rank rounded up to 4."""
+    return ld % 4 == 0 and ld >= (R + 3) // 4 * 4
+
+
 def _run(cpd, c, facs64, mode, R, precision, kernel, variant, tile=0):
     dt = torch.float32 if precision == "fp32" else torch.bfloat16
     dev = [f.to(dt).to("cuda") for f in facs64]
@@ -240,6 +246,8 @@ def test_mttkrp_every_level(case, R, ld):
         depth = c.order.index(mode)
         kernels = ["lane"] + (["row"] if 3 <= t.nmodes <= 5 and depth < t.nmodes - 1 and (ld or R) >= 8
                               and R in (8, 16, 32, 35, 64) else [])
+        if depth == t.nmodes - 1 and _round_ok(R, ld or R):
+            kernels.append("round")
         # private: a copy of Y in LDS per block when it fits 64 KiB, else one
         # HBM copy per XCD summed afterwards
         variants = ["atomic"] + (["private"] if depth >= 1 else [])
@@ -269,9 +277,10 @@ def test_mttkrp_tile_widths(tile):
     for mode in range(3):
         ref = ocoo.mttkrp(t.dims, inds, vals, [f.numpy() for f in facs], mode)
         depth = c.order.index(mode)
-        # the lane-group (row) kernels take tile widths in multiples of 32
+        # the lane-group (row) kernels take tile widths in multiples of 32; the
+        # leaf-level round kernel rounds any width up to a multiple of 64
         row_ok = depth < 2 and tile % 32 == 0
-        for kernel in (["lane", "row"] if row_ok else ["lane"]):
+        for kernel in (["lane", "row"] if row_ok else ["lane"]) + (["round"] if depth == 2 else []):
             y, _ = _run(cpd, c, facs, mode, 16, "fp32", kernel, "auto", tile)
             assert relerr(y, ref) <= 1e-5, (mode, kernel, tile)
     if tile % 32:
@@ -320,6 +329,46 @@ def test_mttkrp_rejects_bad_arguments():
     with pytest.raises(cpd.CpdError) as e:
         cpd.mttkrp(c, facs, c.order[0], kernel="lane", variant="private")
     assert e.value.status == cpd.CPD_EUNSUPPORTED
+    # the round kernel serves the leaf level only, without a privatised variant,
+    # and needs a row stride that is a multiple of 4
+    for mode, variant in ((c.order[0], "auto"), (c.order[1], "auto"), (leaf, "private")):
+        with pytest.raises(cpd.CpdError) as e:
+            cpd.mttkrp(c, facs, mode, kernel="round", variant=variant)
+        assert e.value.status == cpd.CPD_EUNSUPPORTED
+    f6 = [torch.rand((d, 6), device="cuda") for d in t.dims]
+    with pytest.raises(cpd.CpdError) as e:
+        cpd.mttkrp(c, f6, leaf, rank=5, kernel="round")
+    assert e.value.status == cpd.CPD_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("dims,alphas,order", [((2000, 300, 40), (0.5, 1.0, 0.0), (0, 1, 2)),
+                                               ((600, 500, 3000), (0.0, 0.3, 2.0), (0, 1, 2)),
+                                               ((400, 50, 90, 2500), (0.5, 0.5, 0.5, 1.5), (3, 1, 2, 0)),
+                                               ((7, 9, 4000), (0.0, 0.0, 1.0), (0, 1, 2))])
+@pytest.mark.parametrize("R", [8, 35])
+def test_mttkrp_leaf_round_hot_rows(dims, alphas, order, R):
+    """The leaf-level round kernel where every output row fits the block's LDS
+    table (a 40-row leaf mode), where one leaf row takes most updates (Zipf
+    2.0), on a 4-mode tree, and with long fibers (9 x 7 fibers over 4,000
+    leaves each): against the oracle and the LANE kernel, FP32 and BF16."""
+    cpd = _cpd()
+    t = _tensor(dims, 150_000, alphas, 23)
+    inds, vals = t.numpy()
+    c = cpd.csf_build(_dev(t.inds), _dev(t.vals), t.dims, list(order))
+    leaf = order[-1]
+    ld = (R + 3) // 4 * 4
+    facs = _factors(t.dims, R, 31, ld)
+    ref = ocoo.mttkrp(t.dims, inds, vals, [f[:, :R].numpy() for f in facs], leaf)
+    for prec in ("fp32", "bf16"):
+        for tile in (0, 64, 1024):
+            y, used = _run(cpd, c, facs, leaf, R, prec, "round", "auto", tile)
+            lane, _ = _run(cpd, c, facs, leaf, R, prec, "lane", "atomic", tile)
+            ref_b = ocoo.mttkrp(t.dims, inds, vals, used, leaf)
+            assert relerr(y, ref_b) <= 1e-5, (dims, prec, tile)
+            assert relerr(y, lane) <= 1e-5, (dims, prec, tile)
+            if prec == "fp32":
+                assert relerr(y, ref) <= 1e-5
+    c.free()
 
 
 # ----------------------------------------------------------------- dense steps
