@@ -54,9 +54,8 @@ enum { CPD_FP32 = 0, CPD_BF16_GATHER = 1 };
  * output rows accumulated in LDS at levels >= 2). */
 enum { CPD_VARIANT_AUTO = 0, CPD_VARIANT_ATOMIC = 1, CPD_VARIANT_PRIVATE = 2 };
 
-/* Kernel family: AUTO picks (ROW at the root and at internal levels with
- * long enough nodes, ROUND at the leaf level, LANE otherwise, each where
- * eligible -- see cpd_mttkrp_plan); ROW = groups of
+/* Kernel family: AUTO picks (ROW above the leaf level, ROUND at the leaf
+ * level, LANE otherwise, each where eligible -- see cpd_mttkrp_plan); ROW = groups of
  * lanes each holding 16-byte chunks of the factor rows, several leaves per
  * wave step (root and internal levels; tile widths in multiples of 32);
  * LANE = the rank spread over the lanes, one leaf per wave step (any level);
@@ -188,8 +187,6 @@ cpd_status cpd_mttkrp_noalloc(cpd_csf csf, const void *const *factors, int32_t l
  * decided on the host without touching the device.
  *   nmodes         N (MTTKRP kernels exist for 2..5);
  *   dims_by_level  host, N lengths in tree order (dims[order[l]]);
- *   counts_by_level host, N node counts of the tree (cpd_csf_info), or NULL
- *                  when unknown (AUTO then keeps LANE at internal levels);
  *   depth          level of the output mode (0 = root);
  *   ld, rank, precision, kernel: as for cpd_mttkrp (kernel = the request);
  *   rows_aligned   nonzero when every non-output factor starts 16-byte aligned;
@@ -201,16 +198,15 @@ cpd_status cpd_mttkrp_noalloc(cpd_csf csf, const void *const *factors, int32_t l
  * <= 2^32 (its rows are addressed by 32-bit byte offsets).  ROUND is eligible
  * at the leaf level (depth N-1) when the tree has leaf words, ld is a multiple
  * of 4 and at least the rank rounded up to 4, and the factors are 16-byte
- * aligned.  AUTO picks ROW at the root, ROW at an internal level whose nodes
- * hold at least 4 leaves on average (counts[depth] * 4 <= counts[N-1]),
- * ROUND at the leaf level, each when eligible, LANE otherwise (cpd_mttkrp
- * runs LANE instead of ROUND for CPD_VARIANT_PRIVATE).
+ * aligned.  AUTO picks ROW above the leaf level and ROUND at the leaf level,
+ * each when eligible, LANE otherwise (cpd_mttkrp runs LANE instead of ROUND
+ * for CPD_VARIANT_PRIVATE).
  * *kernel_out (host) = CPD_KERNEL_ROW, CPD_KERNEL_LANE or CPD_KERNEL_ROUND;
  * CPD_EUNSUPPORTED when ROW or ROUND is requested and not eligible, or N is
  * outside 2..5. */
-cpd_status cpd_mttkrp_plan(int32_t nmodes, const int64_t *dims_by_level, const int64_t *counts_by_level,
-                           int32_t depth, int32_t ld, int32_t rank, int32_t precision, int32_t kernel,
-                           int32_t rows_aligned, int32_t leaf_words, int32_t *kernel_out);
+cpd_status cpd_mttkrp_plan(int32_t nmodes, const int64_t *dims_by_level, int32_t depth, int32_t ld,
+                           int32_t rank, int32_t precision, int32_t kernel, int32_t rows_aligned,
+                           int32_t leaf_words, int32_t *kernel_out);
 
 /* ---------------------------------------------------------------------------
  * Dense steps of Algorithm 1 (FP64 on the GPU). */

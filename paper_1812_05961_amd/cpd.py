@@ -88,7 +88,7 @@ _SIGS = {
     "cpd_mttkrp": (_I32, [_P, _P, _I32, _I32, _I32, _P, _I32, _P, _P]),
     "cpd_mttkrp_noalloc": (_I32, [_P, _P, _I32, _I32, _I32, _P, _I32, _P, _P]),
     "cpd_mttkrp_noalloc_workspace_bytes": (ctypes.c_size_t, []),
-    "cpd_mttkrp_plan": (_I32, [_I32, _P, _P, _I32, _I32, _I32, _I32, _I32, _I32, _I32, _P]),
+    "cpd_mttkrp_plan": (_I32, [_I32, _P, _I32, _I32, _I32, _I32, _I32, _I32, _I32, _P]),
     "cpd_gram": (_I32, [_P, _I64, _I32, _I32, _P, _P]),
     "cpd_solve_normalize": (_I32, [_P, _I32, _I32, _P, _I64, _I32, _I32, _P, _I32, _P, _I32, _P,
                                    _P, _P, _P]),
@@ -248,13 +248,12 @@ def csf_build_rooted(inds, vals, dims, stream=None) -> list:
 
 
 def mttkrp_plan(dims_by_level, depth, rank, ld=None, precision="fp32", kernel="auto",
-                rows_aligned=True, leaf_words=True, counts_by_level=None):
+                rows_aligned=True, leaf_words=True):
     """Kernel family ("row", "lane" or "round") cpd_mttkrp runs for this
-    request (host only); counts_by_level: the tree's node counts, if known."""
+    request (host only)."""
     out = _I32()
     nm = len(dims_by_level)
-    counts = None if counts_by_level is None else _i64s(counts_by_level)
-    _check(lib().cpd_mttkrp_plan(nm, _i64s(dims_by_level), counts, int(depth), int(ld or rank), int(rank),
+    _check(lib().cpd_mttkrp_plan(nm, _i64s(dims_by_level), int(depth), int(ld or rank), int(rank),
                                  PRECISION[precision], KERNEL[kernel], int(bool(rows_aligned)),
                                  int(bool(leaf_words)), ctypes.byref(out)))
     return _KERNEL_NAME[out.value]

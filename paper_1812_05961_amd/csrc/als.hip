@@ -365,7 +365,7 @@ extern "C" {
 
 const char *cpd_last_error(void) { return cpd::g_err; }
 
-int32_t cpd_abi_version(void) { return 3; }
+int32_t cpd_abi_version(void) { return 4; }
 
 cpd_status cpd_als(int32_t nmodes, const int64_t *dims, int64_t nnz, const int32_t *const *inds, const float *vals,
                    int32_t rank, int32_t max_iters, double tol, const cpd_als_opts *opts, float *const *factors_out,

@@ -296,7 +296,8 @@ cpd_status launch_root(int N, bool bf16, int RP, int d, const int32_t *const *fi
                        const float *vals, const int32_t *leafw, const int32_t *leaf_perm, const int32_t *const *uprow,
                        const int64_t *counts, const int64_t *dims_by_level, const void *const *fac_by_level,
                        int64_t ld, const int32_t *starts, int64_t ntiles, int32_t T, float *Y, int64_t ldo, int R,
-                       void *perm_buf, hipStream_t s);
+                       void *perm_buf, const int32_t *hot_rank, const int32_t *hot_perm, int32_t hot,
+                       hipStream_t s);
 cpd_status launch_root64(int N, int RP, const int32_t *const *fids, const int32_t *const *fptr, const float *vals,
                          const int32_t *leafw, const int32_t *leaf_perm, const int32_t *const *uprow,
                          const int64_t *counts, const int64_t *dims_by_level, const void *const *fac_by_level,
@@ -311,10 +312,12 @@ cpd_status launch_leaf(int N, bool bf16, const int32_t *const *fids, const float
 // Lanes the root kernel gives one leaf for a padded rank RP.
 int root_lanes_per_leaf(int RP, bool bf16);
 
-// Leaves per node from which AUTO takes the ROW kernel at an internal level
-// (measured on the single ascending trees of the three benchmark shapes: ROW
-// 1.1-2.0x faster than LANE at 5.8-11.7 leaves per node, 2.3x slower at 1.5).
-constexpr int64_t MID_ROW_LEAVES = 4;
+// Internal levels with ROW: the hot-row LDS table (variant AUTO) is used
+// when the level's nodes hold fewer than MID_HOT_LEAVES leaves on average.
+// Measured on the single ascending trees of the benchmark shapes: at 5.8-11.7
+// leaves per node the table made ROW 1.2-1.6x slower (its LDS costs resident
+// waves; a row there gets few flushes), at 1.5 leaves per node 3.2x faster.
+constexpr int64_t MID_HOT_LEAVES = 4;
 
 // Kernel family for a request (host-only rule, also exported as
 // cpd_mttkrp_plan).  The ROW kernels are instantiated for 3..5 modes and
@@ -326,8 +329,8 @@ constexpr int64_t MID_ROW_LEAVES = 4;
 // kernel serves the leaf level: it reads the leaf words and gathers rows in
 // 4-element chunks, so ld must be a multiple of 4 covering the rank rounded
 // up to 4, with 16-byte aligned factors.
-cpd_status mttkrp_plan(int N, const int64_t *dims_by_level, const int64_t *counts_by_level, int d, int64_t ld, int R,
-                       bool bf16, int request, bool rows_aligned, bool leaf_words, int *kernel) {
+cpd_status mttkrp_plan(int N, const int64_t *dims_by_level, int d, int64_t ld, int R, bool bf16, int request,
+                       bool rows_aligned, bool leaf_words, int *kernel) {
     if (N < 2 || N > 5) CPD_FAIL(CPD_EUNSUPPORTED, "MTTKRP kernels are built for 2..5 modes, not %d", N);
     if (d < 0 || d >= N) CPD_FAIL(CPD_EINVAL, "depth %d not in [0, %d)", d, N);
     if (R < 1 || R > CPD_MAX_RANK) CPD_FAIL(CPD_EINVAL, "rank %d not in [1, %d]", R, CPD_MAX_RANK);
@@ -354,12 +357,8 @@ cpd_status mttkrp_plan(int N, const int64_t *dims_by_level, const int64_t *count
         CPD_FAIL(CPD_EUNSUPPORTED,
                  "round kernel needs the leaf level, leaf words, ld a multiple of 4 covering the rank and "
                  "16-byte aligned factors");
-    // internal levels: ROW when the level's nodes average at least MID_ROW_LEAVES
-    // leaves (its per-node flushes are then rare), else LANE
-    const bool mid_row = row_ok && d > 0 && counts_by_level &&
-                         counts_by_level[d] * MID_ROW_LEAVES <= counts_by_level[N - 1];
     if (request != CPD_KERNEL_AUTO) *kernel = request;
-    else *kernel = ((row_ok && d == 0) || mid_row) ? CPD_KERNEL_ROW : round_ok ? CPD_KERNEL_ROUND : CPD_KERNEL_LANE;
+    else *kernel = row_ok ? CPD_KERNEL_ROW : round_ok ? CPD_KERNEL_ROUND : CPD_KERNEL_LANE;
     return CPD_OK;
 }
 
@@ -421,8 +420,7 @@ cpd_status mttkrp_ws(cpd_csf_s *c, const void *const *factors, int32_t ld, int32
     for (int l = 0; l < N; ++l)
         if (c->order[l] != mode && (reinterpret_cast<uintptr_t>(factors[c->order[l]]) & 15)) aligned = false;
     int kernel = CPD_KERNEL_LANE;
-    CPD_TRY(mttkrp_plan(N, dims_by_level, c->counts, d, ld, R, bf16, o.kernel, aligned, c->leafw != nullptr,
-                        &kernel));
+    CPD_TRY(mttkrp_plan(N, dims_by_level, d, ld, R, bf16, o.kernel, aligned, c->leafw != nullptr, &kernel));
 
     // zero the output (columns < R)
     {
@@ -454,10 +452,21 @@ cpd_status mttkrp_ws(cpd_csf_s *c, const void *const *factors, int32_t ld, int32
                 CPD_FAIL(CPD_EUNSUPPORTED, "the leaf factor copy (%zu bytes) does not fit the %zu-byte workspace",
                          need, ws->bytes);
         }
+        // internal levels: the most frequent output rows accumulate in LDS
+        // (PRIVATE), or not (ATOMIC); AUTO: when the level's nodes are short
+        const int32_t *hot_perm = nullptr, *hot_rank = nullptr;
+        int32_t hot = 0;
+        const bool use_hot = o.variant == CPD_VARIANT_PRIVATE ||
+                             (o.variant == CPD_VARIANT_AUTO && c->counts[d] * MID_HOT_LEAVES > c->counts[N - 1]);
+        if (d > 0 && use_hot) {
+            if (ws) csf_level_rank_cached(c, d, &hot_perm, &hot_rank);
+            else CPD_TRY(csf_level_rank(c, d, &hot_perm, &hot_rank, s));
+            if (hot_perm) hot = (int32_t)std::min<int64_t>(out_rows, (int64_t)(HOT_LDS / (sizeof(float) * R)));
+        }
         if (ev0) CPD_HIP(hipEventRecord(ev0, s));
         cpd_status st = launch_root(N, bf16, RP, d, cv.fids, cv.fptr, cv.vals, c->leafw, c->leaf_perm, c->uprow,
                                     c->counts, dims_by_level, fac_by_level, ld, starts, ns, T, Y, ldo, R, perm_buf,
-                                    s);
+                                    hot_rank, hot_perm, hot, s);
         if (st == CPD_OK && ev1) CPD_HIP(hipEventRecord(ev1, s));
         return st;
     }
@@ -606,8 +615,7 @@ cpd_status mttkrp64(cpd_csf_s *c, const float *const *factors, int32_t ld, int32
     cv.leafw = c->leafw;
     const int64_t out_rows = c->dims[mode];
     int kernel = CPD_KERNEL_LANE;
-    CPD_TRY(mttkrp_plan(N, dims_by_level, nullptr, d, ld, R, false, CPD_KERNEL_AUTO, aligned, c->leafw != nullptr,
-                        &kernel));
+    CPD_TRY(mttkrp_plan(N, dims_by_level, d, ld, R, false, CPD_KERNEL_AUTO, aligned, c->leafw != nullptr, &kernel));
     {
         const int64_t tot = out_rows * R;
         hipLaunchKernelGGL(k_zero_rows<double>, dim3((unsigned)ceil_div(tot, 256)), dim3(256), 0, s, Y, out_rows,
@@ -661,20 +669,17 @@ cpd_status mttkrp64(cpd_csf_s *c, const float *const *factors, int32_t ld, int32
 
 }  // namespace cpd
 
-extern "C" cpd_status cpd_mttkrp_plan(int32_t nmodes, const int64_t *dims_by_level, const int64_t *counts_by_level,
-                                      int32_t depth, int32_t ld, int32_t rank, int32_t precision, int32_t kernel,
-                                      int32_t rows_aligned, int32_t leaf_words, int32_t *kernel_out) {
+extern "C" cpd_status cpd_mttkrp_plan(int32_t nmodes, const int64_t *dims_by_level, int32_t depth, int32_t ld,
+                                      int32_t rank, int32_t precision, int32_t kernel, int32_t rows_aligned,
+                                      int32_t leaf_words, int32_t *kernel_out) {
     cpd::clear_error();
     if (!dims_by_level || !kernel_out) CPD_FAIL(CPD_EINVAL, "null argument");
     if (precision != CPD_FP32 && precision != CPD_BF16_GATHER) CPD_FAIL(CPD_EINVAL, "unknown precision %d", precision);
     if (nmodes >= 2 && nmodes <= CPD_MAX_MODES)
-        for (int l = 0; l < nmodes; ++l) {
+        for (int l = 0; l < nmodes; ++l)
             if (dims_by_level[l] < 1) CPD_FAIL(CPD_EINVAL, "length %lld at level %d", (long long)dims_by_level[l], l);
-            if (counts_by_level && counts_by_level[l] < 1)
-                CPD_FAIL(CPD_EINVAL, "node count %lld at level %d", (long long)counts_by_level[l], l);
-        }
-    return cpd::mttkrp_plan(nmodes, dims_by_level, counts_by_level, depth, ld, rank, precision == CPD_BF16_GATHER,
-                            kernel, rows_aligned != 0, leaf_words != 0, kernel_out);
+    return cpd::mttkrp_plan(nmodes, dims_by_level, depth, ld, rank, precision == CPD_BF16_GATHER, kernel,
+                            rows_aligned != 0, leaf_words != 0, kernel_out);
 }
 
 extern "C" cpd_status cpd_mttkrp(cpd_csf csf, const void *const *factors, int32_t ld, int32_t rank,

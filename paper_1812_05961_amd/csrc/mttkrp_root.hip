@@ -40,6 +40,11 @@ struct CsfView {
     const float *vals;
     const int32_t *leafw;  // (level << 29) | leaf id
     int64_t nleaves;
+    // internal levels: the `hot` most frequent output rows (by the level's
+    // frequency ranking) accumulate in LDS, the others in Y
+    const int32_t *hot_rank;  // output row -> frequency rank
+    const int32_t *hot_perm;  // frequency rank -> output row
+    int32_t hot;
 };
 
 struct FacView {
@@ -393,15 +398,17 @@ k_mttkrp_root(CsfView cv, FacView fv, const char *__restrict__ a_leaf, uint32_t 
 // each node's partial (times H_above) is added to its output row -- batched:
 // when a node (or the group's run) ends, the group writes its partial into a
 // per-wave LDS list of finished nodes, and when the list is nearly full the
-// wave adds the listed rows to Y one row per instruction, the rank spread
-// over the lanes (consecutive addresses, no loads in between).  A direct add
-// from the lane groups would take E atomic instructions per node with
-// addresses a chunk apart.
+// wave adds the listed rows one row per instruction, the rank spread over
+// the lanes (consecutive addresses, no loads in between): the most frequent
+// output rows into a block-private LDS table (added to Y once, at the end),
+// the others into Y.  A direct add from the lane groups would take E atomic
+// instructions per node with addresses a chunk apart; every atomic add into
+// Y is a request the memory side completes, the limit at these levels.
 template <int N, int G, typename GT>
 __global__ void __launch_bounds__(64 * ROOT_WAVES)
 k_mttkrp_mid(CsfView cv, FacView fv, const char *__restrict__ a_leaf, uint32_t rowb, int d,
              const int32_t *__restrict__ starts, int32_t T, int64_t nsteps, int64_t nwaves, float *__restrict__ Y,
-             int64_t ldo, int R) {
+             int64_t ldo, int R, const int32_t *__restrict__ hot_rank) {
     constexpr int NG = 64 / G;
     constexpr int C = root_chunk<NG>(), U = root_unroll<N, GT>();
     constexpr int W = Chunk<GT>::W;
@@ -418,10 +425,15 @@ k_mttkrp_mid(CsfView cv, FacView fv, const char *__restrict__ a_leaf, uint32_t r
     __shared__ int32_t s_u[ROOT_WAVES][NU][SS];
     __shared__ float4 s_y4[ROOT_WAVES][CAP * SR / 4];
     __shared__ int32_t s_yr[ROOT_WAVES][CAP];
+    extern __shared__ float mid_hot[];  // cv.hot x R floats
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int g = lane / G, lig = lane % G;  // g == NG: idle lane
+    const int hot = cv.hot;
+    const int64_t nloc = (int64_t)hot * R;
+    for (int64_t j = threadIdx.x; j < nloc; j += 64 * ROOT_WAVES) mid_hot[j] = 0.0f;
+    __syncthreads();
     const int64_t gw = (int64_t)blockIdx.x * ROOT_WAVES + wave;
-    if (gw >= nwaves) return;  // waves are independent: no block barriers below
+    if (gw < nwaves) {  // no early return: the block adds its hot rows to Y at the end
     const int64_t nleaves = cv.nleaves;
     const int64_t s_begin = gw * nsteps / nwaves, s_end = (gw + 1) * nsteps / nwaves;
     const int64_t span = NG * (int64_t)T;
@@ -460,13 +472,20 @@ k_mttkrp_mid(CsfView cv, FacView fv, const char *__restrict__ a_leaf, uint32_t r
         }
         nst += __popcll(m);
     };
-    // add the listed rows to Y when fewer than `room` entries are left
+    // add the listed rows (to the hot table or Y) when fewer than `room` entries are left
     auto drain = [&](int room) {
         if (nst <= CAP - room) return;
         wave_sync_lds_root();
         for (int q = 0; q < nst; ++q) {
             const int32_t row = __builtin_amdgcn_readfirstlane(syr[q]);
-            if (lane < R) atomicAdd(Y + (int64_t)row * ldo + lane, sy[q * SR + lane]);
+            // a uniform address: a scalar load, which waits on no vector memory
+            // operation (the atomics and gathers in flight)
+            const int32_t rk = hot > 0 ? hot_rank[row] : INT32_MAX;
+            if (lane < R) {
+                const float v = sy[q * SR + lane];
+                if (rk < hot) atomicAdd(&mid_hot[(int64_t)rk * R + lane], v);
+                else atomicAdd(Y + (int64_t)row * ldo + lane, v);
+            }
         }
         wave_sync_lds_root();
         nst = 0;
@@ -569,6 +588,12 @@ k_mttkrp_mid(CsfView cv, FacView fv, const char *__restrict__ a_leaf, uint32_t r
         drain(NG * U);
     }
     drain(CAP);
+    }
+    __syncthreads();
+    for (int64_t j = threadIdx.x; j < nloc; j += 64 * ROOT_WAVES) {
+        const float v = mid_hot[j];
+        if (v != 0.0f) atomicAdd(Y + (int64_t)cv.hot_perm[j / R] * ldo + (j % R), v);
+    }
 }
 
 // Rows of the leaf factor in rank order: dst row r = src row perm[r] (16-byte chunks).
@@ -596,13 +621,15 @@ static cpd_status launch_mid_g(const CsfView &cv, const FacView &fv, const char 
         int v = 0;
         if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) ncu = v;
     }
+    const size_t lds = sizeof(float) * (size_t)cv.hot * R;
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64 * ROOT_WAVES, 0) != hipSuccess || per_cu < 1)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64 * ROOT_WAVES, lds) != hipSuccess ||
+        per_cu < 1)
         per_cu = 1;
     per_cu = std::min(per_cu, 6);
     const int64_t nwaves = std::max<int64_t>(1, std::min<int64_t>(nsteps, (int64_t)ncu * per_cu * ROOT_WAVES));
-    hipLaunchKernelGGL(kern, dim3((unsigned)ceil_div(nwaves, ROOT_WAVES)), dim3(64 * ROOT_WAVES), 0, s, cv, fv, a_leaf,
-                       rowb, d, starts, T, nsteps, nwaves, Y, ldo, R);
+    hipLaunchKernelGGL(kern, dim3((unsigned)ceil_div(nwaves, ROOT_WAVES)), dim3(64 * ROOT_WAVES), lds, s, cv, fv,
+                       a_leaf, rowb, d, starts, T, nsteps, nwaves, Y, ldo, R, cv.hot_rank);
     CPD_LAUNCH_CHECK();
     return CPD_OK;
 }
@@ -671,7 +698,9 @@ static cpd_status launch_root_t(int N, bool bf16, int RP, int d, const int32_t *
                                 const int32_t *leaf_perm, const int32_t *const *uprow, const int64_t *counts,
                                 const int64_t *dims_by_level, const void *const *fac_by_level, int64_t ld,
                                 const int32_t *starts, int64_t ntiles, int32_t T, AT *Y, int64_t ldo, int R,
-                                void *perm_buf, hipStream_t s) {
+                                void *perm_buf, const int32_t *hot_rank, const int32_t *hot_perm, int32_t hot,
+                                hipStream_t s) {
+    if (hot > 0 && (d == 0 || !hot_rank || !hot_perm)) CPD_FAIL(CPD_EINVAL, "hot rows need an internal level's ranking");
     if (d < 0 || d > N - 2) CPD_FAIL(CPD_EINVAL, "lane-group kernel for depth %d of %d levels", d, N);
     if (!leafw || !leaf_perm) CPD_FAIL(CPD_EUNSUPPORTED, "root kernel needs leaf ids below 2^29");
     const int64_t rowb = ld * (bf16 ? 2 : 4);
@@ -693,6 +722,9 @@ static cpd_status launch_root_t(int N, bool bf16, int RP, int d, const int32_t *
     cv.vals = vals;
     cv.leafw = leafw;
     cv.nleaves = counts[N - 1];
+    cv.hot_rank = hot_rank;
+    cv.hot_perm = hot_perm;
+    cv.hot = hot;
     for (int l = 1; l < N - 1; ++l) {
         if (!uprow[l]) CPD_FAIL(CPD_EUNSUPPORTED, "root kernel needs the per-leaf internal ids");
         cv.uprow[l] = uprow[l];
@@ -744,9 +776,11 @@ cpd_status launch_root(int N, bool bf16, int RP, int d, const int32_t *const *fi
                        const float *vals, const int32_t *leafw, const int32_t *leaf_perm, const int32_t *const *uprow,
                        const int64_t *counts, const int64_t *dims_by_level, const void *const *fac_by_level,
                        int64_t ld, const int32_t *starts, int64_t ntiles, int32_t T, float *Y, int64_t ldo, int R,
-                       void *perm_buf, hipStream_t s) {
+                       void *perm_buf, const int32_t *hot_rank, const int32_t *hot_perm, int32_t hot,
+                       hipStream_t s) {
     return launch_root_t<float>(N, bf16, RP, d, fids, fptr, vals, leafw, leaf_perm, uprow, counts, dims_by_level,
-                                fac_by_level, ld, starts, ntiles, T, Y, ldo, R, perm_buf, s);
+                                fac_by_level, ld, starts, ntiles, T, Y, ldo, R, perm_buf, hot_rank, hot_perm, hot,
+                                s);
 }
 
 // Root-level MTTKRP with float rows and FP64 products and sums (the exact fit pass).
@@ -756,7 +790,7 @@ cpd_status launch_root64(int N, int RP, const int32_t *const *fids, const int32_
                          int64_t ld, const int32_t *starts, int64_t ntiles, int32_t T, double *Y, int64_t ldo, int R,
                          hipStream_t s) {
     return launch_root_t<double>(N, false, RP, 0, fids, fptr, vals, leafw, leaf_perm, uprow, counts, dims_by_level,
-                                 fac_by_level, ld, starts, ntiles, T, Y, ldo, R, nullptr, s);
+                                 fac_by_level, ld, starts, ntiles, T, Y, ldo, R, nullptr, nullptr, nullptr, 0, s);
 }
 
 }  // namespace cpd

@@ -45,7 +45,7 @@ def test_binding_covers_the_header():
 def test_abi_version_and_error_string_without_gpu():
     L = ctypes.CDLL(LIB)
     L.cpd_abi_version.restype = ctypes.c_int32
-    assert L.cpd_abi_version() == 3
+    assert L.cpd_abi_version() == 4
     L.cpd_last_error.restype = ctypes.c_char_p
     assert L.cpd_last_error() == b""
 
@@ -104,22 +104,14 @@ def test_csf_build_rejects_six_to_eight_modes_without_touching_the_gpu():
 def test_mttkrp_plan_rule():
     """The host-side kernel choice: ROW only for 3..5 modes at non-leaf levels,
     with 16-byte rows inside ld and 32-bit row offsets at every gathered level;
-    ROUND only at the leaf level, with ld a multiple of 4 covering the rank."""
+    ROUND only at the leaf level, with ld a multiple of 4 covering the rank;
+    AUTO takes them where eligible, LANE otherwise."""
     from paper_1812_05961_amd import cpd
     plan = cpd.mttkrp_plan
     nell = (9000, 12000, 29000)
     assert plan(nell, 0, 35, ld=36) == "row"
-    assert plan(nell, 1, 35, ld=36) == "lane"      # node counts unknown: LANE below the root
-    # internal levels: ROW when the level's nodes average >= 4 leaves
-    assert plan(nell, 1, 35, ld=36, counts_by_level=(9000, 13053243, 76000000)) == "row"
-    assert plan(nell, 1, 35, ld=36, counts_by_level=(9000, 19000000, 76000000)) == "row"
-    assert plan(nell, 1, 35, ld=36, counts_by_level=(9000, 19000001, 76000000)) == "lane"
-    four = (1000, 10000, 50000, 100000)
-    fc = (1000, 4291277, 34252577, 50000000)
-    assert [plan(four, d, 32, counts_by_level=fc) for d in range(4)] == ["row", "row", "lane", "round"]
-    with pytest.raises(cpd.CpdError) as e:
-        plan(four, 1, 32, counts_by_level=(1000, 0, 34252577, 50000000))
-    assert e.value.status == cpd.CPD_EINVAL
+    assert plan(nell, 1, 35, ld=36) == "row"       # internal levels too
+    assert plan(nell, 1, 35, ld=36, kernel="lane") == "lane"
     assert plan(nell, 1, 35, ld=36, kernel="row") == "row"
     assert plan(nell, 2, 35, ld=36) == "round"     # the leaf level
     assert plan(nell, 2, 35, ld=36, kernel="lane") == "lane"

@@ -252,7 +252,11 @@ def test_mttkrp_every_level(case, R, ld):
         # HBM copy per XCD summed afterwards
         variants = ["atomic"] + (["private"] if depth >= 1 else [])
         for kernel in kernels:
-            for variant in (variants if kernel == "lane" else ["auto"]):
+            # row kernel below the root: without (atomic) and with (private) the
+            # LDS table of the level's most frequent output rows
+            kvars = variants if kernel == "lane" else (["atomic", "private"] if kernel == "row" and depth >= 1
+                                                       else ["auto"])
+            for variant in kvars:
                 for prec in ("fp32", "bf16"):
                     if kernel == "row" and not _row_ok(R, ld or R, prec):
                         continue
