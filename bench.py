@@ -118,18 +118,18 @@ def gather_bytes(counts, R, precision):
     return (counts[nm - 1] + sum(counts[l] for l in range(1, nm - 1))) * width * esz
 
 
-def time_mttkrp(cpd, csf, facs, mode, R, variant, reps=10, kernel="auto"):
+def time_mttkrp(cpd, csf, facs, mode, R, variant, reps=10, kernel="auto", tile=0):
     import statistics as st
 
     import torch
     out = torch.empty((csf.dims[mode], R), dtype=torch.float32, device="cuda")
-    cpd.mttkrp(csf, facs, mode, out=out, rank=R, variant=variant, kernel=kernel)
+    cpd.mttkrp(csf, facs, mode, out=out, rank=R, variant=variant, kernel=kernel, tile_nnz=tile)
     ts = []
     for _ in range(reps):
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record()
-        cpd.mttkrp(csf, facs, mode, out=out, rank=R, variant=variant, kernel=kernel)
+        cpd.mttkrp(csf, facs, mode, out=out, rank=R, variant=variant, kernel=kernel, tile_nnz=tile)
         e1.record()
         e1.synchronize()
         ts.append(e0.elapsed_time(e1))
@@ -162,7 +162,7 @@ def single_tree(cpd, x, R):
         elif depth < x.nmodes - 1:
             runs = [("auto", "auto"), ("lane", "atomic"), ("lane", "private"), ("row", "atomic"), ("row", "private")]
         else:
-            runs = [("auto", "auto"), ("lane", "atomic"), ("lane", "private")]
+            runs = [("auto", "auto"), ("tiled", "auto"), ("lane", "atomic"), ("lane", "private")]
         dims_by_level = [x.dims[m] for m in c.order]
         for kern, v in runs:
             ms = time_mttkrp(cpd, c, facs, mode, R, v, kernel=kern)

@@ -62,8 +62,15 @@ enum { CPD_VARIANT_AUTO = 0, CPD_VARIANT_ATOMIC = 1, CPD_VARIANT_PRIVATE = 2 };
  * ROUND = leaf level only: a wave takes its leaves in rounds of 64, gathers
  * the rows of the round's fibers into LDS, then adds one row per leaf with
  * atomics issued back to back (tile widths rounded up to multiples of 64;
- * no privatised variant: CPD_VARIANT_PRIVATE with AUTO runs LANE). */
-enum { CPD_KERNEL_AUTO = 0, CPD_KERNEL_ROW = 1, CPD_KERNEL_LANE = 2, CPD_KERNEL_ROUND = 3 };
+ * no privatised variant: CPD_VARIANT_PRIVATE with AUTO runs LANE);
+ * TILED = leaf level only, on request: the leaves regrouped by tiles of leaf
+ * indices whose output rows fit a block's LDS (the tree's leaf-mode tiling,
+ * built on the first such call and kept with the tree: 12 bytes per nonzero
+ * plus 4 bytes per fiber and level), every nonzero added in LDS, each tile's
+ * rows added to the output once per block; tile_nnz = the tile height in
+ * leaf indices (0 = the rows 40 KiB of LDS hold), capped by the LDS; no
+ * privatised variant, as ROUND. */
+enum { CPD_KERNEL_AUTO = 0, CPD_KERNEL_ROW = 1, CPD_KERNEL_LANE = 2, CPD_KERNEL_ROUND = 3, CPD_KERNEL_TILED = 4 };
 
 #define CPD_MAX_MODES 8
 #define CPD_MAX_RANK 64
@@ -198,12 +205,14 @@ cpd_status cpd_mttkrp_noalloc(cpd_csf csf, const void *const *factors, int32_t l
  * <= 2^32 (its rows are addressed by 32-bit byte offsets).  ROUND is eligible
  * at the leaf level (depth N-1) when the tree has leaf words, ld is a multiple
  * of 4 and at least the rank rounded up to 4, and the factors are 16-byte
- * aligned.  AUTO picks ROW above the leaf level and ROUND at the leaf level,
- * each when eligible, LANE otherwise (cpd_mttkrp runs LANE instead of ROUND
- * for CPD_VARIANT_PRIVATE).
- * *kernel_out (host) = CPD_KERNEL_ROW, CPD_KERNEL_LANE or CPD_KERNEL_ROUND;
- * CPD_EUNSUPPORTED when ROW or ROUND is requested and not eligible, or N is
- * outside 2..5. */
+ * aligned; TILED under the same conditions.  AUTO picks ROW above the leaf
+ * level and ROUND at the leaf level, each when eligible, LANE otherwise
+ * (cpd_mttkrp runs LANE instead of ROUND or TILED for CPD_VARIANT_PRIVATE;
+ * cpd_mttkrp_noalloc runs ROUND instead of TILED when the tree holds no
+ * tiling yet).
+ * *kernel_out (host) = CPD_KERNEL_ROW, CPD_KERNEL_LANE, CPD_KERNEL_ROUND or
+ * CPD_KERNEL_TILED; CPD_EUNSUPPORTED when ROW, ROUND or TILED is requested and
+ * not eligible, or N is outside 2..5. */
 cpd_status cpd_mttkrp_plan(int32_t nmodes, const int64_t *dims_by_level, int32_t depth, int32_t ld,
                            int32_t rank, int32_t precision, int32_t kernel, int32_t rows_aligned,
                            int32_t leaf_words, int32_t *kernel_out);
@@ -387,8 +396,10 @@ double cpd_zipf_alpha(double top1, int64_t dim);
 
 /* CSF mode orders a candidate can use for MTTKRP of mode n: all modes by
  * ascending length (ties to the lower mode); n first then the rest ascending;
- * the rest ascending then n last; all by descending length. */
-enum { CPD_ORDER_ASC = 0, CPD_ORDER_FIRST = 1, CPD_ORDER_LAST = 2, CPD_ORDER_DESC = 3 };
+ * the rest ascending then n last; all by descending length; n first then the
+ * rest by descending length (the trees cpd_als builds by default). */
+enum { CPD_ORDER_ASC = 0, CPD_ORDER_FIRST = 1, CPD_ORDER_LAST = 2, CPD_ORDER_DESC = 3, CPD_ORDER_ROOTED = 4,
+       CPD_ORDER_KINDS = 5 };
 
 typedef struct {
     int32_t order_kind;              /* CPD_ORDER_* */
@@ -398,13 +409,15 @@ typedef struct {
 } cpd_choice;
 
 #define CPD_SEL_MAX_CAND 24
-#define CPD_SEL_NFEAT 40
+#define CPD_SEL_NFEAT 42
 
 /* Candidates for MTTKRP of `mode` at `rank` (3..5 modes): every distinct
- * order of the four kinds; at the root the root-level kernel with tile widths
- * 32, 128, 512 (or atomic lanes with 64, 256, 1024 when the tree exceeds that
- * kernel's index limits); below the root atomic lanes, and privatised lanes
- * when dims[mode] * rank * 4 <= 64 KiB, each with tile widths 64, 256, 1024.
+ * order of the five kinds; at the root the ROW kernel with tile widths 32,
+ * 128, 512 (or atomic LANE with 64, 256, 1024 when the tree exceeds the ROW
+ * kernels' index limits); at internal levels ROW without and with the LDS
+ * table of hot rows (atomic, private) and atomic LANE, tile 256; at the leaf
+ * level ROUND with tile widths 64, 256, 1024 and atomic LANE, tile 256; below
+ * the root also privatised LANE (tile 256) when dims[mode] * rank * 4 <= 64 KiB.
  * out: host, CPD_SEL_MAX_CAND entries; *n receives the count.
  * Factor rows are assumed padded as cpd_als pads them (stride a multiple of
  * 4 floats, at least the rank rounded up to 8/16/32/36/64). */
@@ -416,9 +429,11 @@ cpd_status cpd_select_candidates(const cpd_stats *st, int32_t rank, int32_t mode
 cpd_status cpd_select_features(const cpd_stats *st, int32_t rank, int32_t mode,
                                const cpd_choice *cand, int32_t n, float *feat);
 
-/* The fallback: ascending-length order; below the root privatised lanes iff
+/* The fallback: ascending-length order; below the root privatised LANE iff
  * dims[mode] * 1024 (the private copies) <= 0.02 * nnz and the copy fits in
- * 64 KiB of LDS, else atomic lanes; default tile widths. */
+ * 64 KiB of LDS (the rule of Section V-D2), else atomics with the level's
+ * default kernel (ROW at internal levels, ROUND at the leaf level); default
+ * tile widths (root 128, below 256).  Always one of the candidates. */
 cpd_status cpd_select_heuristic(const cpd_stats *st, int32_t rank, int32_t mode, cpd_choice *out);
 
 /* Pick the candidate with the smallest predicted time.

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libcpd.so")
 CPD_OK, CPD_EINVAL, CPD_ENOMEM, CPD_EHIP, CPD_EUNSUPPORTED = range(5)
 FP32, BF16_GATHER = 0, 1
 VARIANT = {"auto": 0, "atomic": 1, "private": 2}
-KERNEL = {"auto": 0, "row": 1, "lane": 2, "round": 3}
+KERNEL = {"auto": 0, "row": 1, "lane": 2, "round": 3, "tiled": 4}
 PRECISION = {"fp32": FP32, "bf16": BF16_GATHER}
 MAX_MODES = 8
 
@@ -65,11 +65,11 @@ class Choice(ctypes.Structure):
                     kernel=_KERNEL_NAME[self.opts.kernel], tile_nnz=self.opts.tile_nnz)
 
 
-ORDER_KINDS = ("asc", "first", "last", "desc")
+ORDER_KINDS = ("asc", "first", "last", "desc", "rooted")
 _VARIANT_NAME = {v: k for k, v in VARIANT.items()}
 _KERNEL_NAME = {v: k for k, v in KERNEL.items()}
 SEL_MAX_CAND = 24
-SEL_NFEAT = 40
+SEL_NFEAT = 42
 SELECT = {"none": 0, "network": 1, "heuristic": 2}
 
 
@@ -249,8 +249,8 @@ def csf_build_rooted(inds, vals, dims, stream=None) -> list:
 
 def mttkrp_plan(dims_by_level, depth, rank, ld=None, precision="fp32", kernel="auto",
                 rows_aligned=True, leaf_words=True):
-    """Kernel family ("row", "lane" or "round") cpd_mttkrp runs for this
-    request (host only)."""
+    """Kernel family ("row", "lane", "round" or "tiled") cpd_mttkrp runs for
+    this request (host only)."""
     out = _I32()
     nm = len(dims_by_level)
     _check(lib().cpd_mttkrp_plan(nm, _i64s(dims_by_level), int(depth), int(ld or rank), int(rank),

@@ -40,6 +40,22 @@ struct cpd_csf_s {
         int32_t *starts;                  // (N-1) x ntiles
     };
     std::vector<Tiles> tiles;
+    // The leaves regrouped by leaf-index tile (B consecutive leaf indices per
+    // tile), tree order kept inside each tile: the leaf-mode tiling of the
+    // leaf-level MTTKRP (one tile's output rows fit in LDS).  Built on first
+    // use for a tile height B, cached.
+    struct LeafTiling {
+        int32_t B = 0;
+        int64_t ntiles = 0;
+        int32_t *toff = nullptr;                 // ntiles + 1 offsets into the regrouped leaves
+        float *tv = nullptr;                     // value of each regrouped leaf
+        int32_t *tw = nullptr;                   // its leaf index minus the tile's first index
+        int32_t *tf = nullptr;                   // its fiber (level N-2 node) in the tree
+        int32_t *hid[CPD_MAX_MODES] = {};        // per fiber: the index at levels 0..N-2
+        char *slab = nullptr;
+        size_t bytes = 0;
+    };
+    std::vector<LeafTiling> leaf_tilings;
     std::mutex mu;
 
     int depth_of(int mode) const {
@@ -118,5 +134,11 @@ cpd_status csf_tiles_into(cpd_csf_s *c, int32_t tile, int32_t *dst, size_t dst_b
 // Tile start nodes for a tile width (cached in the handle; created on first use).
 cpd_status csf_tiles(cpd_csf_s *c, int32_t tile, const int32_t **starts, int64_t *ntiles,
                      hipStream_t s);
+
+// The leaf-mode tiling of a tree for tile height B (cached in the handle;
+// built on first use; needs the tree's leaf words); *out receives a copy of
+// its descriptor.  `cached_only`: the cached one or an empty descriptor
+// (B == 0), building nothing.
+cpd_status csf_leaf_tiling(cpd_csf_s *c, int32_t B, bool cached_only, cpd_csf_s::LeafTiling *out, hipStream_t s);
 
 }  // namespace cpd

@@ -633,6 +633,7 @@ void release_arrays(cpd_csf_s *c, hipStream_t s) {
         if (c->lvl_rank[l]) (void)hipFreeAsync(c->lvl_rank[l], s);
     }
     for (auto &t : c->tiles) (void)hipFreeAsync(t.starts, s);
+    for (auto &t : c->leaf_tilings) (void)hipFreeAsync(t.slab, s);
     (void)hipGetLastError();
 }
 

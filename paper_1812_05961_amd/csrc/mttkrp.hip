@@ -286,6 +286,7 @@ cpd_status launch_lane(int G, bool priv, int32_t hot, dim3 grid, size_t lds, hip
 }
 
 constexpr size_t PRIV_LDS_MAX = 64 * 1024;
+constexpr size_t TILED_LDS = 40 * 1024;  // LDS per block of the tiled leaf kernel (tile rows + H tables)
 constexpr size_t HOT_LDS = 16 * 1024;   // hot output rows privatised per block
 constexpr int64_t HOT_BLOCKS = 16384;   // blocks looping over the streams (measured best of 2,048-65,536)
 constexpr double PRIV_THRESH = 0.02;  // privatise iff rows * copies <= 0.02 * nnz
@@ -308,6 +309,10 @@ cpd_status launch_leaf(int N, bool bf16, const int32_t *const *fids, const float
                        const int32_t *const *uprow, const int32_t *hot_perm, int32_t hot, int64_t nleaves,
                        const void *const *fac_by_level, int64_t ld, const int32_t *starts, int64_t ntiles, int32_t T,
                        float *Y, int64_t ldo, int R, hipStream_t s);
+
+int32_t tiled_height(int R, size_t lds_max);
+cpd_status launch_tiled(int N, bool bf16, const cpd_csf_s::LeafTiling &lt, int64_t nleaves,
+                        const void *const *fac_by_level, int64_t ld, float *Y, int64_t ldo, int R, hipStream_t s);
 
 // Lanes the root kernel gives one leaf for a padded rank RP.
 int root_lanes_per_leaf(int RP, bool bf16);
@@ -336,7 +341,7 @@ cpd_status mttkrp_plan(int N, const int64_t *dims_by_level, int d, int64_t ld, i
     if (R < 1 || R > CPD_MAX_RANK) CPD_FAIL(CPD_EINVAL, "rank %d not in [1, %d]", R, CPD_MAX_RANK);
     if (ld < R) CPD_FAIL(CPD_EINVAL, "ld %lld below rank %d", (long long)ld, R);
     if (request != CPD_KERNEL_AUTO && request != CPD_KERNEL_ROW && request != CPD_KERNEL_LANE &&
-        request != CPD_KERNEL_ROUND)
+        request != CPD_KERNEL_ROUND && request != CPD_KERNEL_TILED)
         CPD_FAIL(CPD_EINVAL, "unknown kernel %d", request);
     const int RP = row_width(R, bf16);
     const int64_t rowb = ld * (bf16 ? 2 : 4);
@@ -353,10 +358,10 @@ cpd_status mttkrp_plan(int N, const int64_t *dims_by_level, int d, int64_t ld, i
                  "rows * row bytes <= 2^32 at every gathered level",
                  RP);
     const bool round_ok = d == N - 1 && leaf_words && rows_aligned && ld % 4 == 0 && ld >= ((R + 3) & ~3);
-    if (request == CPD_KERNEL_ROUND && !round_ok)
+    if ((request == CPD_KERNEL_ROUND || request == CPD_KERNEL_TILED) && !round_ok)
         CPD_FAIL(CPD_EUNSUPPORTED,
-                 "round kernel needs the leaf level, leaf words, ld a multiple of 4 covering the rank and "
-                 "16-byte aligned factors");
+                 "round and tiled kernels need the leaf level, leaf words, ld a multiple of 4 covering the rank "
+                 "and 16-byte aligned factors");
     if (request != CPD_KERNEL_AUTO) *kernel = request;
     else *kernel = row_ok ? CPD_KERNEL_ROW : round_ok ? CPD_KERNEL_ROUND : CPD_KERNEL_LANE;
     return CPD_OK;
@@ -470,10 +475,39 @@ cpd_status mttkrp_ws(cpd_csf_s *c, const void *const *factors, int32_t ld, int32
         if (st == CPD_OK && ev1) CPD_HIP(hipEventRecord(ev1, s));
         return st;
     }
-    // the privatised variant at the leaf level runs LANE (AUTO) or is refused (ROUND asked for)
-    if (kernel == CPD_KERNEL_ROUND && o.variant == CPD_VARIANT_PRIVATE) {
-        if (o.kernel == CPD_KERNEL_ROUND) CPD_FAIL(CPD_EUNSUPPORTED, "the round kernel has no privatised variant");
+    // the privatised variant at the leaf level runs LANE (AUTO) or is refused (ROUND, TILED asked for)
+    if ((kernel == CPD_KERNEL_ROUND || kernel == CPD_KERNEL_TILED) && o.variant == CPD_VARIANT_PRIVATE) {
+        if (o.kernel != CPD_KERNEL_AUTO)
+            CPD_FAIL(CPD_EUNSUPPORTED, "the round and tiled kernels have no privatised variant");
         kernel = CPD_KERNEL_LANE;
+    }
+    if (kernel == CPD_KERNEL_TILED) {
+        // the tile height that fits a block's LDS; the tiling is built on first
+        // use (with a workspace only a cached one is used, else ROUND runs)
+        int dev = 0, lds_max = 64 * 1024;
+        if (hipGetDevice(&dev) == hipSuccess) {
+            int v = 0;
+            if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0)
+                lds_max = v;
+        }
+        (void)hipGetLastError();
+        // tile height: tile_nnz when given (capped by the LDS), else the rows
+        // that fit TILED_LDS bytes of tile (several blocks resident per CU)
+        const int32_t Bmax = tiled_height(R, (size_t)std::min(lds_max, 160 * 1024));
+        const int32_t Bdef = tiled_height(R, TILED_LDS);
+        const int32_t B = o.tile_nnz > 0 ? std::min<int32_t>(o.tile_nnz, Bmax) : std::min(Bdef, Bmax);
+        cpd_csf_s::LeafTiling lt;
+        if (B >= 32) CPD_TRY(csf_leaf_tiling(c, B, ws != nullptr, &lt, s));
+        if (lt.B > 0) {
+            const void *fac_by_level[CPD_MAX_MODES];
+            for (int l = 0; l < N; ++l) fac_by_level[l] = fv.a[l];
+            if (ev0) CPD_HIP(hipEventRecord(ev0, s));
+            cpd_status st = launch_tiled(N, bf16, lt, cv.nleaves, fac_by_level, ld, Y, ldo, R, s);
+            if (st == CPD_OK && ev1) CPD_HIP(hipEventRecord(ev1, s));
+            return st;
+        }
+        if (!ws) CPD_FAIL(CPD_EUNSUPPORTED, "no leaf-mode tiling fits %d bytes of LDS at rank %d", lds_max, R);
+        kernel = CPD_KERNEL_ROUND;  // allocation-free call on a tree without a cached tiling
     }
     if (kernel == CPD_KERNEL_ROUND) {
         // tiles of whole 64-leaf rounds

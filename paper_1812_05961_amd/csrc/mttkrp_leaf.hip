@@ -212,6 +212,154 @@ cpd_status launch_leaf_n(const LeafView &cv, const LeafFac &fv, int64_t ld, cons
     return CPD_OK;
 }
 
+// ------------------------------------------------------------ leaf-mode tiling
+// The leaf level on the tree's leaf-mode tiling (the leaves regrouped by tiles
+// of B leaf indices, tree order inside a tile): each block owns a contiguous
+// range of the regrouped leaves and takes it tile by tile, the tile's B x R
+// output rows in LDS, so every nonzero is an LDS add and the tile's rows go to
+// Y once per block (FP32 atomics, nonzero entries only).  Within a tile the
+// waves take rounds of 64 leaves as the ROUND kernel does: value, local row
+// and fiber loaded with coalesced loads, the fibers' level indices gathered,
+// each fiber's H row gathered once into the wave's LDS table (runs of leaves
+// of one fiber share it), then one LDS atomic add per leaf.
+struct TiledView {
+    const int32_t *toff;
+    const float *tv;
+    const int32_t *tw;
+    const int32_t *tf;
+    const int32_t *hid[CPD_MAX_MODES];
+    int64_t n;
+    int64_t ntiles;
+    int32_t B;
+};
+
+// Dynamic LDS: TW x PF x RQ floats (each wave's H rows), then B x R floats (the tile).
+template <int N, typename GT, int UF, int TW>
+__global__ void __launch_bounds__(64 * TW)
+k_mttkrp_tiled(TiledView tv, LeafFac fv, int64_t ld, int64_t per_block, float *__restrict__ Y, int64_t ldo, int R) {
+    extern __shared__ float4 lds4[];
+    __shared__ int32_t s_fpos[TW][65];
+    float *lds = reinterpret_cast<float *>(lds4);
+    const int RQ = (R + 3) & ~3;
+    const int G = RQ >> 2;
+    const int NG = 64 / G;
+    const int PF = NG * UF;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int g = lane / G, lig = lane - (lane / G) * G;
+    float *Hs = lds + (int64_t)wave * PF * RQ;
+    float *tab = lds + (int64_t)TW * PF * RQ;
+    int32_t *fpos = s_fpos[wave];
+    const int64_t nloc = (int64_t)tv.B * R;
+    const int64_t b0 = (int64_t)blockIdx.x * per_block, b1 = min(b0 + per_block, tv.n);
+    int64_t pos = b0;
+    while (pos < b1) {  // the same on every thread of the block
+        // the tile holding regrouped leaf pos: the largest t with toff[t] <= pos
+        int64_t lo = 0, hi = tv.ntiles;
+        while (hi - lo > 1) {
+            const int64_t mid = (lo + hi) >> 1;
+            if ((int64_t)tv.toff[mid] <= pos) lo = mid;
+            else hi = mid;
+        }
+        const int64_t t = lo;
+        const int64_t e = min(b1, (int64_t)tv.toff[t + 1]);
+        for (int64_t j = threadIdx.x; j < nloc; j += 64 * TW) tab[j] = 0.0f;
+        __syncthreads();
+        // the waves split [pos, e) into contiguous runs of whole rounds
+        const int64_t per_wave = ceil_div(ceil_div(e - pos, 64), TW) * 64;
+        const int64_t w0 = pos + wave * per_wave, w1 = min(e, w0 + per_wave);
+        for (int64_t k0 = w0; k0 < w1; k0 += 64) {
+            const int64_t k = k0 + lane;
+            const bool in = k < w1;
+            const int64_t kk = in ? k : w1 - 1;
+            const float x = tv.tv[kk];
+            const int32_t row = tv.tw[kk];
+            const int32_t f = tv.tf[kk];
+            int32_t hid[N - 1];
+#pragma unroll
+            for (int l = 0; l < N - 1; ++l) hid[l] = tv.hid[l][f];
+            const int32_t f_prev = __shfl_up(f, 1, 64);
+            const uint64_t fmask = __ballot(in && (lane == 0 || f_prev != f));
+            const int nin = (int)min<int64_t>(64, w1 - k0);
+            const uint64_t upto = ~0ull >> (63 - lane);
+            const int F = __popcll(fmask);
+            if ((fmask >> lane) & 1ull) fpos[__popcll(fmask & upto) - 1] = lane;
+            if (lane == 0) fpos[F] = nin;
+            wave_sync_lds();
+            for (int f0 = 0; f0 < F; f0 += PF) {
+                const int f1 = min(F, f0 + PF);
+                int32_t ids[UF][N - 1];
+                bool ok[UF];
+#pragma unroll
+                for (int u = 0; u < UF; ++u) {
+                    const int ff = f0 + u * NG + g;
+                    ok[u] = g < NG && ff < f1;
+                    const int p = fpos[ok[u] ? ff : f0];
+#pragma unroll
+                    for (int l = 0; l < N - 1; ++l) ids[u][l] = __shfl(hid[l], p, 64);
+                }
+                float4 rows[UF][N - 1];
+#pragma unroll
+                for (int u = 0; u < UF; ++u)
+#pragma unroll
+                    for (int l = 0; l < N - 1; ++l)
+                        rows[u][l] = Quad<GT>::load(fv.a[l], (int64_t)ids[u][l] * ld + 4 * lig);
+#pragma unroll
+                for (int u = 0; u < UF; ++u) {
+                    float4 h = rows[u][0];
+#pragma unroll
+                    for (int l = 1; l < N - 1; ++l) {
+                        h.x *= rows[u][l].x;
+                        h.y *= rows[u][l].y;
+                        h.z *= rows[u][l].z;
+                        h.w *= rows[u][l].w;
+                    }
+                    if (ok[u]) *reinterpret_cast<float4 *>(Hs + (int64_t)(u * NG + g) * RQ + 4 * lig) = h;
+                }
+                wave_sync_lds();
+                const int jb = __builtin_amdgcn_readfirstlane(fpos[f0]);
+                const int je = __builtin_amdgcn_readfirstlane(fpos[f1]);
+                for (int j = jb; j < je; ++j) {
+                    const int fj = __popcll(fmask & (~0ull >> (63 - j))) - 1 - f0;
+                    const float xj = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), j));
+                    const int32_t rj = __builtin_amdgcn_readlane(row, j);
+                    if (lane < R) atomicAdd(&tab[(int64_t)rj * R + lane], xj * Hs[fj * RQ + lane]);
+                }
+                wave_sync_lds();
+            }
+        }
+        __syncthreads();
+        const int64_t base = t * (int64_t)tv.B;
+        for (int64_t j = threadIdx.x; j < nloc; j += 64 * TW) {
+            const float v = tab[j];
+            if (v != 0.0f) atomicAdd(Y + (base + j / R) * ldo + (j % R), v);
+        }
+        __syncthreads();
+        pos = e;
+    }
+}
+
+constexpr int TILED_WAVES = 8;  // waves per block
+
+template <int N, typename GT>
+cpd_status launch_tiled_n(const TiledView &tv, const LeafFac &fv, int64_t ld, float *Y, int64_t ldo, int R, int UF,
+                          size_t lds, hipStream_t s) {
+    auto kern = UF == 2 ? k_mttkrp_tiled<N, GT, 2, TILED_WAVES> : k_mttkrp_tiled<N, GT, 4, TILED_WAVES>;
+    int dev = 0, ncu = 256;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) ncu = v;
+    }
+    CPD_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    // two blocks per CU over the whole range: each block sees one or two tiles,
+    // so the tile zeroing and adding to Y stays small against the leaves
+    const int64_t nblocks = std::max<int64_t>(1, std::min<int64_t>(ceil_div(tv.n, 64 * TILED_WAVES), 2 * ncu));
+    const int64_t per_block = ceil_div(ceil_div(tv.n, nblocks), 64) * 64;
+    hipLaunchKernelGGL(kern, dim3((unsigned)ceil_div(tv.n, per_block)), dim3(64 * TILED_WAVES), lds, s, tv, fv, ld,
+                       per_block, Y, ldo, R);
+    CPD_LAUNCH_CHECK();
+    return CPD_OK;
+}
+
 }  // namespace
 
 // Leaf-level MTTKRP with the round kernel: Y (out_rows x R floats, stride
@@ -255,6 +403,56 @@ cpd_status launch_leaf(int N, bool bf16, const int32_t *const *fids, const float
         CPD_LEAF_N(4)
         CPD_LEAF_N(5)
 #undef CPD_LEAF_N
+    }
+    return CPD_OK;
+}
+
+
+// Tile height of the leaf-mode tiling for rank R: the tile's R-float rows and
+// the waves' H tables within the LDS a block may use (lds_max bytes).
+int32_t tiled_height(int R, size_t lds_max) {
+    const int RQ = (R + 3) & ~3;
+    const int NG = 64 / (RQ / 4);
+    const int PF = NG * (NG >= 7 ? 2 : 4);
+    const size_t static_lds = sizeof(int32_t) * TILED_WAVES * 65 + 1024;
+    const size_t wave_lds = sizeof(float) * (size_t)TILED_WAVES * PF * RQ;
+    if (lds_max <= static_lds + wave_lds) return 0;
+    return (int32_t)((lds_max - static_lds - wave_lds) / (sizeof(float) * R));
+}
+
+// Leaf-level MTTKRP on the leaf-mode tiling (Y zeroed by the caller; factor
+// rules as for launch_leaf).
+cpd_status launch_tiled(int N, bool bf16, const cpd_csf_s::LeafTiling &lt, int64_t nleaves,
+                        const void *const *fac_by_level, int64_t ld, float *Y, int64_t ldo, int R, hipStream_t s) {
+    if (N < 2 || N > 5) CPD_FAIL(CPD_EUNSUPPORTED, "tiled leaf kernel built for 2..5 modes, not %d", N);
+    if (R < 1 || R > 64 || ld % 4 || ld < ((R + 3) & ~3))
+        CPD_FAIL(CPD_EUNSUPPORTED, "tiled leaf kernel needs rank <= 64 and ld a multiple of 4 covering the rank");
+    TiledView tv{};
+    tv.toff = lt.toff;
+    tv.tv = lt.tv;
+    tv.tw = lt.tw;
+    tv.tf = lt.tf;
+    for (int l = 0; l < N - 1; ++l) tv.hid[l] = lt.hid[l];
+    tv.n = nleaves;
+    tv.ntiles = lt.ntiles;
+    tv.B = lt.B;
+    LeafFac fv{};
+    for (int l = 0; l < N - 1; ++l) fv.a[l] = fac_by_level[l];
+    if (nleaves == 0) return CPD_OK;
+    const int RQ = (R + 3) & ~3;
+    const int NG = 64 / (RQ / 4);
+    const int UF = NG >= 7 ? 2 : 4;
+    const size_t lds = sizeof(float) * ((size_t)TILED_WAVES * NG * UF * RQ + (size_t)lt.B * R);
+    switch (N) {
+#define CPD_TILED_N(n)                                                                         \
+    case n:                                                                                    \
+        return bf16 ? launch_tiled_n<n, uint16_t>(tv, fv, ld, Y, ldo, R, UF, lds, s)           \
+                    : launch_tiled_n<n, float>(tv, fv, ld, Y, ldo, R, UF, lds, s);
+        CPD_TILED_N(2)
+        CPD_TILED_N(3)
+        CPD_TILED_N(4)
+        CPD_TILED_N(5)
+#undef CPD_TILED_N
     }
     return CPD_OK;
 }

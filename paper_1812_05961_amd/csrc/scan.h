@@ -48,7 +48,7 @@ __global__ void __launch_bounds__(SCAN_THREADS) k_scan_reduce(F f, int64_t n, in
 }
 
 // One block scans nb tile sums in place (exclusive) and writes the grand total.
-__global__ void __launch_bounds__(SCAN_THREADS) k_scan_partials(int32_t *partial, int64_t nb,
+static __global__ void __launch_bounds__(SCAN_THREADS) k_scan_partials(int32_t *partial, int64_t nb,
                                                                  int32_t *total) {
     __shared__ int32_t smem[4];
     int32_t carry = 0;

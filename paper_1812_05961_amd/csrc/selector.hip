@@ -57,18 +57,32 @@ void make_order(const cpd_stats &st, int kind, int mode, int32_t *order) {
                 if (asc[l] != mode) order[k++] = asc[l];
             order[k++] = mode;
             break;
+        case CPD_ORDER_ROOTED: {  // the mode, then the rest by descending length (the CP-ALS trees)
+            int32_t desc[CPD_MAX_MODES];
+            for (int l = 0; l < N; ++l) desc[l] = l;
+            std::stable_sort(desc, desc + N, [&](int32_t a, int32_t b) { return st.dims[a] > st.dims[b]; });
+            order[k++] = mode;
+            for (int l = 0; l < N; ++l)
+                if (desc[l] != mode) order[k++] = desc[l];
+            break;
+        }
         default:  // descending lengths, ties to the lower mode
             for (int l = 0; l < N; ++l) order[l] = asc[l];
             std::stable_sort(order, order + N, [&](int32_t a, int32_t b) { return st.dims[a] > st.dims[b]; });
     }
 }
 
-// the root-level kernel's limits: ids below 2^24 under the root, leaf ids
-// below 2^29 (ranked leaf words)
-bool root_kernel_fits(const cpd_stats &st, const int32_t *order) {
-    for (int l = 1; l < st.nmodes; ++l)
-        if (st.dims[order[l]] >= (1 << 24)) return false;
+// the lane-group (ROW) kernels' limits for an output at `depth`: gathered
+// (other) levels with ids below 2^24, leaf ids below 2^29 (ranked leaf words)
+bool row_kernel_fits(const cpd_stats &st, const int32_t *order, int depth) {
+    for (int l = 0; l < st.nmodes; ++l)
+        if (l != depth && st.dims[order[l]] >= (1 << 24)) return false;
     return st.dims[order[st.nmodes - 1]] <= (1 << 29);
+}
+
+// the paper's privatisation rule (Section V-D2): rows x copies <= 0.02 x nnz
+bool priv_rule(const cpd_stats &st, int mode) {
+    return (double)st.dims[mode] * kPrivCopies <= kPrivThresh * (double)st.nnz;
 }
 
 bool priv_fits(const cpd_stats &st, int mode, int rank) {
@@ -158,24 +172,37 @@ cpd_status cpd_select_candidates(const cpd_stats *st, int32_t rank, int32_t mode
     const int N = st->nmodes;
     int cnt = 0;
     std::vector<std::vector<int32_t>> seen;
-    for (int kind = 0; kind < 4; ++kind) {
+    for (int kind = 0; kind < CPD_ORDER_KINDS; ++kind) {
         cpd_choice b = base_choice(*st, kind, mode);
         std::vector<int32_t> ord(b.order, b.order + N);
         if (std::find(seen.begin(), seen.end(), ord) != seen.end()) continue;
         seen.push_back(ord);
         auto push = [&](int variant, int kernel, int tile) {
+            if (cnt >= CPD_SEL_MAX_CAND) return;
             cpd_choice c = b;
             c.opts.variant = variant;
             c.opts.kernel = kernel;
             c.opts.tile_nnz = tile;
             out[cnt++] = c;
         };
-        if (b.depth == 0 && root_kernel_fits(*st, b.order)) {
-            for (int t : {32, 128, 512}) push(CPD_VARIANT_AUTO, CPD_KERNEL_ROW, t);
+        const bool row = row_kernel_fits(*st, b.order, b.depth);
+        if (b.depth == 0) {
+            if (row) {
+                for (int t : {32, 128, 512}) push(CPD_VARIANT_AUTO, CPD_KERNEL_ROW, t);
+            } else {
+                for (int t : {64, 256, 1024}) push(CPD_VARIANT_ATOMIC, CPD_KERNEL_LANE, t);
+            }
+        } else if (b.depth < N - 1) {
+            if (row) {
+                push(CPD_VARIANT_ATOMIC, CPD_KERNEL_ROW, 256);
+                push(CPD_VARIANT_PRIVATE, CPD_KERNEL_ROW, 256);
+            }
+            push(CPD_VARIANT_ATOMIC, CPD_KERNEL_LANE, 256);
+            if (priv_fits(*st, mode, rank)) push(CPD_VARIANT_PRIVATE, CPD_KERNEL_LANE, 256);
         } else {
-            for (int t : {64, 256, 1024}) push(CPD_VARIANT_ATOMIC, CPD_KERNEL_LANE, t);
-            if (b.depth > 0 && priv_fits(*st, mode, rank))
-                for (int t : {64, 256, 1024}) push(CPD_VARIANT_PRIVATE, CPD_KERNEL_LANE, t);
+            for (int t : {64, 256, 1024}) push(CPD_VARIANT_ATOMIC, CPD_KERNEL_ROUND, t);
+            push(CPD_VARIANT_ATOMIC, CPD_KERNEL_LANE, 256);
+            if (priv_fits(*st, mode, rank)) push(CPD_VARIANT_PRIVATE, CPD_KERNEL_LANE, 256);
         }
     }
     *n = cnt;
@@ -218,10 +245,11 @@ cpd_status cpd_select_features(const cpd_stats *st, int32_t rank, int32_t mode, 
         f[31] = c.opts.variant == CPD_VARIANT_PRIVATE ? 1.0f : 0.0f;
         f[32] = c.opts.kernel == CPD_KERNEL_ROW ? 1.0f : 0.0f;
         f[33] = (float)(std::log2((double)std::max(1, c.opts.tile_nnz)) / 10.0);
-        if (c.order_kind < 0 || c.order_kind > 3) CPD_FAIL(CPD_EINVAL, "candidate %d: bad order kind", j);
+        if (c.order_kind < 0 || c.order_kind >= CPD_ORDER_KINDS) CPD_FAIL(CPD_EINVAL, "candidate %d: bad order kind", j);
         f[34 + c.order_kind] = 1.0f;
-        f[38] = lg10(I * rank * 4.0) / 8.0f;
-        f[39] = lg10(I * kPrivCopies / nnz) / 4.0f;
+        f[39] = lg10(I * rank * 4.0) / 8.0f;
+        f[40] = lg10(I * kPrivCopies / nnz) / 4.0f;
+        f[41] = c.opts.kernel == CPD_KERNEL_ROUND ? 1.0f : 0.0f;
     }
     return CPD_OK;
 }
@@ -231,15 +259,21 @@ cpd_status cpd_select_heuristic(const cpd_stats *st, int32_t rank, int32_t mode,
     CPD_TRY(check_stats(st, rank, mode));
     if (!out) CPD_FAIL(CPD_EINVAL, "null output");
     cpd_choice c = base_choice(*st, CPD_ORDER_ASC, mode);
-    if (c.depth == 0 && root_kernel_fits(*st, c.order)) {
-        c.opts.variant = CPD_VARIANT_AUTO;
-        c.opts.kernel = CPD_KERNEL_ROW;
-        c.opts.tile_nnz = 128;
-    } else {
-        const bool priv = c.depth > 0 && priv_fits(*st, mode, rank) &&
-                          (double)st->dims[mode] * kPrivCopies <= kPrivThresh * (double)st->nnz;
-        c.opts.variant = priv ? CPD_VARIANT_PRIVATE : CPD_VARIANT_ATOMIC;
+    const int N = st->nmodes;
+    const bool row = row_kernel_fits(*st, c.order, c.depth);
+    if (c.depth == 0) {
+        c.opts.variant = row ? CPD_VARIANT_AUTO : CPD_VARIANT_ATOMIC;
+        c.opts.kernel = row ? CPD_KERNEL_ROW : CPD_KERNEL_LANE;
+        c.opts.tile_nnz = row ? 128 : 256;
+    } else if (priv_fits(*st, mode, rank) && priv_rule(*st, mode)) {
+        // the paper's privatised accumulation
+        c.opts.variant = CPD_VARIANT_PRIVATE;
         c.opts.kernel = CPD_KERNEL_LANE;
+        c.opts.tile_nnz = 256;
+    } else {
+        // atomics, with the library's default kernel for the level
+        c.opts.variant = CPD_VARIANT_ATOMIC;
+        c.opts.kernel = c.depth == N - 1 ? CPD_KERNEL_ROUND : row ? CPD_KERNEL_ROW : CPD_KERNEL_LANE;
         c.opts.tile_nnz = 256;
     }
     *out = c;

@@ -9,7 +9,8 @@
             the network trained on the GPU (cpd_mlp_train) to predict the
             standardised log(ns per nonzero) of each candidate;
   evaluate  per held-out (tensor, mode): time of the network's choice over the
-            fastest candidate, and the fallback's.
+            fastest candidate, the fallback's, and the library default's (the
+            tree rooted at the mode that cpd_als builds, default tile).
 
 The target times are whole cpd_mttkrp calls (output zeroing and per-call
 copies included) with factors padded to the rank, FP32 gathers.
@@ -72,6 +73,19 @@ def time_call(fn, target_ms=0.5, max_batch=64):
     return float(np.median(res))
 
 
+def rooted_index(cands, dims, mode):
+    """Index of the library's own default for a mode's MTTKRP: the tree cpd_als
+    builds (the mode, then the rest by descending length) with the ROW
+    kernel's default tile of 128 leaves (the LANE default 256 when the ROW
+    kernel does not fit the tree)."""
+    order = [mode] + sorted((m for m in range(len(dims)) if m != mode), key=lambda m: (-dims[m], m))
+    for kernel, tile in (("row", 128), ("lane", 256)):
+        for i, d in enumerate(cands):
+            if d["order"] == order and d["kernel"] == kernel and d["tile_nnz"] == tile:
+                return i
+    raise ValueError("the rooted default is not among the candidates")
+
+
 def time_tensor(x, rank, seed):
     """Exhaustive timing of every candidate of every mode of one tensor."""
     import torch
@@ -101,7 +115,8 @@ def time_tensor(x, rank, seed):
                     cpd.mttkrp(tree, facs, mode, out=out, rank=rank, variant=d["variant"],
                                kernel=d["kernel"], tile_nnz=d["tile_nnz"])
                 ms.append(time_call(fn))
-            recs.append(dict(mode=mode, rank=rank, cands=cd, ms=ms, heur=cd.index(heur)))
+            recs.append(dict(mode=mode, rank=rank, cands=cd, ms=ms, heur=cd.index(heur),
+                             rooted=rooted_index(cd, x.dims, mode)))
     finally:
         for t in trees.values():
             t.free()
@@ -204,21 +219,24 @@ def predict(params, recs, hidden=HIDDEN):
 
 
 def evaluate(recs, preds):
-    """Ratios t(choice) / t(best) for the network and the fallback."""
-    net, heur, fixed = [], [], []
+    """Ratios t(choice) / t(best) for the network, the fallback rule and the
+    library's own default (the rooted tree cpd_als builds, default tile)."""
+    net, heur, rooted = [], [], []
     for r, p in zip(recs, preds):
         ms = np.asarray(r["ms"])
         best = ms.min()
         net.append(ms[int(np.argmin(p))] / best)
         heur.append(ms[r["heur"]] / best)
-    net, heur = np.array(net), np.array(heur)
+        rooted.append(ms[r["rooted"]] / best)
+    net, heur, rooted = np.array(net), np.array(heur), np.array(rooted)
 
     def summ(a):
         return dict(geomean=float(np.exp(np.log(a).mean())), mean=float(a.mean()),
                     median=float(np.median(a)), p90=float(np.quantile(a, 0.9)),
                     max=float(a.max()), within_10pct=float((a <= 1.10).mean()))
-    return dict(cases=len(recs), network=summ(net), heuristic=summ(heur),
-                speedup_over_heuristic_geomean=float(np.exp(np.log(heur / net).mean())))
+    return dict(cases=len(recs), network=summ(net), heuristic=summ(heur), rooted_default=summ(rooted),
+                speedup_over_heuristic_geomean=float(np.exp(np.log(heur / net).mean())),
+                speedup_over_rooted_default_geomean=float(np.exp(np.log(rooted / net).mean())))
 
 
 def save_params(path, params, meta):

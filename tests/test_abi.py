@@ -114,6 +114,8 @@ def test_mttkrp_plan_rule():
     assert plan(nell, 1, 35, ld=36, kernel="lane") == "lane"
     assert plan(nell, 1, 35, ld=36, kernel="row") == "row"
     assert plan(nell, 2, 35, ld=36) == "round"     # the leaf level
+    assert plan(nell, 2, 35, ld=36, kernel="tiled") == "tiled"
+    assert plan(nell, 2, 35, ld=36, kernel="round") == "round"
     assert plan(nell, 2, 35, ld=36, kernel="lane") == "lane"
     with pytest.raises(cpd.CpdError) as e:
         plan(nell, 2, 35, ld=36, kernel="row")
@@ -127,9 +129,10 @@ def test_mttkrp_plan_rule():
     assert plan(nell, 2, 16, rows_aligned=False) == "lane"
     assert plan((300, 500), 1, 16) == "round"
     for depth, ld in ((0, 36), (1, 36), (2, 35)):
-        with pytest.raises(cpd.CpdError) as e:
-            plan(nell, depth, 35, ld=ld, kernel="round")
-        assert e.value.status == cpd.CPD_EUNSUPPORTED
+        for kernel in ("round", "tiled"):
+            with pytest.raises(cpd.CpdError) as e:
+                plan(nell, depth, 35, ld=ld, kernel=kernel)
+            assert e.value.status == cpd.CPD_EUNSUPPORTED
     # two modes: no ROW kernel is built, AUTO takes LANE at the root
     assert plan((300, 500), 0, 16) == "lane"
     with pytest.raises(cpd.CpdError):

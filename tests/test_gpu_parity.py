@@ -247,7 +247,7 @@ def test_mttkrp_every_level(case, R, ld):
         kernels = ["lane"] + (["row"] if 3 <= t.nmodes <= 5 and depth < t.nmodes - 1 and (ld or R) >= 8
                               and R in (8, 16, 32, 35, 64) else [])
         if depth == t.nmodes - 1 and _round_ok(R, ld or R):
-            kernels.append("round")
+            kernels += ["round", "tiled"]
         # private: a copy of Y in LDS per block when it fits 64 KiB, else one
         # HBM copy per XCD summed afterwards
         variants = ["atomic"] + (["private"] if depth >= 1 else [])
@@ -284,7 +284,7 @@ def test_mttkrp_tile_widths(tile):
         # the lane-group (row) kernels take tile widths in multiples of 32; the
         # leaf-level round kernel rounds any width up to a multiple of 64
         row_ok = depth < 2 and tile % 32 == 0
-        for kernel in (["lane", "row"] if row_ok else ["lane"]) + (["round"] if depth == 2 else []):
+        for kernel in (["lane", "row"] if row_ok else ["lane"]) + (["round", "tiled"] if depth == 2 else []):
             y, _ = _run(cpd, c, facs, mode, 16, "fp32", kernel, "auto", tile)
             assert relerr(y, ref) <= 1e-5, (mode, kernel, tile)
     if tile % 32:
@@ -372,7 +372,31 @@ def test_mttkrp_leaf_round_hot_rows(dims, alphas, order, R):
             assert relerr(y, lane) <= 1e-5, (dims, prec, tile)
             if prec == "fp32":
                 assert relerr(y, ref) <= 1e-5
+        # the leaf-mode tiling (one tile or several, by the rank's LDS rows)
+        y, used = _run(cpd, c, facs, leaf, R, prec, "tiled", "auto")
+        assert relerr(y, ocoo.mttkrp(t.dims, inds, vals, used, leaf)) <= 1e-5, (dims, prec, "tiled")
     c.free()
+
+
+@pytest.mark.parametrize("R", [8, 35, 64])
+def test_mttkrp_leaf_tiled_many_tiles(R):
+    """The leaf-mode tiling on a 30,000-row leaf mode (tens of tiles at rank
+    35 and 64, a few at rank 8), Zipf-skewed, 3 and 4 modes: every row against
+    the oracle, and a second call on the cached tiling."""
+    cpd = _cpd()
+    for dims, alphas in (((300, 200, 30_000), (1.0, 0.5, 1.1)), ((40, 50, 60, 30_000), (0.3, 0.8, 0.0, 1.2))):
+        t = _tensor(dims, 400_000, alphas, 29)
+        inds, vals = t.numpy()
+        c = cpd.csf_build(_dev(t.inds), _dev(t.vals), t.dims)
+        leaf = c.order[-1]
+        assert t.dims[leaf] == 30_000
+        ld = (R + 3) // 4 * 4
+        facs = _factors(t.dims, R, 33, ld)
+        ref = ocoo.mttkrp(t.dims, inds, vals, [f[:, :R].numpy() for f in facs], leaf)
+        for _ in range(2):
+            y, _u = _run(cpd, c, facs, leaf, R, "fp32", "tiled", "auto")
+            assert relerr(y, ref) <= 1e-5, (dims, R)
+        c.free()
 
 
 # ----------------------------------------------------------------- dense steps

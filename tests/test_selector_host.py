@@ -47,22 +47,36 @@ def _orders(cands):
 def test_candidates_three_modes():
     st = _stats((100, 2000, 50_000), 1_000_000)
     c1 = [c.as_dict(3) for c in cpd.select_candidates(st, 16, 1)]
-    # asc (0,1,2) depth 1; first (1,0,2) root; last (0,2,1) leaf; desc (2,1,0) depth 1
+    # asc (0,1,2) depth 1; first (1,0,2) root; last (0,2,1) leaf; desc (2,1,0) depth 1;
+    # rooted (1,2,0) root (the CP-ALS tree of mode 1)
     kinds = [(c["order_kind"], tuple(c["order"]), c["depth"]) for c in c1]
     assert sorted(set(kinds)) == sorted({("asc", (0, 1, 2), 1), ("first", (1, 0, 2), 0),
-                                         ("last", (0, 2, 1), 2), ("desc", (2, 1, 0), 1)})
-    # 2000 x 16 x 4 B > 64 KiB: no private copy; root: the root kernel, 3 tiles
-    assert len(c1) == 12
+                                         ("last", (0, 2, 1), 2), ("desc", (2, 1, 0), 1),
+                                         ("rooted", (1, 2, 0), 0)})
+    # 2000 x 16 x 4 B > 64 KiB: no privatised LANE
+    assert len(c1) == 3 + 3 + 4 + 3 + 3
     for c in c1:
         if c["depth"] == 0:
             assert c["kernel"] == "row" and c["variant"] == "auto" and c["tile_nnz"] in (32, 128, 512)
+        elif c["depth"] == 1:
+            assert (c["kernel"], c["variant"], c["tile_nnz"]) in {("row", "atomic", 256), ("row", "private", 256),
+                                                                  ("lane", "atomic", 256)}
         else:
-            assert c["kernel"] == "lane" and c["variant"] == "atomic" and c["tile_nnz"] in (64, 256, 1024)
+            assert (c["kernel"], c["variant"]) in {("round", "atomic"), ("lane", "atomic")}
+            assert c["tile_nnz"] in ((64, 256, 1024) if c["kernel"] == "round" else (256,))
     # mode 0 is the shortest: "first" equals "asc" and is listed once; 100 x 16 x 4 B fits LDS
     c0 = [c.as_dict(3) for c in cpd.select_candidates(st, 16, 0)]
-    assert len(_orders(cpd.select_candidates(st, 16, 0))) == 3
-    assert len(c0) == 3 + 6 + 6
-    assert sum(c["variant"] == "private" for c in c0) == 6
+    assert len(_orders(cpd.select_candidates(st, 16, 0))) == 4
+    assert len(c0) == 3 + 5 + 5 + 3
+    assert sum(c["variant"] == "private" for c in c0) == 2
+    # the CP-ALS layout of every mode (the mode, then the rest by descending
+    # length) is a candidate order, at the root with the default tile among others
+    dims = (100, 2000, 50_000)
+    for mode in range(3):
+        want = [mode] + sorted((m for m in range(3) if m != mode), key=lambda m: -dims[m])
+        rooted = [c.as_dict(3) for c in cpd.select_candidates(st, 16, mode) if c.as_dict(3)["order"] == want]
+        assert rooted and all(c["depth"] == 0 for c in rooted)
+        assert {c["tile_nnz"] for c in rooted} == {32, 128, 512}
 
 
 def test_candidates_ties_and_five_modes():
@@ -72,7 +86,8 @@ def test_candidates_ties_and_five_modes():
     # ascending with ties to the lower mode: (3, 4, 0, 1, 2); descending: (0, 1, 2, 3, 4)
     assert (3, 4, 0, 1, 2) in orders and (0, 1, 2, 3, 4) in orders
     assert (2, 3, 4, 0, 1) in orders          # first
-    assert len(orders) == 3                   # last == asc here
+    assert (2, 0, 1, 3, 4) in orders          # rooted: the mode, then descending lengths
+    assert len(orders) == 4                   # last == asc here
     assert len(cands) <= cpd.SEL_MAX_CAND
     for c in cands:
         d = c.as_dict(5)
@@ -88,9 +103,10 @@ def test_features_layout():
     for c, f in zip(cands, F):
         d = c.as_dict(3)
         assert f[34 + cpd.ORDER_KINDS.index(d["order_kind"])] == 1.0
-        assert f[34:38].sum() == 1.0
+        assert f[34:39].sum() == 1.0
         assert f[29] == (d["depth"] == 0) and f[30] == (d["depth"] == 2)
         assert f[31] == (d["variant"] == "private") and f[32] == (d["kernel"] == "row")
+        assert f[41] == (d["kernel"] == "round")
         assert abs(f[33] - np.log2(d["tile_nnz"]) / 10) < 1e-6
         # per-level statistics follow the tree order
         for l, m in enumerate(d["order"]):
@@ -101,23 +117,29 @@ def test_features_layout():
 
 
 def test_heuristic_rule():
-    # mode 0 (50 rows) sits at the root of the ascending tree: root kernel
+    # mode 0 (50 rows) sits at the root of the ascending tree: the ROW kernel
     st = _stats((50, 3000, 40_000), 2_000_000)
     h = cpd.select_heuristic(st, 16, 0).as_dict(3)
-    assert h["order_kind"] == "asc" and h["depth"] == 0 and h["kernel"] == "row"
-    # mode 1 at depth 1: 3000 x 16 x 4 B > 64 KiB -> atomic
+    assert h["order_kind"] == "asc" and h["depth"] == 0 and h["kernel"] == "row" and h["tile_nnz"] == 128
+    # mode 1 at depth 1: 3000 x 16 x 4 B > 64 KiB -> atomics with ROW
     h = cpd.select_heuristic(st, 16, 1).as_dict(3)
-    assert h["depth"] == 1 and h["variant"] == "atomic" and h["tile_nnz"] == 256
-    # 900 rows x 8 x 4 B fits LDS; 900 x 1024 <= 0.02 x 50M -> private
+    assert h["depth"] == 1 and h["variant"] == "atomic" and h["kernel"] == "row" and h["tile_nnz"] == 256
+    # mode 2 at the leaf: atomics with ROUND
+    h = cpd.select_heuristic(st, 16, 2).as_dict(3)
+    assert h["depth"] == 2 and h["variant"] == "atomic" and h["kernel"] == "round"
+    # 900 rows x 8 x 4 B fits LDS; 900 x 1024 <= 0.02 x 50M -> privatised LANE
     st = _stats((20, 900, 40_000), 50_000_000)
-    assert cpd.select_heuristic(st, 8, 1).as_dict(3)["variant"] == "private"
+    h = cpd.select_heuristic(st, 8, 1).as_dict(3)
+    assert h["variant"] == "private" and h["kernel"] == "lane"
     # the same with too few nonzeros for the rule -> atomic
     st = _stats((20, 900, 40_000), 40_000_000)
     assert cpd.select_heuristic(st, 8, 1).as_dict(3)["variant"] == "atomic"
     # the heuristic is always one of the candidates
-    for mode in range(3):
-        h = cpd.select_heuristic(st, 8, mode).as_dict(3)
-        assert h in [c.as_dict(3) for c in cpd.select_candidates(st, 8, mode)]
+    for stt, R in ((st, 8), (_stats((50, 3000, 40_000), 2_000_000), 16), (_stats((900, 20, 40, 30), 3_000_000), 64)):
+        for mode in range(len(stt.dims[:stt.nmodes])):
+            h = cpd.select_heuristic(stt, R, mode).as_dict(stt.nmodes)
+            assert h in [c.as_dict(stt.nmodes) for c in cpd.select_candidates(stt, R, mode)]
+
 
 
 def test_select_without_network_is_the_heuristic():
