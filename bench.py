@@ -46,13 +46,16 @@ def root_orders(dims):
 
 
 def root_kernel_name(nmodes, R, precision):
-    """Template instance of the root-level MTTKRP kernel used for rank R: G
-    lanes per leaf, one 16-byte chunk each, over the padded row."""
+    """Template instance of the root-level MTTKRP kernel used for rank R (as
+    rocprofv3 names it): G lanes per leaf, one chunk each, over the padded row,
+    float sums."""
     if precision == "fp32":
         width = next(w for w in (8, 16, 32, 36, 64) if w >= R)
-        return "k_mttkrp_root<%d, %d, float>" % (nmodes, width // 4)
+        return "k_mttkrp_root<%d, %d, float, float>" % (nmodes, width // 4)
     width = next(w for w in (16, 16, 32, 40, 64) if w >= R)
-    return "k_mttkrp_root<%d, %d, unsigned short>" % (nmodes, width // 8)
+    if width <= 16:  # 8-byte chunks of 4 bfloat16
+        return "k_mttkrp_root<%d, %d, bf16x4, float>" % (nmodes, width // 4)
+    return "k_mttkrp_root<%d, %d, unsigned short, float>" % (nmodes, width // 8)
 
 
 def alg_bytes(counts, dims, mode, R):

@@ -54,7 +54,7 @@ enum { CPD_FP32 = 0, CPD_BF16_GATHER = 1 };
  * output rows accumulated in LDS at levels >= 2). */
 enum { CPD_VARIANT_AUTO = 0, CPD_VARIANT_ATOMIC = 1, CPD_VARIANT_PRIVATE = 2 };
 
-/* Kernel family: AUTO picks (ROW above the leaf level, ROUND at the leaf
+/* Kernel family: AUTO picks (ROW above the leaf level, TILED at the leaf
  * level, LANE otherwise, each where eligible -- see cpd_mttkrp_plan); ROW = groups of
  * lanes each holding 16-byte chunks of the factor rows, several leaves per
  * wave step (root and internal levels; tile widths in multiples of 32);
@@ -63,13 +63,13 @@ enum { CPD_VARIANT_AUTO = 0, CPD_VARIANT_ATOMIC = 1, CPD_VARIANT_PRIVATE = 2 };
  * the rows of the round's fibers into LDS, then adds one row per leaf with
  * atomics issued back to back (tile widths rounded up to multiples of 64;
  * no privatised variant: CPD_VARIANT_PRIVATE with AUTO runs LANE);
- * TILED = leaf level only, on request: the leaves regrouped by tiles of leaf
- * indices whose output rows fit a block's LDS (the tree's leaf-mode tiling,
- * built on the first such call and kept with the tree: 12 bytes per nonzero
- * plus 4 bytes per fiber and level), every nonzero added in LDS, each tile's
- * rows added to the output once per block; tile_nnz = the tile height in
- * leaf indices (0 = the rows 40 KiB of LDS hold), capped by the LDS; no
- * privatised variant, as ROUND. */
+ * TILED = leaf level only: the leaves regrouped by tiles of leaf indices (the
+ * tree's leaf-mode tiling, built on the first such call and kept with the
+ * tree: 12 bytes per nonzero plus 4 bytes per fiber and level); each wave
+ * adds its leaves into a private LDS copy of its tile's output rows and adds
+ * the copy to the output once per tile; tile_nnz = the tile height in leaf
+ * indices (0 = what 5 KiB of LDS per wave hold, at least 16), capped by the
+ * LDS; no privatised variant, as ROUND. */
 enum { CPD_KERNEL_AUTO = 0, CPD_KERNEL_ROW = 1, CPD_KERNEL_LANE = 2, CPD_KERNEL_ROUND = 3, CPD_KERNEL_TILED = 4 };
 
 #define CPD_MAX_MODES 8
@@ -206,10 +206,10 @@ cpd_status cpd_mttkrp_noalloc(cpd_csf csf, const void *const *factors, int32_t l
  * at the leaf level (depth N-1) when the tree has leaf words, ld is a multiple
  * of 4 and at least the rank rounded up to 4, and the factors are 16-byte
  * aligned; TILED under the same conditions.  AUTO picks ROW above the leaf
- * level and ROUND at the leaf level, each when eligible, LANE otherwise
+ * level and TILED at the leaf level, each when eligible, LANE otherwise
  * (cpd_mttkrp runs LANE instead of ROUND or TILED for CPD_VARIANT_PRIVATE;
  * cpd_mttkrp_noalloc runs ROUND instead of TILED when the tree holds no
- * tiling yet).
+ * tiling of that height yet).
  * *kernel_out (host) = CPD_KERNEL_ROW, CPD_KERNEL_LANE, CPD_KERNEL_ROUND or
  * CPD_KERNEL_TILED; CPD_EUNSUPPORTED when ROW, ROUND or TILED is requested and
  * not eligible, or N is outside 2..5. */
@@ -409,15 +409,16 @@ typedef struct {
 } cpd_choice;
 
 #define CPD_SEL_MAX_CAND 24
-#define CPD_SEL_NFEAT 42
+#define CPD_SEL_NFEAT 43
 
 /* Candidates for MTTKRP of `mode` at `rank` (3..5 modes): every distinct
  * order of the five kinds; at the root the ROW kernel with tile widths 32,
  * 128, 512 (or atomic LANE with 64, 256, 1024 when the tree exceeds the ROW
  * kernels' index limits); at internal levels ROW without and with the LDS
  * table of hot rows (atomic, private) and atomic LANE, tile 256; at the leaf
- * level ROUND with tile widths 64, 256, 1024 and atomic LANE, tile 256; below
- * the root also privatised LANE (tile 256) when dims[mode] * rank * 4 <= 64 KiB.
+ * level TILED (default tile height), ROUND with tile widths 64, 256, 1024 and
+ * atomic LANE, tile 256; below the root also privatised LANE (tile 256) when
+ * dims[mode] * rank * 4 <= 64 KiB.
  * out: host, CPD_SEL_MAX_CAND entries; *n receives the count.
  * Factor rows are assumed padded as cpd_als pads them (stride a multiple of
  * 4 floats, at least the rank rounded up to 8/16/32/36/64). */
@@ -432,8 +433,9 @@ cpd_status cpd_select_features(const cpd_stats *st, int32_t rank, int32_t mode,
 /* The fallback: ascending-length order; below the root privatised LANE iff
  * dims[mode] * 1024 (the private copies) <= 0.02 * nnz and the copy fits in
  * 64 KiB of LDS (the rule of Section V-D2), else atomics with the level's
- * default kernel (ROW at internal levels, ROUND at the leaf level); default
- * tile widths (root 128, below 256).  Always one of the candidates. */
+ * default kernel (ROW at internal levels, TILED at the leaf level); default
+ * tile widths (root 128, internal 256, TILED its default).  Always one of
+ * the candidates. */
 cpd_status cpd_select_heuristic(const cpd_stats *st, int32_t rank, int32_t mode, cpd_choice *out);
 
 /* Pick the candidate with the smallest predicted time.

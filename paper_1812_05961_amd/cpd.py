@@ -69,7 +69,7 @@ ORDER_KINDS = ("asc", "first", "last", "desc", "rooted")
 _VARIANT_NAME = {v: k for k, v in VARIANT.items()}
 _KERNEL_NAME = {v: k for k, v in KERNEL.items()}
 SEL_MAX_CAND = 24
-SEL_NFEAT = 42
+SEL_NFEAT = 43
 SELECT = {"none": 0, "network": 1, "heuristic": 2}
 
 

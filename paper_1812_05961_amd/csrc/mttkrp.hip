@@ -286,7 +286,13 @@ cpd_status launch_lane(int G, bool priv, int32_t hot, dim3 grid, size_t lds, hip
 }
 
 constexpr size_t PRIV_LDS_MAX = 64 * 1024;
-constexpr size_t TILED_LDS = 40 * 1024;  // LDS per block of the tiled leaf kernel (tile rows + H tables)
+// LDS per wave of the tiled leaf kernel (its tile's rows + its H table) by
+// default: 32 waves per CU resident (measured on the three benchmark shapes:
+// NELL-2 rank 35 2.5 ms at 16-24 rows per tile against 4.1 ms at 64 and
+// 10 ms at 256 and more; NETFLIX rank 16 and 4-mode rank 32 flat within 10%
+// from 16 to 64 rows)
+constexpr size_t TILED_LDS = 5 * 1024;
+constexpr int32_t TILED_MIN_ROWS = 16;
 constexpr size_t HOT_LDS = 16 * 1024;   // hot output rows privatised per block
 constexpr int64_t HOT_BLOCKS = 16384;   // blocks looping over the streams (measured best of 2,048-65,536)
 constexpr double PRIV_THRESH = 0.02;  // privatise iff rows * copies <= 0.02 * nnz
@@ -363,7 +369,7 @@ cpd_status mttkrp_plan(int N, const int64_t *dims_by_level, int d, int64_t ld, i
                  "round and tiled kernels need the leaf level, leaf words, ld a multiple of 4 covering the rank "
                  "and 16-byte aligned factors");
     if (request != CPD_KERNEL_AUTO) *kernel = request;
-    else *kernel = row_ok ? CPD_KERNEL_ROW : round_ok ? CPD_KERNEL_ROUND : CPD_KERNEL_LANE;
+    else *kernel = row_ok ? CPD_KERNEL_ROW : round_ok ? CPD_KERNEL_TILED : CPD_KERNEL_LANE;
     return CPD_OK;
 }
 
@@ -492,12 +498,13 @@ cpd_status mttkrp_ws(cpd_csf_s *c, const void *const *factors, int32_t ld, int32
         }
         (void)hipGetLastError();
         // tile height: tile_nnz when given (capped by the LDS), else the rows
-        // that fit TILED_LDS bytes of tile (several blocks resident per CU)
-        const int32_t Bmax = tiled_height(R, (size_t)std::min(lds_max, 160 * 1024));
+        // that fit TILED_LDS bytes per wave (several waves resident per SIMD)
+        const int32_t Bmax = tiled_height(R, (size_t)std::min(lds_max, 160 * 1024) / 4);
         const int32_t Bdef = tiled_height(R, TILED_LDS);
-        const int32_t B = o.tile_nnz > 0 ? std::min<int32_t>(o.tile_nnz, Bmax) : std::min(Bdef, Bmax);
+        const int32_t B =
+            o.tile_nnz > 0 ? std::min<int32_t>(o.tile_nnz, Bmax) : std::min(std::max(Bdef, TILED_MIN_ROWS), Bmax);
         cpd_csf_s::LeafTiling lt;
-        if (B >= 32) CPD_TRY(csf_leaf_tiling(c, B, ws != nullptr, &lt, s));
+        if (B >= 1) CPD_TRY(csf_leaf_tiling(c, B, ws != nullptr, &lt, s));
         if (lt.B > 0) {
             const void *fac_by_level[CPD_MAX_MODES];
             for (int l = 0; l < N; ++l) fac_by_level[l] = fv.a[l];
@@ -508,6 +515,7 @@ cpd_status mttkrp_ws(cpd_csf_s *c, const void *const *factors, int32_t ld, int32
         }
         if (!ws) CPD_FAIL(CPD_EUNSUPPORTED, "no leaf-mode tiling fits %d bytes of LDS at rank %d", lds_max, R);
         kernel = CPD_KERNEL_ROUND;  // allocation-free call on a tree without a cached tiling
+        if (o.tile_nnz == 0) o.tile_nnz = 256;
     }
     if (kernel == CPD_KERNEL_ROUND) {
         // tiles of whole 64-leaf rounds

@@ -214,14 +214,17 @@ cpd_status launch_leaf_n(const LeafView &cv, const LeafFac &fv, int64_t ld, cons
 
 // ------------------------------------------------------------ leaf-mode tiling
 // The leaf level on the tree's leaf-mode tiling (the leaves regrouped by tiles
-// of B leaf indices, tree order inside a tile): each block owns a contiguous
-// range of the regrouped leaves and takes it tile by tile, the tile's B x R
-// output rows in LDS, so every nonzero is an LDS add and the tile's rows go to
-// Y once per block (FP32 atomics, nonzero entries only).  Within a tile the
-// waves take rounds of 64 leaves as the ROUND kernel does: value, local row
-// and fiber loaded with coalesced loads, the fibers' level indices gathered,
-// each fiber's H row gathered once into the wave's LDS table (runs of leaves
-// of one fiber share it), then one LDS atomic add per leaf.
+// of B leaf indices, tree order inside a tile).  Each wave owns a contiguous
+// range of the regrouped leaves and a private LDS table of one tile's B x R
+// output rows: it takes its range tile by tile (zero the table, add every
+// leaf of the tile into it, add the table's nonzero entries to Y), so every
+// nonzero is a plain LDS read-add-write by the one wave that owns the row --
+// no atomics (the LDS FP32 atomic add measured several times slower than a
+// plain read-modify-write here).  Rounds of 64 leaves as in the ROUND kernel:
+// value, local row and fiber loaded with coalesced loads, the fibers' level
+// indices gathered, each fiber's H row gathered once into the wave's H table,
+// then the leaves walked one per step, the rank across the lanes; two
+// consecutive leaves of one row are summed before their read-modify-write.
 struct TiledView {
     const int32_t *toff;
     const float *tv;
@@ -233,26 +236,34 @@ struct TiledView {
     int32_t B;
 };
 
-// Dynamic LDS: TW x PF x RQ floats (each wave's H rows), then B x R floats (the tile).
-template <int N, typename GT, int UF, int TW>
-__global__ void __launch_bounds__(64 * TW)
-k_mttkrp_tiled(TiledView tv, LeafFac fv, int64_t ld, int64_t per_block, float *__restrict__ Y, int64_t ldo, int R) {
+constexpr int TILED_WAVES = 4;  // waves per block (each on its own range and tables)
+
+// Dynamic LDS per wave: PF x RQ floats (H rows), then B x R floats (its tile).
+template <int N, typename GT, int UF>
+__global__ void __launch_bounds__(64 * TILED_WAVES)
+k_mttkrp_tiled(TiledView tv, LeafFac fv, int64_t ld, int64_t nwaves, float *__restrict__ Y, int64_t ldo, int R) {
     extern __shared__ float4 lds4[];
-    __shared__ int32_t s_fpos[TW][65];
-    float *lds = reinterpret_cast<float *>(lds4);
+    __shared__ int32_t s_fpos[TILED_WAVES][65];
     const int RQ = (R + 3) & ~3;
     const int G = RQ >> 2;
     const int NG = 64 / G;
     const int PF = NG * UF;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int g = lane / G, lig = lane - (lane / G) * G;
-    float *Hs = lds + (int64_t)wave * PF * RQ;
-    float *tab = lds + (int64_t)TW * PF * RQ;
-    int32_t *fpos = s_fpos[wave];
     const int64_t nloc = (int64_t)tv.B * R;
-    const int64_t b0 = (int64_t)blockIdx.x * per_block, b1 = min(b0 + per_block, tv.n);
-    int64_t pos = b0;
-    while (pos < b1) {  // the same on every thread of the block
+    // per-wave stride in floats, a multiple of 4 (16-byte aligned H rows)
+    const int64_t stride = ((int64_t)PF * RQ + nloc + 3) & ~int64_t(3);
+    float *Hs = reinterpret_cast<float *>(lds4) + (int64_t)wave * stride;
+    float *tab = Hs + (int64_t)PF * RQ;
+    int32_t *fpos = s_fpos[wave];
+    const int64_t gw = (int64_t)blockIdx.x * TILED_WAVES + wave;
+    if (gw >= nwaves) return;  // waves are independent: no block barriers
+    // this wave's range, whole rounds apart
+    const int64_t nr = ceil_div(tv.n, 64);
+    const int64_t r0 = gw * nr / nwaves, r1 = (gw + 1) * nr / nwaves;
+    const int64_t b1 = min(r1 * 64, tv.n);
+    int64_t pos = r0 * 64;
+    while (pos < b1) {
         // the tile holding regrouped leaf pos: the largest t with toff[t] <= pos
         int64_t lo = 0, hi = tv.ntiles;
         while (hi - lo > 1) {
@@ -262,15 +273,11 @@ k_mttkrp_tiled(TiledView tv, LeafFac fv, int64_t ld, int64_t per_block, float *_
         }
         const int64_t t = lo;
         const int64_t e = min(b1, (int64_t)tv.toff[t + 1]);
-        for (int64_t j = threadIdx.x; j < nloc; j += 64 * TW) tab[j] = 0.0f;
-        __syncthreads();
-        // the waves split [pos, e) into contiguous runs of whole rounds
-        const int64_t per_wave = ceil_div(ceil_div(e - pos, 64), TW) * 64;
-        const int64_t w0 = pos + wave * per_wave, w1 = min(e, w0 + per_wave);
-        for (int64_t k0 = w0; k0 < w1; k0 += 64) {
+        for (int64_t j = lane; j < nloc; j += 64) tab[j] = 0.0f;
+        for (int64_t k0 = pos; k0 < e; k0 += 64) {
             const int64_t k = k0 + lane;
-            const bool in = k < w1;
-            const int64_t kk = in ? k : w1 - 1;
+            const bool in = k < e;
+            const int64_t kk = in ? k : e - 1;
             const float x = tv.tv[kk];
             const int32_t row = tv.tw[kk];
             const int32_t f = tv.tf[kk];
@@ -279,7 +286,7 @@ k_mttkrp_tiled(TiledView tv, LeafFac fv, int64_t ld, int64_t per_block, float *_
             for (int l = 0; l < N - 1; ++l) hid[l] = tv.hid[l][f];
             const int32_t f_prev = __shfl_up(f, 1, 64);
             const uint64_t fmask = __ballot(in && (lane == 0 || f_prev != f));
-            const int nin = (int)min<int64_t>(64, w1 - k0);
+            const int nin = (int)min<int64_t>(64, e - k0);
             const uint64_t upto = ~0ull >> (63 - lane);
             const int F = __popcll(fmask);
             if ((fmask >> lane) & 1ull) fpos[__popcll(fmask & upto) - 1] = lane;
@@ -318,44 +325,67 @@ k_mttkrp_tiled(TiledView tv, LeafFac fv, int64_t ld, int64_t per_block, float *_
                 wave_sync_lds();
                 const int jb = __builtin_amdgcn_readfirstlane(fpos[f0]);
                 const int je = __builtin_amdgcn_readfirstlane(fpos[f1]);
-                for (int j = jb; j < je; ++j) {
-                    const int fj = __popcll(fmask & (~0ull >> (63 - j))) - 1 - f0;
-                    const float xj = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), j));
-                    const int32_t rj = __builtin_amdgcn_readlane(row, j);
-                    if (lane < R) atomicAdd(&tab[(int64_t)rj * R + lane], xj * Hs[fj * RQ + lane]);
+                // two leaves per step: their sum in one read-modify-write when
+                // they share a row, else two (every row is this wave's alone)
+                int j = jb;
+                for (; j + 1 < je; j += 2) {
+                    const int fa = __popcll(fmask & (~0ull >> (63 - j))) - 1 - f0;
+                    const int fb = __popcll(fmask & (~0ull >> (62 - j))) - 1 - f0;
+                    const float xa = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), j));
+                    const float xb = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), j + 1));
+                    const int32_t ra = __builtin_amdgcn_readlane(row, j);
+                    const int32_t rb = __builtin_amdgcn_readlane(row, j + 1);
+                    if (lane < R) {
+                        const float ta = xa * Hs[fa * RQ + lane], tb = xb * Hs[fb * RQ + lane];
+                        float *pa = tab + (int64_t)ra * R + lane, *pb = tab + (int64_t)rb * R + lane;
+                        if (ra == rb) {
+                            *pa += ta + tb;
+                        } else {
+                            const float va = *pa, vb = *pb;
+                            *pa = va + ta;
+                            *pb = vb + tb;
+                        }
+                    }
+                }
+                if (j < je) {
+                    const int fa = __popcll(fmask & (~0ull >> (63 - j))) - 1 - f0;
+                    const float xa = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), j));
+                    const int32_t ra = __builtin_amdgcn_readlane(row, j);
+                    if (lane < R) tab[(int64_t)ra * R + lane] += xa * Hs[fa * RQ + lane];
                 }
                 wave_sync_lds();
             }
         }
-        __syncthreads();
+        // the tile's rows into Y (nonzero entries)
         const int64_t base = t * (int64_t)tv.B;
-        for (int64_t j = threadIdx.x; j < nloc; j += 64 * TW) {
+        for (int64_t j = lane; j < nloc; j += 64) {
             const float v = tab[j];
             if (v != 0.0f) atomicAdd(Y + (base + j / R) * ldo + (j % R), v);
         }
-        __syncthreads();
+        wave_sync_lds();
         pos = e;
     }
 }
 
-constexpr int TILED_WAVES = 8;  // waves per block
-
 template <int N, typename GT>
 cpd_status launch_tiled_n(const TiledView &tv, const LeafFac &fv, int64_t ld, float *Y, int64_t ldo, int R, int UF,
-                          size_t lds, hipStream_t s) {
-    auto kern = UF == 2 ? k_mttkrp_tiled<N, GT, 2, TILED_WAVES> : k_mttkrp_tiled<N, GT, 4, TILED_WAVES>;
+                          size_t lds_wave, hipStream_t s) {
+    auto kern = UF == 2 ? k_mttkrp_tiled<N, GT, 2> : k_mttkrp_tiled<N, GT, 4>;
     int dev = 0, ncu = 256;
     if (hipGetDevice(&dev) == hipSuccess) {
         int v = 0;
         if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) ncu = v;
     }
+    const size_t lds = lds_wave * TILED_WAVES;
     CPD_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    // two blocks per CU over the whole range: each block sees one or two tiles,
-    // so the tile zeroing and adding to Y stays small against the leaves
-    const int64_t nblocks = std::max<int64_t>(1, std::min<int64_t>(ceil_div(tv.n, 64 * TILED_WAVES), 2 * ncu));
-    const int64_t per_block = ceil_div(ceil_div(tv.n, nblocks), 64) * 64;
-    hipLaunchKernelGGL(kern, dim3((unsigned)ceil_div(tv.n, per_block)), dim3(64 * TILED_WAVES), lds, s, tv, fv, ld,
-                       per_block, Y, ldo, R);
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64 * TILED_WAVES, lds) != hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    // one range per resident wave
+    const int64_t nwaves = std::max<int64_t>(1, std::min<int64_t>(ceil_div(tv.n, 64), (int64_t)ncu * per_cu * TILED_WAVES));
+    hipLaunchKernelGGL(kern, dim3((unsigned)ceil_div(nwaves, TILED_WAVES)), dim3(64 * TILED_WAVES), lds, s, tv, fv,
+                       ld, nwaves, Y, ldo, R);
     CPD_LAUNCH_CHECK();
     return CPD_OK;
 }
@@ -408,16 +438,15 @@ cpd_status launch_leaf(int N, bool bf16, const int32_t *const *fids, const float
 }
 
 
-// Tile height of the leaf-mode tiling for rank R: the tile's R-float rows and
-// the waves' H tables within the LDS a block may use (lds_max bytes).
-int32_t tiled_height(int R, size_t lds_max) {
+// Tile height of the leaf-mode tiling for rank R: one wave's tile of R-float
+// rows and its H table within lds_wave bytes of LDS.
+int32_t tiled_height(int R, size_t lds_wave) {
     const int RQ = (R + 3) & ~3;
     const int NG = 64 / (RQ / 4);
     const int PF = NG * (NG >= 7 ? 2 : 4);
-    const size_t static_lds = sizeof(int32_t) * TILED_WAVES * 65 + 1024;
-    const size_t wave_lds = sizeof(float) * (size_t)TILED_WAVES * PF * RQ;
-    if (lds_max <= static_lds + wave_lds) return 0;
-    return (int32_t)((lds_max - static_lds - wave_lds) / (sizeof(float) * R));
+    const size_t fixed = sizeof(float) * ((size_t)PF * RQ + 3) + sizeof(int32_t) * 65;
+    if (lds_wave <= fixed) return 0;
+    return (int32_t)((lds_wave - fixed) / (sizeof(float) * R));
 }
 
 // Leaf-level MTTKRP on the leaf-mode tiling (Y zeroed by the caller; factor
@@ -442,7 +471,7 @@ cpd_status launch_tiled(int N, bool bf16, const cpd_csf_s::LeafTiling &lt, int64
     const int RQ = (R + 3) & ~3;
     const int NG = 64 / (RQ / 4);
     const int UF = NG >= 7 ? 2 : 4;
-    const size_t lds = sizeof(float) * ((size_t)TILED_WAVES * NG * UF * RQ + (size_t)lt.B * R);
+    const size_t lds = sizeof(float) * (((size_t)NG * UF * RQ + (size_t)lt.B * R + 3) & ~size_t(3));  // per wave
     switch (N) {
 #define CPD_TILED_N(n)                                                                         \
     case n:                                                                                    \

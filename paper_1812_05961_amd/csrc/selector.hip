@@ -200,6 +200,7 @@ cpd_status cpd_select_candidates(const cpd_stats *st, int32_t rank, int32_t mode
             push(CPD_VARIANT_ATOMIC, CPD_KERNEL_LANE, 256);
             if (priv_fits(*st, mode, rank)) push(CPD_VARIANT_PRIVATE, CPD_KERNEL_LANE, 256);
         } else {
+            push(CPD_VARIANT_ATOMIC, CPD_KERNEL_TILED, 0);
             for (int t : {64, 256, 1024}) push(CPD_VARIANT_ATOMIC, CPD_KERNEL_ROUND, t);
             push(CPD_VARIANT_ATOMIC, CPD_KERNEL_LANE, 256);
             if (priv_fits(*st, mode, rank)) push(CPD_VARIANT_PRIVATE, CPD_KERNEL_LANE, 256);
@@ -244,12 +245,13 @@ cpd_status cpd_select_features(const cpd_stats *st, int32_t rank, int32_t mode, 
         f[30] = c.depth == N - 1 ? 1.0f : 0.0f;
         f[31] = c.opts.variant == CPD_VARIANT_PRIVATE ? 1.0f : 0.0f;
         f[32] = c.opts.kernel == CPD_KERNEL_ROW ? 1.0f : 0.0f;
-        f[33] = (float)(std::log2((double)std::max(1, c.opts.tile_nnz)) / 10.0);
+        f[33] = c.opts.tile_nnz > 0 ? (float)(std::log2((double)c.opts.tile_nnz) / 10.0) : 0.0f;
         if (c.order_kind < 0 || c.order_kind >= CPD_ORDER_KINDS) CPD_FAIL(CPD_EINVAL, "candidate %d: bad order kind", j);
         f[34 + c.order_kind] = 1.0f;
         f[39] = lg10(I * rank * 4.0) / 8.0f;
         f[40] = lg10(I * kPrivCopies / nnz) / 4.0f;
         f[41] = c.opts.kernel == CPD_KERNEL_ROUND ? 1.0f : 0.0f;
+        f[42] = c.opts.kernel == CPD_KERNEL_TILED ? 1.0f : 0.0f;
     }
     return CPD_OK;
 }
@@ -273,8 +275,8 @@ cpd_status cpd_select_heuristic(const cpd_stats *st, int32_t rank, int32_t mode,
     } else {
         // atomics, with the library's default kernel for the level
         c.opts.variant = CPD_VARIANT_ATOMIC;
-        c.opts.kernel = c.depth == N - 1 ? CPD_KERNEL_ROUND : row ? CPD_KERNEL_ROW : CPD_KERNEL_LANE;
-        c.opts.tile_nnz = 256;
+        c.opts.kernel = c.depth == N - 1 ? CPD_KERNEL_TILED : row ? CPD_KERNEL_ROW : CPD_KERNEL_LANE;
+        c.opts.tile_nnz = c.depth == N - 1 ? 0 : 256;
     }
     *out = c;
     return CPD_OK;

@@ -113,7 +113,7 @@ def test_mttkrp_plan_rule():
     assert plan(nell, 1, 35, ld=36) == "row"       # internal levels too
     assert plan(nell, 1, 35, ld=36, kernel="lane") == "lane"
     assert plan(nell, 1, 35, ld=36, kernel="row") == "row"
-    assert plan(nell, 2, 35, ld=36) == "round"     # the leaf level
+    assert plan(nell, 2, 35, ld=36) == "tiled"     # the leaf level
     assert plan(nell, 2, 35, ld=36, kernel="tiled") == "tiled"
     assert plan(nell, 2, 35, ld=36, kernel="round") == "round"
     assert plan(nell, 2, 35, ld=36, kernel="lane") == "lane"
@@ -123,11 +123,11 @@ def test_mttkrp_plan_rule():
     # ROUND: leaf level, leaf words, ld % 4 == 0 covering the rank rounded up to 4, aligned rows
     assert plan(nell, 2, 35, ld=35) == "lane"
     assert plan(nell, 2, 5, ld=6) == "lane"
-    assert plan(nell, 2, 5, ld=8) == "round"
-    assert plan(nell, 2, 3, ld=4, precision="bf16") == "round"
+    assert plan(nell, 2, 5, ld=8) == "tiled"
+    assert plan(nell, 2, 3, ld=4, precision="bf16") == "tiled"
     assert plan(nell, 2, 16, leaf_words=False) == "lane"
     assert plan(nell, 2, 16, rows_aligned=False) == "lane"
-    assert plan((300, 500), 1, 16) == "round"
+    assert plan((300, 500), 1, 16) == "tiled"
     for depth, ld in ((0, 36), (1, 36), (2, 35)):
         for kernel in ("round", "tiled"):
             with pytest.raises(cpd.CpdError) as e:

@@ -54,7 +54,7 @@ def test_candidates_three_modes():
                                          ("last", (0, 2, 1), 2), ("desc", (2, 1, 0), 1),
                                          ("rooted", (1, 2, 0), 0)})
     # 2000 x 16 x 4 B > 64 KiB: no privatised LANE
-    assert len(c1) == 3 + 3 + 4 + 3 + 3
+    assert len(c1) == 3 + 3 + 5 + 3 + 3
     for c in c1:
         if c["depth"] == 0:
             assert c["kernel"] == "row" and c["variant"] == "auto" and c["tile_nnz"] in (32, 128, 512)
@@ -62,12 +62,12 @@ def test_candidates_three_modes():
             assert (c["kernel"], c["variant"], c["tile_nnz"]) in {("row", "atomic", 256), ("row", "private", 256),
                                                                   ("lane", "atomic", 256)}
         else:
-            assert (c["kernel"], c["variant"]) in {("round", "atomic"), ("lane", "atomic")}
-            assert c["tile_nnz"] in ((64, 256, 1024) if c["kernel"] == "round" else (256,))
+            assert (c["kernel"], c["variant"]) in {("tiled", "atomic"), ("round", "atomic"), ("lane", "atomic")}
+            assert c["tile_nnz"] in {"round": (64, 256, 1024), "tiled": (0,), "lane": (256,)}[c["kernel"]]
     # mode 0 is the shortest: "first" equals "asc" and is listed once; 100 x 16 x 4 B fits LDS
     c0 = [c.as_dict(3) for c in cpd.select_candidates(st, 16, 0)]
     assert len(_orders(cpd.select_candidates(st, 16, 0))) == 4
-    assert len(c0) == 3 + 5 + 5 + 3
+    assert len(c0) == 3 + 6 + 6 + 3
     assert sum(c["variant"] == "private" for c in c0) == 2
     # the CP-ALS layout of every mode (the mode, then the rest by descending
     # length) is a candidate order, at the root with the default tile among others
@@ -106,8 +106,8 @@ def test_features_layout():
         assert f[34:39].sum() == 1.0
         assert f[29] == (d["depth"] == 0) and f[30] == (d["depth"] == 2)
         assert f[31] == (d["variant"] == "private") and f[32] == (d["kernel"] == "row")
-        assert f[41] == (d["kernel"] == "round")
-        assert abs(f[33] - np.log2(d["tile_nnz"]) / 10) < 1e-6
+        assert f[41] == (d["kernel"] == "round") and f[42] == (d["kernel"] == "tiled")
+        assert abs(f[33] - (np.log2(d["tile_nnz"]) / 10 if d["tile_nnz"] else 0.0)) < 1e-6
         # per-level statistics follow the tree order
         for l, m in enumerate(d["order"]):
             assert f[18 + l] == np.float32(st.top1[m])
@@ -124,9 +124,9 @@ def test_heuristic_rule():
     # mode 1 at depth 1: 3000 x 16 x 4 B > 64 KiB -> atomics with ROW
     h = cpd.select_heuristic(st, 16, 1).as_dict(3)
     assert h["depth"] == 1 and h["variant"] == "atomic" and h["kernel"] == "row" and h["tile_nnz"] == 256
-    # mode 2 at the leaf: atomics with ROUND
+    # mode 2 at the leaf: atomics with TILED (its default tile height)
     h = cpd.select_heuristic(st, 16, 2).as_dict(3)
-    assert h["depth"] == 2 and h["variant"] == "atomic" and h["kernel"] == "round"
+    assert h["depth"] == 2 and h["variant"] == "atomic" and h["kernel"] == "tiled" and h["tile_nnz"] == 0
     # 900 rows x 8 x 4 B fits LDS; 900 x 1024 <= 0.02 x 50M -> privatised LANE
     st = _stats((20, 900, 40_000), 50_000_000)
     h = cpd.select_heuristic(st, 8, 1).as_dict(3)
