@@ -99,6 +99,14 @@ __device__ __forceinline__ uint16_t f32_to_bf16(float f) {
     return (uint16_t)(u >> 16);
 }
 
+// A load of data each launch reads once (a tree's leaf stream): the
+// nontemporal hint streams it through the caches, so that it does not evict
+// the factor rows the gathers reuse.
+template <typename T>
+__device__ __forceinline__ T stream_load(const T *p) {
+    return __builtin_nontemporal_load(p);
+}
+
 // Block-wide helpers for 256-thread blocks (4 waves of 64).
 __device__ __forceinline__ double wave_sum(double v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);

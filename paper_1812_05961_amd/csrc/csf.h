@@ -50,8 +50,7 @@ struct cpd_csf_s {
         int32_t *toff = nullptr;                 // ntiles + 1 offsets into the regrouped leaves
         float *tv = nullptr;                     // value of each regrouped leaf
         int32_t *tw = nullptr;                   // its leaf index minus the tile's first index
-        int32_t *tf = nullptr;                   // its fiber (level N-2 node) in the tree
-        int32_t *hid[CPD_MAX_MODES] = {};        // per fiber: the index at levels 0..N-2
+        int32_t *th[CPD_MAX_MODES] = {};         // per leaf: its fiber's index at levels 0..N-2
         char *slab = nullptr;
         size_t bytes = 0;
     };

@@ -5,11 +5,14 @@
 // names as further work, Sections V-A and VII).
 //
 // Per regrouped leaf j (leaf k of the tree): its value, its leaf index minus
-// the tile's first index, and its fiber (the level N-2 node above it, whose
-// rows form the Hadamard product the leaf is scaled by).  Per fiber: its
-// index at every level 0..N-2 (the rows to gather).  Built with the CSF
-// builder's radix sort (key: the tile number, payload: the position) and
-// device-wide scans over the leaf words.
+// the tile's first index, and the indices at levels 0..N-2 of its fiber (the
+// level N-2 node above it, whose rows form the Hadamard product the leaf is
+// scaled by).  The fiber's indices are stored per leaf, not per fiber, so
+// that the MTTKRP reads them in coalesced runs: looked up per fiber they are
+// a random access into arrays of the tree's fiber count, one cache line per
+// fiber run of a tile, which misses the L2.  Built with the CSF builder's
+// radix sort (key: the tile number, payload: the position) and device-wide
+// scans over the leaf words.
 #include <algorithm>
 
 #include "csf.h"
@@ -53,16 +56,24 @@ struct FiberOpensRoot {
     __device__ int32_t operator()(int64_t f) const { return ((uint32_t)leafw[first_leaf[f]] >> 29) == 0 ? 1 : 0; }
 };
 
+struct LeafOut {
+    float *tv;
+    int32_t *tw;
+    int32_t *th[CPD_MAX_MODES];
+    const int32_t *fh[CPD_MAX_MODES];  // per fiber: its index at levels 0..N-2
+};
+
 __global__ void k_tile_gather(const int32_t *__restrict__ pos, const uint64_t *__restrict__ key, int64_t n, int32_t B,
                               const float *__restrict__ vals, const int32_t *__restrict__ leaf_ids,
                               const int32_t *__restrict__ leafw, uint32_t flvl, const int32_t *__restrict__ fexcl,
-                              float *__restrict__ tv, int32_t *__restrict__ tw, int32_t *__restrict__ tf) {
+                              int nl, LeafOut o) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
     const int32_t k = pos[j];
-    tv[j] = vals[k];
-    tw[j] = leaf_ids[k] - (int32_t)key[j] * B;
-    tf[j] = fexcl[k] + (((uint32_t)leafw[k] >> 29) <= flvl ? 1 : 0) - 1;
+    o.tv[j] = vals[k];
+    o.tw[j] = leaf_ids[k] - (int32_t)key[j] * B;
+    const int32_t f = fexcl[k] + (((uint32_t)leafw[k] >> 29) <= flvl ? 1 : 0) - 1;
+    for (int l = 0; l < nl; ++l) o.th[l][j] = o.fh[l][f];
 }
 
 struct FiberIds {
@@ -113,9 +124,8 @@ cpd_status csf_leaf_tiling(cpd_csf_s *c, int32_t B, bool cached_only, cpd_csf_s:
     lt.B = B;
     lt.ntiles = nt;
     auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
-    const size_t b_toff = al(sizeof(int32_t) * (size_t)(nt + 1)), b_leaf = al(sizeof(int32_t) * (size_t)n),
-                 b_fib = al(sizeof(int32_t) * (size_t)nf);
-    lt.bytes = b_toff + 3 * b_leaf + (size_t)(N - 1) * b_fib;
+    const size_t b_toff = al(sizeof(int32_t) * (size_t)(nt + 1)), b_leaf = al(sizeof(int32_t) * (size_t)n);
+    lt.bytes = b_toff + (size_t)(N + 1) * b_leaf;
     if (hipMallocAsync((void **)&lt.slab, lt.bytes, s) != hipSuccess) {
         (void)hipGetLastError();
         CPD_FAIL(CPD_ENOMEM, "device allocation of %zu bytes for the leaf-mode tiling failed", lt.bytes);
@@ -127,11 +137,9 @@ cpd_status csf_leaf_tiling(cpd_csf_s *c, int32_t B, bool cached_only, cpd_csf_s:
     p += b_leaf;
     lt.tw = reinterpret_cast<int32_t *>(p);
     p += b_leaf;
-    lt.tf = reinterpret_cast<int32_t *>(p);
-    p += b_leaf;
     for (int l = 0; l < N - 1; ++l) {
-        lt.hid[l] = reinterpret_cast<int32_t *>(p);
-        p += b_fib;
+        lt.th[l] = reinterpret_cast<int32_t *>(p);
+        p += b_leaf;
     }
     auto fail = [&](cpd_status st) {
         (void)hipFreeAsync(lt.slab, s);
@@ -140,10 +148,11 @@ cpd_status csf_leaf_tiling(cpd_csf_s *c, int32_t B, bool cached_only, cpd_csf_s:
     };
 
     DevBuf<uint64_t> k1, k2;
-    DevBuf<int32_t> p1, p2, fexcl, rexcl;
+    DevBuf<int32_t> p1, p2, fexcl, rexcl, fh;
     cpd_status st = CPD_OK;
     if ((st = k1.alloc(n, s)) || (st = k2.alloc(n, s)) || (st = p1.alloc(n, s)) || (st = p2.alloc(n, s)) ||
-        (st = fexcl.alloc(n, s)) || (st = rexcl.alloc(std::max<int64_t>(nf, 1), s)))
+        (st = fexcl.alloc(n, s)) || (st = rexcl.alloc(std::max<int64_t>(nf, 1), s)) ||
+        (st = fh.alloc((N - 1) * std::max<int64_t>(nf, 1), s)))
         return fail(st);
     const int32_t *leaf_ids = c->fids[N - 1];
     hipLaunchKernelGGL(k_tile_keys, dim3(grid_of(n)), dim3(256), 0, s, leaf_ids, n, B, k1.p, p1.p);
@@ -155,17 +164,11 @@ cpd_status csf_leaf_tiling(cpd_csf_s *c, int32_t B, bool cached_only, cpd_csf_s:
     if ((st = radix_sort(klo, khi, kp, olo, ohi, op, n, bits, s))) return fail(st);
     hipLaunchKernelGGL(k_tile_offsets, dim3(grid_of(nt + 1)), dim3(256), 0, s, (const uint64_t *)klo, n, nt, lt.toff);
     if (hipGetLastError() != hipSuccess) return fail(CPD_EHIP);
-    const uint32_t flvl = (uint32_t)(N - 2);
-    if ((st = exclusive_scan(OpensAt{c->leafw, flvl}, n, fexcl.p, (int32_t *)nullptr, s))) return fail(st);
-    hipLaunchKernelGGL(k_tile_gather, dim3(grid_of(n)), dim3(256), 0, s, (const int32_t *)kp, (const uint64_t *)klo, n,
-                       B, (const float *)c->vals, leaf_ids, (const int32_t *)c->leafw, flvl, (const int32_t *)fexcl.p,
-                       lt.tv, lt.tw, lt.tf);
-    if (hipGetLastError() != hipSuccess) return fail(CPD_EHIP);
     FiberIds fi{};
     for (int l = 0; l < N; ++l) {
         fi.fids[l] = c->fids[l];
         fi.uprow[l] = c->uprow[l];
-        fi.hid[l] = lt.hid[l];
+        fi.hid[l] = l < N - 1 ? fh.p + (int64_t)l * nf : nullptr;
     }
     fi.first_leaf = N >= 3 ? c->fptr[N - 2] : nullptr;
     fi.leafw = c->leafw;
@@ -177,6 +180,19 @@ cpd_status csf_leaf_tiling(cpd_csf_s *c, int32_t B, bool cached_only, cpd_csf_s:
         fi.rexcl = rexcl.p;
     }
     hipLaunchKernelGGL(k_fiber_ids, dim3(grid_of(nf)), dim3(256), 0, s, fi, N, nf);
+    if (hipGetLastError() != hipSuccess) return fail(CPD_EHIP);
+    const uint32_t flvl = (uint32_t)(N - 2);
+    if ((st = exclusive_scan(OpensAt{c->leafw, flvl}, n, fexcl.p, (int32_t *)nullptr, s))) return fail(st);
+    LeafOut o{};
+    o.tv = lt.tv;
+    o.tw = lt.tw;
+    for (int l = 0; l < N - 1; ++l) {
+        o.th[l] = lt.th[l];
+        o.fh[l] = fi.hid[l];
+    }
+    hipLaunchKernelGGL(k_tile_gather, dim3(grid_of(n)), dim3(256), 0, s, (const int32_t *)kp, (const uint64_t *)klo, n,
+                       B, (const float *)c->vals, leaf_ids, (const int32_t *)c->leafw, flvl, (const int32_t *)fexcl.p,
+                       N - 1, o);
     if (hipGetLastError() != hipSuccess) return fail(CPD_EHIP);
     c->leaf_tilings.push_back(lt);
     *out = lt;

@@ -105,12 +105,12 @@ k_mttkrp_leaf(LeafView cv, LeafFac fv, int64_t ld, const int32_t *__restrict__ s
             const bool in = k < ke;
             // lanes past the range load the range's last leaf (straight-line loads) and drop it
             const int64_t kk = in ? k : ke - 1;
-            const int32_t w = cv.leafw[kk];
-            const float x = cv.vals[kk];
-            const int32_t oi = cv.leaf_ids[kk];
+            const int32_t w = stream_load(cv.leafw + kk);
+            const float x = stream_load(cv.vals + kk);
+            const int32_t oi = stream_load(cv.leaf_ids + kk);
             int32_t up[N > 2 ? N - 2 : 1];
 #pragma unroll
-            for (int l = 0; l < N - 2; ++l) up[l] = cv.uprow[l + 1][kk];
+            for (int l = 0; l < N - 2; ++l) up[l] = stream_load(cv.uprow[l + 1] + kk);
             const int lvl = (int)((uint32_t)w >> 29);
             const uint64_t nrmask = __ballot(in && lvl == 0);
             const uint64_t fmask = __ballot(in && (lvl <= N - 2 || lane == 0));
@@ -221,16 +221,16 @@ cpd_status launch_leaf_n(const LeafView &cv, const LeafFac &fv, int64_t ld, cons
 // nonzero is a plain LDS read-add-write by the one wave that owns the row --
 // no atomics (the LDS FP32 atomic add measured several times slower than a
 // plain read-modify-write here).  Rounds of 64 leaves as in the ROUND kernel:
-// value, local row and fiber loaded with coalesced loads, the fibers' level
-// indices gathered, each fiber's H row gathered once into the wave's H table,
+// value, local row and the fiber's level indices loaded with coalesced loads
+// (a fiber run starts where any of those indices changes), each run's H row
+// gathered once into the wave's H table,
 // then the leaves walked one per step, the rank across the lanes; two
 // consecutive leaves of one row are summed before their read-modify-write.
 struct TiledView {
     const int32_t *toff;
     const float *tv;
     const int32_t *tw;
-    const int32_t *tf;
-    const int32_t *hid[CPD_MAX_MODES];
+    const int32_t *th[CPD_MAX_MODES];
     int64_t n;
     int64_t ntiles;
     int32_t B;
@@ -278,14 +278,17 @@ k_mttkrp_tiled(TiledView tv, LeafFac fv, int64_t ld, int64_t nwaves, float *__re
             const int64_t k = k0 + lane;
             const bool in = k < e;
             const int64_t kk = in ? k : e - 1;
-            const float x = tv.tv[kk];
-            const int32_t row = tv.tw[kk];
-            const int32_t f = tv.tf[kk];
+            const float x = stream_load(tv.tv + kk);
+            const int32_t row = stream_load(tv.tw + kk);
             int32_t hid[N - 1];
+            bool newf = lane == 0;
 #pragma unroll
-            for (int l = 0; l < N - 1; ++l) hid[l] = tv.hid[l][f];
-            const int32_t f_prev = __shfl_up(f, 1, 64);
-            const uint64_t fmask = __ballot(in && (lane == 0 || f_prev != f));
+            for (int l = 0; l < N - 1; ++l) {
+                hid[l] = stream_load(tv.th[l] + kk);
+                newf |= __shfl_up(hid[l], 1, 64) != hid[l];
+            }
+            // a fiber is its index tuple: a new run where any level's index changes
+            const uint64_t fmask = __ballot(in && newf);
             const int nin = (int)min<int64_t>(64, e - k0);
             const uint64_t upto = ~0ull >> (63 - lane);
             const int F = __popcll(fmask);
@@ -460,8 +463,7 @@ cpd_status launch_tiled(int N, bool bf16, const cpd_csf_s::LeafTiling &lt, int64
     tv.toff = lt.toff;
     tv.tv = lt.tv;
     tv.tw = lt.tw;
-    tv.tf = lt.tf;
-    for (int l = 0; l < N - 1; ++l) tv.hid[l] = lt.hid[l];
+    for (int l = 0; l < N - 1; ++l) tv.th[l] = lt.th[l];
     tv.n = nleaves;
     tv.ntiles = lt.ntiles;
     tv.B = lt.B;

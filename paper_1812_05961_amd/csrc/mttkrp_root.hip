@@ -243,10 +243,11 @@ k_mttkrp_root(CsfView cv, FacView fv, const char *__restrict__ a_leaf, uint32_t 
                 const int s = e2 / C, j = e2 % C;
                 const int64_t k = base + (int64_t)s * T + t0 + j;
                 const bool in = k < nleaves;
-                sw[s * (C + 1) + j] = in ? leafw[k] : 0;
-                sv[s * (C + 1) + j] = in ? vals[k] : 0.0f;
+                sw[s * (C + 1) + j] = in ? stream_load(leafw + k) : 0;
+                sv[s * (C + 1) + j] = in ? stream_load(vals + k) : 0.0f;
 #pragma unroll
-                for (int l = 0; l < NU; ++l) s_u[wave][l][s * (C + 1) + j] = in ? cv.uprow[l + 1][k] : 0;
+                for (int l = 0; l < NU; ++l)
+                    s_u[wave][l][s * (C + 1) + j] = in ? stream_load(cv.uprow[l + 1] + k) : 0;
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
@@ -509,10 +510,11 @@ k_mttkrp_mid(CsfView cv, FacView fv, const char *__restrict__ a_leaf, uint32_t r
                 const int s = e2 / C, j = e2 % C;
                 const int64_t k = base + (int64_t)s * T + t0 + j;
                 const bool in = k < nleaves;
-                sw[s * (C + 1) + j] = in ? leafw[k] : 0;
-                sv[s * (C + 1) + j] = in ? vals[k] : 0.0f;
+                sw[s * (C + 1) + j] = in ? stream_load(leafw + k) : 0;
+                sv[s * (C + 1) + j] = in ? stream_load(vals + k) : 0.0f;
 #pragma unroll
-                for (int l = 0; l < NU; ++l) s_u[wave][l][s * (C + 1) + j] = in ? cv.uprow[l + 1][k] : 0;
+                for (int l = 0; l < NU; ++l)
+                    s_u[wave][l][s * (C + 1) + j] = in ? stream_load(cv.uprow[l + 1] + k) : 0;
             }
             wave_sync_lds_root();
             const int len = (int)(kend - k0) - t0;  // this group's leaves left in the chunk
