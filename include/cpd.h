@@ -55,7 +55,9 @@ enum { CPD_FP32 = 0, CPD_BF16_GATHER = 1 };
 enum { CPD_VARIANT_AUTO = 0, CPD_VARIANT_ATOMIC = 1, CPD_VARIANT_PRIVATE = 2 };
 
 /* Kernel family: AUTO picks (ROW above the leaf level, TILED at the leaf
- * level, LANE otherwise, each where eligible -- see cpd_mttkrp_plan); ROW = groups of
+ * level, LANE otherwise, each where eligible -- see cpd_mttkrp_plan -- and,
+ * with CPD_VARIANT_AUTO, TILED at an internal level whose nodes hold fewer
+ * than 4 leaves on average); ROW = groups of
  * lanes each holding 16-byte chunks of the factor rows, several leaves per
  * wave step (root and internal levels; tile widths in multiples of 32);
  * LANE = the rank spread over the lanes, one leaf per wave step (any level);
@@ -63,13 +65,16 @@ enum { CPD_VARIANT_AUTO = 0, CPD_VARIANT_ATOMIC = 1, CPD_VARIANT_PRIVATE = 2 };
  * the rows of the round's fibers into LDS, then adds one row per leaf with
  * atomics issued back to back (tile widths rounded up to multiples of 64;
  * no privatised variant: CPD_VARIANT_PRIVATE with AUTO runs LANE);
- * TILED = leaf level only: the leaves regrouped by tiles of leaf indices (the
- * tree's leaf-mode tiling, built on the first such call and kept with the
- * tree: 12 bytes per nonzero plus 4 bytes per fiber and level); each wave
- * adds its leaves into a private LDS copy of its tile's output rows and adds
- * the copy to the output once per tile; tile_nnz = the tile height in leaf
- * indices (0 = what 5 KiB of LDS per wave hold, at least 16), capped by the
- * LDS; no privatised variant, as ROUND. */
+ * TILED = any level below the root: the leaves regrouped by tiles of the
+ * output mode's indices (the level's mode tiling, built on the first such
+ * call and kept with the tree: 4 (N+1) bytes per nonzero); each wave adds its
+ * share into a private LDS copy of its tile's output rows and adds the copy
+ * to the output once per tile -- at the leaf level one row per leaf scaled by
+ * its fiber's Hadamard row, at an internal level one row per node (the sum
+ * of its leaves' rows below, times its ancestors' rows); tile_nnz = the tile
+ * height in output rows (0 = at the leaf level what 5 KiB of LDS per wave
+ * hold, at least 16; at an internal level 16), capped by the LDS; no
+ * privatised variant, as ROUND. */
 enum { CPD_KERNEL_AUTO = 0, CPD_KERNEL_ROW = 1, CPD_KERNEL_LANE = 2, CPD_KERNEL_ROUND = 3, CPD_KERNEL_TILED = 4 };
 
 #define CPD_MAX_MODES 8
@@ -205,11 +210,14 @@ cpd_status cpd_mttkrp_noalloc(cpd_csf csf, const void *const *factors, int32_t l
  * <= 2^32 (its rows are addressed by 32-bit byte offsets).  ROUND is eligible
  * at the leaf level (depth N-1) when the tree has leaf words, ld is a multiple
  * of 4 and at least the rank rounded up to 4, and the factors are 16-byte
- * aligned; TILED under the same conditions.  AUTO picks ROW above the leaf
- * level and TILED at the leaf level, each when eligible, LANE otherwise
- * (cpd_mttkrp runs LANE instead of ROUND or TILED for CPD_VARIANT_PRIVATE;
- * cpd_mttkrp_noalloc runs ROUND instead of TILED when the tree holds no
- * tiling of that height yet).
+ * aligned; TILED under the same conditions at every level below the root.
+ * AUTO picks ROW above the leaf level and TILED at the leaf level, each when
+ * eligible, LANE otherwise (cpd_mttkrp runs LANE instead of ROUND or TILED
+ * for CPD_VARIANT_PRIVATE, and TILED at an internal level whose nodes hold
+ * fewer than 4 leaves on average, a property of the tree this rule does not
+ * see; cpd_mttkrp_noalloc runs ROUND at the leaf level and the shape rule's
+ * kernel at an internal level when the tree holds no tiling of that height
+ * yet).
  * *kernel_out (host) = CPD_KERNEL_ROW, CPD_KERNEL_LANE, CPD_KERNEL_ROUND or
  * CPD_KERNEL_TILED; CPD_EUNSUPPORTED when ROW, ROUND or TILED is requested and
  * not eligible, or N is outside 2..5. */
@@ -415,7 +423,8 @@ typedef struct {
  * order of the five kinds; at the root the ROW kernel with tile widths 32,
  * 128, 512 (or atomic LANE with 64, 256, 1024 when the tree exceeds the ROW
  * kernels' index limits); at internal levels ROW without and with the LDS
- * table of hot rows (atomic, private) and atomic LANE, tile 256; at the leaf
+ * table of hot rows (atomic, private) and atomic LANE, tile 256, and TILED
+ * (default tile height); at the leaf
  * level TILED (default tile height), ROUND with tile widths 64, 256, 1024 and
  * atomic LANE, tile 256; below the root also privatised LANE (tile 256) when
  * dims[mode] * rank * 4 <= 64 KiB.

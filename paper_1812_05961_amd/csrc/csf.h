@@ -40,17 +40,18 @@ struct cpd_csf_s {
         int32_t *starts;                  // (N-1) x ntiles
     };
     std::vector<Tiles> tiles;
-    // The leaves regrouped by leaf-index tile (B consecutive leaf indices per
-    // tile), tree order kept inside each tile: the leaf-mode tiling of the
-    // leaf-level MTTKRP (one tile's output rows fit in LDS).  Built on first
-    // use for a tile height B, cached.
+    // The leaves regrouped by tiles of B consecutive indices of one level d
+    // (1 <= d <= N-1), tree order kept inside each tile: the mode tiling of
+    // that level's MTTKRP (one tile's output rows fit in LDS).  Built on first
+    // use for a level and tile height, cached.
     struct LeafTiling {
+        int32_t depth = 0;
         int32_t B = 0;
         int64_t ntiles = 0;
         int32_t *toff = nullptr;                 // ntiles + 1 offsets into the regrouped leaves
         float *tv = nullptr;                     // value of each regrouped leaf
-        int32_t *tw = nullptr;                   // its leaf index minus the tile's first index
-        int32_t *th[CPD_MAX_MODES] = {};         // per leaf: its fiber's index at levels 0..N-2
+        int32_t *tw = nullptr;                   // its level-d index minus the tile's first index
+        int32_t *th[CPD_MAX_MODES] = {};         // its indices at the other levels, in level order
         char *slab = nullptr;
         size_t bytes = 0;
     };
@@ -134,10 +135,11 @@ cpd_status csf_tiles_into(cpd_csf_s *c, int32_t tile, int32_t *dst, size_t dst_b
 cpd_status csf_tiles(cpd_csf_s *c, int32_t tile, const int32_t **starts, int64_t *ntiles,
                      hipStream_t s);
 
-// The leaf-mode tiling of a tree for tile height B (cached in the handle;
-// built on first use; needs the tree's leaf words); *out receives a copy of
-// its descriptor.  `cached_only`: the cached one or an empty descriptor
-// (B == 0), building nothing.
-cpd_status csf_leaf_tiling(cpd_csf_s *c, int32_t B, bool cached_only, cpd_csf_s::LeafTiling *out, hipStream_t s);
+// The mode tiling of level d (1..N-1) of a tree for tile height B (cached in
+// the handle; built on first use; needs the tree's leaf words and per-leaf
+// internal ids); *out receives a copy of its descriptor.  `cached_only`: the
+// cached one or an empty descriptor (B == 0), building nothing.
+cpd_status csf_level_tiling(cpd_csf_s *c, int d, int32_t B, bool cached_only, cpd_csf_s::LeafTiling *out,
+                            hipStream_t s);
 
 }  // namespace cpd

@@ -293,6 +293,15 @@ constexpr size_t PRIV_LDS_MAX = 64 * 1024;
 // from 16 to 64 rows)
 constexpr size_t TILED_LDS = 5 * 1024;
 constexpr int32_t TILED_MIN_ROWS = 16;
+// tile height of the internal-level tiled kernel (measured on the internal
+// levels of the three benchmark shapes' ascending trees: 16-32 rows best,
+// 1.5-2x slower at 64 and 3-4x at 128, the tables costing resident waves)
+constexpr int32_t TILED_MID_ROWS = 16;
+// AUTO takes TILED at an internal level whose nodes hold fewer leaves than
+// this on average (4-mode shape, level 2: 1.5 leaves per node, 3.0 vs 5.6 ms
+// with ROW; at 5.8-11.7 leaves per node ROW was as fast or faster: NELL-2
+// 3.6 vs 3.4-4.3 ms, NETFLIX 2.6 vs 4.5 ms, 4-mode level 1 2.35 vs 2.26 ms)
+constexpr int64_t TILED_MID_LEAVES = 4;
 constexpr size_t HOT_LDS = 16 * 1024;   // hot output rows privatised per block
 constexpr int64_t HOT_BLOCKS = 16384;   // blocks looping over the streams (measured best of 2,048-65,536)
 constexpr double PRIV_THRESH = 0.02;  // privatise iff rows * copies <= 0.02 * nnz
@@ -319,6 +328,10 @@ cpd_status launch_leaf(int N, bool bf16, const int32_t *const *fids, const float
 int32_t tiled_height(int R, size_t lds_max);
 cpd_status launch_tiled(int N, bool bf16, const cpd_csf_s::LeafTiling &lt, int64_t nleaves,
                         const void *const *fac_by_level, int64_t ld, float *Y, int64_t ldo, int R, hipStream_t s);
+int32_t tiled_mid_height(int R, size_t lds_wave);
+cpd_status launch_tiled_mid(int N, bool bf16, const cpd_csf_s::LeafTiling &lt, int64_t nleaves,
+                            const void *const *fac_by_level, int64_t ld, float *Y, int64_t ldo, int R,
+                            hipStream_t s);
 
 // Lanes the root kernel gives one leaf for a padded rank RP.
 int root_lanes_per_leaf(int RP, bool bf16);
@@ -337,9 +350,11 @@ constexpr int64_t MID_HOT_LEAVES = 4;
 // as a 32-bit byte offset formed by a 24-bit multiply (row id times row
 // bytes), so every gathered level needs row ids below 2^24 and
 // rows * row bytes <= 2^32; they read the tree's leaf words.  The ROUND
-// kernel serves the leaf level: it reads the leaf words and gathers rows in
+// kernel serves the leaf level, the TILED kernels every level below the root
+// (on that level's mode tiling): they read the leaf words and gather rows in
 // 4-element chunks, so ld must be a multiple of 4 covering the rank rounded
-// up to 4, with 16-byte aligned factors.
+// up to 4, with 16-byte aligned factors.  AUTO: ROW where it applies, else
+// TILED at the leaf level, else LANE.
 cpd_status mttkrp_plan(int N, const int64_t *dims_by_level, int d, int64_t ld, int R, bool bf16, int request,
                        bool rows_aligned, bool leaf_words, int *kernel) {
     if (N < 2 || N > 5) CPD_FAIL(CPD_EUNSUPPORTED, "MTTKRP kernels are built for 2..5 modes, not %d", N);
@@ -363,11 +378,19 @@ cpd_status mttkrp_plan(int N, const int64_t *dims_by_level, int d, int64_t ld, i
                  "row kernel needs 3..5 modes, a non-leaf mode, ld >= %d, 16-byte rows, row ids below 2^24 and "
                  "rows * row bytes <= 2^32 at every gathered level",
                  RP);
-    const bool round_ok = d == N - 1 && leaf_words && rows_aligned && ld % 4 == 0 && ld >= ((R + 3) & ~3);
-    if ((request == CPD_KERNEL_ROUND || request == CPD_KERNEL_TILED) && !round_ok)
+    // ROUND (the leaf level) and TILED (every level below the root) gather
+    // 4-element chunks
+    const bool quad_ok = leaf_words && rows_aligned && ld % 4 == 0 && ld >= ((R + 3) & ~3);
+    const bool round_ok = quad_ok && d == N - 1;
+    const bool tiled_ok = quad_ok && d >= 1;
+    if (request == CPD_KERNEL_ROUND && !round_ok)
         CPD_FAIL(CPD_EUNSUPPORTED,
-                 "round and tiled kernels need the leaf level, leaf words, ld a multiple of 4 covering the rank "
-                 "and 16-byte aligned factors");
+                 "round kernel needs the leaf level, leaf words, ld a multiple of 4 covering the rank and 16-byte "
+                 "aligned factors");
+    if (request == CPD_KERNEL_TILED && !tiled_ok)
+        CPD_FAIL(CPD_EUNSUPPORTED,
+                 "tiled kernel needs a level below the root, leaf words, ld a multiple of 4 covering the rank and "
+                 "16-byte aligned factors");
     if (request != CPD_KERNEL_AUTO) *kernel = request;
     else *kernel = row_ok ? CPD_KERNEL_ROW : round_ok ? CPD_KERNEL_TILED : CPD_KERNEL_LANE;
     return CPD_OK;
@@ -432,6 +455,12 @@ cpd_status mttkrp_ws(cpd_csf_s *c, const void *const *factors, int32_t ld, int32
         if (c->order[l] != mode && (reinterpret_cast<uintptr_t>(factors[c->order[l]]) & 15)) aligned = false;
     int kernel = CPD_KERNEL_LANE;
     CPD_TRY(mttkrp_plan(N, dims_by_level, d, ld, R, bf16, o.kernel, aligned, c->leafw != nullptr, &kernel));
+    // AUTO at an internal level whose nodes are short: TILED where it applies
+    // (a property of the tree, which the shape rule above does not see)
+    if (o.kernel == CPD_KERNEL_AUTO && o.variant == CPD_VARIANT_AUTO && d >= 1 && d < N - 1 &&
+        c->counts[d] * TILED_MID_LEAVES > c->counts[N - 1] && c->leafw && aligned && ld % 4 == 0 &&
+        ld >= ((R + 3) & ~3))
+        kernel = CPD_KERNEL_TILED;
 
     // zero the output (columns < R)
     {
@@ -440,7 +469,7 @@ cpd_status mttkrp_ws(cpd_csf_s *c, const void *const *factors, int32_t ld, int32
                            (int64_t)ldo, R);
         CPD_LAUNCH_CHECK();
     }
-    if (kernel == CPD_KERNEL_ROW) {
+    auto row_path = [&]() -> cpd_status {
         // default tile: 128 leaves per group run, halved (down to 32) while
         // the tile steps would not give every resident wave two of them
         int32_t T = o.tile_nnz;
@@ -480,8 +509,9 @@ cpd_status mttkrp_ws(cpd_csf_s *c, const void *const *factors, int32_t ld, int32
                                     hot_rank, hot_perm, hot, s);
         if (st == CPD_OK && ev1) CPD_HIP(hipEventRecord(ev1, s));
         return st;
-    }
-    // the privatised variant at the leaf level runs LANE (AUTO) or is refused (ROUND, TILED asked for)
+    };
+    if (kernel == CPD_KERNEL_ROW) return row_path();
+    // the privatised variant below the root runs LANE (AUTO) or is refused (ROUND, TILED asked for)
     if ((kernel == CPD_KERNEL_ROUND || kernel == CPD_KERNEL_TILED) && o.variant == CPD_VARIANT_PRIVATE) {
         if (o.kernel != CPD_KERNEL_AUTO)
             CPD_FAIL(CPD_EUNSUPPORTED, "the round and tiled kernels have no privatised variant");
@@ -489,7 +519,8 @@ cpd_status mttkrp_ws(cpd_csf_s *c, const void *const *factors, int32_t ld, int32
     }
     if (kernel == CPD_KERNEL_TILED) {
         // the tile height that fits a block's LDS; the tiling is built on first
-        // use (with a workspace only a cached one is used, else ROUND runs)
+        // use (with a workspace only a cached one is used, else the leaf level
+        // runs ROUND and an internal level the kernel AUTO takes there)
         int dev = 0, lds_max = 64 * 1024;
         if (hipGetDevice(&dev) == hipSuccess) {
             int v = 0;
@@ -499,23 +530,33 @@ cpd_status mttkrp_ws(cpd_csf_s *c, const void *const *factors, int32_t ld, int32
         (void)hipGetLastError();
         // tile height: tile_nnz when given (capped by the LDS), else the rows
         // that fit TILED_LDS bytes per wave (several waves resident per SIMD)
-        const int32_t Bmax = tiled_height(R, (size_t)std::min(lds_max, 160 * 1024) / 4);
-        const int32_t Bdef = tiled_height(R, TILED_LDS);
-        const int32_t B =
-            o.tile_nnz > 0 ? std::min<int32_t>(o.tile_nnz, Bmax) : std::min(std::max(Bdef, TILED_MIN_ROWS), Bmax);
+        const bool leaf = d == N - 1;
+        const size_t lds_cap = (size_t)std::min(lds_max, 160 * 1024) / 4;
+        const int32_t Bmax = leaf ? tiled_height(R, lds_cap) : tiled_mid_height(R, lds_cap);
+        const int32_t Bdef = leaf ? std::max(tiled_height(R, TILED_LDS), TILED_MIN_ROWS) : TILED_MID_ROWS;
+        const int32_t B = o.tile_nnz > 0 ? std::min<int32_t>(o.tile_nnz, Bmax) : std::min(Bdef, Bmax);
         cpd_csf_s::LeafTiling lt;
-        if (B >= 1) CPD_TRY(csf_leaf_tiling(c, B, ws != nullptr, &lt, s));
+        if (B >= 1) CPD_TRY(csf_level_tiling(c, d, B, ws != nullptr, &lt, s));
         if (lt.B > 0) {
             const void *fac_by_level[CPD_MAX_MODES];
             for (int l = 0; l < N; ++l) fac_by_level[l] = fv.a[l];
             if (ev0) CPD_HIP(hipEventRecord(ev0, s));
-            cpd_status st = launch_tiled(N, bf16, lt, cv.nleaves, fac_by_level, ld, Y, ldo, R, s);
+            cpd_status st = leaf ? launch_tiled(N, bf16, lt, cv.nleaves, fac_by_level, ld, Y, ldo, R, s)
+                                 : launch_tiled_mid(N, bf16, lt, cv.nleaves, fac_by_level, ld, Y, ldo, R, s);
             if (st == CPD_OK && ev1) CPD_HIP(hipEventRecord(ev1, s));
             return st;
         }
-        if (!ws) CPD_FAIL(CPD_EUNSUPPORTED, "no leaf-mode tiling fits %d bytes of LDS at rank %d", lds_max, R);
-        kernel = CPD_KERNEL_ROUND;  // allocation-free call on a tree without a cached tiling
-        if (o.tile_nnz == 0) o.tile_nnz = 256;
+        if (!ws) CPD_FAIL(CPD_EUNSUPPORTED, "no mode tiling fits %d bytes of LDS at rank %d", lds_max, R);
+        // allocation-free call on a tree without a cached tiling
+        if (leaf) {
+            kernel = CPD_KERNEL_ROUND;
+            if (o.tile_nnz == 0) o.tile_nnz = 256;
+        } else {
+            CPD_TRY(mttkrp_plan(N, dims_by_level, d, ld, R, bf16, CPD_KERNEL_AUTO, aligned, c->leafw != nullptr,
+                                &kernel));
+            o.tile_nnz = 0;
+            if (kernel == CPD_KERNEL_ROW) return row_path();
+        }
     }
     if (kernel == CPD_KERNEL_ROUND) {
         // tiles of whole 64-leaf rounds

@@ -197,6 +197,7 @@ cpd_status cpd_select_candidates(const cpd_stats *st, int32_t rank, int32_t mode
                 push(CPD_VARIANT_ATOMIC, CPD_KERNEL_ROW, 256);
                 push(CPD_VARIANT_PRIVATE, CPD_KERNEL_ROW, 256);
             }
+            push(CPD_VARIANT_ATOMIC, CPD_KERNEL_TILED, 0);
             push(CPD_VARIANT_ATOMIC, CPD_KERNEL_LANE, 256);
             if (priv_fits(*st, mode, rank)) push(CPD_VARIANT_PRIVATE, CPD_KERNEL_LANE, 256);
         } else {

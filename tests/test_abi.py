@@ -104,8 +104,9 @@ def test_csf_build_rejects_six_to_eight_modes_without_touching_the_gpu():
 def test_mttkrp_plan_rule():
     """The host-side kernel choice: ROW only for 3..5 modes at non-leaf levels,
     with 16-byte rows inside ld and 32-bit row offsets at every gathered level;
-    ROUND only at the leaf level, with ld a multiple of 4 covering the rank;
-    AUTO takes them where eligible, LANE otherwise."""
+    ROUND only at the leaf level, TILED at every level below the root, both
+    with ld a multiple of 4 covering the rank; AUTO takes them where eligible,
+    LANE otherwise."""
     from paper_1812_05961_amd import cpd
     plan = cpd.mttkrp_plan
     nell = (9000, 12000, 29000)
@@ -128,11 +129,14 @@ def test_mttkrp_plan_rule():
     assert plan(nell, 2, 16, leaf_words=False) == "lane"
     assert plan(nell, 2, 16, rows_aligned=False) == "lane"
     assert plan((300, 500), 1, 16) == "tiled"
-    for depth, ld in ((0, 36), (1, 36), (2, 35)):
-        for kernel in ("round", "tiled"):
-            with pytest.raises(cpd.CpdError) as e:
-                plan(nell, depth, 35, ld=ld, kernel=kernel)
-            assert e.value.status == cpd.CPD_EUNSUPPORTED
+    # TILED: every level below the root, on the same row rules
+    assert plan(nell, 1, 35, ld=36, kernel="tiled") == "tiled"
+    assert plan((30, 40, 50, 60), 2, 16, kernel="tiled") == "tiled"
+    for depth, ld, kernel in ((0, 36, "round"), (1, 36, "round"), (2, 35, "round"), (0, 36, "tiled"),
+                              (1, 35, "tiled"), (2, 35, "tiled")):
+        with pytest.raises(cpd.CpdError) as e:
+            plan(nell, depth, 35, ld=ld, kernel=kernel)
+        assert e.value.status == cpd.CPD_EUNSUPPORTED
     # two modes: no ROW kernel is built, AUTO takes LANE at the root
     assert plan((300, 500), 0, 16) == "lane"
     with pytest.raises(cpd.CpdError):

@@ -248,6 +248,8 @@ def test_mttkrp_every_level(case, R, ld):
                               and R in (8, 16, 32, 35, 64) else [])
         if depth == t.nmodes - 1 and _round_ok(R, ld or R):
             kernels += ["round", "tiled"]
+        elif depth >= 1 and _round_ok(R, ld or R):
+            kernels += ["tiled"]  # the internal level's mode tiling
         # private: a copy of Y in LDS per block when it fits 64 KiB, else one
         # HBM copy per XCD summed afterwards
         variants = ["atomic"] + (["private"] if depth >= 1 else [])
@@ -282,9 +284,11 @@ def test_mttkrp_tile_widths(tile):
         ref = ocoo.mttkrp(t.dims, inds, vals, [f.numpy() for f in facs], mode)
         depth = c.order.index(mode)
         # the lane-group (row) kernels take tile widths in multiples of 32; the
-        # leaf-level round kernel rounds any width up to a multiple of 64
+        # leaf-level round kernel rounds any width up to a multiple of 64; the
+        # tiled kernels take it as the tile height in rows (capped by the LDS)
         row_ok = depth < 2 and tile % 32 == 0
-        for kernel in (["lane", "row"] if row_ok else ["lane"]) + (["round", "tiled"] if depth == 2 else []):
+        for kernel in ((["lane", "row"] if row_ok else ["lane"]) + (["round", "tiled"] if depth == 2 else [])
+                       + (["tiled"] if depth == 1 else [])):
             y, _ = _run(cpd, c, facs, mode, 16, "fp32", kernel, "auto", tile)
             assert relerr(y, ref) <= 1e-5, (mode, kernel, tile)
     if tile % 32:
@@ -333,16 +337,20 @@ def test_mttkrp_rejects_bad_arguments():
     with pytest.raises(cpd.CpdError) as e:
         cpd.mttkrp(c, facs, c.order[0], kernel="lane", variant="private")
     assert e.value.status == cpd.CPD_EUNSUPPORTED
-    # the round kernel serves the leaf level only, without a privatised variant,
-    # and needs a row stride that is a multiple of 4
-    for mode, variant in ((c.order[0], "auto"), (c.order[1], "auto"), (leaf, "private")):
+    # the round kernel serves the leaf level only, the tiled kernels every level
+    # below the root, neither with a privatised variant, and both need a row
+    # stride that is a multiple of 4
+    for kernel, mode, variant in (("round", c.order[0], "auto"), ("round", c.order[1], "auto"),
+                                  ("round", leaf, "private"), ("tiled", c.order[0], "auto"),
+                                  ("tiled", c.order[1], "private"), ("tiled", leaf, "private")):
         with pytest.raises(cpd.CpdError) as e:
-            cpd.mttkrp(c, facs, mode, kernel="round", variant=variant)
+            cpd.mttkrp(c, facs, mode, kernel=kernel, variant=variant)
         assert e.value.status == cpd.CPD_EUNSUPPORTED
     f6 = [torch.rand((d, 6), device="cuda") for d in t.dims]
-    with pytest.raises(cpd.CpdError) as e:
-        cpd.mttkrp(c, f6, leaf, rank=5, kernel="round")
-    assert e.value.status == cpd.CPD_EUNSUPPORTED
+    for kernel, mode in (("round", leaf), ("tiled", leaf), ("tiled", c.order[1])):
+        with pytest.raises(cpd.CpdError) as e:
+            cpd.mttkrp(c, f6, mode, rank=5, kernel=kernel)
+        assert e.value.status == cpd.CPD_EUNSUPPORTED
 
 
 @pytest.mark.parametrize("dims,alphas,order", [((2000, 300, 40), (0.5, 1.0, 0.0), (0, 1, 2)),
@@ -376,6 +384,33 @@ def test_mttkrp_leaf_round_hot_rows(dims, alphas, order, R):
         y, used = _run(cpd, c, facs, leaf, R, prec, "tiled", "auto")
         assert relerr(y, ocoo.mttkrp(t.dims, inds, vals, used, leaf)) <= 1e-5, (dims, prec, "tiled")
     c.free()
+
+
+@pytest.mark.parametrize("R", [8, 35, 64])
+def test_mttkrp_internal_tiled_many_tiles(R):
+    """The internal-level mode tiling on a 30,000-row internal mode (tens of
+    tiles at rank 35 and 64), Zipf-skewed, with long and single-leaf nodes, at
+    every internal level of 3-, 4- and 5-mode trees, FP32 and BF16: every row
+    against the oracle (BF16 on the rounded rows), a second call on the cached
+    tiling, and ragged tile heights."""
+    cpd = _cpd()
+    for dims, alphas, order in (((300, 30_000, 200), (1.0, 1.1, 0.5), (0, 1, 2)),
+                                ((50, 30_000, 7, 4000), (0.3, 1.2, 0.0, 1.5), (2, 1, 0, 3)),
+                                ((20, 30, 40, 30_000, 500), (0.5, 0.0, 0.8, 1.0, 0.0), (0, 1, 2, 3, 4))):
+        t = _tensor(dims, 300_000, alphas, 37)
+        inds, vals = t.numpy()
+        c = cpd.csf_build(_dev(t.inds), _dev(t.vals), t.dims, list(order))
+        ld = (R + 3) // 4 * 4
+        facs = _factors(t.dims, R, 41, ld)
+        for depth in range(1, t.nmodes - 1):
+            mode = order[depth]
+            ref = ocoo.mttkrp(t.dims, inds, vals, [f[:, :R].numpy() for f in facs], mode)
+            for tile in (0, 0, 5):
+                y, _u = _run(cpd, c, facs, mode, R, "fp32", "tiled", "auto", tile)
+                assert relerr(y, ref) <= 1e-5, (dims, depth, R, tile)
+            y, used = _run(cpd, c, facs, mode, R, "bf16", "tiled", "auto")
+            assert relerr(y, ocoo.mttkrp(t.dims, inds, vals, used, mode)) <= 1e-5, (dims, depth, R, "bf16")
+        c.free()
 
 
 @pytest.mark.parametrize("R", [8, 35, 64])

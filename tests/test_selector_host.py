@@ -54,13 +54,13 @@ def test_candidates_three_modes():
                                          ("last", (0, 2, 1), 2), ("desc", (2, 1, 0), 1),
                                          ("rooted", (1, 2, 0), 0)})
     # 2000 x 16 x 4 B > 64 KiB: no privatised LANE
-    assert len(c1) == 3 + 3 + 5 + 3 + 3
+    assert len(c1) == 3 + 3 + 5 + 4 + 4
     for c in c1:
         if c["depth"] == 0:
             assert c["kernel"] == "row" and c["variant"] == "auto" and c["tile_nnz"] in (32, 128, 512)
         elif c["depth"] == 1:
             assert (c["kernel"], c["variant"], c["tile_nnz"]) in {("row", "atomic", 256), ("row", "private", 256),
-                                                                  ("lane", "atomic", 256)}
+                                                                  ("tiled", "atomic", 0), ("lane", "atomic", 256)}
         else:
             assert (c["kernel"], c["variant"]) in {("tiled", "atomic"), ("round", "atomic"), ("lane", "atomic")}
             assert c["tile_nnz"] in {"round": (64, 256, 1024), "tiled": (0,), "lane": (256,)}[c["kernel"]]
