@@ -143,6 +143,60 @@ __device__ __forceinline__ void wave_sync_lds_root() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Row stride (in words) of a wave's LDS staging of the leaf stream: C leaves
+// per run plus one, so that the groups' reads of one position (one run each)
+// fall in different banks.
+template <int C>
+constexpr int stage_stride() {
+    return C + 1;
+}
+
+typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// Stage leaf words, values and internal ids of positions t0..t0+C-1 of the
+// NG runs of a tile step (run s starts at leaf base + s*T) into the wave's
+// LDS rows: 16-byte loads, four leaves a lane (runs and chunks start at
+// multiples of 4 leaves and the tree's arrays are 16-byte aligned), so a
+// chunk costs a quarter of the load instructions of one leaf a lane.  The
+// four words go to LDS one at a time (the rows' odd stride keeps them in
+// distinct banks across the lanes).
+template <int NG, int C, int NU>
+__device__ __forceinline__ void stage_chunk(const CsfView &cv, int64_t base, int64_t T, int t0, int lane,
+                                            int32_t *sw, float *sv, int32_t (*su)[NG * stage_stride<C>()]) {
+    constexpr int Q = C / 4, S = stage_stride<C>();
+    const int64_t nleaves = cv.nleaves;
+    for (int e2 = lane; e2 < NG * Q; e2 += 64) {
+        const int s = e2 / Q, j = 4 * (e2 % Q);
+        const int64_t k = base + (int64_t)s * T + t0 + j;
+        const int at = s * S + j;
+        if (k + 4 <= nleaves) {
+            const i32x4 w = __builtin_nontemporal_load(reinterpret_cast<const i32x4 *>(cv.leafw + k));
+            const f32x4 v = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(cv.vals + k));
+            i32x4 u[NU > 0 ? NU : 1];
+#pragma unroll
+            for (int l = 0; l < NU; ++l)
+                u[l] = __builtin_nontemporal_load(reinterpret_cast<const i32x4 *>(cv.uprow[l + 1] + k));
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                sw[at + i] = w[i];
+                sv[at + i] = v[i];
+#pragma unroll
+                for (int l = 0; l < NU; ++l) su[l][at + i] = u[l][i];
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const bool in = k + i < nleaves;
+                sw[at + i] = in ? stream_load(cv.leafw + k + i) : 0;
+                sv[at + i] = in ? stream_load(cv.vals + k + i) : 0.0f;
+#pragma unroll
+                for (int l = 0; l < NU; ++l) su[l][at + i] = in ? stream_load(cv.uprow[l + 1] + k + i) : 0;
+            }
+        }
+    }
+}
+
 // One leaf's contribution x * A_leaf(j, c) * H(c) for element e of a lane's
 // chunk, added to the accumulator: FP32 products and sums, or (AT = double,
 // float rows only) FP64 products and sums.
@@ -176,7 +230,7 @@ k_mttkrp_root(CsfView cv, FacView fv, const char *__restrict__ a_leaf, uint32_t 
     constexpr int W = Chunk<GT>::W;
     constexpr int E = W;        // row elements per lane
     constexpr int NU = N - 2;   // internal levels
-    constexpr int SS = NG * (C + 1);
+    constexpr int SS = NG * stage_stride<C>();
     constexpr int32_t IDMASK = (1 << 29) - 1;
     __shared__ int32_t s_w[ROOT_WAVES][SS];
     __shared__ float s_v[ROOT_WAVES][SS];
@@ -239,16 +293,7 @@ k_mttkrp_root(CsfView cv, FacView fv, const char *__restrict__ a_leaf, uint32_t 
         for (int l = 0; l < NU; ++l) last_up[l] = -1;
         for (int t0 = 0; t0 < T; t0 += C) {
             // stage leaf words, values and internal ids: run s, positions t0..t0+C-1
-            for (int e2 = lane; e2 < NG * C; e2 += 64) {
-                const int s = e2 / C, j = e2 % C;
-                const int64_t k = base + (int64_t)s * T + t0 + j;
-                const bool in = k < nleaves;
-                sw[s * (C + 1) + j] = in ? stream_load(leafw + k) : 0;
-                sv[s * (C + 1) + j] = in ? stream_load(vals + k) : 0.0f;
-#pragma unroll
-                for (int l = 0; l < NU; ++l)
-                    s_u[wave][l][s * (C + 1) + j] = in ? stream_load(cv.uprow[l + 1] + k) : 0;
-            }
+            stage_chunk<NG, C, NU>(cv, base, T, t0, lane, sw, sv, s_u[wave]);
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -262,7 +307,7 @@ k_mttkrp_root(CsfView cv, FacView fv, const char *__restrict__ a_leaf, uint32_t 
                 bool need[U][NU];
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    const int at = gs * (C + 1) + j0 + u;
+                    const int at = gs * stage_stride<C>() + j0 + u;
                     wu[u] = sw[at];
                     vu[u] = sv[at];
                     Chunk<GT>::load(a_leaf, __umul24((uint32_t)wu[u] & IDMASK, rowb) + lane_off, rowu[u]);
@@ -415,7 +460,7 @@ k_mttkrp_mid(CsfView cv, FacView fv, const char *__restrict__ a_leaf, uint32_t r
     constexpr int W = Chunk<GT>::W;
     constexpr int E = W;
     constexpr int NU = N - 2;  // internal levels 1..N-2
-    constexpr int SS = NG * (C + 1);
+    constexpr int SS = NG * stage_stride<C>();
     constexpr int32_t IDMASK = (1 << 29) - 1;
     constexpr int SR = G * W;            // row stride of the list of finished nodes
     constexpr int CAP = NG * U + NG;  // its length: drained once more than NG entries wait
@@ -506,16 +551,7 @@ k_mttkrp_mid(CsfView cv, FacView fv, const char *__restrict__ a_leaf, uint32_t r
 #pragma unroll
         for (int l = 0; l < NU; ++l) last_up[l] = -1;
         for (int t0 = 0; t0 < T; t0 += C) {
-            for (int e2 = lane; e2 < NG * C; e2 += 64) {
-                const int s = e2 / C, j = e2 % C;
-                const int64_t k = base + (int64_t)s * T + t0 + j;
-                const bool in = k < nleaves;
-                sw[s * (C + 1) + j] = in ? stream_load(leafw + k) : 0;
-                sv[s * (C + 1) + j] = in ? stream_load(vals + k) : 0.0f;
-#pragma unroll
-                for (int l = 0; l < NU; ++l)
-                    s_u[wave][l][s * (C + 1) + j] = in ? stream_load(cv.uprow[l + 1] + k) : 0;
-            }
+            stage_chunk<NG, C, NU>(cv, base, T, t0, lane, sw, sv, s_u[wave]);
             wave_sync_lds_root();
             const int len = (int)(kend - k0) - t0;  // this group's leaves left in the chunk
             // every group steps through the whole chunk (the list is filled and
@@ -527,7 +563,7 @@ k_mttkrp_mid(CsfView cv, FacView fv, const char *__restrict__ a_leaf, uint32_t r
                 bool need[U][NU];
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    const int at = gs * (C + 1) + j0 + u;
+                    const int at = gs * stage_stride<C>() + j0 + u;
                     wu[u] = sw[at];
                     vu[u] = sv[at];
                     Chunk<GT>::load(a_leaf, __umul24((uint32_t)wu[u] & IDMASK, rowb) + lane_off, rowu[u]);
@@ -548,7 +584,7 @@ k_mttkrp_mid(CsfView cv, FacView fv, const char *__restrict__ a_leaf, uint32_t r
                 for (int u = 0; u < U; ++u) {
                     const int jr = j0 + u;
                     const bool live = active && jr < len;
-                    const int at = gs * (C + 1) + jr;
+                    const int at = gs * stage_stride<C>() + jr;
                     const int lvl = (int)((uint32_t)wu[u] >> 29);
                     const bool first = (t0 | jr) == 0;
                     const bool opens = live && (first || lvl <= d);  // a level-d node opens here
