@@ -57,7 +57,7 @@ enum { CPD_VARIANT_AUTO = 0, CPD_VARIANT_ATOMIC = 1, CPD_VARIANT_PRIVATE = 2 };
 /* Kernel family: AUTO picks (ROW above the leaf level, TILED at the leaf
  * level, LANE otherwise, each where eligible -- see cpd_mttkrp_plan -- and,
  * with CPD_VARIANT_AUTO, TILED at an internal level whose nodes hold fewer
- * than 4 leaves on average); ROW = groups of
+ * than 6 leaves on average); ROW = groups of
  * lanes each holding 16-byte chunks of the factor rows, several leaves per
  * wave step (root and internal levels; tile widths in multiples of 32);
  * LANE = the rank spread over the lanes, one leaf per wave step (any level);
@@ -67,7 +67,7 @@ enum { CPD_VARIANT_AUTO = 0, CPD_VARIANT_ATOMIC = 1, CPD_VARIANT_PRIVATE = 2 };
  * no privatised variant: CPD_VARIANT_PRIVATE with AUTO runs LANE);
  * TILED = any level below the root: the leaves regrouped by tiles of the
  * output mode's indices (the level's mode tiling, built on the first such
- * call and kept with the tree: 4 (N+1) bytes per nonzero); each wave adds its
+ * call and kept with the tree: 16 bytes per nonzero for 2..3 modes, 32 for 4..5); each wave adds its
  * share into a private LDS copy of its tile's output rows and adds the copy
  * to the output once per tile -- at the leaf level one row per leaf scaled by
  * its fiber's Hadamard row, at an internal level one row per node (the sum
@@ -214,7 +214,7 @@ cpd_status cpd_mttkrp_noalloc(cpd_csf csf, const void *const *factors, int32_t l
  * AUTO picks ROW above the leaf level and TILED at the leaf level, each when
  * eligible, LANE otherwise (cpd_mttkrp runs LANE instead of ROUND or TILED
  * for CPD_VARIANT_PRIVATE, and TILED at an internal level whose nodes hold
- * fewer than 4 leaves on average, a property of the tree this rule does not
+ * fewer than 6 leaves on average, a property of the tree this rule does not
  * see; cpd_mttkrp_noalloc runs ROUND at the leaf level and the shape rule's
  * kernel at an internal level when the tree holds no tiling of that height
  * yet).

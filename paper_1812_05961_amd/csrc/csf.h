@@ -49,9 +49,11 @@ struct cpd_csf_s {
         int32_t B = 0;
         int64_t ntiles = 0;
         int32_t *toff = nullptr;                 // ntiles + 1 offsets into the regrouped leaves
-        float *tv = nullptr;                     // value of each regrouped leaf
-        int32_t *tw = nullptr;                   // its level-d index minus the tile's first index
-        int32_t *th[CPD_MAX_MODES] = {};         // its indices at the other levels, in level order
+        // one record of rw words per regrouped leaf (rw = 4 for 2..3 modes, 8
+        // for 4..5): its value's bits, its level-d index minus the tile's
+        // first index, its indices at the other levels in level order, padding
+        int32_t *rec = nullptr;
+        int32_t rw = 0;
         char *slab = nullptr;
         size_t bytes = 0;
     };

@@ -6,14 +6,16 @@
 // Tree order inside a tile keeps the leaves of each level-d node (and of
 // each fiber) consecutive.
 //
-// Per regrouped leaf j (leaf k of the tree): its value, its level-d index
-// minus the tile's first index, and its indices at the other levels in level
-// order (at the leaf level: the fiber whose rows form the Hadamard product
-// the leaf is scaled by; at an internal level: the node's ancestors, then the
-// levels below d).  The indices are stored per leaf so that the MTTKRP reads
-// them in coalesced runs: looked up per fiber or node they are a random
-// access into arrays of the tree's node counts, one cache line per run of a
-// tile, which misses the L2.  Built with the CSF builder's radix sort (key:
+// Per regrouped leaf j (leaf k of the tree) one record: its value, its
+// level-d index minus the tile's first index, and its indices at the other
+// levels in level order (at the leaf level: the fiber whose rows form the
+// Hadamard product the leaf is scaled by; at an internal level: the node's
+// ancestors, then the levels below d), padded to 4 or 8 words so that a lane
+// reads its leaf's record with one or two 16-byte loads (a load instruction
+// costs the vector-memory return path about the same whatever its width).
+// The indices are stored per leaf, not looked up per fiber or node: that
+// would be a random access into arrays of the tree's node counts, one cache
+// line per run of a tile, which misses the L2.  Built with the CSF builder's radix sort (key:
 // the tile number, payload: the position) and a device-wide scan over the
 // leaf words (the root node of every leaf).
 #include <algorithm>
@@ -67,22 +69,18 @@ __global__ void k_tile_offsets(const uint64_t *__restrict__ key, int64_t n, int6
     toff[t] = (int32_t)lo;
 }
 
-struct TileOut {
-    float *tv;
-    int32_t *tw;
-    int32_t *th[CPD_MAX_MODES];
-};
-
 __global__ void k_tile_gather(const int32_t *__restrict__ pos, const uint64_t *__restrict__ key, int64_t n, int32_t B,
-                              const float *__restrict__ vals, LevelIds li, int d, TileOut o) {
+                              const float *__restrict__ vals, LevelIds li, int d, int rw, int32_t *__restrict__ rec) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
     const int32_t k = pos[j];
-    o.tv[j] = vals[k];
-    o.tw[j] = li.at(d, k) - (int32_t)key[j] * B;
-    int m = 0;
+    int32_t *r = rec + j * rw;
+    r[0] = __float_as_int(vals[k]);
+    r[1] = li.at(d, k) - (int32_t)key[j] * B;
+    int m = 2;
     for (int l = 0; l < li.N; ++l)
-        if (l != d) o.th[m++][j] = li.at(l, k);
+        if (l != d) r[m++] = li.at(l, k);
+    for (; m < rw; ++m) r[m] = 0;
 }
 
 inline unsigned grid_of(int64_t n) { return (unsigned)ceil_div(std::max<int64_t>(n, 1), 256); }
@@ -116,8 +114,9 @@ cpd_status csf_level_tiling(cpd_csf_s *c, int d, int32_t B, bool cached_only, cp
     lt.B = B;
     lt.ntiles = nt;
     auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
-    const size_t b_toff = al(sizeof(int32_t) * (size_t)(nt + 1)), b_leaf = al(sizeof(int32_t) * (size_t)n);
-    lt.bytes = b_toff + (size_t)(N + 1) * b_leaf;  // value, local row, N-1 indices
+    lt.rw = N <= 3 ? 4 : 8;  // value, local row, N-1 indices, padding
+    const size_t b_toff = al(sizeof(int32_t) * (size_t)(nt + 1));
+    lt.bytes = b_toff + al(sizeof(int32_t) * (size_t)lt.rw * (size_t)n);
     if (hipMallocAsync((void **)&lt.slab, lt.bytes, s) != hipSuccess) {
         (void)hipGetLastError();
         CPD_FAIL(CPD_ENOMEM, "device allocation of %zu bytes for the mode tiling failed", lt.bytes);
@@ -125,14 +124,7 @@ cpd_status csf_level_tiling(cpd_csf_s *c, int d, int32_t B, bool cached_only, cp
     char *p = lt.slab;
     lt.toff = reinterpret_cast<int32_t *>(p);
     p += b_toff;
-    lt.tv = reinterpret_cast<float *>(p);
-    p += b_leaf;
-    lt.tw = reinterpret_cast<int32_t *>(p);
-    p += b_leaf;
-    for (int m = 0; m < N - 1; ++m) {
-        lt.th[m] = reinterpret_cast<int32_t *>(p);
-        p += b_leaf;
-    }
+    lt.rec = reinterpret_cast<int32_t *>(p);
     auto fail = [&](cpd_status st) {
         (void)hipFreeAsync(lt.slab, s);
         (void)hipGetLastError();
@@ -162,12 +154,8 @@ cpd_status csf_level_tiling(cpd_csf_s *c, int d, int32_t B, bool cached_only, cp
     if ((st = radix_sort(klo, khi, kp, olo, ohi, op, n, bits, s))) return fail(st);
     hipLaunchKernelGGL(k_tile_offsets, dim3(grid_of(nt + 1)), dim3(256), 0, s, (const uint64_t *)klo, n, nt, lt.toff);
     if (hipGetLastError() != hipSuccess) return fail(CPD_EHIP);
-    TileOut o{};
-    o.tv = lt.tv;
-    o.tw = lt.tw;
-    for (int m = 0; m < N - 1; ++m) o.th[m] = lt.th[m];
     hipLaunchKernelGGL(k_tile_gather, dim3(grid_of(n)), dim3(256), 0, s, (const int32_t *)kp, (const uint64_t *)klo, n,
-                       B, (const float *)c->vals, li, d, o);
+                       B, (const float *)c->vals, li, d, (int)lt.rw, lt.rec);
     if (hipGetLastError() != hipSuccess) return fail(CPD_EHIP);
     c->leaf_tilings.push_back(lt);
     *out = lt;

@@ -298,10 +298,10 @@ constexpr int32_t TILED_MIN_ROWS = 16;
 // 1.5-2x slower at 64 and 3-4x at 128, the tables costing resident waves)
 constexpr int32_t TILED_MID_ROWS = 16;
 // AUTO takes TILED at an internal level whose nodes hold fewer leaves than
-// this on average (4-mode shape, level 2: 1.5 leaves per node, 3.0 vs 5.6 ms
-// with ROW; at 5.8-11.7 leaves per node ROW was as fast or faster: NELL-2
-// 3.6 vs 3.4-4.3 ms, NETFLIX 2.6 vs 4.5 ms, 4-mode level 1 2.35 vs 2.26 ms)
-constexpr int64_t TILED_MID_LEAVES = 4;
+// this on average (single ascending trees, ms TILED vs ROW: 4-mode level 2,
+// 1.5 leaves per node: 2.95 vs 5.6; NELL-2 level 1, 5.8: 3.12 vs 3.35; NETFLIX
+// level 1, 8.8: 3.54 vs 2.31; 4-mode level 1, 11.7: 2.44 vs 2.08)
+constexpr int64_t TILED_MID_LEAVES = 6;
 constexpr size_t HOT_LDS = 16 * 1024;   // hot output rows privatised per block
 constexpr int64_t HOT_BLOCKS = 16384;   // blocks looping over the streams (measured best of 2,048-65,536)
 constexpr double PRIV_THRESH = 0.02;  // privatise iff rows * copies <= 0.02 * nnz

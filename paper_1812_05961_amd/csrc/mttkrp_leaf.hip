@@ -221,22 +221,40 @@ cpd_status launch_leaf_n(const LeafView &cv, const LeafFac &fv, int64_t ld, cons
 // nonzero is a plain LDS read-add-write by the one wave that owns the row --
 // no atomics (the LDS FP32 atomic add measured several times slower than a
 // plain read-modify-write here).  Rounds of 64 leaves as in the ROUND kernel:
-// value, local row and the fiber's level indices loaded with coalesced loads
-// (a fiber run starts where any of those indices changes), each run's H row
+// each lane loads its leaf's record (value, local row, the fiber's level
+// indices) with one or two 16-byte loads (a fiber run starts where any of
+// those indices changes), each run's H row
 // gathered once into the wave's H table,
 // then the leaves walked one per step, the rank across the lanes; two
 // consecutive leaves of one row are summed before their read-modify-write.
+typedef int32_t i32x4_t __attribute__((ext_vector_type(4)));
+
 struct TiledView {
     const int32_t *toff;
-    const float *tv;
-    const int32_t *tw;
-    const int32_t *th[CPD_MAX_MODES];
+    const int32_t *rec;  // one record per regrouped leaf: value bits, local row, other levels' indices
     int64_t n;
     int64_t ntiles;
     int32_t B;
 };
 
 constexpr int TILED_WAVES = 4;  // waves per block (each on its own range and tables)
+
+// Leaf k's record of a mode tiling: one 16-byte load for 2..3 modes, two for
+// 4..5 (records of 4 or 8 words, 16-byte aligned).
+template <int N>
+__device__ __forceinline__ void load_record(const int32_t *rec, int64_t k, float &x, int32_t &row, int32_t (&id)[N - 1]) {
+    constexpr int RW = N <= 3 ? 4 : 8;
+    const i32x4_t a = __builtin_nontemporal_load(reinterpret_cast<const i32x4_t *>(rec + k * RW));
+    x = __int_as_float(a.x);
+    row = a.y;
+    id[0] = a.z;
+    if constexpr (N >= 3) id[1] = a.w;
+    if constexpr (N >= 4) {
+        const i32x4_t b = __builtin_nontemporal_load(reinterpret_cast<const i32x4_t *>(rec + k * RW + 4));
+        id[2] = b.x;
+        if constexpr (N >= 5) id[3] = b.y;
+    }
+}
 
 // Dynamic LDS per wave: PF x RQ floats (H rows), then B x R floats (its tile).
 template <int N, typename GT, int UF>
@@ -278,15 +296,12 @@ k_mttkrp_tiled(TiledView tv, LeafFac fv, int64_t ld, int64_t nwaves, float *__re
             const int64_t k = k0 + lane;
             const bool in = k < e;
             const int64_t kk = in ? k : e - 1;
-            const float x = stream_load(tv.tv + kk);
-            const int32_t row = stream_load(tv.tw + kk);
-            int32_t hid[N - 1];
+            float x;
+            int32_t row, hid[N - 1];
+            load_record<N>(tv.rec, kk, x, row, hid);
             bool newf = lane == 0;
 #pragma unroll
-            for (int l = 0; l < N - 1; ++l) {
-                hid[l] = stream_load(tv.th[l] + kk);
-                newf |= __shfl_up(hid[l], 1, 64) != hid[l];
-            }
+            for (int l = 0; l < N - 1; ++l) newf |= __shfl_up(hid[l], 1, 64) != hid[l];
             // a fiber is its index tuple: a new run where any level's index changes
             const uint64_t fmask = __ballot(in && newf);
             const int nin = (int)min<int64_t>(64, e - k0);
@@ -402,8 +417,9 @@ cpd_status launch_tiled_n(const TiledView &tv, const LeafFac &fv, int64_t ld, fl
 // lanes: the running sum of x_k * H_below(k) of the open node, multiplied by
 // H_above and added to the node's row of the wave-private tile table when the
 // node closes (a plain LDS read-add-write: no atomic into Y per node).
-// Rounds of 64 leaves: value, local row and the other levels' indices loaded
-// with coalesced loads (a node starts where the local row or an index above
+// Rounds of 64 leaves: each lane loads its leaf's record (value, local row,
+// the other levels' indices) with one or two 16-byte loads (a node starts
+// where the local row or an index above
 // d changes); per batch of PF leaves the H_below rows of its leaves and the
 // H_above rows of the nodes starting in it are gathered by lane groups into
 // the wave's tables, then the batch is walked.  A node split between two
@@ -454,11 +470,9 @@ k_mttkrp_tiled_mid(TiledView tv, LeafFac fv, int na, int64_t ld, int64_t nwaves,
             const int64_t k = k0 + lane;
             const bool in = k < e;
             const int64_t kk = in ? k : e - 1;
-            const float x = stream_load(tv.tv + kk);
-            const int32_t row = stream_load(tv.tw + kk);
-            int32_t id[N - 1];
-#pragma unroll
-            for (int m = 0; m < N - 1; ++m) id[m] = stream_load(tv.th[m] + kk);
+            float x;
+            int32_t row, id[N - 1];
+            load_record<N>(tv.rec, kk, x, row, id);
             // a node is its local row with its indices above d
             bool newn = __shfl_up(row, 1, 64) != row;
             bool newl = open_row < 0 || row != last_row;
@@ -667,9 +681,8 @@ cpd_status launch_tiled(int N, bool bf16, const cpd_csf_s::LeafTiling &lt, int64
         CPD_FAIL(CPD_EUNSUPPORTED, "tiled leaf kernel needs rank <= 64 and ld a multiple of 4 covering the rank");
     TiledView tv{};
     tv.toff = lt.toff;
-    tv.tv = lt.tv;
-    tv.tw = lt.tw;
-    for (int l = 0; l < N - 1; ++l) tv.th[l] = lt.th[l];
+    if (lt.rw != (N <= 3 ? 4 : 8)) CPD_FAIL(CPD_EINVAL, "mode tiling records of %d words for %d modes", lt.rw, N);
+    tv.rec = lt.rec;
     tv.n = nleaves;
     tv.ntiles = lt.ntiles;
     tv.B = lt.B;
@@ -723,9 +736,8 @@ cpd_status launch_tiled_mid(int N, bool bf16, const cpd_csf_s::LeafTiling &lt, i
         CPD_FAIL(CPD_EUNSUPPORTED, "tiled kernels need rank <= 64 and ld a multiple of 4 covering the rank");
     TiledView tv{};
     tv.toff = lt.toff;
-    tv.tv = lt.tv;
-    tv.tw = lt.tw;
-    for (int m = 0; m < N - 1; ++m) tv.th[m] = lt.th[m];
+    if (lt.rw != (N <= 3 ? 4 : 8)) CPD_FAIL(CPD_EINVAL, "mode tiling records of %d words for %d modes", lt.rw, N);
+    tv.rec = lt.rec;
     tv.n = nleaves;
     tv.ntiles = lt.ntiles;
     tv.B = lt.B;

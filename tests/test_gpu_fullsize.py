@@ -165,17 +165,24 @@ def test_full_size_mttkrp_all_rows_als_layout(name, precision):
 
 @pytest.mark.parametrize("precision", ["fp32", "bf16"])
 def test_full_size_single_tree_every_level(precision):
-    """The heuristic tree of the NELL-2 shape: the root (lane-group and LANE
-    kernels), the internal level (LANE atomic, LANE privatised into per-XCD
-    copies, lane-group) and the leaf level (LANE atomic with the hot-row
-    table, LANE privatised), every row."""
+    """The heuristic tree of the NELL-2 shape, every kernel the single-tree
+    timings run: the root (lane-group and LANE kernels), the internal level
+    (lane-group without and with the hot-row table, TILED on the level's mode
+    tiling, LANE atomic, LANE privatised into per-XCD copies) and the leaf
+    level (TILED, ROUND, LANE atomic with the hot-row table, LANE
+    privatised), every row."""
     cpd = _cpd()
     t = _full("nell2")
     facs, used = _factors(t, precision, 4)
     c = cpd.csf_build(t.inds, t.vals, t.dims, None)
     for depth, m in enumerate(c.order):
         ref = ocoo.mttkrp(t.dims, t.inds_h, t.vals_h, used, m, threads=THREADS)
-        runs = [("row", "auto")] if depth < t.nm - 1 else []
+        if depth == 0:
+            runs = [("row", "auto")]
+        elif depth < t.nm - 1:
+            runs = [("row", "atomic"), ("row", "private"), ("tiled", "auto")]
+        else:
+            runs = [("tiled", "auto"), ("round", "auto")]
         runs += [("lane", "atomic")] + ([("lane", "private")] if depth > 0 else [])
         for kernel, variant in runs:
             y = cpd.mttkrp(c, facs, m, rank=t.R, precision=precision, kernel=kernel, variant=variant)
