@@ -528,8 +528,9 @@ cpd_status mttkrp_ws(cpd_csf_s *c, const void *const *factors, int32_t ld, int32
                 lds_max = v;
         }
         (void)hipGetLastError();
-        // tile height: tile_nnz when given (capped by the LDS), else the rows
-        // that fit TILED_LDS bytes per wave (several waves resident per SIMD)
+        // tile height: tile_nnz when given (capped by the LDS), else at the
+        // leaf level the rows that fit TILED_LDS bytes per wave (several waves
+        // resident per SIMD), at an internal level TILED_MID_ROWS
         const bool leaf = d == N - 1;
         const size_t lds_cap = (size_t)std::min(lds_max, 160 * 1024) / 4;
         const int32_t Bmax = leaf ? tiled_height(R, lds_cap) : tiled_mid_height(R, lds_cap);
