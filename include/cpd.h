@@ -83,6 +83,13 @@ enum { CPD_KERNEL_AUTO = 0, CPD_KERNEL_ROW = 1, CPD_KERNEL_LANE = 2, CPD_KERNEL_
 /* Last error message of the calling thread ("" if none). */
 const char *cpd_last_error(void);
 
+/* Test hook for the allocation-failure paths: from now on every device
+ * allocation request of the library larger than `bytes` fails with
+ * CPD_ENOMEM (cached scratch blocks included), as if the device were out of
+ * memory; bytes < 0 removes the limit (the default).  Process-wide; always
+ * CPD_OK. */
+cpd_status cpd_set_alloc_limit(int64_t bytes);
+
 /* ABI version of this library (incremented on incompatible changes). */
 int32_t cpd_abi_version(void);
 

@@ -78,6 +78,7 @@ _lib = None
 # name -> (restype, argtypes)
 _SIGS = {
     "cpd_last_error": (ctypes.c_char_p, []),
+    "cpd_set_alloc_limit": (_I32, [_I64]),
     "cpd_abi_version": (_I32, []),
     "cpd_csf_build": (_I32, [_I32, _P, _I64, _P, _P, _P, _P, _P]),
     "cpd_csf_build_rooted": (_I32, [_I32, _P, _I64, _P, _P, _P, _P]),
@@ -304,6 +305,12 @@ def mttkrp_noalloc(csf: Csf, factors, mode: int, out, rank=None, precision="fp32
 
 def noalloc_workspace_bytes():
     return int(lib().cpd_mttkrp_noalloc_workspace_bytes())
+
+
+def set_alloc_limit(nbytes):
+    """Test hook: device allocation requests above nbytes fail with
+    CPD_ENOMEM (None or a negative value: no limit)."""
+    lib().cpd_set_alloc_limit(-1 if nbytes is None else int(nbytes))
 
 
 def gram(A, stream=None):

@@ -48,6 +48,9 @@ void keep_pool_memory();
 // Scratch blocks for stream-ordered use on stream s: reused from a cache of
 // blocks released on the same stream, else taken from the stream-ordered pool.
 cpd_status scratch_get(size_t bytes, hipStream_t s, void **p);
+// Every device allocation of the library (stream-ordered): CPD_ENOMEM when
+// the runtime refuses it or when it exceeds the limit cpd_set_alloc_limit set.
+cpd_status device_alloc(void **p, size_t bytes, hipStream_t s);
 void scratch_put(void *p, size_t bytes, hipStream_t s);
 
 // Stream-ordered scratch buffer that returns itself to the scratch cache on

@@ -1267,9 +1267,8 @@ cpd_status csf_level_rank(cpd_csf_s *c, int l, const int32_t **perm, const int32
         int32_t *pp = nullptr, *rr = nullptr;
         DevBuf<int32_t> nr;
         CPD_TRY(nr.alloc(1, s));
-        if (hipMallocAsync((void **)&pp, sizeof(int32_t) * nid, s) != hipSuccess ||
-            hipMallocAsync((void **)&rr, sizeof(int32_t) * nid, s) != hipSuccess) {
-            (void)hipGetLastError();
+        if (device_alloc((void **)&pp, sizeof(int32_t) * nid, s) != CPD_OK ||
+            device_alloc((void **)&rr, sizeof(int32_t) * nid, s) != CPD_OK) {
             if (pp) (void)hipFreeAsync(pp, s);
             CPD_FAIL(CPD_ENOMEM, "device allocation for a level ranking failed");
         }
@@ -1377,10 +1376,8 @@ cpd_status csf_tiles(cpd_csf_s *c, int32_t tile, const int32_t **starts, int64_t
     const int64_t nl = c->counts[nm - 1];
     const int64_t nt = ceil_div(nl, tile);
     int32_t *p = nullptr;
-    if (hipMallocAsync((void **)&p, sizeof(int32_t) * (size_t)std::max<int64_t>(1, (nm - 1) * nt), s) != hipSuccess) {
-        (void)hipGetLastError();
+    if (device_alloc((void **)&p, sizeof(int32_t) * (size_t)std::max<int64_t>(1, (nm - 1) * nt), s) != CPD_OK)
         CPD_FAIL(CPD_ENOMEM, "device allocation for the tile table failed");
-    }
     FptrSet fp{};
     for (int l = 0; l < nm - 1; ++l) {
         fp.p[l] = c->fptr[l];

@@ -117,10 +117,8 @@ cpd_status csf_level_tiling(cpd_csf_s *c, int d, int32_t B, bool cached_only, cp
     lt.rw = N <= 3 ? 4 : 8;  // value, local row, N-1 indices, padding
     const size_t b_toff = al(sizeof(int32_t) * (size_t)(nt + 1));
     lt.bytes = b_toff + al(sizeof(int32_t) * (size_t)lt.rw * (size_t)n);
-    if (hipMallocAsync((void **)&lt.slab, lt.bytes, s) != hipSuccess) {
-        (void)hipGetLastError();
+    if (device_alloc((void **)&lt.slab, lt.bytes, s) != CPD_OK)
         CPD_FAIL(CPD_ENOMEM, "device allocation of %zu bytes for the mode tiling failed", lt.bytes);
-    }
     char *p = lt.slab;
     lt.toff = reinterpret_cast<int32_t *>(p);
     p += b_toff;

@@ -8,6 +8,7 @@
 // using the block has finished before later work touches it.  Blocks are
 // never shared across streams.  The cache is bounded; beyond the bound a
 // released block goes back to the pool.
+#include <atomic>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -18,6 +19,8 @@ namespace cpd {
 namespace {
 
 constexpr size_t kCacheMax = 24ull << 30;  // bytes kept cached per process
+
+std::atomic<int64_t> g_alloc_limit{-1};  // bytes; -1: no limit
 
 struct Cache {
     std::mutex mu;
@@ -44,8 +47,26 @@ size_t size_class(size_t b) {
 
 }  // namespace
 
+cpd_status device_alloc(void **p, size_t bytes, hipStream_t s) {
+    *p = nullptr;
+    const int64_t lim = g_alloc_limit.load();
+    if (lim >= 0 && bytes > (size_t)lim)
+        CPD_FAIL(CPD_ENOMEM, "device allocation of %zu bytes refused (limit %lld bytes)", bytes, (long long)lim);
+    if (hipMallocAsync(p, bytes, s) != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        CPD_FAIL(CPD_ENOMEM, "device allocation of %zu bytes failed", bytes);
+    }
+    return CPD_OK;
+}
+
 cpd_status scratch_get(size_t bytes, hipStream_t s, void **p) {
     *p = nullptr;
+    // the limit applies to cached blocks too (a request is refused or not
+    // whatever the cache holds)
+    const int64_t lim = g_alloc_limit.load();
+    if (lim >= 0 && bytes > (size_t)lim)
+        CPD_FAIL(CPD_ENOMEM, "device allocation of %zu bytes refused (limit %lld bytes)", bytes, (long long)lim);
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) {
         (void)hipGetLastError();
@@ -63,12 +84,7 @@ cpd_status scratch_get(size_t bytes, hipStream_t s, void **p) {
             return CPD_OK;
         }
     }
-    if (hipMallocAsync(p, cls, s) != hipSuccess) {
-        (void)hipGetLastError();
-        *p = nullptr;
-        CPD_FAIL(CPD_ENOMEM, "device allocation of %zu bytes failed", bytes);
-    }
-    return CPD_OK;
+    return device_alloc(p, cls, s);
 }
 
 void scratch_put(void *p, size_t bytes, hipStream_t s) {
@@ -93,3 +109,8 @@ void scratch_put(void *p, size_t bytes, hipStream_t s) {
 }
 
 }  // namespace cpd
+
+extern "C" cpd_status cpd_set_alloc_limit(int64_t bytes) {
+    cpd::g_alloc_limit.store(bytes < 0 ? -1 : bytes);
+    return CPD_OK;
+}

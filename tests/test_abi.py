@@ -168,3 +168,13 @@ def test_mttkrp_plan_rule():
     with pytest.raises(cpd.CpdError) as e:
         plan((4,) * 6, 0, 8)
     assert e.value.status == cpd.CPD_EUNSUPPORTED
+
+
+def test_alloc_limit_hook_without_gpu():
+    """The allocation-failure test hook sets and clears a process-wide limit
+    without touching the GPU."""
+    from paper_1812_05961_amd import cpd
+    L = cpd.lib()
+    assert L.cpd_set_alloc_limit(1 << 20) == cpd.CPD_OK
+    assert L.cpd_set_alloc_limit(-1) == cpd.CPD_OK
+    cpd.set_alloc_limit(None)
