@@ -171,8 +171,8 @@ def single_tree(cpd, x, R):
         for kern, v in runs:
             ms = time_mttkrp(cpd, c, facs, mode, R, v, kernel=kern)
             family = kern if kern != "auto" else cpd.mttkrp_plan(dims_by_level, depth, R, ld=ld)
-            if kern == "auto" and v == "auto" and 0 < depth < x.nmodes - 1 and c.counts[depth] * 6 > nnz:
-                family = "tiled"  # AUTO at an internal level of short nodes (under 6 leaves each)
+            if kern == "auto" and v == "auto" and 0 < depth < x.nmodes - 1 and (R > 16 or c.counts[depth] * 6 > nnz):
+                family = "tiled"  # AUTO at an internal level above rank 16 or of short nodes (under 6 leaves each)
             row = dict(mode=mode, level=level, kernel=family, variant=v, ms=round(ms, 4),
                        ns_per_nnz=round(ms * 1e6 / nnz, 4), alg_bytes=b,
                        roofline_frac=round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4))
@@ -377,7 +377,9 @@ def profile_workload(workload, precision, what):
     FETCH_SIZE / WRITE_SIZE counters: each reads and writes exactly 256 MiB),
     then, on the per-mode trees cpd_als builds, one root-level MTTKRP per mode
     (what = "root"), or on the ascending-length tree every mode's MTTKRP at its
-    level, atomic variant (what = "single")."""
+    level, atomic variant (what = "single": ROW kernels above the leaf level)
+    or the library's default choice (what = "single-auto": TILED kernels at the
+    internal level of the NELL-2 tree and at the leaf level)."""
     import torch
 
     from paper_1812_05961_amd import cpd, synth
@@ -414,7 +416,7 @@ def profile_workload(workload, precision, what):
         for mode in c.order:
             out = torch.empty((x.dims[mode], ld), device=dev)
             cpd.mttkrp(c, facs, mode, out=out, rank=R, precision=precision,
-                       variant="auto" if mode == c.order[0] else "atomic")
+                       variant="auto" if mode == c.order[0] or what == "single-auto" else "atomic")
             torch.cuda.synchronize()
             log("single-tree MTTKRP of mode %d (level %d) done" % (mode, c.order.index(mode)))
         c.free()
@@ -432,7 +434,7 @@ def main():
     ap.add_argument("--no-completion", action="store_true", help="skip the CP-with-missing-values timings")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the FP32 / BF16 per-mode reports of the three benchmark tensors")
-    ap.add_argument("--profile-workload", choices=["root", "single"],
+    ap.add_argument("--profile-workload", choices=["root", "single", "single-auto"],
                     help="run only a short MTTKRP workload for rocprofv3 (no JSON line)")
     args = ap.parse_args()
     if args.profile_workload:

@@ -56,8 +56,8 @@ enum { CPD_VARIANT_AUTO = 0, CPD_VARIANT_ATOMIC = 1, CPD_VARIANT_PRIVATE = 2 };
 
 /* Kernel family: AUTO picks (ROW above the leaf level, TILED at the leaf
  * level, LANE otherwise, each where eligible -- see cpd_mttkrp_plan -- and,
- * with CPD_VARIANT_AUTO, TILED at an internal level whose nodes hold fewer
- * than 6 leaves on average); ROW = groups of
+ * with CPD_VARIANT_AUTO, TILED at an internal level above rank 16 or whose
+ * nodes hold fewer than 6 leaves on average); ROW = groups of
  * lanes each holding 16-byte chunks of the factor rows, several leaves per
  * wave step (root and internal levels; tile widths in multiples of 32);
  * LANE = the rank spread over the lanes, one leaf per wave step (any level);
@@ -67,14 +67,15 @@ enum { CPD_VARIANT_AUTO = 0, CPD_VARIANT_ATOMIC = 1, CPD_VARIANT_PRIVATE = 2 };
  * no privatised variant: CPD_VARIANT_PRIVATE with AUTO runs LANE);
  * TILED = any level below the root: the leaves regrouped by tiles of the
  * output mode's indices (the level's mode tiling, built on the first such
- * call and kept with the tree: 16 bytes per nonzero for 2..3 modes, 32 for 4..5); each wave adds its
- * share into a private LDS copy of its tile's output rows and adds the copy
- * to the output once per tile -- at the leaf level one row per leaf scaled by
- * its fiber's Hadamard row, at an internal level one row per node (the sum
- * of its leaves' rows below, times its ancestors' rows); tile_nnz = the tile
- * height in output rows (0 = at the leaf level what 5 KiB of LDS per wave
- * hold, at least 16; at an internal level 16), capped by the LDS; no
- * privatised variant, as ROUND. */
+ * call and kept with the tree: 16 bytes per nonzero for 2..3 modes, 32 for
+ * 4..5; inside a tile tree order at the leaf level, at an internal level
+ * ordered by the other levels' indices, the largest dimension first); each
+ * wave adds one row per leaf, the Hadamard product of the leaf's rows at the
+ * other levels (gathered once per run of leaves that share them) scaled by
+ * its value, into a private LDS copy of its tile's output rows and adds the
+ * copy to the output once per tile; tile_nnz = the tile height in output
+ * rows (0 = what 5 KiB of LDS per wave hold, at least 16), capped by the
+ * LDS; no privatised variant, as ROUND. */
 enum { CPD_KERNEL_AUTO = 0, CPD_KERNEL_ROW = 1, CPD_KERNEL_LANE = 2, CPD_KERNEL_ROUND = 3, CPD_KERNEL_TILED = 4 };
 
 #define CPD_MAX_MODES 8
@@ -220,9 +221,9 @@ cpd_status cpd_mttkrp_noalloc(cpd_csf csf, const void *const *factors, int32_t l
  * aligned; TILED under the same conditions at every level below the root.
  * AUTO picks ROW above the leaf level and TILED at the leaf level, each when
  * eligible, LANE otherwise (cpd_mttkrp runs LANE instead of ROUND or TILED
- * for CPD_VARIANT_PRIVATE, and TILED at an internal level whose nodes hold
- * fewer than 6 leaves on average, a property of the tree this rule does not
- * see; cpd_mttkrp_noalloc runs ROUND at the leaf level and the shape rule's
+ * for CPD_VARIANT_PRIVATE, and TILED at an internal level above rank 16 or
+ * whose nodes hold fewer than 6 leaves on average, a property of the tree
+ * this rule does not see; cpd_mttkrp_noalloc runs ROUND at the leaf level and the shape rule's
  * kernel at an internal level when the tree holds no tiling of that height
  * yet).
  * *kernel_out (host) = CPD_KERNEL_ROW, CPD_KERNEL_LANE, CPD_KERNEL_ROUND or

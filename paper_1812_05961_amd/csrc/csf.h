@@ -41,12 +41,17 @@ struct cpd_csf_s {
     };
     std::vector<Tiles> tiles;
     // The leaves regrouped by tiles of B consecutive indices of one level d
-    // (1 <= d <= N-1), tree order kept inside each tile: the mode tiling of
-    // that level's MTTKRP (one tile's output rows fit in LDS).  Built on first
-    // use for a level and tile height, cached.
+    // (1 <= d <= N-1): the mode tiling of that level's MTTKRP (one tile's
+    // output rows fit in LDS).  Inside a tile the leaves keep tree order
+    // (TILE_TREE), or are sorted by their other levels' indices, the level
+    // of the largest dimension first (TILE_BY_SIZE: the rows of the largest
+    // factor repeat in runs).  Built on first use for a level, tile height
+    // and order, cached.
+    enum { TILE_TREE = 0, TILE_BY_SIZE = 1 };
     struct LeafTiling {
         int32_t depth = 0;
         int32_t B = 0;
+        int32_t order = TILE_TREE;
         int64_t ntiles = 0;
         int32_t *toff = nullptr;                 // ntiles + 1 offsets into the regrouped leaves
         // one record of rw words per regrouped leaf (rw = 4 for 2..3 modes, 8
@@ -137,11 +142,12 @@ cpd_status csf_tiles_into(cpd_csf_s *c, int32_t tile, int32_t *dst, size_t dst_b
 cpd_status csf_tiles(cpd_csf_s *c, int32_t tile, const int32_t **starts, int64_t *ntiles,
                      hipStream_t s);
 
-// The mode tiling of level d (1..N-1) of a tree for tile height B (cached in
-// the handle; built on first use; needs the tree's leaf words and per-leaf
-// internal ids); *out receives a copy of its descriptor.  `cached_only`: the
-// cached one or an empty descriptor (B == 0), building nothing.
-cpd_status csf_level_tiling(cpd_csf_s *c, int d, int32_t B, bool cached_only, cpd_csf_s::LeafTiling *out,
-                            hipStream_t s);
+// The mode tiling of level d (1..N-1) of a tree for tile height B and the
+// order inside a tile (TILE_TREE or TILE_BY_SIZE; cached in the handle;
+// built on first use; needs the tree's leaf words and per-leaf internal ids);
+// *out receives a copy of its descriptor.  `cached_only`: the cached one or
+// an empty descriptor (B == 0), building nothing.
+cpd_status csf_level_tiling(cpd_csf_s *c, int d, int32_t B, int order, bool cached_only,
+                            cpd_csf_s::LeafTiling *out, hipStream_t s);
 
 }  // namespace cpd

@@ -286,21 +286,19 @@ cpd_status launch_lane(int G, bool priv, int32_t hot, dim3 grid, size_t lds, hip
 }
 
 constexpr size_t PRIV_LDS_MAX = 64 * 1024;
-// LDS per wave of the tiled leaf kernel (its tile's rows + its H table) by
+// LDS per wave of the tiled kernel (its tile's rows + its H table) by
 // default: 32 waves per CU resident (measured on the three benchmark shapes:
 // NELL-2 rank 35 2.5 ms at 16-24 rows per tile against 4.1 ms at 64 and
 // 10 ms at 256 and more; NETFLIX rank 16 and 4-mode rank 32 flat within 10%
 // from 16 to 64 rows)
 constexpr size_t TILED_LDS = 5 * 1024;
 constexpr int32_t TILED_MIN_ROWS = 16;
-// tile height of the internal-level tiled kernel (measured on the internal
-// levels of the three benchmark shapes' ascending trees: 16-32 rows best,
-// 1.5-2x slower at 64 and 3-4x at 128, the tables costing resident waves)
-constexpr int32_t TILED_MID_ROWS = 16;
-// AUTO takes TILED at an internal level whose nodes hold fewer leaves than
-// this on average (single ascending trees, ms TILED vs ROW: 4-mode level 2,
-// 1.5 leaves per node: 2.95 vs 5.6; NELL-2 level 1, 5.8: 3.12 vs 3.35; NETFLIX
-// level 1, 8.8: 3.54 vs 2.31; 4-mode level 1, 11.7: 2.44 vs 2.08)
+// AUTO takes TILED at an internal level above this rank, or where its nodes
+// hold fewer leaves than TILED_MID_LEAVES on average (single ascending
+// trees, ms TILED vs ROW: NELL-2 rank 35 level 1, 5.8 leaves per node: 2.46
+// vs 3.35; 4-mode rank 32 level 1, 11.7: 1.78 vs 2.08, level 2, 1.5: 1.78 vs
+// 5.6; NETFLIX rank 16 level 1, 8.8: 2.94 vs 2.34)
+constexpr int TILED_MID_RANK = 16;
 constexpr int64_t TILED_MID_LEAVES = 6;
 constexpr size_t HOT_LDS = 16 * 1024;   // hot output rows privatised per block
 constexpr int64_t HOT_BLOCKS = 16384;   // blocks looping over the streams (measured best of 2,048-65,536)
@@ -328,10 +326,6 @@ cpd_status launch_leaf(int N, bool bf16, const int32_t *const *fids, const float
 int32_t tiled_height(int R, size_t lds_max);
 cpd_status launch_tiled(int N, bool bf16, const cpd_csf_s::LeafTiling &lt, int64_t nleaves,
                         const void *const *fac_by_level, int64_t ld, float *Y, int64_t ldo, int R, hipStream_t s);
-int32_t tiled_mid_height(int R, size_t lds_wave);
-cpd_status launch_tiled_mid(int N, bool bf16, const cpd_csf_s::LeafTiling &lt, int64_t nleaves,
-                            const void *const *fac_by_level, int64_t ld, float *Y, int64_t ldo, int R,
-                            hipStream_t s);
 
 // Lanes the root kernel gives one leaf for a padded rank RP.
 int root_lanes_per_leaf(int RP, bool bf16);
@@ -455,11 +449,12 @@ cpd_status mttkrp_ws(cpd_csf_s *c, const void *const *factors, int32_t ld, int32
         if (c->order[l] != mode && (reinterpret_cast<uintptr_t>(factors[c->order[l]]) & 15)) aligned = false;
     int kernel = CPD_KERNEL_LANE;
     CPD_TRY(mttkrp_plan(N, dims_by_level, d, ld, R, bf16, o.kernel, aligned, c->leafw != nullptr, &kernel));
-    // AUTO at an internal level whose nodes are short: TILED where it applies
-    // (a property of the tree, which the shape rule above does not see)
+    // AUTO at an internal level: TILED where it applies above rank
+    // TILED_MID_RANK or where the nodes are short (a property of the tree,
+    // which the shape rule above does not see)
     if (o.kernel == CPD_KERNEL_AUTO && o.variant == CPD_VARIANT_AUTO && d >= 1 && d < N - 1 &&
-        c->counts[d] * TILED_MID_LEAVES > c->counts[N - 1] && c->leafw && aligned && ld % 4 == 0 &&
-        ld >= ((R + 3) & ~3))
+        (R > TILED_MID_RANK || c->counts[d] * TILED_MID_LEAVES > c->counts[N - 1]) && c->leafw && aligned &&
+        ld % 4 == 0 && ld >= ((R + 3) & ~3))
         kernel = CPD_KERNEL_TILED;
 
     // zero the output (columns < R)
@@ -528,22 +523,26 @@ cpd_status mttkrp_ws(cpd_csf_s *c, const void *const *factors, int32_t ld, int32
                 lds_max = v;
         }
         (void)hipGetLastError();
-        // tile height: tile_nnz when given (capped by the LDS), else at the
-        // leaf level the rows that fit TILED_LDS bytes per wave (several waves
-        // resident per SIMD), at an internal level TILED_MID_ROWS
+        // tile height: tile_nnz when given (capped by the LDS), else the rows
+        // that fit TILED_LDS bytes per wave (several waves resident per SIMD).
+        // The leaf level's tiling keeps tree order inside a tile (a fiber's
+        // leaves consecutive); an internal level's is ordered by size: the
+        // rows of its largest other factor repeat in runs and stay in the L1,
+        // the rows gathered per leaf come from smaller factors that stay in
+        // the L2 (tree order there gathers a row of the leaf factor per leaf)
         const bool leaf = d == N - 1;
+        const int order = leaf ? cpd_csf_s::TILE_TREE : cpd_csf_s::TILE_BY_SIZE;
         const size_t lds_cap = (size_t)std::min(lds_max, 160 * 1024) / 4;
-        const int32_t Bmax = leaf ? tiled_height(R, lds_cap) : tiled_mid_height(R, lds_cap);
-        const int32_t Bdef = leaf ? std::max(tiled_height(R, TILED_LDS), TILED_MIN_ROWS) : TILED_MID_ROWS;
+        const int32_t Bmax = tiled_height(R, lds_cap);
+        const int32_t Bdef = std::max(tiled_height(R, TILED_LDS), TILED_MIN_ROWS);
         const int32_t B = o.tile_nnz > 0 ? std::min<int32_t>(o.tile_nnz, Bmax) : std::min(Bdef, Bmax);
         cpd_csf_s::LeafTiling lt;
-        if (B >= 1) CPD_TRY(csf_level_tiling(c, d, B, ws != nullptr, &lt, s));
+        if (B >= 1) CPD_TRY(csf_level_tiling(c, d, B, order, ws != nullptr, &lt, s));
         if (lt.B > 0) {
             const void *fac_by_level[CPD_MAX_MODES];
             for (int l = 0; l < N; ++l) fac_by_level[l] = fv.a[l];
             if (ev0) CPD_HIP(hipEventRecord(ev0, s));
-            cpd_status st = leaf ? launch_tiled(N, bf16, lt, cv.nleaves, fac_by_level, ld, Y, ldo, R, s)
-                                 : launch_tiled_mid(N, bf16, lt, cv.nleaves, fac_by_level, ld, Y, ldo, R, s);
+            cpd_status st = launch_tiled(N, bf16, lt, cv.nleaves, fac_by_level, ld, Y, ldo, R, s);
             if (st == CPD_OK && ev1) CPD_HIP(hipEventRecord(ev1, s));
             return st;
         }

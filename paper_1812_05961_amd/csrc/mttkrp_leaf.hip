@@ -212,10 +212,16 @@ cpd_status launch_leaf_n(const LeafView &cv, const LeafFac &fv, int64_t ld, cons
     return CPD_OK;
 }
 
-// ------------------------------------------------------------ leaf-mode tiling
-// The leaf level on the tree's leaf-mode tiling (the leaves regrouped by tiles
-// of B leaf indices, tree order inside a tile).  Each wave owns a contiguous
-// range of the regrouped leaves and a private LDS table of one tile's B x R
+// ------------------------------------------------------------ mode tiling
+// Level d >= 1 on the level's mode tiling (the leaves regrouped by tiles of
+// B level-d indices):
+//     Y(i, :) += x_k * H_k for every leaf k whose level-d index is i,
+// H_k = Hadamard product of leaf k's rows at every other level.  A fiber here
+// is a run of leaves that agree on every other level's index (at the leaf
+// level, in tree order inside a tile, the fibers of the tree; at an internal
+// level, ordered by size, leaves that differ only in their level-d index).
+// Each wave owns a contiguous range of the regrouped leaves and a private LDS
+// table of one tile's B x R
 // output rows: it takes its range tile by tile (zero the table, add every
 // leaf of the tile into it, add the table's nonzero entries to Y), so every
 // nonzero is a plain LDS read-add-write by the one wave that owns the row --
@@ -408,211 +414,6 @@ cpd_status launch_tiled_n(const TiledView &tv, const LeafFac &fv, int64_t ld, fl
     return CPD_OK;
 }
 
-// Internal level d (1 <= d <= N-2) on the level's mode tiling:
-//     Y(i, :) += sum over level-d nodes with index i of
-//                H_above(node) * sum over leaves k below the node of x_k * H_below(k),
-// H_above the Hadamard product of the node's rows at levels 0..d-1, H_below
-// that of leaf k's rows at levels d+1..N-1.  The regrouped leaves keep each
-// node's leaves consecutive, so the wave walks them with the rank across the
-// lanes: the running sum of x_k * H_below(k) of the open node, multiplied by
-// H_above and added to the node's row of the wave-private tile table when the
-// node closes (a plain LDS read-add-write: no atomic into Y per node).
-// Rounds of 64 leaves: each lane loads its leaf's record (value, local row,
-// the other levels' indices) with one or two 16-byte loads (a node starts
-// where the local row or an index above
-// d changes); per batch of PF leaves the H_below rows of its leaves and the
-// H_above rows of the nodes starting in it are gathered by lane groups into
-// the wave's tables, then the batch is walked.  A node split between two
-// waves' ranges is added by both (into Y with atomics when a tile ends).
-// Factors in fv in the order of the stored indices: levels 0..d-1 (the
-// first na = d), then d+1..N-1.
-template <int N, typename GT, int UF>
-__global__ void __launch_bounds__(64 * TILED_WAVES)
-k_mttkrp_tiled_mid(TiledView tv, LeafFac fv, int na, int64_t ld, int64_t nwaves, float *__restrict__ Y, int64_t ldo,
-                   int R) {
-    extern __shared__ float4 lds4[];
-    __shared__ int32_t s_npos[TILED_WAVES][65];
-    const int RQ = (R + 3) & ~3;
-    const int G = RQ >> 2;
-    const int NG = 64 / G;
-    const int PF = NG * UF;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int g = lane / G, lig = lane - (lane / G) * G;
-    const int64_t nloc = (int64_t)tv.B * R;
-    // per-wave stride in floats, a multiple of 4 (16-byte aligned rows)
-    const int64_t stride = ((int64_t)2 * PF * RQ + nloc + 3) & ~int64_t(3);
-    float *Hb = reinterpret_cast<float *>(lds4) + (int64_t)wave * stride;  // a batch's leaves: H_below
-    float *Ha = Hb + (int64_t)PF * RQ;                                     // its nodes: H_above
-    float *tab = Ha + (int64_t)PF * RQ;
-    int32_t *npos = s_npos[wave];
-    const int64_t gw = (int64_t)blockIdx.x * TILED_WAVES + wave;
-    if (gw >= nwaves) return;  // waves are independent: no block barriers
-    const int64_t nr = ceil_div(tv.n, 64);
-    const int64_t r0 = gw * nr / nwaves, r1 = (gw + 1) * nr / nwaves;
-    const int64_t b1 = min(r1 * 64, tv.n);
-    int64_t pos = r0 * 64;
-    while (pos < b1) {
-        int64_t lo = 0, hi = tv.ntiles;
-        while (hi - lo > 1) {
-            const int64_t mid = (lo + hi) >> 1;
-            if ((int64_t)tv.toff[mid] <= pos) lo = mid;
-            else hi = mid;
-        }
-        const int64_t t = lo;
-        const int64_t e = min(b1, (int64_t)tv.toff[t + 1]);
-        for (int64_t j = lane; j < nloc; j += 64) tab[j] = 0.0f;
-        float acc = 0.0f, ha = 0.0f;  // lane r: element r of the open node
-        int32_t open_row = -1;        // local row of the open node (-1: none)
-        int32_t last_row = -1, last[N - 1];
-#pragma unroll
-        for (int m = 0; m < N - 1; ++m) last[m] = -1;
-        for (int64_t k0 = pos; k0 < e; k0 += 64) {
-            const int64_t k = k0 + lane;
-            const bool in = k < e;
-            const int64_t kk = in ? k : e - 1;
-            float x;
-            int32_t row, id[N - 1];
-            load_record<N>(tv.rec, kk, x, row, id);
-            // a node is its local row with its indices above d
-            bool newn = __shfl_up(row, 1, 64) != row;
-            bool newl = open_row < 0 || row != last_row;
-#pragma unroll
-            for (int m = 0; m < N - 1; ++m)
-                if (m < na) {
-                    newn |= __shfl_up(id[m], 1, 64) != id[m];
-                    newl |= id[m] != last[m];
-                }
-            if (lane == 0) newn = newl;
-            const uint64_t nmask = __ballot(in && newn);
-            const int nin = (int)min<int64_t>(64, e - k0);
-            const uint64_t upto = ~0ull >> (63 - lane);
-            if ((nmask >> lane) & 1ull) npos[__popcll(nmask & upto) - 1] = lane;
-            wave_sync_lds();
-            for (int j0 = 0; j0 < nin; j0 += PF) {
-                const int j1 = min(nin, j0 + PF);
-                // H_below of leaves j0..j1-1 (every load issued before any use)
-                {
-                    int32_t ids[UF][N - 1];
-                    bool ok[UF];
-#pragma unroll
-                    for (int u = 0; u < UF; ++u) {
-                        const int jj = j0 + u * NG + g;
-                        ok[u] = g < NG && jj < j1;
-                        const int src = ok[u] ? jj : j0;
-#pragma unroll
-                        for (int m = 0; m < N - 1; ++m) ids[u][m] = __shfl(id[m], src, 64);
-                    }
-                    float4 rows[UF][N - 1];
-#pragma unroll
-                    for (int u = 0; u < UF; ++u)
-#pragma unroll
-                        for (int m = 0; m < N - 1; ++m)
-                            if (m >= na) rows[u][m] = Quad<GT>::load(fv.a[m], (int64_t)ids[u][m] * ld + 4 * lig);
-#pragma unroll
-                    for (int u = 0; u < UF; ++u) {
-                        float4 h = make_float4(1.0f, 1.0f, 1.0f, 1.0f);
-#pragma unroll
-                        for (int m = 0; m < N - 1; ++m)
-                            if (m >= na) {
-                                h.x *= rows[u][m].x;
-                                h.y *= rows[u][m].y;
-                                h.z *= rows[u][m].z;
-                                h.w *= rows[u][m].w;
-                            }
-                        if (ok[u]) *reinterpret_cast<float4 *>(Hb + (int64_t)(u * NG + g) * RQ + 4 * lig) = h;
-                    }
-                }
-                // H_above of the nodes starting in the batch (slots sa..sa+F-1)
-                const uint64_t below_j0 = j0 ? (~0ull >> (64 - j0)) : 0ull;
-                const uint64_t below_j1 = j1 < 64 ? (~0ull >> (64 - j1)) : ~0ull;
-                const int sa = __popcll(nmask & below_j0);
-                const int F = __popcll(nmask & below_j1) - sa;
-                if (F > 0) {
-                    int32_t ids[UF][N - 1];
-                    bool ok[UF];
-#pragma unroll
-                    for (int u = 0; u < UF; ++u) {
-                        const int q = u * NG + g;
-                        ok[u] = g < NG && q < F;
-                        const int src = npos[sa + (ok[u] ? q : 0)];
-#pragma unroll
-                        for (int m = 0; m < N - 1; ++m) ids[u][m] = __shfl(id[m], src, 64);
-                    }
-                    float4 rows[UF][N - 1];
-#pragma unroll
-                    for (int u = 0; u < UF; ++u)
-#pragma unroll
-                        for (int m = 0; m < N - 1; ++m)
-                            if (m < na) rows[u][m] = Quad<GT>::load(fv.a[m], (int64_t)ids[u][m] * ld + 4 * lig);
-#pragma unroll
-                    for (int u = 0; u < UF; ++u) {
-                        float4 h = rows[u][0];
-#pragma unroll
-                        for (int m = 1; m < N - 1; ++m)
-                            if (m < na) {
-                                h.x *= rows[u][m].x;
-                                h.y *= rows[u][m].y;
-                                h.z *= rows[u][m].z;
-                                h.w *= rows[u][m].w;
-                            }
-                        if (ok[u]) *reinterpret_cast<float4 *>(Ha + (int64_t)(u * NG + g) * RQ + 4 * lig) = h;
-                    }
-                }
-                wave_sync_lds();
-                // walk the batch's leaves; a node closes where the next one starts
-                int slot = -1;
-                for (int j = j0; j < j1; ++j) {
-                    if ((nmask >> j) & 1ull) {
-                        if (open_row >= 0 && lane < R) tab[(int64_t)open_row * R + lane] += acc * ha;
-                        acc = 0.0f;
-                        open_row = __builtin_amdgcn_readlane(row, j);
-                        ++slot;
-                        ha = lane < R ? Ha[slot * RQ + lane] : 0.0f;
-                    }
-                    const float xj = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), j));
-                    if (lane < R) acc += xj * Hb[(j - j0) * RQ + lane];
-                }
-                wave_sync_lds();
-            }
-            last_row = __builtin_amdgcn_readlane(row, nin - 1);
-#pragma unroll
-            for (int m = 0; m < N - 1; ++m) last[m] = __builtin_amdgcn_readlane(id[m], nin - 1);
-        }
-        if (open_row >= 0 && lane < R) tab[(int64_t)open_row * R + lane] += acc * ha;
-        wave_sync_lds();
-        // the tile's rows into Y (nonzero entries)
-        const int64_t base = t * (int64_t)tv.B;
-        for (int64_t j = lane; j < nloc; j += 64) {
-            const float v = tab[j];
-            if (v != 0.0f) atomicAdd(Y + (base + j / R) * ldo + (j % R), v);
-        }
-        wave_sync_lds();
-        pos = e;
-    }
-}
-
-template <int N, typename GT>
-cpd_status launch_tiled_mid_n(const TiledView &tv, const LeafFac &fv, int na, int64_t ld, float *Y, int64_t ldo,
-                              int R, int UF, size_t lds_wave, hipStream_t s) {
-    auto kern = UF == 1 ? k_mttkrp_tiled_mid<N, GT, 1> : k_mttkrp_tiled_mid<N, GT, 2>;
-    int dev = 0, ncu = 256;
-    if (hipGetDevice(&dev) == hipSuccess) {
-        int v = 0;
-        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) ncu = v;
-    }
-    const size_t lds = lds_wave * TILED_WAVES;
-    CPD_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64 * TILED_WAVES, lds) != hipSuccess ||
-        per_cu < 1)
-        per_cu = 1;
-    const int64_t nwaves = std::max<int64_t>(1, std::min<int64_t>(ceil_div(tv.n, 64), (int64_t)ncu * per_cu * TILED_WAVES));
-    hipLaunchKernelGGL(kern, dim3((unsigned)ceil_div(nwaves, TILED_WAVES)), dim3(64 * TILED_WAVES), lds, s, tv, fv,
-                       na, ld, nwaves, Y, ldo, R);
-    CPD_LAUNCH_CHECK();
-    return CPD_OK;
-}
-
 }  // namespace
 
 // Leaf-level MTTKRP with the round kernel: Y (out_rows x R floats, stride
@@ -661,7 +462,7 @@ cpd_status launch_leaf(int N, bool bf16, const int32_t *const *fids, const float
 }
 
 
-// Tile height of the leaf-mode tiling for rank R: one wave's tile of R-float
+// Tile height of a mode tiling for rank R: one wave's tile of R-float
 // rows and its H table within lds_wave bytes of LDS.
 int32_t tiled_height(int R, size_t lds_wave) {
     const int RQ = (R + 3) & ~3;
@@ -672,22 +473,26 @@ int32_t tiled_height(int R, size_t lds_wave) {
     return (int32_t)((lds_wave - fixed) / (sizeof(float) * R));
 }
 
-// Leaf-level MTTKRP on the leaf-mode tiling (Y zeroed by the caller; factor
-// rules as for launch_leaf).
+// MTTKRP of level lt.depth (1..N-1) on its mode tiling (Y zeroed by the
+// caller; factor rules as for launch_leaf; fac_by_level: every level's factor
+// in tree order).
 cpd_status launch_tiled(int N, bool bf16, const cpd_csf_s::LeafTiling &lt, int64_t nleaves,
                         const void *const *fac_by_level, int64_t ld, float *Y, int64_t ldo, int R, hipStream_t s) {
-    if (N < 2 || N > 5) CPD_FAIL(CPD_EUNSUPPORTED, "tiled leaf kernel built for 2..5 modes, not %d", N);
+    if (N < 2 || N > 5) CPD_FAIL(CPD_EUNSUPPORTED, "tiled kernel built for 2..5 modes, not %d", N);
     if (R < 1 || R > 64 || ld % 4 || ld < ((R + 3) & ~3))
-        CPD_FAIL(CPD_EUNSUPPORTED, "tiled leaf kernel needs rank <= 64 and ld a multiple of 4 covering the rank");
+        CPD_FAIL(CPD_EUNSUPPORTED, "tiled kernel needs rank <= 64 and ld a multiple of 4 covering the rank");
     TiledView tv{};
     tv.toff = lt.toff;
     if (lt.rw != (N <= 3 ? 4 : 8)) CPD_FAIL(CPD_EINVAL, "mode tiling records of %d words for %d modes", lt.rw, N);
+    if (lt.depth < 1 || lt.depth >= N) CPD_FAIL(CPD_EINVAL, "tiling of level %d of %d", lt.depth, N);
     tv.rec = lt.rec;
     tv.n = nleaves;
     tv.ntiles = lt.ntiles;
     tv.B = lt.B;
+    // the factors of the other levels, in the order of the records' indices
     LeafFac fv{};
-    for (int l = 0; l < N - 1; ++l) fv.a[l] = fac_by_level[l];
+    for (int l = 0, m = 0; l < N; ++l)
+        if (l != lt.depth) fv.a[m++] = fac_by_level[l];
     if (nleaves == 0) return CPD_OK;
     const int RQ = (R + 3) & ~3;
     const int NG = 64 / (RQ / 4);
@@ -703,61 +508,6 @@ cpd_status launch_tiled(int N, bool bf16, const cpd_csf_s::LeafTiling &lt, int64
         CPD_TILED_N(4)
         CPD_TILED_N(5)
 #undef CPD_TILED_N
-    }
-    return CPD_OK;
-}
-
-// Batch of the internal-level tiled kernel for rank R: UF gathers per level.
-static int tiled_mid_uf(int R) {
-    const int NG = 64 / (((R + 3) & ~3) / 4);
-    return NG >= 7 ? 1 : 2;
-}
-
-// Tile height of an internal level's mode tiling for rank R: one wave's tile
-// of R-float rows and its two tables of PF rows within lds_wave bytes.
-int32_t tiled_mid_height(int R, size_t lds_wave) {
-    const int RQ = (R + 3) & ~3;
-    const int PF = (64 / (RQ / 4)) * tiled_mid_uf(R);
-    const size_t fixed = sizeof(float) * (2 * (size_t)PF * RQ + 3) + sizeof(int32_t) * 65;
-    if (lds_wave <= fixed) return 0;
-    return (int32_t)((lds_wave - fixed) / (sizeof(float) * R));
-}
-
-// Internal-level MTTKRP (level lt.depth, 1..N-2) on the level's mode tiling
-// (Y zeroed by the caller; factor rules as for launch_leaf; fac_by_level:
-// every level's factor in tree order).
-cpd_status launch_tiled_mid(int N, bool bf16, const cpd_csf_s::LeafTiling &lt, int64_t nleaves,
-                            const void *const *fac_by_level, int64_t ld, float *Y, int64_t ldo, int R,
-                            hipStream_t s) {
-    if (N < 3 || N > 5) CPD_FAIL(CPD_EUNSUPPORTED, "tiled internal-level kernel built for 3..5 modes, not %d", N);
-    const int d = lt.depth;
-    if (d < 1 || d > N - 2) CPD_FAIL(CPD_EINVAL, "tiling of level %d is not an internal level", d);
-    if (R < 1 || R > 64 || ld % 4 || ld < ((R + 3) & ~3))
-        CPD_FAIL(CPD_EUNSUPPORTED, "tiled kernels need rank <= 64 and ld a multiple of 4 covering the rank");
-    TiledView tv{};
-    tv.toff = lt.toff;
-    if (lt.rw != (N <= 3 ? 4 : 8)) CPD_FAIL(CPD_EINVAL, "mode tiling records of %d words for %d modes", lt.rw, N);
-    tv.rec = lt.rec;
-    tv.n = nleaves;
-    tv.ntiles = lt.ntiles;
-    tv.B = lt.B;
-    LeafFac fv{};
-    for (int l = 0, m = 0; l < N; ++l)
-        if (l != d) fv.a[m++] = fac_by_level[l];
-    if (nleaves == 0) return CPD_OK;
-    const int RQ = (R + 3) & ~3;
-    const int UF = tiled_mid_uf(R);
-    const int PF = (64 / (RQ / 4)) * UF;
-    const size_t lds = sizeof(float) * ((2 * (size_t)PF * RQ + (size_t)lt.B * R + 3) & ~size_t(3));  // per wave
-    switch (N) {
-#define CPD_TILED_MID_N(n)                                                                          \
-    case n:                                                                                         \
-        return bf16 ? launch_tiled_mid_n<n, uint16_t>(tv, fv, d, ld, Y, ldo, R, UF, lds, s)         \
-                    : launch_tiled_mid_n<n, float>(tv, fv, d, ld, Y, ldo, R, UF, lds, s);
-        CPD_TILED_MID_N(3)
-        CPD_TILED_MID_N(4)
-        CPD_TILED_MID_N(5)
-#undef CPD_TILED_MID_N
     }
     return CPD_OK;
 }
