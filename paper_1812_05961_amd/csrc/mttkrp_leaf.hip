@@ -313,8 +313,13 @@ k_mttkrp_tiled(TiledView tv, LeafFac fv, int64_t ld, int64_t nwaves, float *__re
             const int nin = (int)min<int64_t>(64, e - k0);
             const uint64_t upto = ~0ull >> (63 - lane);
             const int F = __popcll(fmask);
-            if ((fmask >> lane) & 1ull) fpos[__popcll(fmask & upto) - 1] = lane;
+            const int fo = __popcll(fmask & upto) - 1;  // fiber of this lane's leaf
+            if ((fmask >> lane) & 1ull) fpos[fo] = lane;
             if (lane == 0) fpos[F] = nin;
+            // this leaf's LDS byte offsets, packed: its fiber's H row (batches
+            // are PF fibers apart) in the low half, its tile row in the high
+            // half (a wave's LDS is below 64 KiB)
+            const uint32_t pk = (uint32_t)((fo % PF) * RQ * 4) | ((uint32_t)(row * R * 4) << 16);
             wave_sync_lds();
             for (int f0 = 0; f0 < F; f0 += PF) {
                 const int f1 = min(F, f0 + PF);
@@ -349,33 +354,34 @@ k_mttkrp_tiled(TiledView tv, LeafFac fv, int64_t ld, int64_t nwaves, float *__re
                 wave_sync_lds();
                 const int jb = __builtin_amdgcn_readfirstlane(fpos[f0]);
                 const int je = __builtin_amdgcn_readfirstlane(fpos[f1]);
-                // two leaves per step: their sum in one read-modify-write when
-                // they share a row, else two (every row is this wave's alone)
-                int j = jb;
-                for (; j + 1 < je; j += 2) {
-                    const int fa = __popcll(fmask & (~0ull >> (63 - j))) - 1 - f0;
-                    const int fb = __popcll(fmask & (~0ull >> (62 - j))) - 1 - f0;
-                    const float xa = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), j));
-                    const float xb = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), j + 1));
-                    const int32_t ra = __builtin_amdgcn_readlane(row, j);
-                    const int32_t rb = __builtin_amdgcn_readlane(row, j + 1);
-                    if (lane < R) {
-                        const float ta = xa * Hs[fa * RQ + lane], tb = xb * Hs[fb * RQ + lane];
-                        float *pa = tab + (int64_t)ra * R + lane, *pb = tab + (int64_t)rb * R + lane;
-                        if (ra == rb) {
-                            *pa += ta + tb;
-                        } else {
-                            const float va = *pa, vb = *pb;
-                            *pa = va + ta;
-                            *pb = vb + tb;
-                        }
+                // two leaves per step, both tile rows read before either is
+                // written: when they share a row, the second write holds both
+                // contributions (every row is this wave's alone)
+                // (the lanes past the rank skip the walk; v_readlane reads
+                // any lane)
+                if (lane < R) {
+                    const char *hl = reinterpret_cast<const char *>(Hs + lane);
+                    char *tl = reinterpret_cast<char *>(tab + lane);
+                    int j = jb;
+                    for (; j + 1 < je; j += 2) {
+                        const uint32_t pa = __builtin_amdgcn_readlane(pk, j);
+                        const uint32_t pb = __builtin_amdgcn_readlane(pk, j + 1);
+                        const float xa = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), j));
+                        const float xb = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), j + 1));
+                        float *ya = reinterpret_cast<float *>(tl + (pa >> 16));
+                        float *yb = reinterpret_cast<float *>(tl + (pb >> 16));
+                        const float ta = xa * *reinterpret_cast<const float *>(hl + (pa & 0xffffu));
+                        const float tb = xb * *reinterpret_cast<const float *>(hl + (pb & 0xffffu));
+                        const float va = *ya, vb = *yb;
+                        *yb = vb + tb;
+                        *ya = va + ta + ((pa >> 16) == (pb >> 16) ? tb : 0.0f);
                     }
-                }
-                if (j < je) {
-                    const int fa = __popcll(fmask & (~0ull >> (63 - j))) - 1 - f0;
-                    const float xa = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), j));
-                    const int32_t ra = __builtin_amdgcn_readlane(row, j);
-                    if (lane < R) tab[(int64_t)ra * R + lane] += xa * Hs[fa * RQ + lane];
+                    if (j < je) {
+                        const uint32_t pa = __builtin_amdgcn_readlane(pk, j);
+                        const float xa = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), j));
+                        float *ya = reinterpret_cast<float *>(tl + (pa >> 16));
+                        *ya += xa * *reinterpret_cast<const float *>(hl + (pa & 0xffffu));
+                    }
                 }
                 wave_sync_lds();
             }
