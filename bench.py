@@ -171,8 +171,8 @@ def single_tree(cpd, x, R):
         for kern, v in runs:
             ms = time_mttkrp(cpd, c, facs, mode, R, v, kernel=kern)
             family = kern if kern != "auto" else cpd.mttkrp_plan(dims_by_level, depth, R, ld=ld)
-            if kern == "auto" and v == "auto" and 0 < depth < x.nmodes - 1 and (R > 16 or c.counts[depth] * 6 > nnz):
-                family = "tiled"  # AUTO at an internal level above rank 16 or of short nodes (under 6 leaves each)
+            if kern == "auto" and v == "auto" and 0 < depth < x.nmodes - 1:
+                family = "tiled"  # AUTO at an internal level
             row = dict(mode=mode, level=level, kernel=family, variant=v, ms=round(ms, 4),
                        ns_per_nnz=round(ms * 1e6 / nnz, 4), alg_bytes=b,
                        roofline_frac=round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4))

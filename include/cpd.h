@@ -56,8 +56,7 @@ enum { CPD_VARIANT_AUTO = 0, CPD_VARIANT_ATOMIC = 1, CPD_VARIANT_PRIVATE = 2 };
 
 /* Kernel family: AUTO picks (ROW above the leaf level, TILED at the leaf
  * level, LANE otherwise, each where eligible -- see cpd_mttkrp_plan -- and,
- * with CPD_VARIANT_AUTO, TILED at an internal level above rank 16 or whose
- * nodes hold fewer than 6 leaves on average); ROW = groups of
+ * with CPD_VARIANT_AUTO, TILED at an internal level); ROW = groups of
  * lanes each holding 16-byte chunks of the factor rows, several leaves per
  * wave step (root and internal levels; tile widths in multiples of 32);
  * LANE = the rank spread over the lanes, one leaf per wave step (any level);
@@ -221,11 +220,10 @@ cpd_status cpd_mttkrp_noalloc(cpd_csf csf, const void *const *factors, int32_t l
  * aligned; TILED under the same conditions at every level below the root.
  * AUTO picks ROW above the leaf level and TILED at the leaf level, each when
  * eligible, LANE otherwise (cpd_mttkrp runs LANE instead of ROUND or TILED
- * for CPD_VARIANT_PRIVATE, and TILED at an internal level above rank 16 or
- * whose nodes hold fewer than 6 leaves on average, a property of the tree
- * this rule does not see; cpd_mttkrp_noalloc runs ROUND at the leaf level and the shape rule's
- * kernel at an internal level when the tree holds no tiling of that height
- * yet).
+ * for CPD_VARIANT_PRIVATE, and TILED at an internal level with
+ * CPD_VARIANT_AUTO; cpd_mttkrp_noalloc runs ROUND at the leaf level and the
+ * shape rule's kernel at an internal level when the tree holds no tiling of
+ * that height yet).
  * *kernel_out (host) = CPD_KERNEL_ROW, CPD_KERNEL_LANE, CPD_KERNEL_ROUND or
  * CPD_KERNEL_TILED; CPD_EUNSUPPORTED when ROW, ROUND or TILED is requested and
  * not eligible, or N is outside 2..5. */

@@ -293,13 +293,10 @@ constexpr size_t PRIV_LDS_MAX = 64 * 1024;
 // from 16 to 64 rows)
 constexpr size_t TILED_LDS = 5 * 1024;
 constexpr int32_t TILED_MIN_ROWS = 16;
-// AUTO takes TILED at an internal level above this rank, or where its nodes
-// hold fewer leaves than TILED_MID_LEAVES on average (single ascending
-// trees, ms TILED vs ROW: NELL-2 rank 35 level 1, 5.8 leaves per node: 2.46
-// vs 3.35; 4-mode rank 32 level 1, 11.7: 1.78 vs 2.08, level 2, 1.5: 1.78 vs
-// 5.6; NETFLIX rank 16 level 1, 8.8: 2.94 vs 2.34)
-constexpr int TILED_MID_RANK = 16;
-constexpr int64_t TILED_MID_LEAVES = 6;
+// AUTO takes TILED at an internal level (single ascending trees, ms TILED
+// vs the fastest other kernel: NELL-2 rank 35 level 1 2.08 vs 3.36 (ROW);
+// NETFLIX rank 16 level 1 2.22 vs 2.30 (ROW); 4-mode rank 32 level 1 1.50 vs
+// 2.07 (ROW), level 2 1.50 vs 4.46 (LANE))
 constexpr size_t HOT_LDS = 16 * 1024;   // hot output rows privatised per block
 constexpr int64_t HOT_BLOCKS = 16384;   // blocks looping over the streams (measured best of 2,048-65,536)
 constexpr double PRIV_THRESH = 0.02;  // privatise iff rows * copies <= 0.02 * nnz
@@ -449,12 +446,10 @@ cpd_status mttkrp_ws(cpd_csf_s *c, const void *const *factors, int32_t ld, int32
         if (c->order[l] != mode && (reinterpret_cast<uintptr_t>(factors[c->order[l]]) & 15)) aligned = false;
     int kernel = CPD_KERNEL_LANE;
     CPD_TRY(mttkrp_plan(N, dims_by_level, d, ld, R, bf16, o.kernel, aligned, c->leafw != nullptr, &kernel));
-    // AUTO at an internal level: TILED where it applies above rank
-    // TILED_MID_RANK or where the nodes are short (a property of the tree,
-    // which the shape rule above does not see)
-    if (o.kernel == CPD_KERNEL_AUTO && o.variant == CPD_VARIANT_AUTO && d >= 1 && d < N - 1 &&
-        (R > TILED_MID_RANK || c->counts[d] * TILED_MID_LEAVES > c->counts[N - 1]) && c->leafw && aligned &&
-        ld % 4 == 0 && ld >= ((R + 3) & ~3))
+    // AUTO at an internal level with the variant left to the library: TILED
+    // where it applies (it has no privatised variant)
+    if (o.kernel == CPD_KERNEL_AUTO && o.variant == CPD_VARIANT_AUTO && d >= 1 && d < N - 1 && c->leafw &&
+        aligned && ld % 4 == 0 && ld >= ((R + 3) & ~3))
         kernel = CPD_KERNEL_TILED;
 
     // zero the output (columns < R)

@@ -244,8 +244,8 @@ def test_mttkrp_every_level(case, R, ld):
     facs = _factors(t.dims, R, 100 + R, ld)
     for mode in range(t.nmodes):
         depth = c.order.index(mode)
-        # auto: the library's pick (TILED at internal levels of short nodes, which
-        # these small trees have)
+        # auto: the library's pick (ROW at the root, TILED below it where it
+        # applies)
         kernels = ["auto", "lane"] + (["row"] if 3 <= t.nmodes <= 5 and depth < t.nmodes - 1 and (ld or R) >= 8
                                       and R in (8, 16, 32, 35, 64) else [])
         if depth == t.nmodes - 1 and _round_ok(R, ld or R):
