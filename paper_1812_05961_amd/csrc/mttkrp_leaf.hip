@@ -298,13 +298,16 @@ k_mttkrp_tiled(TiledView tv, LeafFac fv, int64_t ld, int64_t nwaves, float *__re
         const int64_t t = lo;
         const int64_t e = min(b1, (int64_t)tv.toff[t + 1]);
         for (int64_t j = lane; j < nloc; j += 64) tab[j] = 0.0f;
+        // records of the round (the next round's are loaded during this
+        // round's first batch, so a round does not start waiting on them)
+        float x;
+        int32_t row, hid[N - 1];
+        load_record<N>(tv.rec, min(pos + lane, e - 1), x, row, hid);
         for (int64_t k0 = pos; k0 < e; k0 += 64) {
             const int64_t k = k0 + lane;
             const bool in = k < e;
-            const int64_t kk = in ? k : e - 1;
-            float x;
-            int32_t row, hid[N - 1];
-            load_record<N>(tv.rec, kk, x, row, hid);
+            float nx = 0.0f;
+            int32_t nrow = 0, nhid[N - 1] = {};
             bool newf = lane == 0;
 #pragma unroll
             for (int l = 0; l < N - 1; ++l) newf |= __shfl_up(hid[l], 1, 64) != hid[l];
@@ -339,6 +342,8 @@ k_mttkrp_tiled(TiledView tv, LeafFac fv, int64_t ld, int64_t nwaves, float *__re
 #pragma unroll
                     for (int l = 0; l < N - 1; ++l)
                         rows[u][l] = Quad<GT>::load(fv.a[l], (int64_t)ids[u][l] * ld + 4 * lig);
+                if (f0 == 0 && k0 + 64 < e)
+                    load_record<N>(tv.rec, min(k0 + 64 + lane, e - 1), nx, nrow, nhid);
 #pragma unroll
                 for (int u = 0; u < UF; ++u) {
                     float4 h = rows[u][0];
@@ -385,6 +390,10 @@ k_mttkrp_tiled(TiledView tv, LeafFac fv, int64_t ld, int64_t nwaves, float *__re
                 }
                 wave_sync_lds();
             }
+            x = nx;
+            row = nrow;
+#pragma unroll
+            for (int l = 0; l < N - 1; ++l) hid[l] = nhid[l];
         }
         // the tile's rows into Y (nonzero entries)
         const int64_t base = t * (int64_t)tv.B;
