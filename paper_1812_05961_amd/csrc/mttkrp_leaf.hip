@@ -245,6 +245,16 @@ struct TiledView {
 
 constexpr int TILED_WAVES = 4;  // waves per block (each on its own range and tables)
 
+// Minimum resident waves per SIMD asked of the compiler: 8 for three modes
+// with two gathers per lane group (64 registers, no spills; the record
+// prefetch would otherwise take it to 66 and 7 waves), no constraint
+// elsewhere (the forms with four gathers, or four and five modes, would
+// spill).
+template <int N, int UF>
+constexpr int tiled_min_waves() {
+    return N == 3 && UF == 2 ? 8 : 1;
+}
+
 // Leaf k's record of a mode tiling: one 16-byte load for 2..3 modes, two for
 // 4..5 (records of 4 or 8 words, 16-byte aligned).
 template <int N>
@@ -262,9 +272,10 @@ __device__ __forceinline__ void load_record(const int32_t *rec, int64_t k, float
     }
 }
 
-// Dynamic LDS per wave: PF x RQ floats (H rows), then B x R floats (its tile).
+// Dynamic LDS per wave: (PF + 1) x RQ floats (H rows and a spare row), then
+// B x R floats (its tile).
 template <int N, typename GT, int UF>
-__global__ void __launch_bounds__(64 * TILED_WAVES)
+__global__ void __launch_bounds__(64 * TILED_WAVES, (tiled_min_waves<N, UF>()))
 k_mttkrp_tiled(TiledView tv, LeafFac fv, int64_t ld, int64_t nwaves, float *__restrict__ Y, int64_t ldo, int R) {
     extern __shared__ float4 lds4[];
     __shared__ int32_t s_fpos[TILED_WAVES][65];
@@ -272,13 +283,16 @@ k_mttkrp_tiled(TiledView tv, LeafFac fv, int64_t ld, int64_t nwaves, float *__re
     const int G = RQ >> 2;
     const int NG = 64 / G;
     const int PF = NG * UF;
+    // x mod PF for 0 <= x < 64 as x - ((x * pf_inv) >> 16) * PF: exact, as
+    // pf_inv * PF - 2^16 < PF and x * PF < 2^16
+    const uint32_t pf_inv = (65536u + (uint32_t)PF - 1) / (uint32_t)PF;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int g = lane / G, lig = lane - (lane / G) * G;
     const int64_t nloc = (int64_t)tv.B * R;
     // per-wave stride in floats, a multiple of 4 (16-byte aligned H rows)
-    const int64_t stride = ((int64_t)PF * RQ + nloc + 3) & ~int64_t(3);
+    const int64_t stride = ((int64_t)(PF + 1) * RQ + nloc + 3) & ~int64_t(3);
     float *Hs = reinterpret_cast<float *>(lds4) + (int64_t)wave * stride;
-    float *tab = Hs + (int64_t)PF * RQ;
+    float *tab = Hs + (int64_t)(PF + 1) * RQ;
     int32_t *fpos = s_fpos[wave];
     const int64_t gw = (int64_t)blockIdx.x * TILED_WAVES + wave;
     if (gw >= nwaves) return;  // waves are independent: no block barriers
@@ -322,9 +336,12 @@ k_mttkrp_tiled(TiledView tv, LeafFac fv, int64_t ld, int64_t nwaves, float *__re
             // this leaf's LDS byte offsets, packed: its fiber's H row (batches
             // are PF fibers apart) in the low half, its tile row in the high
             // half (a wave's LDS is below 64 KiB)
-            const uint32_t pk = (uint32_t)((fo % PF) * RQ * 4) | ((uint32_t)(row * R * 4) << 16);
+            const uint32_t fb = (uint32_t)fo - (((uint32_t)fo * pf_inv) >> 16) * (uint32_t)PF;  // fo mod PF
+            const uint32_t pk = fb * (uint32_t)(RQ * 4) | ((uint32_t)(row * R * 4) << 16);
             wave_sync_lds();
-            for (int f0 = 0; f0 < F; f0 += PF) {
+            // one batch of PF fibers from fiber f0 (the round's last batch, which
+            // always exists, also loads the next round's records)
+            auto batch = [&](const int f0, auto last) {
                 const int f1 = min(F, f0 + PF);
                 int32_t ids[UF][N - 1];
                 bool ok[UF];
@@ -342,7 +359,11 @@ k_mttkrp_tiled(TiledView tv, LeafFac fv, int64_t ld, int64_t nwaves, float *__re
 #pragma unroll
                     for (int l = 0; l < N - 1; ++l)
                         rows[u][l] = Quad<GT>::load(fv.a[l], (int64_t)ids[u][l] * ld + 4 * lig);
-                if (f0 == 0 && k0 + 64 < e)
+                // the next round's records, after the gathers of the round's last
+                // batch: the wait for the gathers leaves them in flight during
+                // the walk, and no later gather waits behind them (past the
+                // tile's end: its last record again)
+                if constexpr (decltype(last)::value)
                     load_record<N>(tv.rec, min(k0 + 64 + lane, e - 1), nx, nrow, nhid);
 #pragma unroll
                 for (int u = 0; u < UF; ++u) {
@@ -354,7 +375,9 @@ k_mttkrp_tiled(TiledView tv, LeafFac fv, int64_t ld, int64_t nwaves, float *__re
                         h.z *= rows[u][l].z;
                         h.w *= rows[u][l].w;
                     }
-                    if (ok[u]) *reinterpret_cast<float4 *>(Hs + (int64_t)(u * NG + g) * RQ + 4 * lig) = h;
+                    // lanes without a fiber write the spare row PF (the store is
+                    // unconditional, so the gathers stay ahead of the prefetch)
+                    *reinterpret_cast<float4 *>(Hs + (int64_t)(ok[u] ? u * NG + g : PF) * RQ + 4 * lig) = h;
                 }
                 wave_sync_lds();
                 const int jb = __builtin_amdgcn_readfirstlane(fpos[f0]);
@@ -389,7 +412,10 @@ k_mttkrp_tiled(TiledView tv, LeafFac fv, int64_t ld, int64_t nwaves, float *__re
                     }
                 }
                 wave_sync_lds();
-            }
+            };
+            int f0 = 0;
+            for (; f0 + PF < F; f0 += PF) batch(f0, std::false_type{});
+            batch(f0, std::true_type{});
             x = nx;
             row = nrow;
 #pragma unroll
@@ -483,7 +509,7 @@ int32_t tiled_height(int R, size_t lds_wave) {
     const int RQ = (R + 3) & ~3;
     const int NG = 64 / (RQ / 4);
     const int PF = NG * (NG >= 7 ? 2 : 4);
-    const size_t fixed = sizeof(float) * ((size_t)PF * RQ + 3) + sizeof(int32_t) * 65;
+    const size_t fixed = sizeof(float) * ((size_t)(PF + 1) * RQ + 3) + sizeof(int32_t) * 65;
     if (lds_wave <= fixed) return 0;
     return (int32_t)((lds_wave - fixed) / (sizeof(float) * R));
 }
@@ -512,7 +538,7 @@ cpd_status launch_tiled(int N, bool bf16, const cpd_csf_s::LeafTiling &lt, int64
     const int RQ = (R + 3) & ~3;
     const int NG = 64 / (RQ / 4);
     const int UF = NG >= 7 ? 2 : 4;
-    const size_t lds = sizeof(float) * (((size_t)NG * UF * RQ + (size_t)lt.B * R + 3) & ~size_t(3));  // per wave
+    const size_t lds = sizeof(float) * ((((size_t)NG * UF + 1) * RQ + (size_t)lt.B * R + 3) & ~size_t(3));  // per wave
     switch (N) {
 #define CPD_TILED_N(n)                                                                         \
     case n:                                                                                    \
