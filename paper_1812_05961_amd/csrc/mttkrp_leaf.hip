@@ -375,9 +375,11 @@ k_mttkrp_tiled(TiledView tv, LeafFac fv, int64_t ld, int64_t nwaves, float *__re
                         h.z *= rows[u][l].z;
                         h.w *= rows[u][l].w;
                     }
-                    // lanes without a fiber write the spare row PF (the store is
-                    // unconditional, so the gathers stay ahead of the prefetch)
-                    *reinterpret_cast<float4 *>(Hs + (int64_t)(ok[u] ? u * NG + g : PF) * RQ + 4 * lig) = h;
+                    // unconditional store, so the gathers stay ahead of the
+                    // prefetch: a group without a fiber writes its own slot,
+                    // which this batch's walk does not read, the idle lanes
+                    // the spare row PF (distinct rows: no bank conflicts)
+                    *reinterpret_cast<float4 *>(Hs + (int64_t)(g < NG ? u * NG + g : PF) * RQ + 4 * lig) = h;
                 }
                 wave_sync_lds();
                 const int jb = __builtin_amdgcn_readfirstlane(fpos[f0]);
