@@ -379,7 +379,8 @@ def profile_workload(workload, precision, what):
     (what = "root"), or on the ascending-length tree every mode's MTTKRP at its
     level, atomic variant (what = "single": ROW kernels above the leaf level)
     or the library's default choice (what = "single-auto": TILED kernels at the
-    internal level of the NELL-2 tree and at the leaf level)."""
+    internal level of the NELL-2 tree and at the leaf level), or on the rooted
+    trees the row Grams of CP completion per mode (what = "gram")."""
     import torch
 
     from paper_1812_05961_amd import cpd, synth
@@ -403,7 +404,16 @@ def profile_workload(workload, precision, what):
         f = torch.zeros((d, ld), dtype=torch.float32, device=dev)
         f[:, :R] = torch.rand((d, R), device=dev, generator=g)
         facs.append(f if precision == "fp32" else f.to(torch.bfloat16))
-    if what == "root":
+    if what == "gram":
+        trees = cpd.csf_build_rooted(x.inds, x.vals, x.dims)
+        f32 = [f.float() for f in facs]
+        for m, c in enumerate(trees):
+            G = cpd.row_gram(c, f32, m, rank=R)
+            torch.cuda.synchronize()
+            del G
+            c.free()
+            log("row Grams of mode %d done" % m)
+    elif what == "root":
         for mode, order in enumerate(root_orders(x.dims)):
             c = cpd.csf_build(x.inds, x.vals, x.dims, order)
             out = torch.empty((x.dims[mode], ld), device=dev)
@@ -434,7 +444,7 @@ def main():
     ap.add_argument("--no-completion", action="store_true", help="skip the CP-with-missing-values timings")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the FP32 / BF16 per-mode reports of the three benchmark tensors")
-    ap.add_argument("--profile-workload", choices=["root", "single", "single-auto"],
+    ap.add_argument("--profile-workload", choices=["root", "single", "single-auto", "gram"],
                     help="run only a short MTTKRP workload for rocprofv3 (no JSON line)")
     args = ap.parse_args()
     if args.profile_workload:
