@@ -415,6 +415,31 @@ def test_mttkrp_internal_tiled_many_tiles(R):
         c.free()
 
 
+def test_mttkrp_internal_tiled_wide_key():
+    """A size-ordered internal tiling whose sort key does not fit 64 bits:
+    three 2^23-row modes and a 60-row root, so at depth 1 the tile number
+    (17 bits) and the two large other levels (23 bits each) fill the key and
+    the root index is left out of it (the order inside a tile then only
+    partly by size; any order is correct).  Every internal level and the
+    leaf level against the oracle, FP32, rank 8."""
+    cpd = _cpd()
+    dims = (1 << 23, 1 << 23, 1 << 23, 60)
+    # one batch of draws, de-duplicated (top-up needs fewer than 2^62 cells)
+    t = synth.gen_sparse(dims, 200_000, (0.5, 0.5, 0.5, 0.0), "lognormal:1.0", 43, device="cpu", topup=False,
+                         fp32=True)
+    inds, vals = t.numpy()
+    order = [3, 0, 1, 2]
+    c = cpd.csf_build(_dev(t.inds), _dev(t.vals), t.dims, order)
+    R = 8
+    facs = _factors(t.dims, R, 47)
+    for depth in (1, 2, 3):
+        mode = order[depth]
+        ref = ocoo.mttkrp(t.dims, inds, vals, [f.numpy() for f in facs], mode)
+        y, _u = _run(cpd, c, facs, mode, R, "fp32", "tiled", "auto")
+        assert relerr(y, ref) <= 1e-5, (depth, relerr(y, ref))
+    c.free()
+
+
 @pytest.mark.parametrize("R", [8, 35, 64])
 def test_mttkrp_leaf_tiled_many_tiles(R):
     """The leaf-mode tiling on a 30,000-row leaf mode (tens of tiles at rank
