@@ -221,18 +221,17 @@ cpd_status launch_leaf_n(const LeafView &cv, const LeafFac &fv, int64_t ld, cons
 // level, in tree order inside a tile, the fibers of the tree; at an internal
 // level, ordered by size, leaves that differ only in their level-d index).
 // Each wave owns a contiguous range of the regrouped leaves and a private LDS
-// table of one tile's B x R
-// output rows: it takes its range tile by tile (zero the table, add every
-// leaf of the tile into it, add the table's nonzero entries to Y), so every
-// nonzero is a plain LDS read-add-write by the one wave that owns the row --
-// no atomics (the LDS FP32 atomic add measured several times slower than a
-// plain read-modify-write here).  Rounds of 64 leaves as in the ROUND kernel:
-// each lane loads its leaf's record (value, local row, the fiber's level
-// indices) with one or two 16-byte loads (a fiber run starts where any of
-// those indices changes), each run's H row
-// gathered once into the wave's H table,
-// then the leaves walked one per step, the rank across the lanes; two
-// consecutive leaves of one row are summed before their read-modify-write.
+// table of one tile's B x R output rows: it takes its range tile by tile
+// (zero the table, add every leaf of the tile into it, add the table's
+// nonzero entries to Y), so every nonzero is a plain LDS read-add-write by
+// the one wave that owns the row -- no atomics (the LDS FP32 atomic add
+// measured several times slower than a plain read-modify-write here).
+// Rounds of 64 leaves as in the ROUND kernel: each lane loads its leaf's
+// record (value, local row, the other levels' indices) with one or two
+// 16-byte loads (a fiber run starts where any of those indices changes),
+// each run's H row is gathered once into the wave's H table, a batch of PF
+// runs at a time, then the batch's leaves are walked two per step, the rank
+// across the lanes.
 typedef int32_t i32x4_t __attribute__((ext_vector_type(4)));
 
 struct TiledView {
