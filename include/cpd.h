@@ -223,7 +223,9 @@ cpd_status cpd_mttkrp_noalloc(cpd_csf csf, const void *const *factors, int32_t l
  * for CPD_VARIANT_PRIVATE, and TILED at an internal level with
  * CPD_VARIANT_AUTO; cpd_mttkrp_noalloc runs ROUND at the leaf level and the
  * shape rule's kernel at an internal level when the tree holds no tiling of
- * that height yet).
+ * that height yet, and so does cpd_mttkrp with CPD_KERNEL_AUTO when the
+ * device has no room for the tiling; TILED requested explicitly returns
+ * CPD_ENOMEM then).
  * *kernel_out (host) = CPD_KERNEL_ROW, CPD_KERNEL_LANE, CPD_KERNEL_ROUND or
  * CPD_KERNEL_TILED; CPD_EUNSUPPORTED when ROW, ROUND or TILED is requested and
  * not eligible, or N is outside 2..5. */

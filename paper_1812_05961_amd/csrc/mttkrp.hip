@@ -532,7 +532,12 @@ cpd_status mttkrp_ws(cpd_csf_s *c, const void *const *factors, int32_t ld, int32
         const int32_t Bdef = std::max(tiled_height(R, TILED_LDS), TILED_MIN_ROWS);
         const int32_t B = o.tile_nnz > 0 ? std::min<int32_t>(o.tile_nnz, Bmax) : std::min(Bdef, Bmax);
         cpd_csf_s::LeafTiling lt;
-        if (B >= 1) CPD_TRY(csf_level_tiling(c, d, B, order, ws != nullptr, &lt, s));
+        bool no_room = false;  // AUTO and no device memory for the tiling
+        if (B >= 1) {
+            const cpd_status st = csf_level_tiling(c, d, B, order, ws != nullptr, &lt, s);
+            if (st == CPD_ENOMEM && o.kernel == CPD_KERNEL_AUTO) no_room = true;
+            else if (st != CPD_OK) return st;
+        }
         if (lt.B > 0) {
             const void *fac_by_level[CPD_MAX_MODES];
             for (int l = 0; l < N; ++l) fac_by_level[l] = fv.a[l];
@@ -541,8 +546,9 @@ cpd_status mttkrp_ws(cpd_csf_s *c, const void *const *factors, int32_t ld, int32
             if (st == CPD_OK && ev1) CPD_HIP(hipEventRecord(ev1, s));
             return st;
         }
-        if (!ws) CPD_FAIL(CPD_EUNSUPPORTED, "no mode tiling fits %d bytes of LDS at rank %d", lds_max, R);
-        // allocation-free call on a tree without a cached tiling
+        if (!ws && !no_room) CPD_FAIL(CPD_EUNSUPPORTED, "no mode tiling fits %d bytes of LDS at rank %d", lds_max, R);
+        // allocation-free call on a tree without a cached tiling, or AUTO
+        // without the device memory to build one: a kernel that needs no tiling
         if (leaf) {
             kernel = CPD_KERNEL_ROUND;
             if (o.tile_nnz == 0) o.tile_nnz = 256;

@@ -91,3 +91,28 @@ def test_als_fails_cleanly_and_recovers(limit):
     limit(None)
     got = cpd.als(inds, vals, t.dims, rank=8, iters=2, seed=3)
     assert np.isfinite(got["fit"])
+
+
+def test_auto_runs_without_the_tiling_when_it_does_not_fit(limit):
+    """AUTO takes TILED at an internal level; when the level's mode tiling
+    cannot be allocated it runs the shape rule's kernel instead (ROW here),
+    while TILED asked for explicitly fails with CPD_ENOMEM.  A 1 MiB limit
+    refuses the tiling (16 bytes per nonzero) and admits ROW's tables (the
+    leaf factor in rank order: 5,000 rows of 64 bytes)."""
+    cpd = _cpd()
+    t = synth.gen_sparse((30, 40, 5000), 200_000, (0.5, 0.5, 1.0), "lognormal:1.0", 67, device="cpu",
+                         topup=True, fp32=True)
+    c = cpd.csf_build(t.inds.cuda(), t.vals.cuda(), t.dims, [0, 1, 2])
+    facs = [torch.rand((d, 16), device="cuda") for d in t.dims]
+    ih, vh = t.numpy()
+    ref = ocoo.mttkrp(t.dims, ih, vh, [f.cpu().double().numpy() for f in facs], 1)
+    limit(1 << 20)
+    with pytest.raises(cpd.CpdError) as e:
+        cpd.mttkrp(c, facs, 1, rank=16, kernel="tiled")
+    assert e.value.status == cpd.CPD_ENOMEM
+    y = cpd.mttkrp(c, facs, 1, rank=16).cpu().numpy()
+    assert _relerr(y, ref) <= 1e-5
+    limit(None)
+    y = cpd.mttkrp(c, facs, 1, rank=16).cpu().numpy()  # TILED, the tiling built now
+    assert _relerr(y, ref) <= 1e-5
+    c.free()
